@@ -1,0 +1,170 @@
+/*
+ * kkt.h -- C ABI of the MI355X sparse KKT refactorization library.
+ *
+ * The library solves a sequence of linear systems K_k x_k = b_k, k = 1..M, whose matrices
+ * share one sparsity pattern while their values change (the interior-point Newton systems
+ * of Section II, eq. (12)).  It follows the refactorization strategy of Section III,
+ * Algorithm 1: the first system is analysed and factored once on the host (ordering,
+ * equilibration, pivot order and the pattern of L and U, as in the analysis stage of the
+ * three-stage direct solver of Section II); every later system is refactored on the GPU
+ * with that pattern and pivot order fixed, solved by forward/backward substitution and
+ * refined iteratively.  The paper allows the permutations to come from any LU solver;
+ * kkt_opts.fixed_p / fixed_q accept them.
+ *
+ * Conventions
+ *  - Matrices are square, in CSR with int64 row pointers and int32 column indices, rows
+ *    sorted ascending, no duplicates, every diagonal entry present, both triangles stored
+ *    (no symmetry is assumed).  Values are FP64 in that CSR order.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are GPU memory of the
+ *    device that was current at kkt_bind.  Every buffer belongs to the caller; the library
+ *    owns only the host handle.  The device workspace (kkt_workspace_bytes) is caller
+ *    memory that the library carves up; it must stay allocated until kkt_destroy.
+ *  - Calls that take a stream are enqueued on it and return without waiting unless stated.
+ *  - Indices of the symbolic export are 0-based in the permuted index space: row k of
+ *    P A Q is row P[k] of A and column k is column Q[k].
+ *  - Return value: 0 = KKT_OK, > 0 = warning, < 0 = error.  A handle is not thread safe;
+ *    distinct handles are independent.
+ */
+#ifndef KKT_H
+#define KKT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *hipStream_t;   /* identical to HIP's own typedef */
+
+#define KKT_OK 0
+#define KKT_WARN_PIVOT_PERTURBED 1  /* a refactor replaced tiny pivots (kkt_info) */
+#define KKT_WARN_NOT_CONVERGED 2    /* refinement stopped at max_iters above berr_tol */
+#define KKT_ERR_ARG (-1)            /* null pointer, bad size, bad option */
+#define KKT_ERR_PATTERN (-2)        /* non-square, unsorted, duplicate, out of range, no diagonal */
+#define KKT_ERR_SINGULAR (-3)       /* analyze found a pivot step with no nonzero candidate */
+#define KKT_ERR_NONFINITE (-4)      /* NaN/Inf in values or factors */
+#define KKT_ERR_STATE (-5)          /* call order: refactor before bind, solve before refactor */
+#define KKT_ERR_NOMEM (-6)          /* host allocation failed or workspace too small */
+#define KKT_ERR_DEVICE (-7)         /* a HIP call failed */
+
+typedef struct kkt_handle kkt_handle;
+
+typedef struct {
+    /* Pivot rule at analyze (Algorithm 1, first system): the diagonal candidate is kept
+     * when it is nonzero and |x_diag| >= pivot_tau * max|candidates|; otherwise the largest
+     * candidate (lowest row index on ties).  0 = static diagonal pivoting (default). */
+    double pivot_tau;
+    /* Refactor: |u_kk| < tiny_pivot * ||A~||_inf is replaced by +-tiny_pivot*||A~||_inf
+     * (sign kept, zero counts as +) and counted.  Default 2^-26. */
+    double tiny_pivot;
+    /* 1 = power-of-two row-then-column max equilibration, recomputed per refactor. */
+    int32_t equilibrate;
+    /* FGMRES restart length m (1..64), iteration cap, backward-error target. */
+    int32_t gmres_restart;
+    int32_t max_iters;
+    double berr_tol;
+    /* Maximum width of a structural supernode in the symbolic export (>= 1). */
+    int32_t sn_max_width;
+    /* Optional externally chosen permutations (host, int32[n]); fixed_p requires fixed_q.
+     * With fixed_q the ordering step is skipped; with both, pivoting is skipped too. */
+    const int32_t *fixed_p;
+    const int32_t *fixed_q;
+} kkt_opts;
+
+typedef struct {
+    int32_t iters;              /* FGMRES (Arnoldi) steps after the first solve */
+    int32_t status;             /* KKT_OK, KKT_WARN_NOT_CONVERGED or an error */
+    double berr;                /* ||b - A x||_inf / (||A||_inf ||x||_inf + ||b||_inf) */
+    int64_t perturbed_pivots;   /* pivots replaced by the last kkt_refactor */
+} kkt_info;
+
+typedef struct {
+    int32_t n;                  /* order N */
+    int32_t nsn;                /* structural supernodes */
+    int64_t nnz_a;              /* entries of A */
+    int64_t nnz_lu;             /* entries of the combined L+U (diagonal included) */
+    int32_t levels_f;           /* refactor dependency levels (columns) */
+    int32_t levels_l;           /* forward-solve levels (rows) */
+    int32_t levels_u;           /* backward-solve levels (rows) */
+    int32_t gpu_levels_f;       /* launches of one GPU refactorization */
+    int32_t gpu_levels_l;       /* launches of one GPU forward solve */
+    int32_t gpu_levels_u;       /* launches of one GPU backward solve */
+    double flops_refactor;      /* sum_k 2 |L(:,k)| |U(k,:)| + |L(:,k)| */
+} kkt_stats;
+
+/* Fills *o with the defaults listed in kkt_opts. */
+void kkt_default_opts(kkt_opts *o);
+
+/* Analysis stage (Section II; Algorithm 1, factor the first system, extract the
+ * permutations and the L/U pattern, convert the layout).  Host only, no device work.
+ * rowptr int64[n+1], colind int32[nnz], values_k1 FP64[nnz] (all host, borrowed for the
+ * call only); opts may be NULL for defaults.  On success *out owns a new handle.
+ * Errors: ARG, PATTERN, SINGULAR, NONFINITE, NOMEM. */
+int kkt_analyze(int32_t n, const int64_t *rowptr, const int32_t *colind,
+                const double *values_k1, const kkt_opts *opts, kkt_handle **out);
+
+/* Sizes and schedule statistics of an analysed handle. */
+int kkt_get_stats(const kkt_handle *h, kkt_stats *out);
+
+/* Canonical symbolic factorization (host copies; every pointer is caller memory of the
+ * stated size, any may be NULL to skip it):
+ *   P, Q int32[n]; colptr int64[n+1]; rowidx int32[nnz_lu] -- combined L+U in CSC, per
+ *   column U rows ascending, the diagonal, then L rows ascending; parent int32[n] (first
+ *   L row below the diagonal, -1 if none); lev_f, lev_l, lev_u int32[n]; sn_start
+ *   int32[nsn+1]; map int64[nnz_a] (slot in rowidx of each input entry, CSR order). */
+int kkt_export_symbolic(const kkt_handle *h, int32_t *P, int32_t *Q, int64_t *colptr,
+                        int32_t *rowidx, int32_t *parent, int32_t *lev_f, int32_t *lev_l,
+                        int32_t *lev_u, int32_t *sn_start, int64_t *map);
+
+/* Device bytes that kkt_bind needs for right-hand sides of up to max_nrhs columns. */
+int kkt_workspace_bytes(const kkt_handle *h, int32_t max_nrhs, size_t *bytes);
+
+/* Setup (Algorithm 1, set up the GPU refactorization): uploads the symbolic structure and
+ * schedules into d_workspace (device, >= kkt_workspace_bytes, 256-byte aligned) on stream
+ * and records the device.  Waits for the upload.  Errors: ARG, NOMEM (too small), DEVICE. */
+int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs,
+             hipStream_t stream);
+
+/* Value update and refactorization without pivoting (Algorithm 1, update the factor
+ * object with the new values, refactor).  d_values: device FP64[nnz_a] in the analysed
+ * CSR order, BORROWED until the next kkt_refactor or kkt_destroy (kkt_refine reads it for
+ * residuals).  Asynchronous.  Errors: ARG, STATE (not bound), DEVICE.  Tiny pivots and
+ * non-finite factors are reported by kkt_refine / kkt_refactor_status. */
+int kkt_refactor(kkt_handle *h, const double *d_values, hipStream_t stream);
+
+/* Waits for the last refactorization; *perturbed = replaced pivots.  Returns OK,
+ * WARN_PIVOT_PERTURBED, ERR_NONFINITE or ERR_STATE. */
+int kkt_refactor_status(kkt_handle *h, int64_t *perturbed, hipStream_t stream);
+
+/* Triangular solves (Algorithm 1, triangular solve), no refinement:
+ * x = Q C (L U)^-1 P R b.  d_b, d_x: device FP64, column j at offset j*ld, nrhs columns,
+ * ld >= n; d_x may equal d_b.  Asynchronous.  Errors: ARG, STATE, DEVICE. */
+int kkt_solve(kkt_handle *h, const double *d_b, double *d_x, int32_t nrhs, int64_t ld,
+              hipStream_t stream);
+
+/* Solve followed by FGMRES(m) iterative refinement with FP64 residuals on the original A
+ * (Algorithm 1: the solve is always followed by iterative refinement; Section V: a
+ * configurable refinement).  Stops when berr <= berr_tol or after max_iters Arnoldi steps.
+ * info: host kkt_info[nrhs] (may be NULL).  Waits for completion.  Returns OK,
+ * WARN_NOT_CONVERGED (some column missed the target), or an error. */
+int kkt_refine(kkt_handle *h, const double *d_b, double *d_x, int32_t nrhs, int64_t ld,
+               kkt_info *info, hipStream_t stream);
+
+/* Test hook: copies the factors of the last refactorization to host memory in the
+ * canonical L+U CSC order (FP64[nnz_lu]) and the scale factors (FP64[n] each, may be
+ * NULL).  Waits. */
+int kkt_export_factors(kkt_handle *h, double *h_lu, double *h_r, double *h_c,
+                       hipStream_t stream);
+
+/* Frees the handle (not the caller's workspace).  NULL is ignored. */
+void kkt_destroy(kkt_handle *h);
+
+/* Static description of a status code. */
+const char *kkt_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KKT_H */

@@ -1,0 +1,256 @@
+"""Python binding of the MI355X sparse KKT refactorization library (libkkt.so).
+
+Argument marshalling only: every step of the analysis runs in the library's C++ host code
+and every step of the refactorization, solves and refinement runs in its HIP kernels.
+PyTorch supplies device memory (the workspace and vectors) and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkkt.so")
+
+OK, WARN_PIVOT_PERTURBED, WARN_NOT_CONVERGED = 0, 1, 2
+ERR_ARG, ERR_PATTERN, ERR_SINGULAR, ERR_NONFINITE, ERR_STATE, ERR_NOMEM, ERR_DEVICE = -1, -2, -3, -4, -5, -6, -7
+
+
+class KKTError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib().kkt_strerror(code).decode() if _LIB is not None else str(code)
+        super().__init__(f"{where}: {msg} ({code})")
+        self.code = code
+
+
+class _Opts(C.Structure):
+    _fields_ = [("pivot_tau", C.c_double), ("tiny_pivot", C.c_double), ("equilibrate", C.c_int32),
+                ("gmres_restart", C.c_int32), ("max_iters", C.c_int32), ("berr_tol", C.c_double),
+                ("sn_max_width", C.c_int32), ("fixed_p", C.c_void_p), ("fixed_q", C.c_void_p)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("berr", C.c_double),
+                ("perturbed_pivots", C.c_int64)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nsn", C.c_int32), ("nnz_a", C.c_int64), ("nnz_lu", C.c_int64),
+                ("levels_f", C.c_int32), ("levels_l", C.c_int32), ("levels_u", C.c_int32),
+                ("gpu_levels_f", C.c_int32), ("gpu_levels_l", C.c_int32), ("gpu_levels_u", C.c_int32),
+                ("flops_refactor", C.c_double)]
+
+
+EXPORTS = ["kkt_default_opts", "kkt_analyze", "kkt_get_stats", "kkt_export_symbolic",
+           "kkt_workspace_bytes", "kkt_bind", "kkt_refactor", "kkt_refactor_status", "kkt_solve",
+           "kkt_refine", "kkt_export_factors", "kkt_destroy", "kkt_strerror"]
+
+_LIB = None
+
+
+def _lib():
+    """Loads the HIP library; there is no fallback path."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2302_08656_amd/build.py "
+                              "(hipcc --offload-arch=gfx950)")
+        L = C.CDLL(LIB_PATH)
+        p = C.c_void_p
+        L.kkt_default_opts.argtypes = [C.POINTER(_Opts)]
+        L.kkt_default_opts.restype = None
+        L.kkt_analyze.argtypes = [C.c_int32, p, p, p, C.POINTER(_Opts), C.POINTER(C.c_void_p)]
+        L.kkt_get_stats.argtypes = [p, C.POINTER(_Stats)]
+        L.kkt_export_symbolic.argtypes = [p] * 11
+        L.kkt_workspace_bytes.argtypes = [p, C.c_int32, C.POINTER(C.c_size_t)]
+        L.kkt_bind.argtypes = [p, p, C.c_size_t, C.c_int32, p]
+        L.kkt_refactor.argtypes = [p, p, p]
+        L.kkt_refactor_status.argtypes = [p, C.POINTER(C.c_int64), p]
+        L.kkt_solve.argtypes = [p, p, p, C.c_int32, C.c_int64, p]
+        L.kkt_refine.argtypes = [p, p, p, C.c_int32, C.c_int64, C.POINTER(_Info), p]
+        L.kkt_export_factors.argtypes = [p, p, p, p, p]
+        L.kkt_destroy.argtypes = [p]
+        L.kkt_destroy.restype = None
+        L.kkt_strerror.argtypes = [C.c_int]
+        L.kkt_strerror.restype = C.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def default_opts() -> dict:
+    o = _Opts()
+    _lib().kkt_default_opts(C.byref(o))
+    return {f: getattr(o, f) for f, _ in _Opts._fields_ if f not in ("fixed_p", "fixed_q")}
+
+
+@dataclasses.dataclass
+class Info:
+    iters: int
+    status: int
+    berr: float
+    perturbed_pivots: int
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class KKTSolver:
+    """One sparsity pattern: analyze once on construction, then bind a device workspace
+    and refactor / solve / refine each new system."""
+
+    def __init__(self, n, rowptr, colind, values_k1, *, pivot_tau=None, tiny_pivot=None,
+                 equilibrate=None, gmres_restart=None, max_iters=None, berr_tol=None,
+                 sn_max_width=None, fixed_p=None, fixed_q=None):
+        L = _lib()
+        self.n = int(n)
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        colind = np.ascontiguousarray(colind, dtype=np.int32)
+        v = np.ascontiguousarray(values_k1, dtype=np.float64)
+        o = _Opts()
+        L.kkt_default_opts(C.byref(o))
+        for name, val in (("pivot_tau", pivot_tau), ("tiny_pivot", tiny_pivot), ("equilibrate", equilibrate),
+                          ("gmres_restart", gmres_restart), ("max_iters", max_iters), ("berr_tol", berr_tol),
+                          ("sn_max_width", sn_max_width)):
+            if val is not None:
+                setattr(o, name, val)
+        fp = None if fixed_p is None else np.ascontiguousarray(fixed_p, dtype=np.int32)
+        fq = None if fixed_q is None else np.ascontiguousarray(fixed_q, dtype=np.int32)
+        o.fixed_p = None if fp is None else fp.ctypes.data
+        o.fixed_q = None if fq is None else fq.ctypes.data
+        h = C.c_void_p()
+        rc = L.kkt_analyze(self.n, _np_ptr(rowptr), _np_ptr(colind), _np_ptr(v), C.byref(o), C.byref(h))
+        if rc != OK:
+            raise KKTError(rc, "kkt_analyze")
+        self._h = h
+        self.opts = {f: getattr(o, f) for f, _ in _Opts._fields_ if f not in ("fixed_p", "fixed_q")}
+        st = _Stats()
+        L.kkt_get_stats(h, C.byref(st))
+        self.stats = {f: getattr(st, f) for f, _ in _Stats._fields_}
+        self.nnz_a = st.nnz_a
+        self.nnz_lu = st.nnz_lu
+        self.nsn = st.nsn
+        self._ws = None
+        self._values = None
+
+    # ---------------------------------------------------------------- host-only queries
+    def export_symbolic(self) -> dict:
+        n, nlu, na, ns = self.n, self.nnz_lu, self.nnz_a, self.nsn
+        out = dict(P=np.empty(n, np.int32), Q=np.empty(n, np.int32), colptr=np.empty(n + 1, np.int64),
+                   rowidx=np.empty(nlu, np.int32), parent=np.empty(n, np.int32),
+                   lev_f=np.empty(n, np.int32), lev_l=np.empty(n, np.int32), lev_u=np.empty(n, np.int32),
+                   sn_start=np.empty(ns + 1, np.int32), map=np.empty(na, np.int64))
+        rc = _lib().kkt_export_symbolic(self._h, *[_np_ptr(out[k]) for k in
+                                                   ("P", "Q", "colptr", "rowidx", "parent", "lev_f",
+                                                    "lev_l", "lev_u", "sn_start", "map")])
+        if rc != OK:
+            raise KKTError(rc, "kkt_export_symbolic")
+        return out
+
+    def workspace_bytes(self, max_nrhs=1) -> int:
+        b = C.c_size_t()
+        rc = _lib().kkt_workspace_bytes(self._h, int(max_nrhs), C.byref(b))
+        if rc != OK:
+            raise KKTError(rc, "kkt_workspace_bytes")
+        return b.value
+
+    # ---------------------------------------------------------------- device work
+    def bind(self, device=None, max_nrhs=1, stream=None):
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        nbytes = self.workspace_bytes(max_nrhs)
+        with torch.cuda.device(dev):
+            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+            base = self._ws.data_ptr()
+            off = (-base) % 256
+            rc = _lib().kkt_bind(self._h, C.c_void_p(base + off), nbytes, int(max_nrhs), _stream_ptr(stream))
+        if rc != OK:
+            raise KKTError(rc, "kkt_bind")
+        self.device = dev
+        return self
+
+    def refactor(self, values, stream=None):
+        """values: cuda float64 tensor [nnz_a] in the analysed CSR order (kept alive here,
+        the library reads it again for residuals)."""
+        self._check_vec(values, self.nnz_a)
+        rc = _lib().kkt_refactor(self._h, _dev_ptr(values), _stream_ptr(stream))
+        if rc != OK:
+            raise KKTError(rc, "kkt_refactor")
+        self._values = values
+        return self
+
+    def refactor_status(self, stream=None):
+        pert = C.c_int64()
+        rc = _lib().kkt_refactor_status(self._h, C.byref(pert), _stream_ptr(stream))
+        if rc < 0:
+            raise KKTError(rc, "kkt_refactor_status")
+        return rc, pert.value
+
+    def solve(self, b, x=None, stream=None):
+        import torch
+        nrhs, ld = self._rhs_shape(b)
+        if x is None:
+            x = torch.empty_like(b)
+        rc = _lib().kkt_solve(self._h, _dev_ptr(b), _dev_ptr(x), nrhs, ld, _stream_ptr(stream))
+        if rc != OK:
+            raise KKTError(rc, "kkt_solve")
+        return x
+
+    def refine(self, b, x=None, stream=None):
+        import torch
+        nrhs, ld = self._rhs_shape(b)
+        if x is None:
+            x = torch.empty_like(b)
+        info = (_Info * nrhs)()
+        rc = _lib().kkt_refine(self._h, _dev_ptr(b), _dev_ptr(x), nrhs, ld, info, _stream_ptr(stream))
+        if rc < 0:
+            raise KKTError(rc, "kkt_refine")
+        return x, [Info(i.iters, i.status, i.berr, i.perturbed_pivots) for i in info]
+
+    def export_factors(self, stream=None):
+        lu = np.empty(self.nnz_lu)
+        r = np.empty(self.n)
+        c = np.empty(self.n)
+        rc = _lib().kkt_export_factors(self._h, _np_ptr(lu), _np_ptr(r), _np_ptr(c), _stream_ptr(stream))
+        if rc != OK:
+            raise KKTError(rc, "kkt_export_factors")
+        return lu, r, c
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _LIB is not None:
+            _LIB.kkt_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        self.close()
+
+    # ---------------------------------------------------------------- helpers
+    def _check_vec(self, t, size):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and t.numel() == size):
+            raise ValueError(f"expected a contiguous cuda float64 tensor with {size} elements")
+
+    def _rhs_shape(self, b):
+        import torch
+        if not (isinstance(b, torch.Tensor) and b.is_cuda and b.dtype == torch.float64 and b.is_contiguous()):
+            raise ValueError("expected a contiguous cuda float64 tensor")
+        if b.dim() == 1 and b.numel() == self.n:
+            return 1, self.n
+        if b.dim() == 2 and b.shape[1] == self.n:
+            return b.shape[0], self.n
+        raise ValueError(f"right-hand side must have shape [{self.n}] or [nrhs, {self.n}]")

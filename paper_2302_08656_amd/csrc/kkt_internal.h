@@ -1,0 +1,74 @@
+// Internal declarations shared by the host symbolic phase, the schedule builder and the
+// HIP runtime of the KKT refactorization library.  Not part of the public ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/kkt.h"
+
+namespace kkt {
+
+// Canonical symbolic factorization (analysis stage).  Permuted index space: row k of
+// P A Q is row P[k] of A, column k is column Q[k].
+struct Symbolic {
+    int32_t n = 0;
+    int64_t nnz_a = 0;
+    std::vector<int64_t> a_rowptr;
+    std::vector<int32_t> a_colind;
+    std::vector<int32_t> P, Q, pinv, qinv;
+    std::vector<int64_t> colptr;   // combined L+U, CSC, rows ascending per column
+    std::vector<int32_t> rowidx;
+    std::vector<int32_t> ulen;     // entries above the diagonal per column
+    std::vector<int32_t> parent, lev_f, lev_l, lev_u, sn_start;
+    std::vector<int64_t> map;      // CSR entry of A -> slot of L+U
+    int32_t nsn() const { return (int32_t)sn_start.size() - 1; }
+    int64_t nnz_lu() const { return colptr.empty() ? 0 : colptr.back(); }
+};
+
+// Status-returning host steps of the analysis.
+int validate_pattern(int32_t n, const int64_t *rowptr, const int32_t *colind);
+int exact_min_degree(int32_t n, const int64_t *rowptr, const int32_t *colind,
+                     std::vector<int32_t> &order);
+int pow2_scaling(int32_t n, const int64_t *rowptr, const int32_t *colind, const double *v,
+                 bool scale, std::vector<double> &r, std::vector<double> &c);
+int analyze_symbolic(int32_t n, const int64_t *rowptr, const int32_t *colind,
+                     const double *values, const kkt_opts &o, Symbolic &s);
+
+// Maximum width of a GPU panel (a column range of a structural supernode handled by one
+// work item).  Panels never cross supernode boundaries.
+constexpr int kPanelMax = 32;
+// Width-1 panels of the triangular solves are packed this many to a wavefront.
+constexpr int kSolvePack = 8;
+
+// Device schedule, built on the host once per pattern and uploaded by kkt_bind.
+struct Schedule {
+    int32_t npan = 0;
+    std::vector<int32_t> pan_start;     // [npan+1] first column of each panel
+    std::vector<int32_t> pan_r;         // [npan] L rows below the panel (= U columns right)
+    // refactorization: launch l runs items [f_lvl[l], f_lvl[l+1])
+    std::vector<int32_t> f_lvl;
+    std::vector<int32_t> f_item_panel;  // panel to factor after the pulls, or -1
+    std::vector<int32_t> f_item_tgt;    // [nitems+1] range into f_tgt_col
+    std::vector<int32_t> f_tgt_col;     // target columns
+    std::vector<int32_t> f_tgt_src;     // [ntgt+1] range into f_src_panel
+    std::vector<int32_t> f_src_panel;   // source panels, ascending
+    // triangular solves: launch l runs items [x_lvl[l], x_lvl[l+1]); item = panel range
+    std::vector<int32_t> l_lvl, l_item_p0, l_item_np;
+    std::vector<int32_t> u_lvl, u_item_p0, u_item_np;
+    // level-sorted panel lists referenced by the solve items
+    std::vector<int32_t> l_pan, u_pan;
+    // combined L+U in CSR for the row-oriented solves
+    std::vector<int32_t> csr_rowptr, csr_col, csr_src, csr_diag;
+    // value update: for each L+U slot, the CSR entry of A it receives (-1: fill)
+    std::vector<int32_t> lu_src;
+    // CSC view of A's pattern (positions into the CSR value array)
+    std::vector<int32_t> a_cptr, a_cpos, a_rowid;
+    double flops = 0.0;
+};
+
+int build_schedule(const Symbolic &s, Schedule &g);
+
+}  // namespace kkt

@@ -1,0 +1,23 @@
+// Device-side types shared by the kernels and the runtime of the KKT library.
+#pragma once
+
+#include <cstdint>
+
+#include "kkt_internal.h"
+
+namespace kkt {
+
+constexpr int kFlagNonfinite = 1;
+constexpr int kFlagInternal = 2;   // a pull found no slot for a row (schedule bug)
+
+// Scalars written by the kernels and read back by the host.
+struct DevStatus {
+    double anorm_scaled;          // ||R A C||_inf of the last refactorization
+    double anorm;                 // ||A||_inf of the last refactorization
+    unsigned long long perturbed; // pivots replaced by the last refactorization
+    int flags;                    // kFlagNonfinite
+    int pad;
+    double rnorm, xnorm, bnorm;   // infinity norms of the last residual evaluation
+};
+
+}  // namespace kkt

@@ -1,0 +1,546 @@
+// C ABI of the KKT refactorization library: handle lifetime, workspace binding, and the
+// enqueueing of the value update, refactorization, solves and FGMRES refinement.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kkt_kernels.h"
+#include "kkt_kernels.hip"
+
+using namespace kkt;
+
+namespace {
+
+// device pointers carved out of the caller's workspace
+struct Dev {
+    int32_t *a_rowptr, *a_colind, *a_rowid, *a_cptr, *a_cpos, *lu_src;
+    int32_t *colptr, *rowidx, *ulen, *pan_start, *pan_r;
+    int32_t *f_item_panel, *f_item_tgt, *f_tgt_col, *f_tgt_src, *f_src_panel;
+    int32_t *l_item_p0, *l_item_np, *l_pan, *u_item_p0, *u_item_np, *u_pan;
+    int32_t *csr_rowptr, *csr_col, *csr_src, *csr_diag, *P, *Q;
+    double *r, *c, *lu, *lucsr, *y, *xt, *bsave;
+    double *V, *Z, *w, *res, *part, *hbuf, *ybuf;
+    DevStatus *st;
+};
+
+constexpr int kDotBlocks = 512;
+constexpr int kMaxRestart = 64;
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <class T> T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace
+
+struct kkt_handle {
+    kkt_opts opts{};
+    Symbolic sym;
+    Schedule sch;
+    bool bound = false;
+    bool factored = false;
+    int device = -1;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    int32_t max_nrhs = 1;
+    Dev d{};
+    const double *d_values = nullptr;
+    double *h_small = nullptr;   // pinned host staging for small read-backs
+};
+
+namespace {
+
+void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
+    const Symbolic &s = h->sym;
+    const Schedule &g = h->sch;
+    const size_t n = s.n, nlu = s.nnz_lu(), na = s.nnz_a;
+    const int m = h->opts.gmres_restart;
+    Carver c{base};
+    d.a_rowptr = c.take<int32_t>(n + 1);
+    d.a_colind = c.take<int32_t>(na);
+    d.a_rowid = c.take<int32_t>(na);
+    d.a_cptr = c.take<int32_t>(n + 1);
+    d.a_cpos = c.take<int32_t>(na);
+    d.lu_src = c.take<int32_t>(nlu);
+    d.colptr = c.take<int32_t>(n + 1);
+    d.rowidx = c.take<int32_t>(nlu);
+    d.ulen = c.take<int32_t>(n);
+    d.pan_start = c.take<int32_t>(g.pan_start.size());
+    d.pan_r = c.take<int32_t>(g.pan_r.size());
+    d.f_item_panel = c.take<int32_t>(g.f_item_panel.size());
+    d.f_item_tgt = c.take<int32_t>(g.f_item_tgt.size());
+    d.f_tgt_col = c.take<int32_t>(g.f_tgt_col.size());
+    d.f_tgt_src = c.take<int32_t>(g.f_tgt_src.size());
+    d.f_src_panel = c.take<int32_t>(std::max<size_t>(1, g.f_src_panel.size()));
+    d.l_item_p0 = c.take<int32_t>(g.l_item_p0.size());
+    d.l_item_np = c.take<int32_t>(g.l_item_np.size());
+    d.l_pan = c.take<int32_t>(g.l_pan.size());
+    d.u_item_p0 = c.take<int32_t>(g.u_item_p0.size());
+    d.u_item_np = c.take<int32_t>(g.u_item_np.size());
+    d.u_pan = c.take<int32_t>(g.u_pan.size());
+    d.csr_rowptr = c.take<int32_t>(n + 1);
+    d.csr_col = c.take<int32_t>(nlu);
+    d.csr_src = c.take<int32_t>(nlu);
+    d.csr_diag = c.take<int32_t>(n);
+    d.P = c.take<int32_t>(n);
+    d.Q = c.take<int32_t>(n);
+    d.r = c.take<double>(n);
+    d.c = c.take<double>(n);
+    d.lu = c.take<double>(nlu);
+    d.lucsr = c.take<double>(nlu);
+    d.y = c.take<double>(n);
+    d.xt = c.take<double>(n);
+    d.bsave = c.take<double>(n);
+    d.V = c.take<double>((size_t)(m + 1) * n);
+    d.Z = c.take<double>((size_t)m * n);
+    d.w = c.take<double>(n);
+    d.res = c.take<double>(n);
+    d.part = c.take<double>((size_t)kDotBlocks * (m + 2));
+    d.hbuf = c.take<double>(4 * (size_t)(m + 2));
+    d.ybuf = c.take<double>((size_t)m + 2);
+    d.st = c.take<DevStatus>(1);
+    *bytes = c.off + 256;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        if ((x) != hipSuccess) return KKT_ERR_DEVICE; \
+    } while (0)
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <class T>
+int upload(T *dst, const std::vector<T> &src, hipStream_t s) {
+    if (src.empty()) return KKT_OK;
+    HIPCHK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return KKT_OK;
+}
+
+// x = Q C (L U)^-1 P R b for one column (both in original order)
+int enqueue_solve(kkt_handle *h, const double *b, double *x, hipStream_t s) {
+    const Schedule &g = h->sch;
+    const Dev &d = h->d;
+    SolveArgs a{d.pan_start, d.l_item_p0, d.l_item_np, d.l_pan, d.csr_rowptr, d.csr_col, d.csr_diag,
+                d.P, d.Q, d.lucsr, d.r, d.c, b, d.y, d.xt, x};
+    for (size_t l = 0; l + 1 < g.l_lvl.size(); ++l) {
+        const int cnt = g.l_lvl[l + 1] - g.l_lvl[l];
+        if (cnt) k_lsolve_level<<<cnt, 64, 0, s>>>(g.l_lvl[l], a);
+    }
+    a.item_p0 = d.u_item_p0;
+    a.item_np = d.u_item_np;
+    a.pan = d.u_pan;
+    for (size_t l = 0; l + 1 < g.u_lvl.size(); ++l) {
+        const int cnt = g.u_lvl[l + 1] - g.u_lvl[l];
+        if (cnt) k_usolve_level<<<cnt, 64, 0, s>>>(g.u_lvl[l], a);
+    }
+    HIPCHK(hipGetLastError());
+    return KKT_OK;
+}
+
+int enqueue_refactor(kkt_handle *h, const double *v, hipStream_t s) {
+    const Schedule &g = h->sch;
+    const Dev &d = h->d;
+    const int n = h->sym.n;
+    const int64_t nlu = h->sym.nnz_lu();
+    const int eq = h->opts.equilibrate != 0;
+    k_row_scale<<<blocks_for(n, 256), 256, 0, s>>>(n, d.a_rowptr, v, eq, d.r, d.st);
+    k_col_scale<<<blocks_for(n, 256), 256, 0, s>>>(n, d.a_cptr, d.a_cpos, d.a_rowid, v, d.r, eq, d.c);
+    k_norms<<<blocks_for(n, 256), 256, 0, s>>>(n, d.a_rowptr, d.a_colind, v, d.r, d.c, d.st);
+    k_gather_lu<<<blocks_for(nlu, 256), 256, 0, s>>>(nlu, d.lu_src, d.a_rowid, d.a_colind, v, d.r, d.c, d.lu);
+    RefArgs a{d.colptr, d.rowidx, d.ulen, d.pan_start, d.pan_r, d.f_item_panel, d.f_item_tgt,
+              d.f_tgt_col, d.f_tgt_src, d.f_src_panel, d.lu, d.st, h->opts.tiny_pivot};
+    for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
+        const int cnt = g.f_lvl[l + 1] - g.f_lvl[l];
+        if (cnt) k_refactor_level<<<cnt, 64, 0, s>>>(g.f_lvl[l], a);
+    }
+    k_to_csr<<<blocks_for(nlu, 256), 256, 0, s>>>(nlu, d.csr_src, d.lu, d.lucsr);
+    HIPCHK(hipGetLastError());
+    return KKT_OK;
+}
+
+// dst[0..nv) = V[0..nv) . w  (deterministic two-pass reduction)
+void enqueue_dots(kkt_handle *h, int nv, const double *V, const double *w, double *dst, int accumulate,
+                  hipStream_t s) {
+    const int n = h->sym.n;
+    k_multidot<<<kDotBlocks, 256, 0, s>>>(n, nv, V, (int64_t)n, w, h->d.part);
+    k_reduce_parts<<<nv, 256, 0, s>>>(nv, kDotBlocks, h->d.part, dst, accumulate);
+}
+
+// infinity norms of b - A x into the status block; returns berr on the host
+int residual_berr(kkt_handle *h, const double *x, const double *b, double *berr, double *den, hipStream_t s) {
+    const Dev &d = h->d;
+    const int n = h->sym.n;
+    k_reset_norms<<<1, 1, 0, s>>>(d.st);
+    k_residual<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_rowptr, d.a_colind, h->d_values, x, b,
+                                                                 d.res, d.st);
+    HIPCHK(hipMemcpyAsync(h->h_small, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    DevStatus st;
+    std::memcpy(&st, h->h_small, sizeof(st));
+    *den = st.anorm * st.xnorm + st.bnorm;
+    if (*den == 0.0) *berr = st.rnorm == 0.0 ? 0.0 : INFINITY;
+    else *berr = st.rnorm / *den;
+    return KKT_OK;
+}
+
+int fgmres_column(kkt_handle *h, const double *b, double *x, kkt_info *info, hipStream_t s) {
+    const Dev &d = h->d;
+    const int n = h->sym.n;
+    const int m = h->opts.gmres_restart;
+    const double tol = h->opts.berr_tol;
+    int rc = enqueue_solve(h, b, x, s);
+    if (rc) return rc;
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1), yv(m);
+    int it = 0;
+    double berr = 0.0, den = 0.0;
+    int status = KKT_OK;
+    const unsigned nb = blocks_for(n, 256);
+    for (;;) {
+        rc = residual_berr(h, x, b, &berr, &den, s);
+        if (rc) return rc;
+        if (berr <= tol) { status = KKT_OK; break; }
+        if (it >= h->opts.max_iters || !std::isfinite(berr)) { status = KKT_WARN_NOT_CONVERGED; break; }
+        const double target = tol * den;
+        double *beta2 = d.hbuf + 3 * (m + 2);
+        enqueue_dots(h, 1, d.res, d.res, beta2, 0, s);
+        k_scale_by_norm<<<nb, 256, 0, s>>>(n, d.res, beta2, d.V);
+        std::fill(gv.begin(), gv.end(), 0.0);
+        int jend = -1;
+        for (int j = 0; j < m; ++j) {
+            double *vj = d.V + (size_t)j * n, *zj = d.Z + (size_t)j * n;
+            rc = enqueue_solve(h, vj, zj, s);
+            if (rc) return rc;
+            k_spmv<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_rowptr, d.a_colind, h->d_values, zj, d.w);
+            double *h1 = d.hbuf, *h2 = d.hbuf + (m + 2), *hn2 = d.hbuf + 2 * (m + 2);
+            enqueue_dots(h, j + 1, d.V, d.w, h1, 0, s);
+            k_sub_combo<<<nb, 256, 0, s>>>(n, j + 1, d.V, n, h1, d.w);
+            enqueue_dots(h, j + 1, d.V, d.w, h2, 0, s);
+            k_sub_combo<<<nb, 256, 0, s>>>(n, j + 1, d.V, n, h2, d.w);
+            enqueue_dots(h, 1, d.w, d.w, hn2, 0, s);
+            k_scale_by_norm<<<nb, 256, 0, s>>>(n, d.w, hn2, d.V + (size_t)(j + 1) * n);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(h->h_small, d.hbuf, sizeof(double) * 4 * (m + 2), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const double *hs = h->h_small;
+            if (j == 0) gv[0] = std::sqrt(hs[3 * (m + 2)]);
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hs[i] + hs[(m + 2) + i];
+            const double hn = std::sqrt(hs[2 * (m + 2)]);
+            H[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                const double a0 = H[(size_t)i * m + j], b0 = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a0 + sn[i] * b0;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a0 + cs[i] * b0;
+            }
+            const double a0 = H[(size_t)j * m + j], b0 = H[(size_t)(j + 1) * m + j];
+            const double rr = std::hypot(a0, b0);
+            cs[j] = rr > 0.0 ? a0 / rr : 1.0;
+            sn[j] = rr > 0.0 ? b0 / rr : 0.0;
+            H[(size_t)j * m + j] = rr;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            ++it;
+            jend = j;
+            if (std::fabs(gv[j + 1]) <= target || it >= h->opts.max_iters || hn == 0.0) break;
+        }
+        for (int i = jend; i >= 0; --i) {
+            double t = gv[i];
+            for (int q = i + 1; q <= jend; ++q) t -= H[(size_t)i * m + q] * yv[q];
+            yv[i] = H[(size_t)i * m + i] != 0.0 ? t / H[(size_t)i * m + i] : 0.0;
+        }
+        std::memcpy(h->h_small, yv.data(), sizeof(double) * (jend + 1));
+        HIPCHK(hipMemcpyAsync(d.ybuf, h->h_small, sizeof(double) * (jend + 1), hipMemcpyHostToDevice, s));
+        k_add_combo<<<nb, 256, 0, s>>>(n, jend + 1, d.Z, n, d.ybuf, x);
+        HIPCHK(hipGetLastError());
+        // the staging buffer is reused by the next read-back: wait for the upload
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    if (info) {
+        info->iters = it;
+        info->berr = berr;
+        info->status = status;
+    }
+    return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+void kkt_default_opts(kkt_opts *o) {
+    if (!o) return;
+    o->pivot_tau = 0.0;
+    o->tiny_pivot = std::ldexp(1.0, -26);
+    o->equilibrate = 1;
+    o->gmres_restart = 30;
+    o->max_iters = 100;
+    o->berr_tol = 1e-10;
+    o->sn_max_width = 256;
+    o->fixed_p = nullptr;
+    o->fixed_q = nullptr;
+}
+
+int kkt_analyze(int32_t n, const int64_t *rowptr, const int32_t *colind, const double *values_k1,
+                const kkt_opts *opts, kkt_handle **out) {
+    if (!out) return KKT_ERR_ARG;
+    *out = nullptr;
+    kkt_opts o;
+    kkt_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.gmres_restart < 1 || o.gmres_restart > kMaxRestart || o.max_iters < 0 || !(o.berr_tol >= 0.0) ||
+        !(o.tiny_pivot >= 0.0))
+        return KKT_ERR_ARG;
+    kkt_handle *h = new (std::nothrow) kkt_handle;
+    if (!h) return KKT_ERR_NOMEM;
+    int rc;
+    try {
+        rc = analyze_symbolic(n, rowptr, colind, values_k1, o, h->sym);
+        if (rc == KKT_OK) rc = build_schedule(h->sym, h->sch);
+    } catch (const std::bad_alloc &) {
+        rc = KKT_ERR_NOMEM;
+    }
+    if (rc != KKT_OK) {
+        delete h;
+        return rc;
+    }
+    o.fixed_p = nullptr;   // borrowed for the call only
+    o.fixed_q = nullptr;
+    h->opts = o;
+    *out = h;
+    return KKT_OK;
+}
+
+int kkt_get_stats(const kkt_handle *h, kkt_stats *out) {
+    if (!h || !out) return KKT_ERR_ARG;
+    const Symbolic &s = h->sym;
+    out->n = s.n;
+    out->nsn = s.nsn();
+    out->nnz_a = s.nnz_a;
+    out->nnz_lu = s.nnz_lu();
+    auto mx = [](const std::vector<int32_t> &v) { return v.empty() ? 0 : 1 + *std::max_element(v.begin(), v.end()); };
+    out->levels_f = mx(s.lev_f);
+    out->levels_l = mx(s.lev_l);
+    out->levels_u = mx(s.lev_u);
+    out->gpu_levels_f = (int32_t)h->sch.f_lvl.size() - 1;
+    out->gpu_levels_l = (int32_t)h->sch.l_lvl.size() - 1;
+    out->gpu_levels_u = (int32_t)h->sch.u_lvl.size() - 1;
+    out->flops_refactor = h->sch.flops;
+    return KKT_OK;
+}
+
+int kkt_export_symbolic(const kkt_handle *h, int32_t *P, int32_t *Q, int64_t *colptr, int32_t *rowidx,
+                        int32_t *parent, int32_t *lev_f, int32_t *lev_l, int32_t *lev_u, int32_t *sn_start,
+                        int64_t *map) {
+    if (!h) return KKT_ERR_ARG;
+    const Symbolic &s = h->sym;
+    auto cp = [](auto *dst, const auto &v) {
+        if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+    };
+    cp(P, s.P);
+    cp(Q, s.Q);
+    cp(colptr, s.colptr);
+    cp(rowidx, s.rowidx);
+    cp(parent, s.parent);
+    cp(lev_f, s.lev_f);
+    cp(lev_l, s.lev_l);
+    cp(lev_u, s.lev_u);
+    cp(sn_start, s.sn_start);
+    cp(map, s.map);
+    return KKT_OK;
+}
+
+int kkt_workspace_bytes(const kkt_handle *h, int32_t max_nrhs, size_t *bytes) {
+    if (!h || !bytes || max_nrhs < 1) return KKT_ERR_ARG;
+    Dev scratch{};
+    carve(h, nullptr, scratch, bytes);
+    return KKT_OK;
+}
+
+int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, hipStream_t stream) {
+    if (!h || !d_workspace || max_nrhs < 1) return KKT_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256) return KKT_ERR_ARG;
+    size_t need = 0;
+    Dev scratch{};
+    carve(h, nullptr, scratch, &need);
+    if (bytes < need) return KKT_ERR_NOMEM;
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (!h->h_small) HIPCHK(hipHostMalloc(&h->h_small, sizeof(double) * 4 * (kMaxRestart + 2) + sizeof(DevStatus)));
+    carve(h, static_cast<char *>(d_workspace), h->d, &need);
+    const Symbolic &s = h->sym;
+    const Schedule &g = h->sch;
+    const Dev &d = h->d;
+    std::vector<int32_t> rp32(s.n + 1), cp32(s.n + 1);
+    for (int32_t i = 0; i <= s.n; ++i) {
+        rp32[i] = (int32_t)s.a_rowptr[i];
+        cp32[i] = (int32_t)s.colptr[i];
+    }
+    int rc = KKT_OK;
+    rc |= upload(d.a_rowptr, rp32, stream);
+    rc |= upload(d.a_colind, s.a_colind, stream);
+    rc |= upload(d.a_rowid, g.a_rowid, stream);
+    rc |= upload(d.a_cptr, g.a_cptr, stream);
+    rc |= upload(d.a_cpos, g.a_cpos, stream);
+    rc |= upload(d.lu_src, g.lu_src, stream);
+    rc |= upload(d.colptr, cp32, stream);
+    rc |= upload(d.rowidx, s.rowidx, stream);
+    rc |= upload(d.ulen, s.ulen, stream);
+    rc |= upload(d.pan_start, g.pan_start, stream);
+    rc |= upload(d.pan_r, g.pan_r, stream);
+    rc |= upload(d.f_item_panel, g.f_item_panel, stream);
+    rc |= upload(d.f_item_tgt, g.f_item_tgt, stream);
+    rc |= upload(d.f_tgt_col, g.f_tgt_col, stream);
+    rc |= upload(d.f_tgt_src, g.f_tgt_src, stream);
+    rc |= upload(d.f_src_panel, g.f_src_panel, stream);
+    rc |= upload(d.l_item_p0, g.l_item_p0, stream);
+    rc |= upload(d.l_item_np, g.l_item_np, stream);
+    rc |= upload(d.l_pan, g.l_pan, stream);
+    rc |= upload(d.u_item_p0, g.u_item_p0, stream);
+    rc |= upload(d.u_item_np, g.u_item_np, stream);
+    rc |= upload(d.u_pan, g.u_pan, stream);
+    rc |= upload(d.csr_rowptr, g.csr_rowptr, stream);
+    rc |= upload(d.csr_col, g.csr_col, stream);
+    rc |= upload(d.csr_src, g.csr_src, stream);
+    rc |= upload(d.csr_diag, g.csr_diag, stream);
+    rc |= upload(d.P, s.P, stream);
+    rc |= upload(d.Q, s.Q, stream);
+    if (rc) return KKT_ERR_DEVICE;
+    HIPCHK(hipMemsetAsync(d.st, 0, sizeof(DevStatus), stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    h->device = dev;
+    h->ws = static_cast<char *>(d_workspace);
+    h->ws_bytes = bytes;
+    h->max_nrhs = max_nrhs;
+    h->bound = true;
+    h->factored = false;
+    return KKT_OK;
+}
+
+int kkt_refactor(kkt_handle *h, const double *d_values, hipStream_t stream) {
+    if (!h || !d_values) return KKT_ERR_ARG;
+    if (!h->bound) return KKT_ERR_STATE;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return KKT_ERR_DEVICE;
+    int rc = enqueue_refactor(h, d_values, stream);
+    if (rc) return rc;
+    h->d_values = d_values;
+    h->factored = true;
+    return KKT_OK;
+}
+
+int kkt_refactor_status(kkt_handle *h, int64_t *perturbed, hipStream_t stream) {
+    if (!h) return KKT_ERR_ARG;
+    if (!h->factored) return KKT_ERR_STATE;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return KKT_ERR_DEVICE;
+    HIPCHK(hipMemcpyAsync(h->h_small, h->d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    DevStatus st;
+    std::memcpy(&st, h->h_small, sizeof(st));
+    if (perturbed) *perturbed = (int64_t)st.perturbed;
+    if (st.flags & kFlagInternal) return KKT_ERR_DEVICE;
+    if (st.flags & kFlagNonfinite) return KKT_ERR_NONFINITE;
+    return st.perturbed ? KKT_WARN_PIVOT_PERTURBED : KKT_OK;
+}
+
+int kkt_solve(kkt_handle *h, const double *d_b, double *d_x, int32_t nrhs, int64_t ld, hipStream_t stream) {
+    if (!h || !d_b || !d_x || nrhs < 1 || ld < h->sym.n) return KKT_ERR_ARG;
+    if (!h->factored) return KKT_ERR_STATE;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return KKT_ERR_DEVICE;
+    for (int32_t j = 0; j < nrhs; ++j) {
+        const int rc = enqueue_solve(h, d_b + (size_t)j * ld, d_x + (size_t)j * ld, stream);
+        if (rc) return rc;
+    }
+    return KKT_OK;
+}
+
+int kkt_refine(kkt_handle *h, const double *d_b, double *d_x, int32_t nrhs, int64_t ld, kkt_info *info,
+               hipStream_t stream) {
+    if (!h || !d_b || !d_x || nrhs < 1 || ld < h->sym.n) return KKT_ERR_ARG;
+    if (!h->factored) return KKT_ERR_STATE;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return KKT_ERR_DEVICE;
+    int64_t pert = 0;
+    const int fst = kkt_refactor_status(h, &pert, stream);
+    if (fst < 0) {
+        if (info)
+            for (int32_t j = 0; j < nrhs; ++j) info[j] = kkt_info{0, fst, INFINITY, pert};
+        return fst;
+    }
+    int worst = KKT_OK;
+    for (int32_t j = 0; j < nrhs; ++j) {
+        const double *b = d_b + (size_t)j * ld;
+        double *x = d_x + (size_t)j * ld;
+        if (b == x) {
+            HIPCHK(hipMemcpyAsync(h->d.bsave, b, sizeof(double) * h->sym.n, hipMemcpyDeviceToDevice, stream));
+            b = h->d.bsave;
+        }
+        kkt_info inf{};
+        const int rc = fgmres_column(h, b, x, &inf, stream);
+        if (rc < 0) return rc;
+        inf.perturbed_pivots = pert;
+        if (info) info[j] = inf;
+        worst = std::max(worst, rc);
+    }
+    return worst;
+}
+
+int kkt_export_factors(kkt_handle *h, double *h_lu, double *h_r, double *h_c, hipStream_t stream) {
+    if (!h || !h_lu) return KKT_ERR_ARG;
+    if (!h->factored) return KKT_ERR_STATE;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return KKT_ERR_DEVICE;
+    HIPCHK(hipMemcpyAsync(h_lu, h->d.lu, sizeof(double) * h->sym.nnz_lu(), hipMemcpyDeviceToHost, stream));
+    if (h_r) HIPCHK(hipMemcpyAsync(h_r, h->d.r, sizeof(double) * h->sym.n, hipMemcpyDeviceToHost, stream));
+    if (h_c) HIPCHK(hipMemcpyAsync(h_c, h->d.c, sizeof(double) * h->sym.n, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    return KKT_OK;
+}
+
+void kkt_destroy(kkt_handle *h) {
+    if (!h) return;
+    if (h->h_small) (void)hipHostFree(h->h_small);
+    delete h;
+}
+
+const char *kkt_strerror(int status) {
+    switch (status) {
+        case KKT_OK: return "ok";
+        case KKT_WARN_PIVOT_PERTURBED: return "tiny pivots were replaced during refactorization";
+        case KKT_WARN_NOT_CONVERGED: return "iterative refinement did not reach the backward-error target";
+        case KKT_ERR_ARG: return "invalid argument";
+        case KKT_ERR_PATTERN: return "invalid sparsity pattern";
+        case KKT_ERR_SINGULAR: return "structurally or numerically singular at analysis";
+        case KKT_ERR_NONFINITE: return "non-finite value in matrix or factors";
+        case KKT_ERR_STATE: return "call out of order";
+        case KKT_ERR_NOMEM: return "out of memory or workspace too small";
+        case KKT_ERR_DEVICE: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,253 @@
+// Device schedule of the refactorization and of the triangular solves, built once per
+// pattern on the host (the one-time data movement and mapping of Section III).
+//
+// Panels.  Each structural supernode is cut into panels of at most kPanelMax consecutive
+// columns.  Every column j of a panel [s, e) has the L rows {j+1..e-1} followed by the
+// panel's common rows R below e-1, and every row of the panel has the same U columns C to
+// the right of e-1; consequently each column k in C holds the rows s..e-1 consecutively.
+//
+// Refactorization (right-looking over panel levels, values pulled by their owner).  The
+// level of a panel is one more than the highest level of any panel S with U(S, T) != 0 or
+// L(T, S) != 0.  Launch l (l = 0..max level):
+//   - every target column k of a panel S at level l-1 pulls S's update: the rows s..e-1
+//     of column k are solved with S's unit lower diagonal block (they become final U
+//     entries) and the rows R of column k lose L(R, S) times them;
+//   - every panel at level l, whose columns are then complete, is factored densely
+//     without pivoting (diagonal block, then the L rows R).
+// A column is written only by the one work item that owns it in a launch, so no atomics
+// are needed and the result is deterministic.
+//
+// Triangular solves (row oriented on a combined L+U CSR copy).  Forward level of a panel:
+// one more than the highest level of a panel owning a column j of an L entry L(i, j) of one
+// of its rows; backward level likewise over U entries to the right.
+#include <algorithm>
+#include <numeric>
+
+#include "kkt_internal.h"
+
+namespace kkt {
+
+int build_schedule(const Symbolic &s, Schedule &g) {
+    const int32_t n = s.n;
+    const int64_t nlu = s.nnz_lu();
+    if (nlu >= INT32_MAX || s.nnz_a >= INT32_MAX) return KKT_ERR_NOMEM;
+    // panels
+    g.pan_start.clear();
+    for (int32_t t = 0; t + 1 < (int32_t)s.sn_start.size(); ++t) {
+        const int32_t a = s.sn_start[t], b = s.sn_start[t + 1], w = b - a;
+        const int32_t m = (w + kPanelMax - 1) / kPanelMax;
+        for (int32_t q = 0; q < m; ++q) g.pan_start.push_back(a + (int32_t)((int64_t)w * q / m));
+    }
+    g.pan_start.push_back(n);
+    const int32_t np = g.npan = (int32_t)g.pan_start.size() - 1;
+    std::vector<int32_t> pan_of(n);
+    for (int32_t p = 0; p < np; ++p)
+        for (int32_t j = g.pan_start[p]; j < g.pan_start[p + 1]; ++j) pan_of[j] = p;
+    auto lbeg = [&](int32_t j) { return s.colptr[j] + s.ulen[j] + 1; };
+    g.pan_r.resize(np);
+    for (int32_t p = 0; p < np; ++p) {
+        const int32_t sp = g.pan_start[p], e = g.pan_start[p + 1];
+        g.pan_r[p] = (int32_t)(s.colptr[e] - lbeg(e - 1));
+        // structure check: column j's L part is {j+1..e-1} followed by R
+        const int64_t r0 = lbeg(e - 1);
+        for (int32_t j = sp; j < e; ++j) {
+            const int64_t l = lbeg(j);
+            if (s.colptr[j + 1] - l != (e - 1 - j) + g.pan_r[p]) return KKT_ERR_PATTERN;
+            for (int32_t t = 0; t < e - 1 - j; ++t)
+                if (s.rowidx[l + t] != j + 1 + t) return KKT_ERR_PATTERN;
+            if (!std::equal(s.rowidx.begin() + l + (e - 1 - j), s.rowidx.begin() + s.colptr[j + 1],
+                            s.rowidx.begin() + r0))
+                return KKT_ERR_PATTERN;
+            // U rows s..j-1 directly above the diagonal
+            if (s.ulen[j] < j - sp) return KKT_ERR_PATTERN;
+            for (int32_t t = 0; t < j - sp; ++t)
+                if (s.rowidx[s.colptr[j] + s.ulen[j] - (j - sp) + t] != sp + t) return KKT_ERR_PATTERN;
+        }
+    }
+    // refactor levels of panels and (source, target) pairs.  A panel T waits for every
+    // panel S with U(S, T) != 0 (its columns need S's update) and for every panel S with
+    // L(T, S) != 0 (its rows of a later column must be updated by S before T's own update
+    // of that column solves them); for symmetric patterns the two sets coincide.
+    std::vector<int32_t> plev(np, 0);
+    std::vector<std::pair<int32_t, int32_t>> pairs;   // (source panel, target column)
+    for (int32_t T = 0; T < np; ++T) {
+        for (int32_t k = g.pan_start[T]; k < g.pan_start[T + 1]; ++k)
+            for (int64_t p = s.colptr[k]; p < s.colptr[k] + s.ulen[k]; ++p) {
+                const int32_t j = s.rowidx[p];
+                const int32_t S = pan_of[j];
+                if (S == T) continue;
+                plev[T] = std::max(plev[T], plev[S] + 1);
+                if (j == g.pan_start[S + 1] - 1) pairs.emplace_back(S, k);
+            }
+        // plev[T] is final: push it along the L entries of T's columns
+        for (int32_t j = g.pan_start[T]; j < g.pan_start[T + 1]; ++j)
+            for (int64_t p = lbeg(j); p < s.colptr[j + 1]; ++p) {
+                const int32_t R = pan_of[s.rowidx[p]];
+                if (R != T) plev[R] = std::max(plev[R], plev[T] + 1);
+            }
+    }
+    // every target column of S must hold the rows of S consecutively
+    for (const auto &pr : pairs) {
+        const int32_t S = pr.first, k = pr.second;
+        const int32_t sp = g.pan_start[S], e = g.pan_start[S + 1];
+        const auto b = s.rowidx.begin() + s.colptr[k], en = s.rowidx.begin() + s.colptr[k] + s.ulen[k];
+        const auto it = std::lower_bound(b, en, sp);
+        if (en - it < e - sp) return KKT_ERR_PATTERN;
+        for (int32_t t = 0; t < e - sp; ++t)
+            if (it[t] != sp + t) return KKT_ERR_PATTERN;
+    }
+    const int32_t nlev = np ? 1 + *std::max_element(plev.begin(), plev.end()) : 0;
+    // group pairs by launch (= source level + 1), then target column, then source
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> by_launch(nlev + 1);
+    for (const auto &pr : pairs) by_launch[plev[pr.first] + 1].emplace_back(pr.second, pr.first);
+    std::vector<std::vector<int32_t>> panels_at(nlev);
+    for (int32_t p = 0; p < np; ++p) panels_at[plev[p]].push_back(p);
+    g.f_lvl.assign(1, 0);
+    g.f_item_panel.clear();
+    g.f_item_tgt.assign(1, 0);
+    g.f_tgt_col.clear();
+    g.f_tgt_src.assign(1, 0);
+    g.f_src_panel.clear();
+    for (int32_t l = 0; l < nlev; ++l) {
+        auto &pl = by_launch[l];
+        std::sort(pl.begin(), pl.end());
+        // sources of each target column at this launch
+        std::vector<int32_t> cols;
+        std::vector<int32_t> cptr(1, 0), srcs;
+        for (size_t q = 0; q < pl.size(); ++q) {
+            if (q == 0 || pl[q].first != pl[q - 1].first) {
+                if (q) cptr.push_back((int32_t)srcs.size());
+                cols.push_back(pl[q].first);
+            }
+            srcs.push_back(pl[q].second);
+        }
+        cptr.push_back((int32_t)srcs.size());
+        auto sources_of = [&](int32_t k, std::vector<int32_t> &out) {
+            out.clear();
+            const auto it = std::lower_bound(cols.begin(), cols.end(), k);
+            if (it != cols.end() && *it == k) {
+                const size_t q = it - cols.begin();
+                out.assign(srcs.begin() + cptr[q], srcs.begin() + cptr[q + 1]);
+            }
+        };
+        // factor items: widest panels first
+        auto fac = panels_at[l];
+        std::stable_sort(fac.begin(), fac.end(), [&](int32_t a, int32_t b) {
+            return g.pan_start[a + 1] - g.pan_start[a] > g.pan_start[b + 1] - g.pan_start[b];
+        });
+        std::vector<int32_t> tmp;
+        for (int32_t T : fac) {
+            g.f_item_panel.push_back(T);
+            for (int32_t k = g.pan_start[T]; k < g.pan_start[T + 1]; ++k) {
+                sources_of(k, tmp);
+                g.f_tgt_col.push_back(k);
+                g.f_src_panel.insert(g.f_src_panel.end(), tmp.begin(), tmp.end());
+                g.f_tgt_src.push_back((int32_t)g.f_src_panel.size());
+            }
+            g.f_item_tgt.push_back((int32_t)g.f_tgt_col.size());
+        }
+        // pull-only items: target columns not in a panel of this level
+        for (size_t q = 0; q < cols.size(); ++q) {
+            const int32_t k = cols[q];
+            if (plev[pan_of[k]] == l) continue;
+            g.f_item_panel.push_back(-1);
+            g.f_tgt_col.push_back(k);
+            g.f_src_panel.insert(g.f_src_panel.end(), srcs.begin() + cptr[q], srcs.begin() + cptr[q + 1]);
+            g.f_tgt_src.push_back((int32_t)g.f_src_panel.size());
+            g.f_item_tgt.push_back((int32_t)g.f_tgt_col.size());
+        }
+        g.f_lvl.push_back((int32_t)g.f_item_panel.size());
+    }
+    if (!by_launch[nlev].empty()) return KKT_ERR_PATTERN;   // top panels have no targets
+    // solve levels
+    std::vector<int32_t> llev(np, 0), ulev(np, 0);
+    for (int32_t j = 0; j < n; ++j)
+        for (int64_t p = lbeg(j); p < s.colptr[j + 1]; ++p) {
+            const int32_t T = pan_of[s.rowidx[p]], S = pan_of[j];
+            if (T != S) llev[T] = std::max(llev[T], llev[S] + 1);
+        }
+    for (int32_t j = n - 1; j >= 0; --j)
+        for (int64_t p = s.colptr[j]; p < s.colptr[j] + s.ulen[j]; ++p) {
+            const int32_t T = pan_of[s.rowidx[p]], S = pan_of[j];
+            if (T != S) ulev[T] = std::max(ulev[T], ulev[S] + 1);
+        }
+    auto build_solve = [&](const std::vector<int32_t> &lev, std::vector<int32_t> &lvl,
+                           std::vector<int32_t> &p0, std::vector<int32_t> &cnt, std::vector<int32_t> &pan) {
+        const int32_t nl = np ? 1 + *std::max_element(lev.begin(), lev.end()) : 0;
+        std::vector<std::vector<int32_t>> at(nl);
+        for (int32_t p = 0; p < np; ++p) at[lev[p]].push_back(p);
+        lvl.assign(1, 0);
+        p0.clear();
+        cnt.clear();
+        pan.clear();
+        for (int32_t l = 0; l < nl; ++l) {
+            std::vector<int32_t> wide, narrow;
+            for (int32_t p : at[l]) (g.pan_start[p + 1] - g.pan_start[p] > 1 ? wide : narrow).push_back(p);
+            std::stable_sort(wide.begin(), wide.end(), [&](int32_t a, int32_t b) {
+                return g.pan_start[a + 1] - g.pan_start[a] > g.pan_start[b + 1] - g.pan_start[b];
+            });
+            for (int32_t p : wide) {
+                p0.push_back((int32_t)pan.size());
+                cnt.push_back(1);
+                pan.push_back(p);
+            }
+            for (size_t q = 0; q < narrow.size(); q += kSolvePack) {
+                const int32_t c = (int32_t)std::min<size_t>(kSolvePack, narrow.size() - q);
+                p0.push_back((int32_t)pan.size());
+                cnt.push_back(-c);     // negative: a pack of width-1 panels
+                for (int32_t t = 0; t < c; ++t) pan.push_back(narrow[q + t]);
+            }
+            lvl.push_back((int32_t)p0.size());
+        }
+    };
+    build_solve(llev, g.l_lvl, g.l_item_p0, g.l_item_np, g.l_pan);
+    build_solve(ulev, g.u_lvl, g.u_item_p0, g.u_item_np, g.u_pan);
+    // combined L+U in CSR: row i lists (i, j) by ascending j, csr_src = CSC slot
+    g.csr_rowptr.assign(n + 1, 0);
+    for (int64_t p = 0; p < nlu; ++p) g.csr_rowptr[s.rowidx[p] + 1]++;
+    for (int32_t i = 0; i < n; ++i) g.csr_rowptr[i + 1] += g.csr_rowptr[i];
+    g.csr_col.resize(nlu);
+    g.csr_src.resize(nlu);
+    g.csr_diag.resize(n);
+    {
+        std::vector<int32_t> nxt(g.csr_rowptr.begin(), g.csr_rowptr.end() - 1);
+        for (int32_t j = 0; j < n; ++j)
+            for (int64_t p = s.colptr[j]; p < s.colptr[j + 1]; ++p) {
+                const int32_t i = s.rowidx[p];
+                const int32_t q = nxt[i]++;
+                g.csr_col[q] = j;
+                g.csr_src[q] = (int32_t)p;
+                if (i == j) g.csr_diag[i] = q;
+            }
+    }
+    // value update map and CSC view of A
+    g.lu_src.assign(nlu, -1);
+    for (int64_t e = 0; e < s.nnz_a; ++e) g.lu_src[s.map[e]] = (int32_t)e;
+    g.a_cptr.assign(n + 1, 0);
+    g.a_rowid.resize(s.nnz_a);
+    for (int32_t i = 0; i < n; ++i)
+        for (int64_t p = s.a_rowptr[i]; p < s.a_rowptr[i + 1]; ++p) {
+            g.a_rowid[p] = i;
+            g.a_cptr[s.a_colind[p] + 1]++;
+        }
+    for (int32_t j = 0; j < n; ++j) g.a_cptr[j + 1] += g.a_cptr[j];
+    g.a_cpos.resize(s.nnz_a);
+    {
+        std::vector<int32_t> nxt(g.a_cptr.begin(), g.a_cptr.end() - 1);
+        for (int32_t i = 0; i < n; ++i)
+            for (int64_t p = s.a_rowptr[i]; p < s.a_rowptr[i + 1]; ++p) g.a_cpos[nxt[s.a_colind[p]]++] = (int32_t)p;
+    }
+    // refactor flops: sum_k 2 |L(:,k)| |U(k,:)| + |L(:,k)|
+    std::vector<int64_t> urow(n, 0);
+    for (int32_t k = 0; k < n; ++k)
+        for (int64_t p = s.colptr[k]; p < s.colptr[k] + s.ulen[k]; ++p) urow[s.rowidx[p]]++;
+    double fl = 0.0;
+    for (int32_t k = 0; k < n; ++k) {
+        const double lk = (double)(s.colptr[k + 1] - lbeg(k));
+        fl += 2.0 * lk * (double)urow[k] + lk;
+    }
+    g.flops = fl;
+    return KKT_OK;
+}
+
+}  // namespace kkt

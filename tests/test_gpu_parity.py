@@ -1,0 +1,219 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Bars (derived from the arithmetic, see the factor bound below):
+  * symbolic arrays and power-of-two scale factors: bit-exact;
+  * perturbed-pivot counts: equal;
+  * factors: both the GPU and the oracle factor the same scaled, permuted matrix PA~Q with
+    the same pattern, so |PA~Q - L U| <= g |L||U| holds for each of them with
+    g = (m + 2) u, m the largest number of terms in one entry; hence
+    |L^U^ - L U| <= g (|L^||U^| + |L||U|) entrywise (plus 2 eps ||A~|| on a perturbed
+    pivot whose pre-perturbation sign may differ);
+  * solutions: backward error <= 1e-10 after refinement, recomputed on the host in FP64
+    by the oracle's residual from the returned x; forward error is not compared because
+    the KKT systems are nearly singular.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import kktgen
+import oracle
+import paper_2302_08656_amd as K
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U_RND = np.finfo(np.float64).eps / 2
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def factors(n, colptr, rowidx, lu):
+    cols = np.repeat(np.arange(n), np.diff(colptr))
+    low = rowidx > cols
+    up = ~low
+    L = sp.csc_matrix((lu[low], (rowidx[low], cols[low])), shape=(n, n)) + sp.identity(n, format="csc")
+    Um = sp.csc_matrix((lu[up], (rowidx[up], cols[up])), shape=(n, n))
+    return L.tocsr(), Um.tocsr()
+
+
+def check_factor_parity(so, lu_g, lu_o, npert, thresh):
+    n = so.n
+    Lg, Ug = factors(n, so.colptr, so.rowidx, lu_g)
+    Lo, Uo = factors(n, so.colptr, so.rowidx, lu_o)
+    m = int(np.diff(so.colptr).max())
+    g = (m + 2) * U_RND
+    D = abs(Lg @ Ug - Lo @ Uo)
+    B = abs(Lg) @ abs(Ug) + abs(Lo) @ abs(Uo)
+    E = (D - g * B).tocsr()
+    E.data[E.data < 0] = 0
+    E.eliminate_zeros()
+    excess = E.diagonal()
+    off = E - sp.diags(excess)
+    off.eliminate_zeros()
+    assert off.nnz == 0 or off.max() == 0, f"off-diagonal excess {off.max():.3e}"
+    assert np.all(excess <= (2 * thresh if npert else 0.0)), f"diagonal excess {excess.max():.3e}"
+
+
+def setup(q, t0=0, **kw):
+    v0 = q.values(t0)
+    so = oracle.Symbolic(q.n, q.rowptr, q.colind, v0, **{k: v for k, v in kw.items() if k == "tau"})
+    sk = K.KKTSolver(q.n, q.rowptr, q.colind, v0, **{("pivot_tau" if k == "tau" else k): v for k, v in kw.items()})
+    sk.bind()
+    return so, sk
+
+
+CASES = [
+    ("grid200", kktgen.config(0), {}),
+    ("grid300_widening", kktgen.small(300, config_id=140, steps=4), {}),
+    ("grid60_tau1e-3", kktgen.small(60, config_id=141, steps=3, schedule="fixed"), {"tau": 1e-3}),
+    ("grid40_flows1", kktgen.small(40, config_id=142, steps=2, flows=1), {}),
+]
+
+
+@pytest.mark.parametrize("name,spec,kw", CASES, ids=[c[0] for c in CASES])
+def test_refactor_parity(name, spec, kw):
+    print(f"[gpu] refactor parity {name}", flush=True)
+    q = kktgen.make_sequence(spec)
+    so, sk = setup(q, **kw)
+    for t in range(q.steps):
+        v = q.values(t)
+        lu_o, r_o, c_o, np_o, _ = so.refactor(v)
+        vd = cuda(v)
+        sk.refactor(vd)
+        st, np_g = sk.refactor_status()
+        lu_g, r_g, c_g = sk.export_factors()
+        assert np.array_equal(r_g, r_o) and np.array_equal(c_g, c_o)
+        assert np_g == np_o and st == (K.WARN_PIVOT_PERTURBED if np_o else K.OK)
+        A = q.scipy(t)
+        At = sp.diags(r_o) @ A @ sp.diags(c_o)
+        thresh = oracle.EPS * abs(At).sum(axis=1).max()
+        check_factor_parity(so, lu_g, lu_o, np_o, thresh)
+
+
+@pytest.mark.parametrize("name,spec,kw", CASES, ids=[c[0] for c in CASES])
+def test_refine_reaches_target(name, spec, kw):
+    print(f"[gpu] refine {name}", flush=True)
+    q = kktgen.make_sequence(spec)
+    so, sk = setup(q, **kw)
+    for t in range(q.steps):
+        v = q.values(t)
+        b = q.rhs(t)
+        vd = cuda(v)
+        sk.refactor(vd)
+        x, info = sk.refine(cuda(b))
+        xh = x.cpu().numpy()
+        _, berr = oracle.residual(q.n, q.rowptr, q.colind, v, xh, b)
+        assert info[0].status == K.OK and berr <= 1e-10, (t, berr, info)
+        assert abs(info[0].berr - berr) <= 1e-6 * berr + 1e-20
+
+
+def test_solve_matches_oracle_on_well_conditioned():
+    print("[gpu] solve vs oracle, well conditioned", flush=True)
+    rng = np.random.default_rng(11)
+    q = kktgen.make_sequence(kktgen.small(100, config_id=143))
+    # same pattern, diagonally dominant values: small condition number
+    n = q.n
+    v = rng.standard_normal(q.nnz)
+    rows = np.repeat(np.arange(n), np.diff(q.rowptr))
+    diag = rows == q.colind
+    v[diag] = 20.0 + rng.random(diag.sum())
+    so = oracle.Symbolic(n, q.rowptr, q.colind, v)
+    sk = K.KKTSolver(n, q.rowptr, q.colind, v).bind()
+    lu_o, r_o, c_o, _, _ = so.refactor(v)
+    sk.refactor(cuda(v))
+    b = rng.standard_normal((3, n))
+    x = sk.solve(cuda(b)).cpu().numpy()
+    for j in range(3):
+        xo = so.solve(lu_o, r_o, c_o, b[j])
+        assert np.allclose(x[j], xo, rtol=1e-12, atol=1e-13 * np.abs(xo).max())
+
+
+def test_deterministic_refactor_and_solve():
+    print("[gpu] determinism", flush=True)
+    q = kktgen.make_sequence(kktgen.small(500, config_id=144))
+    so, sk = setup(q)
+    v = cuda(q.values(2))
+    b = cuda(q.rhs(2))
+    sk.refactor(v)
+    lu1, _, _ = sk.export_factors()
+    x1 = sk.solve(b).cpu().numpy()
+    sk.refactor(v)
+    lu2, _, _ = sk.export_factors()
+    x2 = sk.solve(b).cpu().numpy()
+    assert np.array_equal(lu1, lu2) and np.array_equal(x1, x2)
+
+
+def test_nonfinite_values_reported():
+    print("[gpu] non-finite values", flush=True)
+    q = kktgen.make_sequence(kktgen.small(30, config_id=145))
+    so, sk = setup(q)
+    v = q.values(1)
+    v[5] = np.nan
+    vd = cuda(v)
+    sk.refactor(vd)
+    with pytest.raises(K.KKTError) as e:
+        sk.refactor_status()
+    assert e.value.code == K.ERR_NONFINITE
+    with pytest.raises(K.KKTError) as e:
+        sk.refine(cuda(q.rhs(1)))
+    assert e.value.code == K.ERR_NONFINITE
+    vd = cuda(q.values(1))                   # recovers with finite values
+    sk.refactor(vd)
+    x, info = sk.refine(cuda(q.rhs(1)))
+    assert info[0].status == K.OK
+
+
+def test_multiple_rhs_and_aliasing():
+    print("[gpu] multiple rhs, aliasing", flush=True)
+    q = kktgen.make_sequence(kktgen.config(0))
+    so, sk = setup(q)
+    v = q.values(4)
+    vd = cuda(v)
+    sk.refactor(vd)
+    B = q.rhs(4, nrhs=3)
+    x, info = sk.refine(cuda(B))
+    xb = cuda(B)
+    x_alias, info2 = sk.refine(xb, xb)
+    for j in range(3):
+        for xx in (x, x_alias):
+            _, berr = oracle.residual(q.n, q.rowptr, q.colind, v, xx[j].cpu().numpy(), B[j])
+            assert berr <= 1e-10
+
+
+def test_not_converged_is_reported():
+    print("[gpu] not converged", flush=True)
+    q = kktgen.make_sequence(kktgen.small(60, config_id=146, schedule="fixed"))
+    v0 = q.values(0)
+    sk = K.KKTSolver(q.n, q.rowptr, q.colind, v0, berr_tol=1e-30, max_iters=2, gmres_restart=2).bind()
+    vd = cuda(q.values(1))
+    sk.refactor(vd)
+    x, info = sk.refine(cuda(q.rhs(1)))
+    assert info[0].status == K.WARN_NOT_CONVERGED and info[0].iters == 2
+
+
+@pytest.mark.parametrize("cid,steps", [(1, (0, 1, 29)), (2, (0, 1, 49))], ids=["grid25k", "grid70k"])
+def test_full_size_grids(cid, steps):
+    """Full-size parity: scale factors bit-exact, equal perturbation counts, factors within
+    the bound above, and backward error <= 1e-10 after refinement."""
+    print(f"[gpu] full size config {cid}", flush=True)
+    q = kktgen.make_sequence(kktgen.config(cid))
+    so, sk = setup(q)
+    for t in steps:
+        print(f"[gpu]   step {t}", flush=True)
+        v = q.values(t)
+        b = q.rhs(t)
+        vd = cuda(v)
+        sk.refactor(vd)
+        st, np_g = sk.refactor_status()
+        lu_g, r_g, c_g = sk.export_factors()
+        lu_o, r_o, c_o, np_o, _ = so.refactor(v)
+        assert np.array_equal(r_g, r_o) and np.array_equal(c_g, c_o)
+        assert np_g == np_o
+        At = sp.diags(r_o) @ q.scipy(t) @ sp.diags(c_o)
+        check_factor_parity(so, lu_g, lu_o, np_o, oracle.EPS * abs(At).sum(axis=1).max())
+        x, info = sk.refine(cuda(b))
+        _, berr = oracle.residual(q.n, q.rowptr, q.colind, v, x.cpu().numpy(), b)
+        assert info[0].status == K.OK and berr <= 1e-10, (t, berr, info)
