@@ -40,21 +40,28 @@ int analyze_symbolic(int32_t n, const int64_t *rowptr, const int32_t *colind,
 // Maximum width of a GPU panel (a column range of a structural supernode handled by one
 // work item).  Panels never cross supernode boundaries.
 constexpr int kPanelMax = 32;
-// Width-1 panels of the triangular solves are packed this many to a wavefront.
-constexpr int kSolvePack = 8;
+// Width-1 panels of the triangular solves are packed this many to a 256-thread block.
+constexpr int kSolvePack = 32;
+// Refactorization items whose panel and sources all have at most kSmallW columns and
+// kSmallR rows below run on 16 lanes with registers only; the others on 256 threads with
+// the source panel staged in LDS.  Targets sharing one source are grouped kGroup per item.
+constexpr int kSmallW = 4;
+constexpr int kSmallR = 64;
+constexpr int kGroup = 32;
 
 // Device schedule, built on the host once per pattern and uploaded by kkt_bind.
 struct Schedule {
     int32_t npan = 0;
     std::vector<int32_t> pan_start;     // [npan+1] first column of each panel
     std::vector<int32_t> pan_r;         // [npan] L rows below the panel (= U columns right)
-    // refactorization: launch l runs items [f_lvl[l], f_lvl[l+1])
-    std::vector<int32_t> f_lvl;
+    // refactorization: launch l runs items [f_lvl[l], f_lvl[l+1]); the first f_nlarge[l] of
+    // them take the 256-thread path, the rest the 16-lane path.  An item owns the target
+    // columns of its (source panel, target column) pairs, listed source-major, and then
+    // factors its panel (f_item_panel >= 0).
+    std::vector<int32_t> f_lvl, f_nlarge;
     std::vector<int32_t> f_item_panel;  // panel to factor after the pulls, or -1
-    std::vector<int32_t> f_item_tgt;    // [nitems+1] range into f_tgt_col
-    std::vector<int32_t> f_tgt_col;     // target columns
-    std::vector<int32_t> f_tgt_src;     // [ntgt+1] range into f_src_panel
-    std::vector<int32_t> f_src_panel;   // source panels, ascending
+    std::vector<int32_t> f_item_pair;   // [nitems+1] range into f_pair_src / f_pair_tgt
+    std::vector<int32_t> f_pair_src, f_pair_tgt;
     // triangular solves: launch l runs items [x_lvl[l], x_lvl[l+1]); item = panel range
     std::vector<int32_t> l_lvl, l_item_p0, l_item_np;
     std::vector<int32_t> u_lvl, u_item_p0, u_item_np;

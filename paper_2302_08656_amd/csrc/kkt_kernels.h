@@ -13,11 +13,15 @@ constexpr int kFlagInternal = 2;   // a pull found no slot for a row (schedule b
 // Scalars written by the kernels and read back by the host.
 struct DevStatus {
     double anorm_scaled;          // ||R A C||_inf of the last refactorization
-    double anorm;                 // ||A||_inf of the last refactorization
+    double anorm;                 // ||A||_inf of the last refactorization (same order)
     unsigned long long perturbed; // pivots replaced by the last refactorization
     int flags;                    // kFlagNonfinite
     int pad;
-    double rnorm, xnorm, bnorm;   // infinity norms of the last residual evaluation
+};
+
+// Infinity norms of the last residual evaluation, read back by the host.
+struct ResNorms {
+    double rnorm, xnorm, bnorm;
 };
 
 }  // namespace kkt

@@ -75,26 +75,59 @@ __global__ void k_col_scale(int n, const int32_t *__restrict__ cptr, const int32
     c[j] = scale ? inv_pow2_floor_log2(m) : 1.0;
 }
 
-// ||A||_inf and ||R A C||_inf (row sums in CSR order)
-__global__ void k_norms(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                        const double *__restrict__ v, const double *__restrict__ r,
-                        const double *__restrict__ c, DevStatus *st) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// ||A||_inf and ||R A C||_inf (row sums in CSR order): block maxima into part[2 * block]
+__global__ __launch_bounds__(256) void k_norms(int n, const int32_t *__restrict__ rowptr,
+                                               const int32_t *__restrict__ col, const double *__restrict__ v,
+                                               const double *__restrict__ r, const double *__restrict__ c,
+                                               double *__restrict__ part) {
+    __shared__ double red[2][4];
     double s = 0.0, a = 0.0;
-    if (i < n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double si = 0.0, ai = 0.0;
         for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-            a = a + fabs(v[p]);
-            s = s + fabs((r[i] * v[p]) * c[col[p]]);
+            ai = ai + fabs(v[p]);
+            si = si + fabs((r[i] * v[p]) * c[col[p]]);
         }
+        s = fmax(s, si);
+        a = fmax(a, ai);
     }
-    // block max, then one atomic per block
     for (int o = 32; o > 0; o >>= 1) {
         s = fmax(s, __shfl_xor(s, o));
         a = fmax(a, __shfl_xor(a, o));
     }
     if ((threadIdx.x & 63) == 0) {
-        atomic_max_pos(&st->anorm_scaled, s);
-        atomic_max_pos(&st->anorm, a);
+        red[0][threadIdx.x >> 6] = s;
+        red[1][threadIdx.x >> 6] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+        part[2 * blockIdx.x + 1] = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+    }
+}
+
+// dst[j] = max over blocks b of part[nfield * b + j] (NaN propagates), j < nfield
+__global__ __launch_bounds__(256) void k_max_parts(int nblk, int nfield, const double *__restrict__ part,
+                                                   double *__restrict__ dst) {
+    __shared__ double red[4];
+    for (int j = 0; j < nfield; ++j) {
+        double m = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+            const double x = part[nfield * b + j];
+            m = (isnan(x) || isnan(m)) ? x + m : fmax(m, x);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double y = __shfl_xor(m, o);
+            m = (isnan(y) || isnan(m)) ? y + m : fmax(m, y);
+        }
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = red[0];
+            for (int q = 1; q < 4; ++q) t = (isnan(t) || isnan(red[q])) ? t + red[q] : fmax(t, red[q]);
+            dst[j] = t;
+        }
+        __syncthreads();
     }
 }
 
@@ -129,115 +162,305 @@ __device__ __forceinline__ int lower_bound_row(const int32_t *__restrict__ rowid
 
 struct RefArgs {
     const int32_t *colptr, *rowidx, *ulen, *pan_start, *pan_r;
-    const int32_t *item_panel, *item_tgt, *tgt_col, *tgt_src, *src_panel;
+    const int32_t *item_panel, *item_pair, *pair_src, *pair_tgt;
     double *lu;
     DevStatus *st;
     double tiny;
 };
 
-// Update of target column k by source panel S: rows s..e-1 of column k become final U
-// entries (unit lower solve with S's diagonal block), rows R of S lose L(R, S) times them.
-__device__ void pull_update(const RefArgs &a, int k, int S, int lane) {
+// position of the first L entry (row j+1 or below) of column j
+__device__ __forceinline__ int lbeg(const RefArgs &a, int j) { return a.colptr[j] + a.ulen[j] + 1; }
+// position of row s (the panel's first row) in column j of a panel starting at s
+__device__ __forceinline__ int seg(const RefArgs &a, int j, int jj) { return a.colptr[j] + a.ulen[j] - jj; }
+
+__device__ __forceinline__ double perturb(double p, double thresh, int &npert) {
+    if (fabs(p) < thresh) {
+        ++npert;
+        return p < 0.0 ? -thresh : thresh;
+    }
+    return p;
+}
+
+// ----------------------------------------------------------------- 16-lane path
+
+// Update of target column k by a narrow source panel S (w <= kSmallW, r <= kSmallR): rows
+// s..e-1 of column k become final U entries (unit lower solve with S's diagonal block) and
+// the rows R of S lose L(R, S) times them.
+__device__ void small_pull(const RefArgs &a, int k, int S, int gl) {
     const int s = a.pan_start[S], e = a.pan_start[S + 1], w = e - s, r = a.pan_r[S];
     const int c0 = a.colptr[k], c1 = a.colptr[k + 1];
     const int ps = lower_bound_row(a.rowidx, c0, c0 + a.ulen[k], s);
-    double u = lane < w ? a.lu[ps + lane] : 0.0;
-    for (int j = 0; j + 1 < w; ++j) {
-        const double uj = bcast(u, j);
-        if (lane > j && lane < w) {
-            const int lb = a.colptr[s + j] + a.ulen[s + j] + 1;
-            u = fma(-a.lu[lb + (lane - j - 1)], uj, u);
-        }
+    double u = gl < w ? a.lu[ps + gl] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kSmallW - 1; ++j) {
+        const double uj = __shfl(u, j, 16);
+        if (j + 1 < w && gl > j && gl < w) u = fma(-a.lu[lbeg(a, s + j) + (gl - j - 1)], uj, u);
     }
-    if (lane < w) a.lu[ps + lane] = u;
-    const int r0 = a.colptr[e - 1] + a.ulen[e - 1] + 1;   // rows R in the last column
-    for (int i = lane; i < r; i += 64) {
+    if (gl < w) a.lu[ps + gl] = u;
+    double uu[kSmallW];
+    int lb[kSmallW];
+#pragma unroll
+    for (int j = 0; j < kSmallW; ++j) {
+        uu[j] = __shfl(u, j, 16);
+        lb[j] = j < w ? lbeg(a, s + j) + (w - 1 - j) : 0;
+    }
+    const int r0 = lbeg(a, e - 1);
+    for (int i = gl; i < r; i += 16) {
         double acc = 0.0;
-        for (int j = 0; j < w; ++j) {
-            const int lb = a.colptr[s + j] + a.ulen[s + j] + 1 + (w - 1 - j);
-            acc = fma(a.lu[lb + i], bcast(u, j), acc);
-        }
+#pragma unroll
+        for (int j = 0; j < kSmallW; ++j)
+            if (j < w) acc = fma(a.lu[lb[j] + i], uu[j], acc);
         const int row = a.rowidx[r0 + i];
         const int pos = lower_bound_row(a.rowidx, ps + w, c1, row);
         if (pos < c1 && a.rowidx[pos] == row) a.lu[pos] -= acc;
         else atomicOr(&a.st->flags, kFlagInternal);   // the fill pattern guarantees a slot
     }
-    // rows of a later source may lie in R: make this update visible to the whole wave
-    __threadfence_block();
-    __syncthreads();
+    __threadfence_block();   // a later source of the same column may read these rows
 }
 
-// Dense LU without pivoting of the block column of panel T (diagonal block + rows R).
-__device__ void factor_panel(const RefArgs &a, int T, int lane, double *sm) {
+// Dense LU without pivoting of a narrow panel's block column (w <= kSmallW, r <= kSmallR).
+// Returns the number of replaced pivots (the same value on every lane of the group).
+__device__ int small_factor(const RefArgs &a, int T, int gl, double thresh) {
     const int s = a.pan_start[T], e = a.pan_start[T + 1], w = e - s, r = a.pan_r[T];
-    const double thresh = a.tiny * a.st->anorm_scaled;
-    double *D = sm;                    // w x w, column-major
-    double *X = sm + kPanelMax * kPanelMax;   // w x 64, one row of R per lane
-    for (int jj = 0; jj < w; ++jj) {
-        const int seg = a.colptr[s + jj] + a.ulen[s + jj] - jj;
-        for (int ii = lane; ii < w; ii += 64) D[jj * w + ii] = a.lu[seg + ii];
+    int sg[kSmallW];
+    double d[kSmallW];          // lane gl < w: row gl of the diagonal block
+#pragma unroll
+    for (int c = 0; c < kSmallW; ++c) {
+        sg[c] = c < w ? seg(a, s + c, c) : 0;
+        d[c] = (c < w && gl < w) ? a.lu[sg[c] + gl] : 0.0;
+    }
+    int npert = 0, bad = 0;
+    double U[kSmallW][kSmallW];   // final U of the diagonal block, known to every lane
+#pragma unroll
+    for (int jj = 0; jj < kSmallW; ++jj) {
+        if (jj < w) {
+            double ur[kSmallW];
+#pragma unroll
+            for (int c = 0; c < kSmallW; ++c) ur[c] = __shfl(d[c], jj, 16);
+            const double p = perturb(ur[jj], thresh, npert);
+            bad |= !isfinite(p);
+            if (gl == jj) d[jj] = p;
+            ur[jj] = p;
+#pragma unroll
+            for (int c = 0; c < kSmallW; ++c) U[jj][c] = ur[c];
+            if (gl > jj && gl < w) {
+                const double l = d[jj] / p;
+                d[jj] = l;
+#pragma unroll
+                for (int c = jj + 1; c < kSmallW; ++c)
+                    if (c < w) d[c] = fma(-l, ur[c], d[c]);
+            }
+        }
+    }
+    if (gl < w) {
+#pragma unroll
+        for (int c = 0; c < kSmallW; ++c)
+            if (c < w) a.lu[sg[c] + gl] = d[c];
+    }
+    for (int i = gl; i < r; i += 16) {
+        double x[kSmallW];
+#pragma unroll
+        for (int c = 0; c < kSmallW; ++c) x[c] = c < w ? a.lu[sg[c] + w + i] : 0.0;
+#pragma unroll
+        for (int jj = 0; jj < kSmallW; ++jj) {
+            if (jj < w) {
+                const double l = x[jj] / U[jj][jj];
+                bad |= !isfinite(l);
+                x[jj] = l;
+#pragma unroll
+                for (int c = jj + 1; c < kSmallW; ++c)
+                    if (c < w) x[c] = fma(-l, U[jj][c], x[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kSmallW; ++c)
+            if (c < w) a.lu[sg[c] + w + i] = x[c];
+    }
+    if (bad) atomicOr(&a.st->flags, kFlagNonfinite);
+    return npert;
+}
+
+// ----------------------------------------------------------------- 256-thread path
+
+constexpr int kLargeThreads = 256;
+constexpr int kRChunk = 128;
+constexpr int kColCache = 768;     // keeps the block under 64 KiB of LDS
+// LDS layout (bytes): Ld | Ub | Lr | Rrow | psbuf | column-row cache per wave
+constexpr int kOffLd = 0;
+constexpr int kOffUb = kOffLd + kPanelMax * kPanelMax * 8;
+constexpr int kOffLr = kOffUb + kPanelMax * kGroup * 8;
+constexpr int kOffRrow = kOffLr + kRChunk * kPanelMax * 8;
+constexpr int kOffPs = kOffRrow + kRChunk * 4;
+constexpr int kOffCol = kOffPs + kGroup * 4;
+constexpr int kLargeLds = kOffCol + (kLargeThreads / 64) * kColCache * 4;
+
+__device__ void large_factor(const RefArgs &a, int T, char *sm, double thresh) {
+    const int tid = threadIdx.x;
+    const int s = a.pan_start[T], e = a.pan_start[T + 1], w = e - s, r = a.pan_r[T];
+    double *D = reinterpret_cast<double *>(sm + kOffLd);   // column-major, ld kPanelMax
+    double *X = reinterpret_cast<double *>(sm + kOffLr);   // kRChunk rows x w, column-major
+    for (int t = tid; t < w * w; t += kLargeThreads) {
+        const int jj = t / w, ii = t % w;
+        D[jj * kPanelMax + ii] = a.lu[seg(a, s + jj, jj) + ii];
     }
     __syncthreads();
-    int bad = 0, npert = 0;
+    int npert = 0, bad = 0;
     for (int jj = 0; jj < w; ++jj) {
-        double p = D[jj * w + jj];
+        const double p = perturb(D[jj * kPanelMax + jj], thresh, npert);
         bad |= !isfinite(p);
-        if (fabs(p) < thresh) {
-            p = p < 0.0 ? -thresh : thresh;
-            ++npert;
-        }
         __syncthreads();
-        if (lane == 0) D[jj * w + jj] = p;
-        for (int ii = jj + 1 + lane; ii < w; ii += 64) D[jj * w + ii] = D[jj * w + ii] / p;
+        if (tid == 0) D[jj * kPanelMax + jj] = p;
+        for (int ii = jj + 1 + tid; ii < w; ii += kLargeThreads) D[jj * kPanelMax + ii] /= p;
         __syncthreads();
         const int m = w - jj - 1;
-        for (int t = lane; t < m * m; t += 64) {
+        for (int t = tid; t < m * m; t += kLargeThreads) {
             const int c2 = jj + 1 + t / m, ii = jj + 1 + t % m;
-            D[c2 * w + ii] = fma(-D[jj * w + ii], D[c2 * w + jj], D[c2 * w + ii]);
+            D[c2 * kPanelMax + ii] = fma(-D[jj * kPanelMax + ii], D[c2 * kPanelMax + jj], D[c2 * kPanelMax + ii]);
         }
         __syncthreads();
     }
-    for (int jj = 0; jj < w; ++jj) {
-        const int seg = a.colptr[s + jj] + a.ulen[s + jj] - jj;
-        for (int ii = lane; ii < w; ii += 64) a.lu[seg + ii] = D[jj * w + ii];
+    for (int t = tid; t < w * w; t += kLargeThreads) {
+        const int jj = t / w, ii = t % w;
+        a.lu[seg(a, s + jj, jj) + ii] = D[jj * kPanelMax + ii];
     }
-    for (int i0 = 0; i0 < r; i0 += 64) {
-        const int i = i0 + lane;
-        if (i < r) {
+    for (int i0 = 0; i0 < r; i0 += kRChunk) {
+        const int nr = min(kRChunk, r - i0);
+        for (int t = tid; t < w * nr; t += kLargeThreads) {
+            const int jj = t / nr, i = t % nr;
+            X[jj * kRChunk + i] = a.lu[seg(a, s + jj, jj) + w + i0 + i];
+        }
+        __syncthreads();
+        if (tid < nr) {
             for (int jj = 0; jj < w; ++jj) {
-                const int seg = a.colptr[s + jj] + a.ulen[s + jj] - jj;
-                X[jj * 64 + lane] = a.lu[seg + w + i];
-            }
-            for (int jj = 0; jj < w; ++jj) {
-                const double v = X[jj * 64 + lane] / D[jj * w + jj];
-                bad |= !isfinite(v);
-                X[jj * 64 + lane] = v;
-                for (int c2 = jj + 1; c2 < w; ++c2) X[c2 * 64 + lane] = fma(-v, D[c2 * w + jj], X[c2 * 64 + lane]);
-            }
-            for (int jj = 0; jj < w; ++jj) {
-                const int seg = a.colptr[s + jj] + a.ulen[s + jj] - jj;
-                a.lu[seg + w + i] = X[jj * 64 + lane];
+                const double l = X[jj * kRChunk + tid] / D[jj * kPanelMax + jj];
+                bad |= !isfinite(l);
+                X[jj * kRChunk + tid] = l;
+                for (int c2 = jj + 1; c2 < w; ++c2)
+                    X[c2 * kRChunk + tid] = fma(-l, D[c2 * kPanelMax + jj], X[c2 * kRChunk + tid]);
             }
         }
+        __syncthreads();
+        for (int t = tid; t < w * nr; t += kLargeThreads) {
+            const int jj = t / nr, i = t % nr;
+            a.lu[seg(a, s + jj, jj) + w + i0 + i] = X[jj * kRChunk + i];
+        }
+        __syncthreads();
     }
-    if (lane == 0 && npert) atomicAdd(&a.st->perturbed, (unsigned long long)npert);
-    if (__any(bad) && lane == 0) atomicOr(&a.st->flags, kFlagNonfinite);
+    if (tid == 0 && npert) atomicAdd(&a.st->perturbed, (unsigned long long)npert);
+    if (__any(bad) && (tid & 63) == 0) atomicOr(&a.st->flags, kFlagNonfinite);
 }
 
-__global__ __launch_bounds__(64) void k_refactor_level(int item0, RefArgs a) {
-    __shared__ double sm[kPanelMax * kPanelMax + kPanelMax * 64];
-    const int item = item0 + blockIdx.x;
-    const int lane = threadIdx.x;
-    for (int t = a.item_tgt[item]; t < a.item_tgt[item + 1]; ++t) {
-        const int k = a.tgt_col[t];
-        for (int q = a.tgt_src[t]; q < a.tgt_src[t + 1]; ++q) pull_update(a, k, a.src_panel[q], lane);
+// All pulls of one item with the source panel staged in LDS, then the panel factorization.
+__device__ void large_item(const RefArgs &a, int item, char *sm, double thresh) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double *Ld = reinterpret_cast<double *>(sm + kOffLd);
+    double *Ub = reinterpret_cast<double *>(sm + kOffUb);
+    double *Lr = reinterpret_cast<double *>(sm + kOffLr);
+    int *Rrow = reinterpret_cast<int *>(sm + kOffRrow);
+    int *psb = reinterpret_cast<int *>(sm + kOffPs);
+    int *colc = reinterpret_cast<int *>(sm + kOffCol) + wv * kColCache;
+    const int p1 = a.item_pair[item + 1];
+    for (int g0 = a.item_pair[item], g1; g0 < p1; g0 = g1) {
+        const int S = a.pair_src[g0];
+        g1 = g0 + 1;
+        while (g1 < p1 && a.pair_src[g1] == S) ++g1;
+        const int s = a.pan_start[S], e = a.pan_start[S + 1], w = e - s, r = a.pan_r[S];
+        for (int t = tid; t < w * w; t += kLargeThreads) {
+            const int j = t / w, i = t % w;
+            if (i > j) Ld[j * kPanelMax + i] = a.lu[lbeg(a, s + j) + (i - j - 1)];
+        }
+        __syncthreads();
+        for (int q = g0 + wv; q < g1; q += kLargeThreads / 64) {
+            const int k = a.pair_tgt[q];
+            const int c0 = a.colptr[k];
+            const int ps = lower_bound_row(a.rowidx, c0, c0 + a.ulen[k], s);
+            double u = lane < w ? a.lu[ps + lane] : 0.0;
+            for (int j = 0; j + 1 < w; ++j) {
+                const double uj = bcast(u, j);
+                if (lane > j && lane < w) u = fma(-Ld[j * kPanelMax + lane], uj, u);
+            }
+            if (lane < w) {
+                a.lu[ps + lane] = u;
+                Ub[(q - g0) * kPanelMax + lane] = u;
+            }
+            if (lane == 0) psb[q - g0] = ps;
+        }
+        __syncthreads();
+        const int r0 = lbeg(a, e - 1);
+        for (int i0 = 0; i0 < r; i0 += kRChunk) {
+            const int nr = min(kRChunk, r - i0);
+            for (int t = tid; t < w * nr; t += kLargeThreads) {
+                const int j = t / nr, i = t % nr;
+                Lr[j * kRChunk + i] = a.lu[lbeg(a, s + j) + (w - 1 - j) + i0 + i];
+            }
+            for (int i = tid; i < nr; i += kLargeThreads) Rrow[i] = a.rowidx[r0 + i0 + i];
+            __syncthreads();
+            for (int q = g0 + wv; q < g1; q += kLargeThreads / 64) {
+                const int k = a.pair_tgt[q];
+                const int lo = psb[q - g0] + w, hi = a.colptr[k + 1];
+                const bool cached = hi - lo <= kColCache;
+                if (cached)
+                    for (int t = lane; t < hi - lo; t += 64) colc[t] = a.rowidx[lo + t];
+                __threadfence_block();
+                const double *ub = Ub + (q - g0) * kPanelMax;
+                for (int i = lane; i < nr; i += 64) {
+                    double acc = 0.0;
+                    for (int j = 0; j < w; ++j) acc = fma(Lr[j * kRChunk + i], ub[j], acc);
+                    const int row = Rrow[i];
+                    int pos;
+                    if (cached) {
+                        int l2 = 0, h2 = hi - lo;
+                        while (l2 < h2) {
+                            const int mid = (l2 + h2) >> 1;
+                            if (colc[mid] < row) l2 = mid + 1;
+                            else h2 = mid;
+                        }
+                        pos = lo + l2;
+                    } else {
+                        pos = lower_bound_row(a.rowidx, lo, hi, row);
+                    }
+                    if (pos < hi && a.rowidx[pos] == row) a.lu[pos] -= acc;
+                    else atomicOr(&a.st->flags, kFlagInternal);
+                }
+                __threadfence_block();
+            }
+            __syncthreads();
+        }
+        __threadfence_block();
+        __syncthreads();
     }
     const int T = a.item_panel[item];
-    if (T >= 0) factor_panel(a, T, lane, sm);
+    if (T >= 0) large_factor(a, T, sm, thresh);
+}
+
+// One launch per panel level: blocks [0, nlarge) take one large item each, the remaining
+// blocks take kLargeThreads/16 small items each (one per 16-lane group).
+__global__ __launch_bounds__(256) void k_refactor_level(int item0, int nlarge, int nsmall, RefArgs a) {
+    extern __shared__ __align__(16) char dsm[];
+    const double thresh = a.tiny * a.st->anorm_scaled;
+    if ((int)blockIdx.x < nlarge) {
+        large_item(a, item0 + blockIdx.x, dsm, thresh);
+        return;
+    }
+    const int g = (blockIdx.x - nlarge) * (kLargeThreads / 16) + (threadIdx.x >> 4);
+    const int gl = threadIdx.x & 15;
+    int npert = 0;
+    if (g < nsmall) {
+        const int item = item0 + nlarge + g;
+        for (int q = a.item_pair[item]; q < a.item_pair[item + 1]; ++q)
+            small_pull(a, a.pair_tgt[q], a.pair_src[q], gl);
+        const int T = a.item_panel[item];
+        if (T >= 0) npert = small_factor(a, T, gl, thresh);
+    }
+    // one counter update per wavefront: group leaders contribute their count
+    int c = gl == 0 ? npert : 0;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&a.st->perturbed, (unsigned long long)c);
 }
 
 // ---------------------------------------------------------------------------------------
-// triangular solves, one wavefront per item
+// triangular solves: one 256-thread block per wide panel or per pack of kSolvePack
+// width-1 panels (8 lanes per row)
 
 struct SolveArgs {
     const int32_t *pan_start, *item_p0, *item_np, *pan;
@@ -249,35 +472,45 @@ struct SolveArgs {
     double *x;            // backward output (original order)
 };
 
-__global__ __launch_bounds__(64) void k_lsolve_level(int item0, SolveArgs a) {
+// sum over q in [q0, q1) of lucsr[q] * v[col[q]] on a group of `width` lanes
+__device__ __forceinline__ double row_dot(const SolveArgs &a, const double *v, int q0, int q1, int gl, int width) {
+    double s0 = 0.0, s1 = 0.0;
+    int q = q0 + gl;
+    for (; q + width < q1; q += 2 * width) {
+        s0 = fma(a.lucsr[q], v[a.col[q]], s0);
+        s1 = fma(a.lucsr[q + width], v[a.col[q + width]], s1);
+    }
+    if (q < q1) s0 = fma(a.lucsr[q], v[a.col[q]], s0);
+    return group_sum(s0 + s1, width);
+}
+
+__global__ __launch_bounds__(256) void k_lsolve_level(int item0, SolveArgs a) {
     __shared__ double ext[kPanelMax];
-    const int item = item0 + blockIdx.x, lane = threadIdx.x;
+    const int item = item0 + blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const int np = a.item_np[item], p0 = a.item_p0[item];
-    const int g = lane >> 3, gl = lane & 7;
-    if (np < 0) {                                    // pack of width-1 panels
-        double acc = 0.0;
-        int i = -1;
+    if (np < 0) {                                    // pack of width-1 panels, 8 lanes each
+        const int g = tid >> 3, gl = tid & 7;
+        int i = -1, q0 = 0, q1 = 0;
         if (g < -np) {
             i = a.pan_start[a.pan[p0 + g]];
-            for (int q = a.rowptr[i] + gl; q < a.diag[i]; q += 8) acc = fma(a.lucsr[q], a.y[a.col[q]], acc);
+            q0 = a.rowptr[i];
+            q1 = a.diag[i];
         }
-        acc = group_sum(acc, 8);
+        const double acc = row_dot(a, a.y, q0, q1, gl, 8);
         if (i >= 0 && gl == 0) a.y[i] = a.r[a.P[i]] * a.b[a.P[i]] - acc;
         return;
     }
     const int T = a.pan[p0];
     const int s = a.pan_start[T], w = a.pan_start[T + 1] - s;
-    for (int t0 = 0; t0 < w; t0 += 8) {
-        const int t = t0 + g;
-        double acc = 0.0;
-        if (t < w) {
-            const int i = s + t;
-            for (int q = a.rowptr[i] + gl; q < a.diag[i] - t; q += 8) acc = fma(a.lucsr[q], a.y[a.col[q]], acc);
-        }
-        acc = group_sum(acc, 8);
-        if (t < w && gl == 0) ext[t] = acc;
+    // external part of each row (columns left of the panel): 32 lanes per row, 8 rows at once
+    const int g = tid >> 5, gl = tid & 31;
+    for (int t = g; t < w; t += kLargeThreads / 32) {
+        const int i = s + t;
+        const double acc = row_dot(a, a.y, a.rowptr[i], a.diag[i] - t, gl, 32);
+        if (gl == 0) ext[t] = acc;
     }
     __syncthreads();
+    if (tid >= 64) return;
     double yv = 0.0;
     if (lane < w) yv = a.r[a.P[s + lane]] * a.b[a.P[s + lane]] - ext[lane];
     for (int t = 0; t + 1 < w; ++t) {
@@ -287,19 +520,19 @@ __global__ __launch_bounds__(64) void k_lsolve_level(int item0, SolveArgs a) {
     if (lane < w) a.y[s + lane] = yv;
 }
 
-__global__ __launch_bounds__(64) void k_usolve_level(int item0, SolveArgs a) {
+__global__ __launch_bounds__(256) void k_usolve_level(int item0, SolveArgs a) {
     __shared__ double ext[kPanelMax];
-    const int item = item0 + blockIdx.x, lane = threadIdx.x;
+    const int item = item0 + blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const int np = a.item_np[item], p0 = a.item_p0[item];
-    const int g = lane >> 3, gl = lane & 7;
     if (np < 0) {
-        double acc = 0.0;
-        int i = -1;
+        const int g = tid >> 3, gl = tid & 7;
+        int i = -1, q0 = 0, q1 = 0;
         if (g < -np) {
             i = a.pan_start[a.pan[p0 + g]];
-            for (int q = a.diag[i] + 1 + gl; q < a.rowptr[i + 1]; q += 8) acc = fma(a.lucsr[q], a.xt[a.col[q]], acc);
+            q0 = a.diag[i] + 1;
+            q1 = a.rowptr[i + 1];
         }
-        acc = group_sum(acc, 8);
+        const double acc = row_dot(a, a.xt, q0, q1, gl, 8);
         if (i >= 0 && gl == 0) {
             const double xv = (a.y[i] - acc) / a.lucsr[a.diag[i]];
             a.xt[i] = xv;
@@ -309,17 +542,14 @@ __global__ __launch_bounds__(64) void k_usolve_level(int item0, SolveArgs a) {
     }
     const int T = a.pan[p0];
     const int s = a.pan_start[T], w = a.pan_start[T + 1] - s;
-    for (int t0 = 0; t0 < w; t0 += 8) {
-        const int t = t0 + g;
-        double acc = 0.0;
-        if (t < w) {
-            const int i = s + t;
-            for (int q = a.diag[i] + (w - t) + gl; q < a.rowptr[i + 1]; q += 8) acc = fma(a.lucsr[q], a.xt[a.col[q]], acc);
-        }
-        acc = group_sum(acc, 8);
-        if (t < w && gl == 0) ext[t] = acc;
+    const int g = tid >> 5, gl = tid & 31;
+    for (int t = g; t < w; t += kLargeThreads / 32) {
+        const int i = s + t;
+        const double acc = row_dot(a, a.xt, a.diag[i] + (w - t), a.rowptr[i + 1], gl, 32);
+        if (gl == 0) ext[t] = acc;
     }
     __syncthreads();
+    if (tid >= 64) return;
     double val = 0.0, xv = 0.0;
     if (lane < w) val = a.y[s + lane] - ext[lane];
     for (int t = w - 1; t >= 0; --t) {
@@ -336,39 +566,47 @@ __global__ __launch_bounds__(64) void k_usolve_level(int item0, SolveArgs a) {
 // ---------------------------------------------------------------------------------------
 // residual, sparse products and Krylov vector kernels (FP64)
 
-__global__ void k_reset_norms(DevStatus *st) {
-    st->rnorm = 0.0;
-    st->xnorm = 0.0;
-    st->bnorm = 0.0;
-}
-
-// res = b - A x with infinity norms of res, x and b (8 lanes per row)
-__global__ void k_residual(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                           const double *__restrict__ v, const double *__restrict__ x,
-                           const double *__restrict__ b, double *__restrict__ res, DevStatus *st) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = gid >> 3, gl = gid & 7;
-    double s = 0.0;
-    if (i < n)
-        for (int p = rowptr[i] + gl; p < rowptr[i + 1]; p += 8) s = fma(v[p], x[col[p]], s);
-    s = group_sum(s, 8);
+// res = b - A x (8 lanes per row, grid-stride) and block maxima of |res|, |x|, |b| into
+// part[3 * block + {0, 1, 2}]
+__global__ __launch_bounds__(256) void k_residual(int n, const int32_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col, const double *__restrict__ v,
+                                                  const double *__restrict__ x, const double *__restrict__ b,
+                                                  double *__restrict__ res, double *__restrict__ part) {
+    __shared__ double red[3][4];
+    const double qnan = __longlong_as_double(0x7ff8000000000000LL);
     double rn = 0.0, xn = 0.0, bn = 0.0;
-    if (i < n && gl == 0) {
-        const double ri = b[i] - s;
-        res[i] = ri;
-        rn = isnan(ri) ? __longlong_as_double(0x7ff8000000000000LL) : fabs(ri);
-        xn = isnan(x[i]) ? __longlong_as_double(0x7ff8000000000000LL) : fabs(x[i]);
-        bn = fabs(b[i]);
+    const int gl = threadIdx.x & 7;
+    for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; i < n; i += (gridDim.x * blockDim.x) >> 3) {
+        double s = 0.0;
+        for (int p = rowptr[i] + gl; p < rowptr[i + 1]; p += 8) s = fma(v[p], x[col[p]], s);
+        s = group_sum(s, 8);
+        if (gl == 0) {
+            const double ri = b[i] - s;
+            res[i] = ri;
+            rn = isnan(ri) ? qnan : fmax(rn, fabs(ri));
+            xn = isnan(x[i]) ? qnan : fmax(xn, fabs(x[i]));
+            bn = fmax(bn, fabs(b[i]));
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
-        rn = fmax(rn, __shfl_xor(rn, o));
-        xn = fmax(xn, __shfl_xor(xn, o));
+        const double r2 = __shfl_xor(rn, o), x2 = __shfl_xor(xn, o);
+        rn = (isnan(r2) || isnan(rn)) ? r2 + rn : fmax(rn, r2);
+        xn = (isnan(x2) || isnan(xn)) ? x2 + xn : fmax(xn, x2);
         bn = fmax(bn, __shfl_xor(bn, o));
     }
     if ((threadIdx.x & 63) == 0) {
-        atomic_max_pos(&st->rnorm, rn);
-        atomic_max_pos(&st->xnorm, xn);
-        atomic_max_pos(&st->bnorm, bn);
+        red[0][threadIdx.x >> 6] = rn;
+        red[1][threadIdx.x >> 6] = xn;
+        red[2][threadIdx.x >> 6] = bn;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = red[threadIdx.x][0];
+        for (int q = 1; q < 4; ++q) {
+            const double y = red[threadIdx.x][q];
+            t = (isnan(t) || isnan(y)) ? t + y : fmax(t, y);
+        }
+        part[3 * blockIdx.x + threadIdx.x] = t;
     }
 }
 

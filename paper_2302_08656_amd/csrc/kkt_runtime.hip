@@ -19,15 +19,17 @@ namespace {
 struct Dev {
     int32_t *a_rowptr, *a_colind, *a_rowid, *a_cptr, *a_cpos, *lu_src;
     int32_t *colptr, *rowidx, *ulen, *pan_start, *pan_r;
-    int32_t *f_item_panel, *f_item_tgt, *f_tgt_col, *f_tgt_src, *f_src_panel;
+    int32_t *f_item_panel, *f_item_pair, *f_pair_src, *f_pair_tgt;
     int32_t *l_item_p0, *l_item_np, *l_pan, *u_item_p0, *u_item_np, *u_pan;
     int32_t *csr_rowptr, *csr_col, *csr_src, *csr_diag, *P, *Q;
     double *r, *c, *lu, *lucsr, *y, *xt, *bsave;
     double *V, *Z, *w, *res, *part, *hbuf, *ybuf;
     DevStatus *st;
+    ResNorms *rn;
 };
 
 constexpr int kDotBlocks = 512;
+constexpr int kNormBlocks = 1024;
 constexpr int kMaxRestart = 64;
 
 struct Carver {
@@ -78,10 +80,9 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.pan_start = c.take<int32_t>(g.pan_start.size());
     d.pan_r = c.take<int32_t>(g.pan_r.size());
     d.f_item_panel = c.take<int32_t>(g.f_item_panel.size());
-    d.f_item_tgt = c.take<int32_t>(g.f_item_tgt.size());
-    d.f_tgt_col = c.take<int32_t>(g.f_tgt_col.size());
-    d.f_tgt_src = c.take<int32_t>(g.f_tgt_src.size());
-    d.f_src_panel = c.take<int32_t>(std::max<size_t>(1, g.f_src_panel.size()));
+    d.f_item_pair = c.take<int32_t>(g.f_item_pair.size());
+    d.f_pair_src = c.take<int32_t>(std::max<size_t>(1, g.f_pair_src.size()));
+    d.f_pair_tgt = c.take<int32_t>(std::max<size_t>(1, g.f_pair_tgt.size()));
     d.l_item_p0 = c.take<int32_t>(g.l_item_p0.size());
     d.l_item_np = c.take<int32_t>(g.l_item_np.size());
     d.l_pan = c.take<int32_t>(g.l_pan.size());
@@ -105,10 +106,11 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.Z = c.take<double>((size_t)m * n);
     d.w = c.take<double>(n);
     d.res = c.take<double>(n);
-    d.part = c.take<double>((size_t)kDotBlocks * (m + 2));
+    d.part = c.take<double>(std::max((size_t)kDotBlocks * (m + 2), (size_t)kNormBlocks * 3));
     d.hbuf = c.take<double>(4 * (size_t)(m + 2));
     d.ybuf = c.take<double>((size_t)m + 2);
     d.st = c.take<DevStatus>(1);
+    d.rn = c.take<ResNorms>(1);
     *bytes = c.off + 256;
 }
 
@@ -147,14 +149,14 @@ int enqueue_solve(kkt_handle *h, const double *b, double *x, hipStream_t s) {
                 d.P, d.Q, d.lucsr, d.r, d.c, b, d.y, d.xt, x};
     for (size_t l = 0; l + 1 < g.l_lvl.size(); ++l) {
         const int cnt = g.l_lvl[l + 1] - g.l_lvl[l];
-        if (cnt) k_lsolve_level<<<cnt, 64, 0, s>>>(g.l_lvl[l], a);
+        if (cnt) k_lsolve_level<<<cnt, kLargeThreads, 0, s>>>(g.l_lvl[l], a);
     }
     a.item_p0 = d.u_item_p0;
     a.item_np = d.u_item_np;
     a.pan = d.u_pan;
     for (size_t l = 0; l + 1 < g.u_lvl.size(); ++l) {
         const int cnt = g.u_lvl[l + 1] - g.u_lvl[l];
-        if (cnt) k_usolve_level<<<cnt, 64, 0, s>>>(g.u_lvl[l], a);
+        if (cnt) k_usolve_level<<<cnt, kLargeThreads, 0, s>>>(g.u_lvl[l], a);
     }
     HIPCHK(hipGetLastError());
     return KKT_OK;
@@ -168,13 +170,15 @@ int enqueue_refactor(kkt_handle *h, const double *v, hipStream_t s) {
     const int eq = h->opts.equilibrate != 0;
     k_row_scale<<<blocks_for(n, 256), 256, 0, s>>>(n, d.a_rowptr, v, eq, d.r, d.st);
     k_col_scale<<<blocks_for(n, 256), 256, 0, s>>>(n, d.a_cptr, d.a_cpos, d.a_rowid, v, d.r, eq, d.c);
-    k_norms<<<blocks_for(n, 256), 256, 0, s>>>(n, d.a_rowptr, d.a_colind, v, d.r, d.c, d.st);
+    k_norms<<<kNormBlocks, 256, 0, s>>>(n, d.a_rowptr, d.a_colind, v, d.r, d.c, d.part);
+    k_max_parts<<<1, 256, 0, s>>>(kNormBlocks, 2, d.part, &d.st->anorm_scaled);
     k_gather_lu<<<blocks_for(nlu, 256), 256, 0, s>>>(nlu, d.lu_src, d.a_rowid, d.a_colind, v, d.r, d.c, d.lu);
-    RefArgs a{d.colptr, d.rowidx, d.ulen, d.pan_start, d.pan_r, d.f_item_panel, d.f_item_tgt,
-              d.f_tgt_col, d.f_tgt_src, d.f_src_panel, d.lu, d.st, h->opts.tiny_pivot};
+    RefArgs a{d.colptr, d.rowidx, d.ulen, d.pan_start, d.pan_r, d.f_item_panel, d.f_item_pair,
+              d.f_pair_src, d.f_pair_tgt, d.lu, d.st, h->opts.tiny_pivot};
     for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
-        const int cnt = g.f_lvl[l + 1] - g.f_lvl[l];
-        if (cnt) k_refactor_level<<<cnt, 64, 0, s>>>(g.f_lvl[l], a);
+        const int nl = g.f_nlarge[l], ns = g.f_lvl[l + 1] - g.f_lvl[l] - nl;
+        const unsigned nb = (unsigned)nl + blocks_for(ns, kLargeThreads / 16);
+        if (nb) k_refactor_level<<<nb, kLargeThreads, nl ? kLargeLds : 0, s>>>(g.f_lvl[l], nl, ns, a);
     }
     k_to_csr<<<blocks_for(nlu, 256), 256, 0, s>>>(nlu, d.csr_src, d.lu, d.lucsr);
     HIPCHK(hipGetLastError());
@@ -193,16 +197,18 @@ void enqueue_dots(kkt_handle *h, int nv, const double *V, const double *w, doubl
 int residual_berr(kkt_handle *h, const double *x, const double *b, double *berr, double *den, hipStream_t s) {
     const Dev &d = h->d;
     const int n = h->sym.n;
-    k_reset_norms<<<1, 1, 0, s>>>(d.st);
-    k_residual<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_rowptr, d.a_colind, h->d_values, x, b,
-                                                                 d.res, d.st);
+    k_residual<<<kNormBlocks, 256, 0, s>>>(n, d.a_rowptr, d.a_colind, h->d_values, x, b, d.res, d.part);
+    k_max_parts<<<1, 256, 0, s>>>(kNormBlocks, 3, d.part, &d.rn->rnorm);
     HIPCHK(hipMemcpyAsync(h->h_small, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h->h_small + 8, d.rn, sizeof(ResNorms), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     DevStatus st;
+    ResNorms rn;
     std::memcpy(&st, h->h_small, sizeof(st));
-    *den = st.anorm * st.xnorm + st.bnorm;
-    if (*den == 0.0) *berr = st.rnorm == 0.0 ? 0.0 : INFINITY;
-    else *berr = st.rnorm / *den;
+    std::memcpy(&rn, h->h_small + 8, sizeof(rn));
+    *den = st.anorm * rn.xnorm + rn.bnorm;
+    if (*den == 0.0) *berr = rn.rnorm == 0.0 ? 0.0 : INFINITY;
+    else *berr = rn.rnorm / *den;
     return KKT_OK;
 }
 
@@ -388,7 +394,7 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     if (bytes < need) return KKT_ERR_NOMEM;
     int dev = -1;
     HIPCHK(hipGetDevice(&dev));
-    if (!h->h_small) HIPCHK(hipHostMalloc(&h->h_small, sizeof(double) * 4 * (kMaxRestart + 2) + sizeof(DevStatus)));
+    if (!h->h_small) HIPCHK(hipHostMalloc(&h->h_small, sizeof(double) * 4 * (kMaxRestart + 2) + 256));
     carve(h, static_cast<char *>(d_workspace), h->d, &need);
     const Symbolic &s = h->sym;
     const Schedule &g = h->sch;
@@ -411,10 +417,9 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     rc |= upload(d.pan_start, g.pan_start, stream);
     rc |= upload(d.pan_r, g.pan_r, stream);
     rc |= upload(d.f_item_panel, g.f_item_panel, stream);
-    rc |= upload(d.f_item_tgt, g.f_item_tgt, stream);
-    rc |= upload(d.f_tgt_col, g.f_tgt_col, stream);
-    rc |= upload(d.f_tgt_src, g.f_tgt_src, stream);
-    rc |= upload(d.f_src_panel, g.f_src_panel, stream);
+    rc |= upload(d.f_item_pair, g.f_item_pair, stream);
+    rc |= upload(d.f_pair_src, g.f_pair_src, stream);
+    rc |= upload(d.f_pair_tgt, g.f_pair_tgt, stream);
     rc |= upload(d.l_item_p0, g.l_item_p0, stream);
     rc |= upload(d.l_item_np, g.l_item_np, stream);
     rc |= upload(d.l_pan, g.l_pan, stream);

@@ -102,60 +102,82 @@ int build_schedule(const Symbolic &s, Schedule &g) {
     for (const auto &pr : pairs) by_launch[plev[pr.first] + 1].emplace_back(pr.second, pr.first);
     std::vector<std::vector<int32_t>> panels_at(nlev);
     for (int32_t p = 0; p < np; ++p) panels_at[plev[p]].push_back(p);
+    auto pw = [&](int32_t p) { return g.pan_start[p + 1] - g.pan_start[p]; };
+    auto is_small = [&](int32_t p) { return pw(p) <= kSmallW && g.pan_r[p] <= kSmallR; };
     g.f_lvl.assign(1, 0);
+    g.f_nlarge.clear();
     g.f_item_panel.clear();
-    g.f_item_tgt.assign(1, 0);
-    g.f_tgt_col.clear();
-    g.f_tgt_src.assign(1, 0);
-    g.f_src_panel.clear();
+    g.f_item_pair.assign(1, 0);
+    g.f_pair_src.clear();
+    g.f_pair_tgt.clear();
+    std::vector<int32_t> fac_index(np, -1);
+    struct Item {
+        int32_t panel;
+        std::vector<std::pair<int32_t, int32_t>> pairs;   // (source, target)
+        bool small;
+        double cost;
+    };
     for (int32_t l = 0; l < nlev; ++l) {
-        auto &pl = by_launch[l];
+        auto &pl = by_launch[l];                  // (target, source)
         std::sort(pl.begin(), pl.end());
-        // sources of each target column at this launch
-        std::vector<int32_t> cols;
-        std::vector<int32_t> cptr(1, 0), srcs;
-        for (size_t q = 0; q < pl.size(); ++q) {
-            if (q == 0 || pl[q].first != pl[q - 1].first) {
-                if (q) cptr.push_back((int32_t)srcs.size());
-                cols.push_back(pl[q].first);
-            }
-            srcs.push_back(pl[q].second);
+        std::vector<Item> items;
+        // factor items: the panel and every pair that targets one of its columns
+        for (int32_t T : panels_at[l]) {
+            Item it{T, {}, is_small(T), 0.0};
+            items.push_back(it);
         }
-        cptr.push_back((int32_t)srcs.size());
-        auto sources_of = [&](int32_t k, std::vector<int32_t> &out) {
-            out.clear();
-            const auto it = std::lower_bound(cols.begin(), cols.end(), k);
-            if (it != cols.end() && *it == k) {
-                const size_t q = it - cols.begin();
-                out.assign(srcs.begin() + cptr[q], srcs.begin() + cptr[q + 1]);
+        for (size_t i = 0; i < items.size(); ++i) fac_index[items[i].panel] = (int32_t)i;
+        // pull-only targets: single-source targets are grouped by source
+        std::vector<std::pair<int32_t, int32_t>> single;   // (source, target)
+        for (size_t q = 0; q < pl.size();) {
+            size_t q1 = q;
+            while (q1 < pl.size() && pl[q1].first == pl[q].first) ++q1;
+            const int32_t k = pl[q].first, T = pan_of[k];
+            if (fac_index[T] >= 0) {
+                for (size_t t = q; t < q1; ++t) items[fac_index[T]].pairs.emplace_back(pl[t].second, k);
+            } else if (q1 - q == 1) {
+                single.emplace_back(pl[q].second, k);
+            } else {
+                Item it{-1, {}, true, 0.0};
+                for (size_t t = q; t < q1; ++t) it.pairs.emplace_back(pl[t].second, k);
+                items.push_back(it);
             }
-        };
-        // factor items: widest panels first
-        auto fac = panels_at[l];
-        std::stable_sort(fac.begin(), fac.end(), [&](int32_t a, int32_t b) {
-            return g.pan_start[a + 1] - g.pan_start[a] > g.pan_start[b + 1] - g.pan_start[b];
+            q = q1;
+        }
+        std::sort(single.begin(), single.end());
+        for (size_t q = 0; q < single.size();) {
+            const int32_t S = single[q].first;
+            const size_t cap = is_small(S) ? 1 : kGroup;
+            Item it{-1, {}, true, 0.0};
+            size_t q1 = q;
+            while (q1 < single.size() && single[q1].first == S && q1 - q < cap) it.pairs.push_back(single[q1++]);
+            items.push_back(it);
+            q = q1;
+        }
+        for (auto &it : items) {
+            std::sort(it.pairs.begin(), it.pairs.end());
+            for (const auto &pr : it.pairs) {
+                if (!is_small(pr.first)) it.small = false;
+                it.cost += (double)pw(pr.first) * (pw(pr.first) + g.pan_r[pr.first]);
+            }
+            if (it.panel >= 0) it.cost += (double)pw(it.panel) * pw(it.panel) * (pw(it.panel) + g.pan_r[it.panel]);
+        }
+        for (int32_t T : panels_at[l]) fac_index[T] = -1;
+        std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
+            if (a.small != b.small) return !a.small;
+            return a.cost > b.cost;
         });
-        std::vector<int32_t> tmp;
-        for (int32_t T : fac) {
-            g.f_item_panel.push_back(T);
-            for (int32_t k = g.pan_start[T]; k < g.pan_start[T + 1]; ++k) {
-                sources_of(k, tmp);
-                g.f_tgt_col.push_back(k);
-                g.f_src_panel.insert(g.f_src_panel.end(), tmp.begin(), tmp.end());
-                g.f_tgt_src.push_back((int32_t)g.f_src_panel.size());
+        int32_t nlarge = 0;
+        for (const auto &it : items) {
+            nlarge += !it.small;
+            g.f_item_panel.push_back(it.panel);
+            for (const auto &pr : it.pairs) {
+                g.f_pair_src.push_back(pr.first);
+                g.f_pair_tgt.push_back(pr.second);
             }
-            g.f_item_tgt.push_back((int32_t)g.f_tgt_col.size());
+            g.f_item_pair.push_back((int32_t)g.f_pair_src.size());
         }
-        // pull-only items: target columns not in a panel of this level
-        for (size_t q = 0; q < cols.size(); ++q) {
-            const int32_t k = cols[q];
-            if (plev[pan_of[k]] == l) continue;
-            g.f_item_panel.push_back(-1);
-            g.f_tgt_col.push_back(k);
-            g.f_src_panel.insert(g.f_src_panel.end(), srcs.begin() + cptr[q], srcs.begin() + cptr[q + 1]);
-            g.f_tgt_src.push_back((int32_t)g.f_src_panel.size());
-            g.f_item_tgt.push_back((int32_t)g.f_tgt_col.size());
-        }
+        g.f_nlarge.push_back(nlarge);
         g.f_lvl.push_back((int32_t)g.f_item_panel.size());
     }
     if (!by_launch[nlev].empty()) return KKT_ERR_PATTERN;   // top panels have no targets
