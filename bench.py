@@ -3,8 +3,9 @@
 70,000-bus-shaped synthetic grid (N = 665,000, 5,285,000 nonzeros), with p50/p99 latency,
 the roofline position of the dominant kernel and the CPU-oracle baseline.
 
-One step (unit) = kkt_refactor(K_t) + kkt_solve(b_t) + kkt_refine(b_t) that ends with a
-backward error <= 1e-10, for t cycling through the 50-system sequence.  All values and
+One step (unit) = kkt_refactor(K_t) followed by kkt_refine(b_t) (triangular solve plus FGMRES
+refinement, as Algorithm 1 pairs every solve with refinement) that ends with a backward error
+<= 1e-10, for t cycling through the 50-system sequence.  All values and
 right-hand sides are resident in HBM before the timed region starts; analysis (host, once
 per pattern) is timed separately.  One GPU only.
 """
@@ -91,7 +92,6 @@ def main():
 
     def unit(t):
         sk.refactor(dvals[t])
-        sk.solve(drhs[t], x)
         _, info = sk.refine(drhs[t], x)
         return info[0]
 
@@ -114,27 +114,44 @@ def main():
     ok_units = args.steps - fails
     value = ok_units / elapsed
 
-    # phase timing with events on the library's stream (torch's current stream)
-    s = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    nrep = 10
-    ev[0].record(s)
-    for i in range(nrep):
-        sk.refactor(dvals[i % T])
-    ev[1].record(s)
-    for i in range(nrep):
-        sk.solve(drhs[i % T], x)
-    ev[2].record(s)
-    torch.cuda.synchronize()
-    ms_refactor = ev[0].elapsed_time(ev[1]) / nrep
-    ms_solve = ev[1].elapsed_time(ev[2]) / nrep
-    b_ref, b_sol, b_spmv = algorithmic_bytes(q.n, q.nnz, st["nnz_lu"])
-    ach = b_ref / (ms_refactor * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
-                "kernel": "refactorization (value update + panel levels + CSR copy)",
-                "bytes_per_launch": b_ref, "ms_per_launch": round(ms_refactor, 4),
-                "solve_ms": round(ms_solve, 4), "solve_bytes": b_sol}
+    # per-kernel-class launch timing with HIP events on the library's stream (torch's
+    # current stream), over a second pass of the same workload
+    nprof = min(args.steps, 50)
+    sk.profile(True)
+    solves = 0
+    for i in range(nprof):
+        solves += 1 + unit(i % T).iters
+    prof = sk.profile_read()
+    sk.profile(False)
+    sym = sk.export_symbolic()
+    cols = np.repeat(np.arange(q.n), np.diff(sym["colptr"]))
+    nnz_l = int(np.count_nonzero(sym["rowidx"] > cols))
+    nnz_u = st["nnz_lu"] - q.n - nnz_l
+    # algorithmic bytes per unit of each class (int32 indices, FP64 values)
+    per_unit = {
+        "refactor_large": None, "refactor_small": None,
+        "refactor": 16 * st["nnz_lu"] * nprof,                       # every factor value read + written once
+        "lsolve": (12 * nnz_l + 48 * q.n) * solves,                  # L values + columns, pointers, b, r, P, y
+        "usolve": (12 * (nnz_u + q.n) + 48 * q.n) * solves,          # U values + columns, pointers, y, x, c, Q
+        "to_csr": 20 * st["nnz_lu"] * nprof,
+        "update": (12 * q.nnz + 12 * st["nnz_lu"] + 40 * q.n) * nprof,
+    }
+    prof["refactor"] = (prof["refactor_large"][0] + prof["refactor_small"][0],
+                        prof["refactor_large"][1] + prof["refactor_small"][1])
+    ranked = sorted((v[1], k) for k, v in prof.items() if k not in ("refactor_large", "refactor_small"))
+    dom = ranked[-1][1]
+    launches, ms = prof[dom]
+    if per_unit.get(dom):
+        ach = per_unit[dom] / (ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(ach, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 6), "traffic": None,
+                    "kernel": dom, "launches": launches, "avg_launch_us": round(ms / launches * 1e3, 3),
+                    "bytes_per_launch": per_unit[dom] // launches}
+    else:
+        roofline = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                    "traffic": None, "kernel": dom}
+    breakdown = {k: {"launches_per_unit": round(v[0] / nprof, 2), "ms_per_unit": round(v[1] / nprof, 4)}
+                 for k, v in prof.items()}
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "units/s", "n_gpus": 1,
@@ -148,6 +165,7 @@ def main():
         "failures": fails, "fgmres_iters_mean": round(float(np.mean(iters)), 3),
         "berr_max": float(np.max(berrs)),
         "roofline": roofline,
+        "kernel_breakdown": breakdown,
     }
     if not args.no_cpu_baseline:
         import oracle

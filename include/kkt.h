@@ -70,6 +70,9 @@ typedef struct {
      * With fixed_q the ordering step is skipped; with both, pivoting is skipped too. */
     const int32_t *fixed_p;
     const int32_t *fixed_q;
+    /* 1 = dense supernodal update blocks (a wide source panel updating several target
+     * columns) run on the FP64 matrix cores (default); 0 = vector FMAs. */
+    int32_t dense_mfma;
 } kkt_opts;
 
 typedef struct {
@@ -156,6 +159,30 @@ int kkt_refine(kkt_handle *h, const double *d_b, double *d_x, int32_t nrhs, int6
  * NULL).  Waits. */
 int kkt_export_factors(kkt_handle *h, double *h_lu, double *h_r, double *h_c,
                        hipStream_t stream);
+
+/* Kernel classes timed by the optional launch profiler. */
+#define KKT_PROF_UPDATE 0          /* equilibration, norms, value gather, counters */
+#define KKT_PROF_REFACTOR_LARGE 1  /* wide panel items (LDS-staged, matrix cores) */
+#define KKT_PROF_REFACTOR_SMALL 2  /* narrow panel items (16 lanes each) */
+#define KKT_PROF_TO_CSR 3          /* row-ordered copy of the factors */
+#define KKT_PROF_LSOLVE 4          /* forward-substitution levels */
+#define KKT_PROF_USOLVE 5          /* backward-substitution levels */
+#define KKT_PROF_RESIDUAL 6        /* residual, products with A */
+#define KKT_PROF_KRYLOV 7          /* FGMRES vector kernels */
+#define KKT_PROF_NCLASS 8
+
+typedef struct {
+    int64_t launches[KKT_PROF_NCLASS];
+    double ms[KKT_PROF_NCLASS];      /* summed GPU time between events around each launch */
+} kkt_profile;
+
+/* Test and benchmark hook: on = 1 resets the counters and records a pair of HIP events
+ * around every later kernel launch of the handle (on the caller's stream); on = 0 stops.
+ * Adds a few microseconds per launch while on. */
+int kkt_profile_enable(kkt_handle *h, int32_t on);
+
+/* Waits for the stream and returns the accumulated launch counts and times. */
+int kkt_profile_read(kkt_handle *h, kkt_profile *out, hipStream_t stream);
 
 /* Frees the handle (not the caller's workspace).  NULL is ignored. */
 void kkt_destroy(kkt_handle *h);

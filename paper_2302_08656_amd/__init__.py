@@ -29,12 +29,21 @@ class KKTError(RuntimeError):
 class _Opts(C.Structure):
     _fields_ = [("pivot_tau", C.c_double), ("tiny_pivot", C.c_double), ("equilibrate", C.c_int32),
                 ("gmres_restart", C.c_int32), ("max_iters", C.c_int32), ("berr_tol", C.c_double),
-                ("sn_max_width", C.c_int32), ("fixed_p", C.c_void_p), ("fixed_q", C.c_void_p)]
+                ("sn_max_width", C.c_int32), ("fixed_p", C.c_void_p), ("fixed_q", C.c_void_p),
+                ("dense_mfma", C.c_int32)]
 
 
 class _Info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("berr", C.c_double),
                 ("perturbed_pivots", C.c_int64)]
+
+
+PROFILE_CLASSES = ["update", "refactor_large", "refactor_small", "to_csr", "lsolve", "usolve",
+                   "residual", "krylov"]
+
+
+class _Profile(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 8), ("ms", C.c_double * 8)]
 
 
 class _Stats(C.Structure):
@@ -46,7 +55,8 @@ class _Stats(C.Structure):
 
 EXPORTS = ["kkt_default_opts", "kkt_analyze", "kkt_get_stats", "kkt_export_symbolic",
            "kkt_workspace_bytes", "kkt_bind", "kkt_refactor", "kkt_refactor_status", "kkt_solve",
-           "kkt_refine", "kkt_export_factors", "kkt_destroy", "kkt_strerror"]
+           "kkt_refine", "kkt_export_factors", "kkt_profile_enable", "kkt_profile_read",
+           "kkt_destroy", "kkt_strerror"]
 
 _LIB = None
 
@@ -72,6 +82,8 @@ def _lib():
         L.kkt_solve.argtypes = [p, p, p, C.c_int32, C.c_int64, p]
         L.kkt_refine.argtypes = [p, p, p, C.c_int32, C.c_int64, C.POINTER(_Info), p]
         L.kkt_export_factors.argtypes = [p, p, p, p, p]
+        L.kkt_profile_enable.argtypes = [p, C.c_int32]
+        L.kkt_profile_read.argtypes = [p, C.POINTER(_Profile), p]
         L.kkt_destroy.argtypes = [p]
         L.kkt_destroy.restype = None
         L.kkt_strerror.argtypes = [C.c_int]
@@ -114,7 +126,7 @@ class KKTSolver:
 
     def __init__(self, n, rowptr, colind, values_k1, *, pivot_tau=None, tiny_pivot=None,
                  equilibrate=None, gmres_restart=None, max_iters=None, berr_tol=None,
-                 sn_max_width=None, fixed_p=None, fixed_q=None):
+                 sn_max_width=None, fixed_p=None, fixed_q=None, dense_mfma=None):
         L = _lib()
         self.n = int(n)
         rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
@@ -124,7 +136,7 @@ class KKTSolver:
         L.kkt_default_opts(C.byref(o))
         for name, val in (("pivot_tau", pivot_tau), ("tiny_pivot", tiny_pivot), ("equilibrate", equilibrate),
                           ("gmres_restart", gmres_restart), ("max_iters", max_iters), ("berr_tol", berr_tol),
-                          ("sn_max_width", sn_max_width)):
+                          ("sn_max_width", sn_max_width), ("dense_mfma", dense_mfma)):
             if val is not None:
                 setattr(o, name, val)
         fp = None if fixed_p is None else np.ascontiguousarray(fixed_p, dtype=np.int32)
@@ -228,6 +240,19 @@ class KKTSolver:
         if rc != OK:
             raise KKTError(rc, "kkt_export_factors")
         return lu, r, c
+
+    def profile(self, on: bool):
+        rc = _lib().kkt_profile_enable(self._h, int(bool(on)))
+        if rc != OK:
+            raise KKTError(rc, "kkt_profile_enable")
+
+    def profile_read(self, stream=None) -> dict:
+        """{class: (launches, total ms)} accumulated since profile(True)."""
+        pr = _Profile()
+        rc = _lib().kkt_profile_read(self._h, C.byref(pr), _stream_ptr(stream))
+        if rc != OK:
+            raise KKTError(rc, "kkt_profile_read")
+        return {name: (pr.launches[i], pr.ms[i]) for i, name in enumerate(PROFILE_CLASSES)}
 
     def close(self):
         if getattr(self, "_h", None) is not None and _LIB is not None:

@@ -62,6 +62,14 @@ struct Schedule {
     std::vector<int32_t> f_item_panel;  // panel to factor after the pulls, or -1
     std::vector<int32_t> f_item_pair;   // [nitems+1] range into f_pair_src / f_pair_tgt
     std::vector<int32_t> f_pair_src, f_pair_tgt;
+    std::vector<int32_t> f_pair_pos;    // slot of the source's first row in the target column
+    std::vector<int64_t> f_pair_rel;    // [npairs+1] range into f_rel
+    std::vector<int32_t> f_rel;         // slot of each row R of the source in the target column
+    // packed records read by the refactorization kernels (4 x int32 each):
+    // pan4[S] = {first column, width, rows below, 0};
+    // pair4[q] = {source panel, f_pair_pos, f_pair_rel (first index), target column}
+    std::vector<int32_t> pan4, pair4;
+    std::vector<int32_t> ldiag;         // slot of the diagonal of each column
     // triangular solves: launch l runs items [x_lvl[l], x_lvl[l+1]); item = panel range
     std::vector<int32_t> l_lvl, l_item_p0, l_item_np;
     std::vector<int32_t> u_lvl, u_item_p0, u_item_np;

@@ -8,7 +8,8 @@
 namespace kkt {
 
 constexpr int kFlagNonfinite = 1;
-constexpr int kFlagInternal = 2;   // a pull found no slot for a row (schedule bug)
+constexpr int kFlagInternal = 2;
+constexpr int kCountSlots = 1024;   // spread counter for replaced pivots   // a pull found no slot for a row (schedule bug)
 
 // Scalars written by the kernels and read back by the host.
 struct DevStatus {

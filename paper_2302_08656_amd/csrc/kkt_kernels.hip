@@ -41,38 +41,55 @@ __device__ __forceinline__ double group_sum(double v, int width) {
 // ---------------------------------------------------------------------------------------
 // value update
 
-__global__ void k_row_scale(int n, const int32_t *__restrict__ rowptr, const double *__restrict__ v,
-                            int scale, double *__restrict__ r, DevStatus *st) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
+// r_i = 2^-floor(log2 max_j |a_ij|), 8 lanes per row; also clears the status words
+__global__ __launch_bounds__(256) void k_row_scale(int n, const int32_t *__restrict__ rowptr,
+                                                   const double *__restrict__ v, int scale,
+                                                   double *__restrict__ r, DevStatus *st,
+                                                   unsigned long long *pcount) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid == 0) {
         st->anorm_scaled = 0.0;
         st->anorm = 0.0;
         st->perturbed = 0;
         st->flags = 0;
     }
-    if (i >= n) return;
+    if (blockIdx.x == 0)
+        for (int t = threadIdx.x; t < kCountSlots; t += blockDim.x) pcount[t] = 0;
+    const int i = gid >> 3, gl = gid & 7;
     double m = 0.0;
     int bad = 0;
-    for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-        const double a = fabs(v[p]);
-        bad |= !isfinite(a);
-        m = fmax(m, a);
+    if (i < n)
+        for (int p = rowptr[i] + gl; p < rowptr[i + 1]; p += 8) {
+            const double x = fabs(v[p]);
+            bad |= !isfinite(x);
+            m = fmax(m, x);
+        }
+    for (int o = 4; o > 0; o >>= 1) {
+        m = fmax(m, __shfl_xor(m, o, 8));
+        bad |= __shfl_xor(bad, o, 8);
     }
-    if (bad) atomicOr(&st->flags, kFlagNonfinite);
-    r[i] = scale ? inv_pow2_floor_log2(m) : 1.0;
+    if (i < n && gl == 0) {
+        if (bad) atomicOr(&st->flags, kFlagNonfinite);
+        r[i] = scale ? inv_pow2_floor_log2(m) : 1.0;
+    }
 }
 
-__global__ void k_col_scale(int n, const int32_t *__restrict__ cptr, const int32_t *__restrict__ cpos,
-                            const int32_t *__restrict__ rowid, const double *__restrict__ v,
-                            const double *__restrict__ r, int scale, double *__restrict__ c) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
+// c_j from the row-scaled matrix, 8 lanes per column of the CSC view
+__global__ __launch_bounds__(256) void k_col_scale(int n, const int32_t *__restrict__ cptr,
+                                                   const int32_t *__restrict__ cpos,
+                                                   const int32_t *__restrict__ rowid,
+                                                   const double *__restrict__ v, const double *__restrict__ r,
+                                                   int scale, double *__restrict__ c) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = gid >> 3, gl = gid & 7;
     double m = 0.0;
-    for (int t = cptr[j]; t < cptr[j + 1]; ++t) {
-        const int p = cpos[t];
-        m = fmax(m, fabs(r[rowid[p]] * v[p]));
-    }
-    c[j] = scale ? inv_pow2_floor_log2(m) : 1.0;
+    if (j < n)
+        for (int t = cptr[j] + gl; t < cptr[j + 1]; t += 8) {
+            const int p = cpos[t];
+            m = fmax(m, fabs(r[rowid[p]] * v[p]));
+        }
+    for (int o = 4; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 8));
+    if (j < n && gl == 0) c[j] = scale ? inv_pow2_floor_log2(m) : 1.0;
 }
 
 // ||A||_inf and ||R A C||_inf (row sums in CSR order): block maxima into part[2 * block]
@@ -141,6 +158,18 @@ __global__ void k_gather_lu(int64_t nlu, const int32_t *__restrict__ src, const 
     lu[p] = e < 0 ? 0.0 : (r[rowid[e]] * v[e]) * c[col[e]];
 }
 
+// st->perturbed = sum of the spread counter slots
+__global__ __launch_bounds__(256) void k_sum_counts(const unsigned long long *__restrict__ pcount,
+                                                    unsigned long long *out) {
+    __shared__ unsigned long long red[4];
+    unsigned long long c = 0;
+    for (int i = threadIdx.x; i < kCountSlots; i += blockDim.x) c += pcount[i];
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
+}
+
 __global__ void k_to_csr(int64_t nlu, const int32_t *__restrict__ csr_src, const double *__restrict__ lu,
                          double *__restrict__ lucsr) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -160,18 +189,29 @@ __device__ __forceinline__ int lower_bound_row(const int32_t *__restrict__ rowid
     return lo;
 }
 
+constexpr int kBlock = 256;   // threads of the elementwise, small-item and solve blocks
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// pan[S] = {first column, width, rows below, 0}; pair[q] = {source panel, slot of the
+// source's first row in the target column, first index into rel, target column}
 struct RefArgs {
-    const int32_t *colptr, *rowidx, *ulen, *pan_start, *pan_r;
-    const int32_t *item_panel, *item_pair, *pair_src, *pair_tgt;
+    const int32_t *ldiag;      // slot of the diagonal of each column
+    const int4 *pan;
+    const int32_t *item_panel, *item_pair;
+    const int4 *pair;
+    const int32_t *rel;
     double *lu;
     DevStatus *st;
+    unsigned long long *pcount;   // replaced-pivot counter, spread over kCountSlots slots
     double tiny;
+    int use_mfma;                 // dense update blocks on the matrix cores
 };
 
-// position of the first L entry (row j+1 or below) of column j
-__device__ __forceinline__ int lbeg(const RefArgs &a, int j) { return a.colptr[j] + a.ulen[j] + 1; }
-// position of row s (the panel's first row) in column j of a panel starting at s
-__device__ __forceinline__ int seg(const RefArgs &a, int j, int jj) { return a.colptr[j] + a.ulen[j] - jj; }
+// slot of the first L entry (row j+1 or below) of column j
+__device__ __forceinline__ int lbeg(const RefArgs &a, int j) { return a.ldiag[j] + 1; }
+// slot of row s (the panel's first row) in column j = s + jj of a panel starting at s
+__device__ __forceinline__ int seg(const RefArgs &a, int j, int jj) { return a.ldiag[j] - jj; }
 
 __device__ __forceinline__ double perturb(double p, double thresh, int &npert) {
     if (fabs(p) < thresh) {
@@ -184,17 +224,25 @@ __device__ __forceinline__ double perturb(double p, double thresh, int &npert) {
 // ----------------------------------------------------------------- 16-lane path
 
 // Update of target column k by a narrow source panel S (w <= kSmallW, r <= kSmallR): rows
-// s..e-1 of column k become final U entries (unit lower solve with S's diagonal block) and
-// the rows R of S lose L(R, S) times them.
-__device__ void small_pull(const RefArgs &a, int k, int S, int gl) {
-    const int s = a.pan_start[S], e = a.pan_start[S + 1], w = e - s, r = a.pan_r[S];
-    const int c0 = a.colptr[k], c1 = a.colptr[k + 1];
-    const int ps = lower_bound_row(a.rowidx, c0, c0 + a.ulen[k], s);
+// s..e-1 of column k (from slot ps on) become final U entries (unit lower solve with S's
+// diagonal block) and the rows R of S lose L(R, S) times them.
+__device__ __forceinline__ void small_pull(const RefArgs &a, int4 pr, int gl) {
+    const int4 pn = a.pan[pr.x];
+    const int s = pn.x, w = pn.y, r = pn.z, ps = pr.y;
+    const int32_t *rel = a.rel + pr.z;
+    // diagonal slots of the source's columns, one per lane, then shared by shuffles
+    const int ldg = gl < w ? a.ldiag[s + gl] : 0;
+    int ld[kSmallW];
+#pragma unroll
+    for (int j = 0; j < kSmallW; ++j) ld[j] = __shfl(ldg, j, 16);
+    double l_row[kSmallW - 1];   // L(s + gl, s + j) for j < gl
+#pragma unroll
+    for (int j = 0; j < kSmallW - 1; ++j) l_row[j] = (j + 1 < w && gl > j && gl < w) ? a.lu[ld[j] + (gl - j)] : 0.0;
     double u = gl < w ? a.lu[ps + gl] : 0.0;
 #pragma unroll
     for (int j = 0; j < kSmallW - 1; ++j) {
         const double uj = __shfl(u, j, 16);
-        if (j + 1 < w && gl > j && gl < w) u = fma(-a.lu[lbeg(a, s + j) + (gl - j - 1)], uj, u);
+        if (j + 1 < w && gl > j && gl < w) u = fma(-l_row[j], uj, u);
     }
     if (gl < w) a.lu[ps + gl] = u;
     double uu[kSmallW];
@@ -202,33 +250,31 @@ __device__ void small_pull(const RefArgs &a, int k, int S, int gl) {
 #pragma unroll
     for (int j = 0; j < kSmallW; ++j) {
         uu[j] = __shfl(u, j, 16);
-        lb[j] = j < w ? lbeg(a, s + j) + (w - 1 - j) : 0;
+        lb[j] = ld[j] + 1 + (w - 1 - j);
     }
-    const int r0 = lbeg(a, e - 1);
     for (int i = gl; i < r; i += 16) {
+        const int pos = rel[i];
         double acc = 0.0;
 #pragma unroll
         for (int j = 0; j < kSmallW; ++j)
             if (j < w) acc = fma(a.lu[lb[j] + i], uu[j], acc);
-        const int row = a.rowidx[r0 + i];
-        const int pos = lower_bound_row(a.rowidx, ps + w, c1, row);
-        if (pos < c1 && a.rowidx[pos] == row) a.lu[pos] -= acc;
-        else atomicOr(&a.st->flags, kFlagInternal);   // the fill pattern guarantees a slot
+        a.lu[pos] -= acc;
     }
     __threadfence_block();   // a later source of the same column may read these rows
 }
 
 // Dense LU without pivoting of a narrow panel's block column (w <= kSmallW, r <= kSmallR).
 // Returns the number of replaced pivots (the same value on every lane of the group).
-__device__ int small_factor(const RefArgs &a, int T, int gl, double thresh) {
-    const int s = a.pan_start[T], e = a.pan_start[T + 1], w = e - s, r = a.pan_r[T];
+__device__ __forceinline__ int small_factor(const RefArgs &a, int T, int gl, double thresh) {
+    const int4 pn = a.pan[T];
+    const int s = pn.x, w = pn.y, r = pn.z;
+    const int ldg = gl < w ? a.ldiag[s + gl] : 0;
     int sg[kSmallW];
     double d[kSmallW];          // lane gl < w: row gl of the diagonal block
 #pragma unroll
-    for (int c = 0; c < kSmallW; ++c) {
-        sg[c] = c < w ? seg(a, s + c, c) : 0;
-        d[c] = (c < w && gl < w) ? a.lu[sg[c] + gl] : 0.0;
-    }
+    for (int c = 0; c < kSmallW; ++c) sg[c] = __shfl(ldg, c, 16) - c;
+#pragma unroll
+    for (int c = 0; c < kSmallW; ++c) d[c] = (c < w && gl < w) ? a.lu[sg[c] + gl] : 0.0;
     int npert = 0, bad = 0;
     double U[kSmallW][kSmallW];   // final U of the diagonal block, known to every lane
 #pragma unroll
@@ -280,100 +326,129 @@ __device__ int small_factor(const RefArgs &a, int T, int gl, double thresh) {
     return npert;
 }
 
-// ----------------------------------------------------------------- 256-thread path
+// kBlock/16 items per block, one per 16-lane group
+__global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, RefArgs a) {
+    const double thresh = a.tiny * a.st->anorm_scaled;
+    const int g = blockIdx.x * (kBlock / 16) + (threadIdx.x >> 4);
+    const int gl = threadIdx.x & 15;
+    int npert = 0;
+    if (g < nsmall) {
+        const int item = item0 + g;
+        for (int q = a.item_pair[item]; q < a.item_pair[item + 1]; ++q) small_pull(a, a.pair[q], gl);
+        const int T = a.item_panel[item];
+        if (T >= 0) npert = small_factor(a, T, gl, thresh);
+    }
+    // one counter update per wavefront: group leaders contribute their count
+    int c = gl == 0 ? npert : 0;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0 && c)
+        atomicAdd(&a.pcount[(blockIdx.x * 4 + (threadIdx.x >> 6)) % kCountSlots], (unsigned long long)c);
+}
 
-constexpr int kLargeThreads = 256;
+// ----------------------------------------------------------------- 512-thread path
+
+constexpr int kBigThreads = 512;
 constexpr int kRChunk = 128;
-constexpr int kColCache = 768;     // keeps the block under 64 KiB of LDS
-// LDS layout (bytes): Ld | Ub | Lr | Rrow | psbuf | column-row cache per wave
+// LDS layout (bytes): Ld (source diagonal block, later the factored panel's U) | Ub (solved
+// rows per target) | Lr (a chunk of the source's L rows)
 constexpr int kOffLd = 0;
 constexpr int kOffUb = kOffLd + kPanelMax * kPanelMax * 8;
 constexpr int kOffLr = kOffUb + kPanelMax * kGroup * 8;
-constexpr int kOffRrow = kOffLr + kRChunk * kPanelMax * 8;
-constexpr int kOffPs = kOffRrow + kRChunk * 4;
-constexpr int kOffCol = kOffPs + kGroup * 4;
-constexpr int kLargeLds = kOffCol + (kLargeThreads / 64) * kColCache * 4;
+constexpr int kLargeLds = kOffLr + kRChunk * kPanelMax * 8 + kPanelMax * 4;
 
-__device__ void large_factor(const RefArgs &a, int T, char *sm, double thresh) {
-    const int tid = threadIdx.x;
-    const int s = a.pan_start[T], e = a.pan_start[T + 1], w = e - s, r = a.pan_r[T];
-    double *D = reinterpret_cast<double *>(sm + kOffLd);   // column-major, ld kPanelMax
-    double *X = reinterpret_cast<double *>(sm + kOffLr);   // kRChunk rows x w, column-major
-    for (int t = tid; t < w * w; t += kLargeThreads) {
-        const int jj = t / w, ii = t % w;
-        D[jj * kPanelMax + ii] = a.lu[seg(a, s + jj, jj) + ii];
-    }
+// Dense LU without pivoting of a wide panel's block column: the diagonal block in the
+// registers of wavefront 0 (lane = row), then every row below on its own thread.
+__device__ __forceinline__ void large_factor(const RefArgs &a, int T, char *sm, double thresh) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int4 pn = a.pan[T];
+    const int s = pn.x, w = pn.y, r = pn.z;
+    double *D = reinterpret_cast<double *>(sm + kOffLd);   // D[c * kPanelMax + row]
+    int *sgs = reinterpret_cast<int *>(sm + kOffUb);        // slot of row s in each column
+    if (tid < w) sgs[tid] = seg(a, s + tid, tid);
     __syncthreads();
     int npert = 0, bad = 0;
-    for (int jj = 0; jj < w; ++jj) {
-        const double p = perturb(D[jj * kPanelMax + jj], thresh, npert);
-        bad |= !isfinite(p);
-        __syncthreads();
-        if (tid == 0) D[jj * kPanelMax + jj] = p;
-        for (int ii = jj + 1 + tid; ii < w; ii += kLargeThreads) D[jj * kPanelMax + ii] /= p;
-        __syncthreads();
-        const int m = w - jj - 1;
-        for (int t = tid; t < m * m; t += kLargeThreads) {
-            const int c2 = jj + 1 + t / m, ii = jj + 1 + t % m;
-            D[c2 * kPanelMax + ii] = fma(-D[jj * kPanelMax + ii], D[c2 * kPanelMax + jj], D[c2 * kPanelMax + ii]);
-        }
-        __syncthreads();
-    }
-    for (int t = tid; t < w * w; t += kLargeThreads) {
-        const int jj = t / w, ii = t % w;
-        a.lu[seg(a, s + jj, jj) + ii] = D[jj * kPanelMax + ii];
-    }
-    for (int i0 = 0; i0 < r; i0 += kRChunk) {
-        const int nr = min(kRChunk, r - i0);
-        for (int t = tid; t < w * nr; t += kLargeThreads) {
-            const int jj = t / nr, i = t % nr;
-            X[jj * kRChunk + i] = a.lu[seg(a, s + jj, jj) + w + i0 + i];
-        }
-        __syncthreads();
-        if (tid < nr) {
-            for (int jj = 0; jj < w; ++jj) {
-                const double l = X[jj * kRChunk + tid] / D[jj * kPanelMax + jj];
-                bad |= !isfinite(l);
-                X[jj * kRChunk + tid] = l;
-                for (int c2 = jj + 1; c2 < w; ++c2)
-                    X[c2 * kRChunk + tid] = fma(-l, D[c2 * kPanelMax + jj], X[c2 * kRChunk + tid]);
+    if (tid < 64) {
+        double d[kPanelMax];
+#pragma unroll
+        for (int c = 0; c < kPanelMax; ++c) d[c] = (c < w && lane < w) ? a.lu[sgs[c] + lane] : 0.0;
+#pragma unroll
+        for (int jj = 0; jj < kPanelMax; ++jj) {
+            if (jj < w) {
+                const double p = perturb(bcast(d[jj], jj), thresh, npert);
+                bad |= !isfinite(p);
+                if (lane == jj) d[jj] = p;
+                const double l = d[jj] / p;
+                const bool below = lane > jj && lane < w;
+                if (below) d[jj] = l;
+#pragma unroll
+                for (int c = jj + 1; c < kPanelMax; ++c) {
+                    if (c < w) {
+                        const double ujc = bcast(d[c], jj);
+                        if (below) d[c] = fma(-l, ujc, d[c]);
+                    }
+                }
             }
         }
-        __syncthreads();
-        for (int t = tid; t < w * nr; t += kLargeThreads) {
-            const int jj = t / nr, i = t % nr;
-            a.lu[seg(a, s + jj, jj) + w + i0 + i] = X[jj * kRChunk + i];
+#pragma unroll
+        for (int c = 0; c < kPanelMax; ++c) {
+            if (c < w && lane < w) {
+                a.lu[sgs[c] + lane] = d[c];
+                D[c * kPanelMax + lane] = d[c];
+            }
         }
-        __syncthreads();
     }
-    if (tid == 0 && npert) atomicAdd(&a.st->perturbed, (unsigned long long)npert);
-    if (__any(bad) && (tid & 63) == 0) atomicOr(&a.st->flags, kFlagNonfinite);
+    __syncthreads();
+    for (int i = tid; i < r; i += kBigThreads) {
+        double x[kPanelMax];
+#pragma unroll
+        for (int c = 0; c < kPanelMax; ++c) x[c] = c < w ? a.lu[sgs[c] + w + i] : 0.0;
+#pragma unroll
+        for (int jj = 0; jj < kPanelMax; ++jj) {
+            if (jj < w) {
+                const double l = x[jj] / D[jj * kPanelMax + jj];
+                bad |= !isfinite(l);
+                x[jj] = l;
+#pragma unroll
+                for (int c = jj + 1; c < kPanelMax; ++c)
+                    if (c < w) x[c] = fma(-l, D[c * kPanelMax + jj], x[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kPanelMax; ++c)
+            if (c < w) a.lu[sgs[c] + w + i] = x[c];
+    }
+    if (tid == 0 && npert) atomicAdd(&a.pcount[blockIdx.x % kCountSlots], (unsigned long long)npert);
+    if (__any(bad) && lane == 0) atomicOr(&a.st->flags, kFlagNonfinite);
 }
 
 // All pulls of one item with the source panel staged in LDS, then the panel factorization.
-__device__ void large_item(const RefArgs &a, int item, char *sm, double thresh) {
+__global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefArgs a) {
+    extern __shared__ __align__(16) char sm[];
+    const double thresh = a.tiny * a.st->anorm_scaled;
+    const int item = item0 + blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int nw = kBigThreads / 64;
     double *Ld = reinterpret_cast<double *>(sm + kOffLd);
     double *Ub = reinterpret_cast<double *>(sm + kOffUb);
     double *Lr = reinterpret_cast<double *>(sm + kOffLr);
-    int *Rrow = reinterpret_cast<int *>(sm + kOffRrow);
-    int *psb = reinterpret_cast<int *>(sm + kOffPs);
-    int *colc = reinterpret_cast<int *>(sm + kOffCol) + wv * kColCache;
     const int p1 = a.item_pair[item + 1];
+    int *lds = reinterpret_cast<int *>(sm + kOffLr + kRChunk * kPanelMax * 8);   // diagonal slots
     for (int g0 = a.item_pair[item], g1; g0 < p1; g0 = g1) {
-        const int S = a.pair_src[g0];
+        const int S = a.pair[g0].x;
         g1 = g0 + 1;
-        while (g1 < p1 && a.pair_src[g1] == S) ++g1;
-        const int s = a.pan_start[S], e = a.pan_start[S + 1], w = e - s, r = a.pan_r[S];
-        for (int t = tid; t < w * w; t += kLargeThreads) {
+        while (g1 < p1 && a.pair[g1].x == S) ++g1;
+        const int4 pn = a.pan[S];
+        const int s = pn.x, w = pn.y, r = pn.z;
+        if (tid < w) lds[tid] = a.ldiag[s + tid];
+        __syncthreads();
+        for (int t = tid; t < w * w; t += kBigThreads) {
             const int j = t / w, i = t % w;
-            if (i > j) Ld[j * kPanelMax + i] = a.lu[lbeg(a, s + j) + (i - j - 1)];
+            if (i > j) Ld[j * kPanelMax + i] = a.lu[lds[j] + (i - j)];
         }
         __syncthreads();
-        for (int q = g0 + wv; q < g1; q += kLargeThreads / 64) {
-            const int k = a.pair_tgt[q];
-            const int c0 = a.colptr[k];
-            const int ps = lower_bound_row(a.rowidx, c0, c0 + a.ulen[k], s);
+        // rows of S in each target: unit lower solve, one wavefront per target
+        for (int q = g0 + wv; q < g1; q += nw) {
+            const int ps = a.pair[q].y;
             double u = lane < w ? a.lu[ps + lane] : 0.0;
             for (int j = 0; j + 1 < w; ++j) {
                 const double uj = bcast(u, j);
@@ -383,46 +458,52 @@ __device__ void large_item(const RefArgs &a, int item, char *sm, double thresh) 
                 a.lu[ps + lane] = u;
                 Ub[(q - g0) * kPanelMax + lane] = u;
             }
-            if (lane == 0) psb[q - g0] = ps;
         }
         __syncthreads();
-        const int r0 = lbeg(a, e - 1);
+        // rows R of each target: chunks of S's L rows staged in LDS, precomputed slots
         for (int i0 = 0; i0 < r; i0 += kRChunk) {
             const int nr = min(kRChunk, r - i0);
-            for (int t = tid; t < w * nr; t += kLargeThreads) {
+            for (int t = tid; t < w * nr; t += kBigThreads) {
                 const int j = t / nr, i = t % nr;
-                Lr[j * kRChunk + i] = a.lu[lbeg(a, s + j) + (w - 1 - j) + i0 + i];
+                Lr[j * kRChunk + i] = a.lu[lds[j] + 1 + (w - 1 - j) + i0 + i];
             }
-            for (int i = tid; i < nr; i += kLargeThreads) Rrow[i] = a.rowidx[r0 + i0 + i];
             __syncthreads();
-            for (int q = g0 + wv; q < g1; q += kLargeThreads / 64) {
-                const int k = a.pair_tgt[q];
-                const int lo = psb[q - g0] + w, hi = a.colptr[k + 1];
-                const bool cached = hi - lo <= kColCache;
-                if (cached)
-                    for (int t = lane; t < hi - lo; t += 64) colc[t] = a.rowidx[lo + t];
-                __threadfence_block();
-                const double *ub = Ub + (q - g0) * kPanelMax;
-                for (int i = lane; i < nr; i += 64) {
-                    double acc = 0.0;
-                    for (int j = 0; j < w; ++j) acc = fma(Lr[j * kRChunk + i], ub[j], acc);
-                    const int row = Rrow[i];
-                    int pos;
-                    if (cached) {
-                        int l2 = 0, h2 = hi - lo;
-                        while (l2 < h2) {
-                            const int mid = (l2 + h2) >> 1;
-                            if (colc[mid] < row) l2 = mid + 1;
-                            else h2 = mid;
-                        }
-                        pos = lo + l2;
-                    } else {
-                        pos = lower_bound_row(a.rowidx, lo, hi, row);
+            const int m = g1 - g0;
+            if (a.use_mfma && m > 1) {
+                // update block Lr (nr x w) times the solved rows (w x m) on the matrix cores:
+                // 16x16 output tiles, k in steps of 4; lane holds A[i][k], B[k][t] and four
+                // outputs D[4 * (lane / 16) + v][lane % 16]
+                const int mt = (nr + 15) >> 4, nt = (m + 15) >> 4;
+                const int li = lane & 15, lk = lane >> 4;
+                for (int tile = wv; tile < mt * nt; tile += nw) {
+                    const int ti = tile % mt, tt = tile / mt;
+                    const int ia = ti * 16 + li, tb = tt * 16 + li;
+                    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+                    for (int k0 = 0; k0 < w; k0 += 4) {
+                        const int k = k0 + lk;
+                        const double av = (k < w && ia < nr) ? Lr[k * kRChunk + ia] : 0.0;
+                        const double bv = (k < w && tb < m) ? Ub[tb * kPanelMax + k] : 0.0;
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
                     }
-                    if (pos < hi && a.rowidx[pos] == row) a.lu[pos] -= acc;
-                    else atomicOr(&a.st->flags, kFlagInternal);
+                    if (tb < m) {
+                        const int32_t *rel = a.rel + a.pair[g0 + tb].z + i0;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = ti * 16 + 4 * lk + v;
+                            if (i < nr) a.lu[rel[i]] -= acc[v];
+                        }
+                    }
                 }
-                __threadfence_block();
+            } else {
+                for (int q = g0 + wv; q < g1; q += nw) {
+                    const int32_t *rel = a.rel + a.pair[q].z + i0;
+                    const double *ub = Ub + (q - g0) * kPanelMax;
+                    for (int i = lane; i < nr; i += 64) {
+                        double acc = 0.0;
+                        for (int j = 0; j < w; ++j) acc = fma(Lr[j * kRChunk + i], ub[j], acc);
+                        a.lu[rel[i]] -= acc;
+                    }
+                }
             }
             __syncthreads();
         }
@@ -431,31 +512,6 @@ __device__ void large_item(const RefArgs &a, int item, char *sm, double thresh) 
     }
     const int T = a.item_panel[item];
     if (T >= 0) large_factor(a, T, sm, thresh);
-}
-
-// One launch per panel level: blocks [0, nlarge) take one large item each, the remaining
-// blocks take kLargeThreads/16 small items each (one per 16-lane group).
-__global__ __launch_bounds__(256) void k_refactor_level(int item0, int nlarge, int nsmall, RefArgs a) {
-    extern __shared__ __align__(16) char dsm[];
-    const double thresh = a.tiny * a.st->anorm_scaled;
-    if ((int)blockIdx.x < nlarge) {
-        large_item(a, item0 + blockIdx.x, dsm, thresh);
-        return;
-    }
-    const int g = (blockIdx.x - nlarge) * (kLargeThreads / 16) + (threadIdx.x >> 4);
-    const int gl = threadIdx.x & 15;
-    int npert = 0;
-    if (g < nsmall) {
-        const int item = item0 + nlarge + g;
-        for (int q = a.item_pair[item]; q < a.item_pair[item + 1]; ++q)
-            small_pull(a, a.pair_tgt[q], a.pair_src[q], gl);
-        const int T = a.item_panel[item];
-        if (T >= 0) npert = small_factor(a, T, gl, thresh);
-    }
-    // one counter update per wavefront: group leaders contribute their count
-    int c = gl == 0 ? npert : 0;
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&a.st->perturbed, (unsigned long long)c);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -472,16 +528,20 @@ struct SolveArgs {
     double *x;            // backward output (original order)
 };
 
-// sum over q in [q0, q1) of lucsr[q] * v[col[q]] on a group of `width` lanes
+// sum over q in [q0, q1) of lucsr[q] * v[col[q]] on a group of `width` lanes; four
+// independent gathers in flight per lane
 __device__ __forceinline__ double row_dot(const SolveArgs &a, const double *v, int q0, int q1, int gl, int width) {
-    double s0 = 0.0, s1 = 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int q = q0 + gl;
-    for (; q + width < q1; q += 2 * width) {
-        s0 = fma(a.lucsr[q], v[a.col[q]], s0);
-        s1 = fma(a.lucsr[q + width], v[a.col[q + width]], s1);
+    for (; q + 3 * width < q1; q += 4 * width) {
+        const int c0 = a.col[q], c1 = a.col[q + width], c2 = a.col[q + 2 * width], c3 = a.col[q + 3 * width];
+        s0 = fma(a.lucsr[q], v[c0], s0);
+        s1 = fma(a.lucsr[q + width], v[c1], s1);
+        s2 = fma(a.lucsr[q + 2 * width], v[c2], s2);
+        s3 = fma(a.lucsr[q + 3 * width], v[c3], s3);
     }
-    if (q < q1) s0 = fma(a.lucsr[q], v[a.col[q]], s0);
-    return group_sum(s0 + s1, width);
+    for (; q < q1; q += width) s0 = fma(a.lucsr[q], v[a.col[q]], s0);
+    return group_sum((s0 + s1) + (s2 + s3), width);
 }
 
 __global__ __launch_bounds__(256) void k_lsolve_level(int item0, SolveArgs a) {
@@ -504,7 +564,7 @@ __global__ __launch_bounds__(256) void k_lsolve_level(int item0, SolveArgs a) {
     const int s = a.pan_start[T], w = a.pan_start[T + 1] - s;
     // external part of each row (columns left of the panel): 32 lanes per row, 8 rows at once
     const int g = tid >> 5, gl = tid & 31;
-    for (int t = g; t < w; t += kLargeThreads / 32) {
+    for (int t = g; t < w; t += kBlock / 32) {
         const int i = s + t;
         const double acc = row_dot(a, a.y, a.rowptr[i], a.diag[i] - t, gl, 32);
         if (gl == 0) ext[t] = acc;
@@ -543,7 +603,7 @@ __global__ __launch_bounds__(256) void k_usolve_level(int item0, SolveArgs a) {
     const int T = a.pan[p0];
     const int s = a.pan_start[T], w = a.pan_start[T + 1] - s;
     const int g = tid >> 5, gl = tid & 31;
-    for (int t = g; t < w; t += kLargeThreads / 32) {
+    for (int t = g; t < w; t += kBlock / 32) {
         const int i = s + t;
         const double acc = row_dot(a, a.xt, a.diag[i] + (w - t), a.rowptr[i + 1], gl, 32);
         if (gl == 0) ext[t] = acc;

@@ -19,7 +19,9 @@ namespace {
 struct Dev {
     int32_t *a_rowptr, *a_colind, *a_rowid, *a_cptr, *a_cpos, *lu_src;
     int32_t *colptr, *rowidx, *ulen, *pan_start, *pan_r;
-    int32_t *f_item_panel, *f_item_pair, *f_pair_src, *f_pair_tgt;
+    int32_t *f_item_panel, *f_item_pair, *f_rel, *ldiag;
+    int4 *pan4, *pair4;
+    unsigned long long *pcount;
     int32_t *l_item_p0, *l_item_np, *l_pan, *u_item_p0, *u_item_np, *u_pan;
     int32_t *csr_rowptr, *csr_col, *csr_src, *csr_diag, *P, *Q;
     double *r, *c, *lu, *lucsr, *y, *xt, *bsave;
@@ -58,6 +60,11 @@ struct kkt_handle {
     Dev d{};
     const double *d_values = nullptr;
     double *h_small = nullptr;   // pinned host staging for small read-backs
+    // launch profiler
+    bool prof = false;
+    kkt_profile acc{};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
 };
 
 namespace {
@@ -81,8 +88,11 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.pan_r = c.take<int32_t>(g.pan_r.size());
     d.f_item_panel = c.take<int32_t>(g.f_item_panel.size());
     d.f_item_pair = c.take<int32_t>(g.f_item_pair.size());
-    d.f_pair_src = c.take<int32_t>(std::max<size_t>(1, g.f_pair_src.size()));
-    d.f_pair_tgt = c.take<int32_t>(std::max<size_t>(1, g.f_pair_tgt.size()));
+    d.pair4 = c.take<int4>(std::max<size_t>(1, g.pair4.size() / 4));
+    d.pan4 = c.take<int4>(g.pan4.size() / 4);
+    d.ldiag = c.take<int32_t>(n);
+    d.f_rel = c.take<int32_t>(std::max<size_t>(1, g.f_rel.size()));
+    d.pcount = c.take<unsigned long long>(kCountSlots);
     d.l_item_p0 = c.take<int32_t>(g.l_item_p0.size());
     d.l_item_np = c.take<int32_t>(g.l_item_np.size());
     d.l_pan = c.take<int32_t>(g.l_pan.size());
@@ -134,6 +144,50 @@ struct DeviceGuard {
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// Runs `launch` (which enqueues one kernel on s); with the profiler on, brackets it with a
+// pair of events attributed to kernel class cls.
+template <class F>
+void timed(kkt_handle *h, int cls, hipStream_t s, F &&launch) {
+    if (!h->prof) {
+        launch();
+        return;
+    }
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (!h->ev_free.empty()) {
+        ev = h->ev_free.back();
+        h->ev_free.pop_back();
+    } else if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
+        launch();
+        return;
+    }
+    (void)hipEventRecord(ev.first, s);
+    launch();
+    (void)hipEventRecord(ev.second, s);
+    h->ev_pending.emplace_back(cls, ev);
+}
+
+void fold_events(kkt_handle *h);
+
+// waits for the stream, then folds the profiler's completed events
+hipError_t sync_fold(kkt_handle *h, hipStream_t s) {
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess && !h->ev_pending.empty()) fold_events(h);
+    return e;
+}
+
+// folds completed event pairs into the profile (call after the stream was synchronized)
+void fold_events(kkt_handle *h) {
+    for (auto &pe : h->ev_pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
+            h->acc.ms[pe.first] += ms;
+            h->acc.launches[pe.first] += 1;
+        }
+        h->ev_free.push_back(pe.second);
+    }
+    h->ev_pending.clear();
+}
+
 template <class T>
 int upload(T *dst, const std::vector<T> &src, hipStream_t s) {
     if (src.empty()) return KKT_OK;
@@ -149,14 +203,14 @@ int enqueue_solve(kkt_handle *h, const double *b, double *x, hipStream_t s) {
                 d.P, d.Q, d.lucsr, d.r, d.c, b, d.y, d.xt, x};
     for (size_t l = 0; l + 1 < g.l_lvl.size(); ++l) {
         const int cnt = g.l_lvl[l + 1] - g.l_lvl[l];
-        if (cnt) k_lsolve_level<<<cnt, kLargeThreads, 0, s>>>(g.l_lvl[l], a);
+        if (cnt) timed(h, KKT_PROF_LSOLVE, s, [&] { k_lsolve_level<<<cnt, kBlock, 0, s>>>(g.l_lvl[l], a); });
     }
     a.item_p0 = d.u_item_p0;
     a.item_np = d.u_item_np;
     a.pan = d.u_pan;
     for (size_t l = 0; l + 1 < g.u_lvl.size(); ++l) {
         const int cnt = g.u_lvl[l + 1] - g.u_lvl[l];
-        if (cnt) k_usolve_level<<<cnt, kLargeThreads, 0, s>>>(g.u_lvl[l], a);
+        if (cnt) timed(h, KKT_PROF_USOLVE, s, [&] { k_usolve_level<<<cnt, kBlock, 0, s>>>(g.u_lvl[l], a); });
     }
     HIPCHK(hipGetLastError());
     return KKT_OK;
@@ -168,19 +222,32 @@ int enqueue_refactor(kkt_handle *h, const double *v, hipStream_t s) {
     const int n = h->sym.n;
     const int64_t nlu = h->sym.nnz_lu();
     const int eq = h->opts.equilibrate != 0;
-    k_row_scale<<<blocks_for(n, 256), 256, 0, s>>>(n, d.a_rowptr, v, eq, d.r, d.st);
-    k_col_scale<<<blocks_for(n, 256), 256, 0, s>>>(n, d.a_cptr, d.a_cpos, d.a_rowid, v, d.r, eq, d.c);
-    k_norms<<<kNormBlocks, 256, 0, s>>>(n, d.a_rowptr, d.a_colind, v, d.r, d.c, d.part);
-    k_max_parts<<<1, 256, 0, s>>>(kNormBlocks, 2, d.part, &d.st->anorm_scaled);
-    k_gather_lu<<<blocks_for(nlu, 256), 256, 0, s>>>(nlu, d.lu_src, d.a_rowid, d.a_colind, v, d.r, d.c, d.lu);
-    RefArgs a{d.colptr, d.rowidx, d.ulen, d.pan_start, d.pan_r, d.f_item_panel, d.f_item_pair,
-              d.f_pair_src, d.f_pair_tgt, d.lu, d.st, h->opts.tiny_pivot};
+    timed(h, KKT_PROF_UPDATE, s, [&] {
+        k_row_scale<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_rowptr, v, eq, d.r, d.st, d.pcount);
+    });
+    timed(h, KKT_PROF_UPDATE, s, [&] {
+        k_col_scale<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_cptr, d.a_cpos, d.a_rowid, v, d.r, eq, d.c);
+    });
+    timed(h, KKT_PROF_UPDATE, s, [&] {
+        k_norms<<<kNormBlocks, 256, 0, s>>>(n, d.a_rowptr, d.a_colind, v, d.r, d.c, d.part);
+    });
+    timed(h, KKT_PROF_UPDATE, s, [&] { k_max_parts<<<1, 256, 0, s>>>(kNormBlocks, 2, d.part, &d.st->anorm_scaled); });
+    timed(h, KKT_PROF_UPDATE, s, [&] {
+        k_gather_lu<<<blocks_for(nlu, 256), 256, 0, s>>>(nlu, d.lu_src, d.a_rowid, d.a_colind, v, d.r, d.c, d.lu);
+    });
+    RefArgs a{d.ldiag, d.pan4, d.f_item_panel, d.f_item_pair, d.pair4, d.f_rel, d.lu, d.st, d.pcount,
+              h->opts.tiny_pivot, h->opts.dense_mfma != 0};
     for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
         const int nl = g.f_nlarge[l], ns = g.f_lvl[l + 1] - g.f_lvl[l] - nl;
-        const unsigned nb = (unsigned)nl + blocks_for(ns, kLargeThreads / 16);
-        if (nb) k_refactor_level<<<nb, kLargeThreads, nl ? kLargeLds : 0, s>>>(g.f_lvl[l], nl, ns, a);
+        if (nl)
+            timed(h, KKT_PROF_REFACTOR_LARGE, s, [&] { k_refactor_large<<<nl, kBigThreads, kLargeLds, s>>>(g.f_lvl[l], a); });
+        if (ns)
+            timed(h, KKT_PROF_REFACTOR_SMALL, s, [&] {
+                k_refactor_small<<<blocks_for(ns, kBlock / 16), kBlock, 0, s>>>(g.f_lvl[l] + nl, ns, a);
+            });
     }
-    k_to_csr<<<blocks_for(nlu, 256), 256, 0, s>>>(nlu, d.csr_src, d.lu, d.lucsr);
+    timed(h, KKT_PROF_TO_CSR, s, [&] { k_to_csr<<<blocks_for(nlu, 256), 256, 0, s>>>(nlu, d.csr_src, d.lu, d.lucsr); });
+    timed(h, KKT_PROF_UPDATE, s, [&] { k_sum_counts<<<1, 256, 0, s>>>(d.pcount, &d.st->perturbed); });
     HIPCHK(hipGetLastError());
     return KKT_OK;
 }
@@ -189,19 +256,21 @@ int enqueue_refactor(kkt_handle *h, const double *v, hipStream_t s) {
 void enqueue_dots(kkt_handle *h, int nv, const double *V, const double *w, double *dst, int accumulate,
                   hipStream_t s) {
     const int n = h->sym.n;
-    k_multidot<<<kDotBlocks, 256, 0, s>>>(n, nv, V, (int64_t)n, w, h->d.part);
-    k_reduce_parts<<<nv, 256, 0, s>>>(nv, kDotBlocks, h->d.part, dst, accumulate);
+    timed(h, KKT_PROF_KRYLOV, s, [&] { k_multidot<<<kDotBlocks, 256, 0, s>>>(n, nv, V, (int64_t)n, w, h->d.part); });
+    timed(h, KKT_PROF_KRYLOV, s, [&] { k_reduce_parts<<<nv, 256, 0, s>>>(nv, kDotBlocks, h->d.part, dst, accumulate); });
 }
 
 // infinity norms of b - A x into the status block; returns berr on the host
 int residual_berr(kkt_handle *h, const double *x, const double *b, double *berr, double *den, hipStream_t s) {
     const Dev &d = h->d;
     const int n = h->sym.n;
-    k_residual<<<kNormBlocks, 256, 0, s>>>(n, d.a_rowptr, d.a_colind, h->d_values, x, b, d.res, d.part);
-    k_max_parts<<<1, 256, 0, s>>>(kNormBlocks, 3, d.part, &d.rn->rnorm);
+    timed(h, KKT_PROF_RESIDUAL, s, [&] {
+        k_residual<<<kNormBlocks, 256, 0, s>>>(n, d.a_rowptr, d.a_colind, h->d_values, x, b, d.res, d.part);
+    });
+    timed(h, KKT_PROF_RESIDUAL, s, [&] { k_max_parts<<<1, 256, 0, s>>>(kNormBlocks, 3, d.part, &d.rn->rnorm); });
     HIPCHK(hipMemcpyAsync(h->h_small, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(h->h_small + 8, d.rn, sizeof(ResNorms), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(sync_fold(h, s));
     DevStatus st;
     ResNorms rn;
     std::memcpy(&st, h->h_small, sizeof(st));
@@ -232,24 +301,27 @@ int fgmres_column(kkt_handle *h, const double *b, double *x, kkt_info *info, hip
         const double target = tol * den;
         double *beta2 = d.hbuf + 3 * (m + 2);
         enqueue_dots(h, 1, d.res, d.res, beta2, 0, s);
-        k_scale_by_norm<<<nb, 256, 0, s>>>(n, d.res, beta2, d.V);
+        timed(h, KKT_PROF_KRYLOV, s, [&] { k_scale_by_norm<<<nb, 256, 0, s>>>(n, d.res, beta2, d.V); });
         std::fill(gv.begin(), gv.end(), 0.0);
         int jend = -1;
         for (int j = 0; j < m; ++j) {
             double *vj = d.V + (size_t)j * n, *zj = d.Z + (size_t)j * n;
             rc = enqueue_solve(h, vj, zj, s);
             if (rc) return rc;
-            k_spmv<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_rowptr, d.a_colind, h->d_values, zj, d.w);
+            timed(h, KKT_PROF_RESIDUAL, s, [&] {
+                k_spmv<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_rowptr, d.a_colind, h->d_values, zj, d.w);
+            });
             double *h1 = d.hbuf, *h2 = d.hbuf + (m + 2), *hn2 = d.hbuf + 2 * (m + 2);
             enqueue_dots(h, j + 1, d.V, d.w, h1, 0, s);
-            k_sub_combo<<<nb, 256, 0, s>>>(n, j + 1, d.V, n, h1, d.w);
+            timed(h, KKT_PROF_KRYLOV, s, [&] { k_sub_combo<<<nb, 256, 0, s>>>(n, j + 1, d.V, n, h1, d.w); });
             enqueue_dots(h, j + 1, d.V, d.w, h2, 0, s);
-            k_sub_combo<<<nb, 256, 0, s>>>(n, j + 1, d.V, n, h2, d.w);
+            timed(h, KKT_PROF_KRYLOV, s, [&] { k_sub_combo<<<nb, 256, 0, s>>>(n, j + 1, d.V, n, h2, d.w); });
             enqueue_dots(h, 1, d.w, d.w, hn2, 0, s);
-            k_scale_by_norm<<<nb, 256, 0, s>>>(n, d.w, hn2, d.V + (size_t)(j + 1) * n);
+            timed(h, KKT_PROF_KRYLOV, s,
+                  [&] { k_scale_by_norm<<<nb, 256, 0, s>>>(n, d.w, hn2, d.V + (size_t)(j + 1) * n); });
             HIPCHK(hipGetLastError());
             HIPCHK(hipMemcpyAsync(h->h_small, d.hbuf, sizeof(double) * 4 * (m + 2), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(sync_fold(h, s));
             const double *hs = h->h_small;
             if (j == 0) gv[0] = std::sqrt(hs[3 * (m + 2)]);
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hs[i] + hs[(m + 2) + i];
@@ -279,10 +351,10 @@ int fgmres_column(kkt_handle *h, const double *b, double *x, kkt_info *info, hip
         }
         std::memcpy(h->h_small, yv.data(), sizeof(double) * (jend + 1));
         HIPCHK(hipMemcpyAsync(d.ybuf, h->h_small, sizeof(double) * (jend + 1), hipMemcpyHostToDevice, s));
-        k_add_combo<<<nb, 256, 0, s>>>(n, jend + 1, d.Z, n, d.ybuf, x);
+        timed(h, KKT_PROF_KRYLOV, s, [&] { k_add_combo<<<nb, 256, 0, s>>>(n, jend + 1, d.Z, n, d.ybuf, x); });
         HIPCHK(hipGetLastError());
         // the staging buffer is reused by the next read-back: wait for the upload
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(sync_fold(h, s));
     }
     if (info) {
         info->iters = it;
@@ -307,6 +379,7 @@ void kkt_default_opts(kkt_opts *o) {
     o->sn_max_width = 256;
     o->fixed_p = nullptr;
     o->fixed_q = nullptr;
+    o->dense_mfma = 1;
 }
 
 int kkt_analyze(int32_t n, const int64_t *rowptr, const int32_t *colind, const double *values_k1,
@@ -418,8 +491,10 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     rc |= upload(d.pan_r, g.pan_r, stream);
     rc |= upload(d.f_item_panel, g.f_item_panel, stream);
     rc |= upload(d.f_item_pair, g.f_item_pair, stream);
-    rc |= upload(d.f_pair_src, g.f_pair_src, stream);
-    rc |= upload(d.f_pair_tgt, g.f_pair_tgt, stream);
+    rc |= upload(reinterpret_cast<int32_t *>(d.pair4), g.pair4, stream);
+    rc |= upload(reinterpret_cast<int32_t *>(d.pan4), g.pan4, stream);
+    rc |= upload(d.ldiag, g.ldiag, stream);
+    rc |= upload(d.f_rel, g.f_rel, stream);
     rc |= upload(d.l_item_p0, g.l_item_p0, stream);
     rc |= upload(d.l_item_np, g.l_item_np, stream);
     rc |= upload(d.l_pan, g.l_pan, stream);
@@ -462,7 +537,7 @@ int kkt_refactor_status(kkt_handle *h, int64_t *perturbed, hipStream_t stream) {
     DeviceGuard dg(h->device);
     if (!dg.ok) return KKT_ERR_DEVICE;
     HIPCHK(hipMemcpyAsync(h->h_small, h->d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
+    HIPCHK(sync_fold(h, stream));
     DevStatus st;
     std::memcpy(&st, h->h_small, sizeof(st));
     if (perturbed) *perturbed = (int64_t)st.perturbed;
@@ -526,9 +601,28 @@ int kkt_export_factors(kkt_handle *h, double *h_lu, double *h_r, double *h_c, hi
     return KKT_OK;
 }
 
+int kkt_profile_enable(kkt_handle *h, int32_t on) {
+    if (!h) return KKT_ERR_ARG;
+    h->prof = on != 0;
+    if (h->prof) h->acc = kkt_profile{};
+    return KKT_OK;
+}
+
+int kkt_profile_read(kkt_handle *h, kkt_profile *out, hipStream_t stream) {
+    if (!h || !out) return KKT_ERR_ARG;
+    if (!h->ev_pending.empty()) HIPCHK(sync_fold(h, stream));
+    *out = h->acc;
+    return KKT_OK;
+}
+
 void kkt_destroy(kkt_handle *h) {
     if (!h) return;
     if (h->h_small) (void)hipHostFree(h->h_small);
+    for (auto &pe : h->ev_pending) h->ev_free.push_back(pe.second);
+    for (auto &ev : h->ev_free) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
     delete h;
 }
 

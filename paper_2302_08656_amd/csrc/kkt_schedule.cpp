@@ -110,6 +110,9 @@ int build_schedule(const Symbolic &s, Schedule &g) {
     g.f_item_pair.assign(1, 0);
     g.f_pair_src.clear();
     g.f_pair_tgt.clear();
+    g.f_pair_pos.clear();
+    g.f_pair_rel.assign(1, 0);
+    g.f_rel.clear();
     std::vector<int32_t> fac_index(np, -1);
     struct Item {
         int32_t panel;
@@ -174,6 +177,20 @@ int build_schedule(const Symbolic &s, Schedule &g) {
             for (const auto &pr : it.pairs) {
                 g.f_pair_src.push_back(pr.first);
                 g.f_pair_tgt.push_back(pr.second);
+                const int32_t k = pr.second, S = pr.first, sp = g.pan_start[S], e = g.pan_start[S + 1];
+                const auto b = s.rowidx.begin() + s.colptr[k];
+                const int64_t ps = std::lower_bound(b, b + s.ulen[k], sp) - s.rowidx.begin();
+                g.f_pair_pos.push_back((int32_t)ps);
+                // rows R of S (ascending) matched against the rest of column k (ascending)
+                int64_t p = ps + (e - sp);
+                const int64_t pend = s.colptr[k + 1];
+                for (int64_t t = lbeg(e - 1); t < s.colptr[e]; ++t) {
+                    const int32_t row = s.rowidx[t];
+                    while (p < pend && s.rowidx[p] < row) ++p;
+                    if (p == pend || s.rowidx[p] != row) return KKT_ERR_PATTERN;
+                    g.f_rel.push_back((int32_t)p);
+                }
+                g.f_pair_rel.push_back((int64_t)g.f_rel.size());
             }
             g.f_item_pair.push_back((int32_t)g.f_pair_src.size());
         }
@@ -181,6 +198,24 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         g.f_lvl.push_back((int32_t)g.f_item_panel.size());
     }
     if (!by_launch[nlev].empty()) return KKT_ERR_PATTERN;   // top panels have no targets
+    if (g.f_rel.size() >= (size_t)INT32_MAX) return KKT_ERR_NOMEM;
+    g.ldiag.resize(n);
+    for (int32_t j = 0; j < n; ++j) g.ldiag[j] = (int32_t)(s.colptr[j] + s.ulen[j]);
+    g.pan4.resize(4 * (size_t)np);
+    for (int32_t p = 0; p < np; ++p) {
+        g.pan4[4 * p] = g.pan_start[p];
+        g.pan4[4 * p + 1] = pw(p);
+        g.pan4[4 * p + 2] = g.pan_r[p];
+        g.pan4[4 * p + 3] = 0;
+    }
+    const size_t npairs = g.f_pair_src.size();
+    g.pair4.resize(4 * npairs);
+    for (size_t q = 0; q < npairs; ++q) {
+        g.pair4[4 * q] = g.f_pair_src[q];
+        g.pair4[4 * q + 1] = g.f_pair_pos[q];
+        g.pair4[4 * q + 2] = (int32_t)g.f_pair_rel[q];
+        g.pair4[4 * q + 3] = g.f_pair_tgt[q];
+    }
     // solve levels
     std::vector<int32_t> llev(np, 0), ulev(np, 0);
     for (int32_t j = 0; j < n; ++j)

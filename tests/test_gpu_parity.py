@@ -60,6 +60,7 @@ def check_factor_parity(so, lu_g, lu_o, npert, thresh):
 def setup(q, t0=0, **kw):
     v0 = q.values(t0)
     so = oracle.Symbolic(q.n, q.rowptr, q.colind, v0, **{k: v for k, v in kw.items() if k == "tau"})
+    kw = dict(kw)
     sk = K.KKTSolver(q.n, q.rowptr, q.colind, v0, **{("pivot_tau" if k == "tau" else k): v for k, v in kw.items()})
     sk.bind()
     return so, sk
@@ -70,6 +71,8 @@ CASES = [
     ("grid300_widening", kktgen.small(300, config_id=140, steps=4), {}),
     ("grid60_tau1e-3", kktgen.small(60, config_id=141, steps=3, schedule="fixed"), {"tau": 1e-3}),
     ("grid40_flows1", kktgen.small(40, config_id=142, steps=2, flows=1), {}),
+    ("grid2000_vector_fma", kktgen.small(2000, config_id=147, steps=2), {"dense_mfma": 0}),
+    ("grid2000_mfma", kktgen.small(2000, config_id=147, steps=2), {}),
 ]
 
 
