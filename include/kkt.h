@@ -73,6 +73,11 @@ typedef struct {
     /* 1 = dense supernodal update blocks (a wide source panel updating several target
      * columns) run on the FP64 matrix cores (default); 0 = vector FMAs. */
     int32_t dense_mfma;
+    /* 1 = hybrid triangular solves (default): one launch per dependency level while levels
+     * are wide, and one persistent launch for the narrow levels at the top of the tree, in
+     * which blocks take work items in dependency order and wait, bounded, for the unknowns
+     * they read; 0 = one launch per dependency level throughout. */
+    int32_t persistent_solve;
 } kkt_opts;
 
 typedef struct {
@@ -93,6 +98,8 @@ typedef struct {
     int32_t gpu_levels_f;       /* launches of one GPU refactorization */
     int32_t gpu_levels_l;       /* launches of one GPU forward solve */
     int32_t gpu_levels_u;       /* launches of one GPU backward solve */
+    int32_t persistent_levels_l; /* forward levels run by the persistent launch */
+    int32_t persistent_levels_u; /* backward levels run by the persistent launch */
     double flops_refactor;      /* sum_k 2 |L(:,k)| |U(k,:)| + |L(:,k)| */
 } kkt_stats;
 

@@ -48,6 +48,7 @@ constexpr int kSolvePack = 32;
 constexpr int kSmallW = 4;
 constexpr int kSmallR = 64;
 constexpr int kGroup = 32;
+constexpr int kPersistItems = 64;
 
 // Device schedule, built on the host once per pattern and uploaded by kkt_bind.
 struct Schedule {
@@ -75,6 +76,9 @@ struct Schedule {
     std::vector<int32_t> u_lvl, u_item_p0, u_item_np;
     // level-sorted panel lists referenced by the solve items
     std::vector<int32_t> l_pan, u_pan;
+    // hybrid solves: forward levels >= l_split and backward levels < u_split (the narrow top
+    // of the tree, at most kPersistItems items per level) run in one persistent launch
+    int32_t l_split = 0, u_split = 0;
     // combined L+U in CSR for the row-oriented solves
     std::vector<int32_t> csr_rowptr, csr_col, csr_src, csr_diag;
     // value update: for each L+U slot, the CSR entry of A it receives (-1: fill)

@@ -17,7 +17,8 @@ struct DevStatus {
     double anorm;                 // ||A||_inf of the last refactorization (same order)
     unsigned long long perturbed; // pivots replaced by the last refactorization
     int flags;                    // kFlagNonfinite
-    int pad;
+    int abort;                    // a persistent solve timed out waiting (sticky until refactor)
+    int queue[4];                 // work queues of the persistent solves
 };
 
 // Infinity norms of the last residual evaluation, read back by the host.

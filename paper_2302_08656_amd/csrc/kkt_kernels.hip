@@ -52,6 +52,7 @@ __global__ __launch_bounds__(256) void k_row_scale(int n, const int32_t *__restr
         st->anorm = 0.0;
         st->perturbed = 0;
         st->flags = 0;
+        st->abort = 0;
     }
     if (blockIdx.x == 0)
         for (int t = threadIdx.x; t < kCountSlots; t += blockDim.x) pcount[t] = 0;
@@ -471,8 +472,8 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
             const int m = g1 - g0;
             if (a.use_mfma && m > 1) {
                 // update block Lr (nr x w) times the solved rows (w x m) on the matrix cores:
-                // 16x16 output tiles, k in steps of 4; lane holds A[i][k], B[k][t] and four
-                // outputs D[4 * (lane / 16) + v][lane % 16]
+                // 16x16 output tiles, k in steps of 4; lane holds A[lane % 16][lane / 16],
+                // B[lane / 16][lane % 16] and the four outputs D[lane / 16 + 4 v][lane % 16]
                 const int mt = (nr + 15) >> 4, nt = (m + 15) >> 4;
                 const int li = lane & 15, lk = lane >> 4;
                 for (int tile = wv; tile < mt * nt; tile += nw) {
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
                         const int32_t *rel = a.rel + a.pair[g0 + tb].z + i0;
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
-                            const int i = ti * 16 + 4 * lk + v;
+                            const int i = ti * 16 + lk + 4 * v;
                             if (i < nr) a.lu[rel[i]] -= acc[v];
                         }
                     }
@@ -620,6 +621,170 @@ __global__ __launch_bounds__(256) void k_usolve_level(int item0, SolveArgs a) {
     if (lane < w) {
         a.xt[s + lane] = xv;
         a.x[a.Q[s + lane]] = a.c[a.Q[s + lane]] * xv;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// persistent triangular solves (the narrow top of the tree): blocks take the solve items of
+// a range of levels from a queue in level order.
+// Every unknown starts as a signaling-NaN sentinel (arithmetic never produces one) and is
+// published by one 64-bit device-coherent store, so the value is its own ready flag.
+// A read of a not-yet-published unknown waits (bounded); items only depend on items that
+// were taken earlier, so the earliest unfinished item can always proceed.
+
+constexpr unsigned long long kUnset = 0x7ff4dead0badf00dULL;   // signaling NaN
+constexpr int kSpinLimit = 1 << 21;
+
+__device__ __forceinline__ unsigned long long load_coherent(const double *p) {
+    return __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void publish(double *p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// value of an unknown, waiting until it is published; on timeout or abort returns 0 and
+// raises *abort (the solve result is then invalid and reported as a device error)
+__device__ __forceinline__ double wait_value(const double *p, int *abort) {
+    unsigned long long b = load_coherent(p);
+    if (b != kUnset) return __longlong_as_double((long long)b);
+    for (int it = 0; it < kSpinLimit; ++it) {
+        __builtin_amdgcn_s_sleep(2);
+        b = load_coherent(p);
+        if (b != kUnset) return __longlong_as_double((long long)b);
+        if ((it & 63) == 63 &&
+            __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return 0.0;
+    }
+    atomicOr(abort, 1);
+    return 0.0;
+}
+
+// row_dot with waits; same summation order, so both solve modes give identical results
+__device__ __forceinline__ double row_dot_wait(const SolveArgs &a, const double *v, int q0, int q1, int gl,
+                                               int width, int *abort) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int q = q0 + gl;
+    for (; q + 3 * width < q1; q += 4 * width) {
+        const int c0 = a.col[q], c1 = a.col[q + width], c2 = a.col[q + 2 * width], c3 = a.col[q + 3 * width];
+        s0 = fma(a.lucsr[q], wait_value(v + c0, abort), s0);
+        s1 = fma(a.lucsr[q + width], wait_value(v + c1, abort), s1);
+        s2 = fma(a.lucsr[q + 2 * width], wait_value(v + c2, abort), s2);
+        s3 = fma(a.lucsr[q + 3 * width], wait_value(v + c3, abort), s3);
+    }
+    for (; q < q1; q += width) s0 = fma(a.lucsr[q], wait_value(v + a.col[q], abort), s0);
+    return group_sum((s0 + s1) + (s2 + s3), width);
+}
+
+// y[:] = xt[:] = unset, work queues cleared
+__global__ void k_solve_reset(int n, double *__restrict__ y, double *__restrict__ xt, DevStatus *st) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const double u = __longlong_as_double((long long)kUnset);
+    if (i < n) {
+        y[i] = u;
+        xt[i] = u;
+    }
+    if (i < 4) st->queue[i] = 0;
+}
+
+__device__ __forceinline__ int next_item(int *queue) {
+    __shared__ int s_item;
+    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    return item;
+}
+
+__global__ __launch_bounds__(256) void k_lsolve_persistent(int i0, int i1, SolveArgs a, int *queue, int *abort) {
+    __shared__ double ext[kPanelMax];
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (;;) {
+        const int item = i0 + next_item(queue);
+        if (item >= i1 || __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+        const int np = a.item_np[item], p0 = a.item_p0[item];
+        if (np < 0) {                                    // pack of width-1 panels, 8 lanes each
+            const int g = tid >> 3, gl = tid & 7;
+            int i = -1, q0 = 0, q1 = 0;
+            if (g < -np) {
+                i = a.pan_start[a.pan[p0 + g]];
+                q0 = a.rowptr[i];
+                q1 = a.diag[i];
+            }
+            const double acc = row_dot_wait(a, a.y, q0, q1, gl, 8, abort);
+            if (i >= 0 && gl == 0) publish(a.y + i, a.r[a.P[i]] * a.b[a.P[i]] - acc);
+            continue;
+        }
+        const int T = a.pan[p0];
+        const int s = a.pan_start[T], w = a.pan_start[T + 1] - s;
+        const int g = tid >> 5, gl = tid & 31;
+        for (int t = g; t < w; t += kBlock / 32) {
+            const int i = s + t;
+            const double acc = row_dot_wait(a, a.y, a.rowptr[i], a.diag[i] - t, gl, 32, abort);
+            if (gl == 0) ext[t] = acc;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            double yv = 0.0;
+            if (lane < w) yv = a.r[a.P[s + lane]] * a.b[a.P[s + lane]] - ext[lane];
+            for (int t = 0; t + 1 < w; ++t) {
+                const double yt = bcast(yv, t);
+                if (lane > t && lane < w) yv = fma(-a.lucsr[a.diag[s + lane] - (lane - t)], yt, yv);
+            }
+            if (lane < w) publish(a.y + s + lane, yv);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_usolve_persistent(int i0, int i1, SolveArgs a, int *queue, int *abort) {
+    __shared__ double ext[kPanelMax];
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (;;) {
+        const int item = i0 + next_item(queue);
+        if (item >= i1 || __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+        const int np = a.item_np[item], p0 = a.item_p0[item];
+        if (np < 0) {
+            const int g = tid >> 3, gl = tid & 7;
+            int i = -1, q0 = 0, q1 = 0;
+            if (g < -np) {
+                i = a.pan_start[a.pan[p0 + g]];
+                q0 = a.diag[i] + 1;
+                q1 = a.rowptr[i + 1];
+            }
+            const double acc = row_dot_wait(a, a.xt, q0, q1, gl, 8, abort);
+            if (i >= 0 && gl == 0) {
+                const double xv = (a.y[i] - acc) / a.lucsr[a.diag[i]];
+                a.x[a.Q[i]] = a.c[a.Q[i]] * xv;
+                publish(a.xt + i, xv);
+            }
+            continue;
+        }
+        const int T = a.pan[p0];
+        const int s = a.pan_start[T], w = a.pan_start[T + 1] - s;
+        const int g = tid >> 5, gl = tid & 31;
+        for (int t = g; t < w; t += kBlock / 32) {
+            const int i = s + t;
+            const double acc = row_dot_wait(a, a.xt, a.diag[i] + (w - t), a.rowptr[i + 1], gl, 32, abort);
+            if (gl == 0) ext[t] = acc;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            double val = 0.0, xv = 0.0;
+            if (lane < w) val = a.y[s + lane] - ext[lane];
+            for (int t = w - 1; t >= 0; --t) {
+                if (lane == t) xv = val / a.lucsr[a.diag[s + t]];
+                const double xt = bcast(xv, t);
+                if (lane < t) val = fma(-a.lucsr[a.diag[s + lane] + (t - lane)], xt, val);
+            }
+            if (lane < w) {
+                a.x[a.Q[s + lane]] = a.c[a.Q[s + lane]] * xv;
+                publish(a.xt + s + lane, xv);
+            }
+        }
+        __syncthreads();
     }
 }
 

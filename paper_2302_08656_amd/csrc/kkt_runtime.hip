@@ -60,6 +60,7 @@ struct kkt_handle {
     Dev d{};
     const double *d_values = nullptr;
     double *h_small = nullptr;   // pinned host staging for small read-backs
+    int resident_blocks = 1024;  // grid of the persistent solves (blocks of 256 threads)
     // launch profiler
     bool prof = false;
     kkt_profile acc{};
@@ -201,6 +202,37 @@ int enqueue_solve(kkt_handle *h, const double *b, double *x, hipStream_t s) {
     const Dev &d = h->d;
     SolveArgs a{d.pan_start, d.l_item_p0, d.l_item_np, d.l_pan, d.csr_rowptr, d.csr_col, d.csr_diag,
                 d.P, d.Q, d.lucsr, d.r, d.c, b, d.y, d.xt, x};
+    if (h->opts.persistent_solve) {
+        // hybrid: level launches for the wide levels, one persistent launch for the narrow
+        // levels at the top of the tree (last forward levels, first backward levels)
+        const int n = h->sym.n;
+        timed(h, KKT_PROF_LSOLVE, s, [&] { k_solve_reset<<<blocks_for(n, 256), 256, 0, s>>>(n, d.y, d.xt, d.st); });
+        for (int l = 0; l < g.l_split; ++l) {
+            const int cnt = g.l_lvl[l + 1] - g.l_lvl[l];
+            if (cnt) timed(h, KKT_PROF_LSOLVE, s, [&] { k_lsolve_level<<<cnt, kBlock, 0, s>>>(g.l_lvl[l], a); });
+        }
+        const int li0 = g.l_lvl[g.l_split], li1 = g.l_lvl.back();
+        if (li1 > li0)
+            timed(h, KKT_PROF_LSOLVE, s, [&] {
+                k_lsolve_persistent<<<std::min(li1 - li0, h->resident_blocks), kBlock, 0, s>>>(
+                    li0, li1, a, &d.st->queue[0], &d.st->abort);
+            });
+        a.item_p0 = d.u_item_p0;
+        a.item_np = d.u_item_np;
+        a.pan = d.u_pan;
+        const int ui1 = g.u_lvl[g.u_split];
+        if (ui1 > 0)
+            timed(h, KKT_PROF_USOLVE, s, [&] {
+                k_usolve_persistent<<<std::min(ui1, h->resident_blocks), kBlock, 0, s>>>(0, ui1, a, &d.st->queue[1],
+                                                                                       &d.st->abort);
+            });
+        for (size_t l = g.u_split; l + 1 < g.u_lvl.size(); ++l) {
+            const int cnt = g.u_lvl[l + 1] - g.u_lvl[l];
+            if (cnt) timed(h, KKT_PROF_USOLVE, s, [&] { k_usolve_level<<<cnt, kBlock, 0, s>>>(g.u_lvl[l], a); });
+        }
+        HIPCHK(hipGetLastError());
+        return KKT_OK;
+    }
     for (size_t l = 0; l + 1 < g.l_lvl.size(); ++l) {
         const int cnt = g.l_lvl[l + 1] - g.l_lvl[l];
         if (cnt) timed(h, KKT_PROF_LSOLVE, s, [&] { k_lsolve_level<<<cnt, kBlock, 0, s>>>(g.l_lvl[l], a); });
@@ -275,6 +307,7 @@ int residual_berr(kkt_handle *h, const double *x, const double *b, double *berr,
     ResNorms rn;
     std::memcpy(&st, h->h_small, sizeof(st));
     std::memcpy(&rn, h->h_small + 8, sizeof(rn));
+    if (st.abort) return KKT_ERR_DEVICE;
     *den = st.anorm * rn.xnorm + rn.bnorm;
     if (*den == 0.0) *berr = rn.rnorm == 0.0 ? 0.0 : INFINITY;
     else *berr = rn.rnorm / *den;
@@ -380,6 +413,7 @@ void kkt_default_opts(kkt_opts *o) {
     o->fixed_p = nullptr;
     o->fixed_q = nullptr;
     o->dense_mfma = 1;
+    o->persistent_solve = 1;
 }
 
 int kkt_analyze(int32_t n, const int64_t *rowptr, const int32_t *colind, const double *values_k1,
@@ -426,6 +460,8 @@ int kkt_get_stats(const kkt_handle *h, kkt_stats *out) {
     out->gpu_levels_f = (int32_t)h->sch.f_lvl.size() - 1;
     out->gpu_levels_l = (int32_t)h->sch.l_lvl.size() - 1;
     out->gpu_levels_u = (int32_t)h->sch.u_lvl.size() - 1;
+    out->persistent_levels_l = out->gpu_levels_l - h->sch.l_split;
+    out->persistent_levels_u = h->sch.u_split;
     out->flops_refactor = h->sch.flops;
     return KKT_OK;
 }
@@ -467,6 +503,9 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     if (bytes < need) return KKT_ERR_NOMEM;
     int dev = -1;
     HIPCHK(hipGetDevice(&dev));
+    int ncu = 0;
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    h->resident_blocks = std::max(1, ncu) * 4;
     if (!h->h_small) HIPCHK(hipHostMalloc(&h->h_small, sizeof(double) * 4 * (kMaxRestart + 2) + 256));
     carve(h, static_cast<char *>(d_workspace), h->d, &need);
     const Symbolic &s = h->sym;
@@ -541,7 +580,7 @@ int kkt_refactor_status(kkt_handle *h, int64_t *perturbed, hipStream_t stream) {
     DevStatus st;
     std::memcpy(&st, h->h_small, sizeof(st));
     if (perturbed) *perturbed = (int64_t)st.perturbed;
-    if (st.flags & kFlagInternal) return KKT_ERR_DEVICE;
+    if ((st.flags & kFlagInternal) || st.abort) return KKT_ERR_DEVICE;
     if (st.flags & kFlagNonfinite) return KKT_ERR_NONFINITE;
     return st.perturbed ? KKT_WARN_PIVOT_PERTURBED : KKT_OK;
 }

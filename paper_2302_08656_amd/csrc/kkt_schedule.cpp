@@ -259,6 +259,13 @@ int build_schedule(const Symbolic &s, Schedule &g) {
     };
     build_solve(llev, g.l_lvl, g.l_item_p0, g.l_item_np, g.l_pan);
     build_solve(ulev, g.u_lvl, g.u_item_p0, g.u_item_np, g.u_pan);
+    {
+        const int32_t nl = (int32_t)g.l_lvl.size() - 1, nu = (int32_t)g.u_lvl.size() - 1;
+        g.l_split = nl;
+        while (g.l_split > 0 && g.l_lvl[g.l_split] - g.l_lvl[g.l_split - 1] <= kPersistItems) --g.l_split;
+        g.u_split = 0;
+        while (g.u_split < nu && g.u_lvl[g.u_split + 1] - g.u_lvl[g.u_split] <= kPersistItems) ++g.u_split;
+    }
     // combined L+U in CSR: row i lists (i, j) by ascending j, csr_src = CSC slot
     g.csr_rowptr.assign(n + 1, 0);
     for (int64_t p = 0; p < nlu; ++p) g.csr_rowptr[s.rowidx[p] + 1]++;

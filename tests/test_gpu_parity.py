@@ -73,6 +73,7 @@ CASES = [
     ("grid40_flows1", kktgen.small(40, config_id=142, steps=2, flows=1), {}),
     ("grid2000_vector_fma", kktgen.small(2000, config_id=147, steps=2), {"dense_mfma": 0}),
     ("grid2000_mfma", kktgen.small(2000, config_id=147, steps=2), {}),
+    ("grid2000_level_solves", kktgen.small(2000, config_id=147, steps=2), {"persistent_solve": 0}),
 ]
 
 
@@ -132,6 +133,23 @@ def test_solve_matches_oracle_on_well_conditioned():
     for j in range(3):
         xo = so.solve(lu_o, r_o, c_o, b[j])
         assert np.allclose(x[j], xo, rtol=1e-12, atol=1e-13 * np.abs(xo).max())
+
+
+def test_persistent_and_level_solves_agree_bitwise():
+    print("[gpu] persistent vs level-launch solves", flush=True)
+    q = kktgen.make_sequence(kktgen.small(1500, config_id=148, steps=2))
+    v = q.values(1)
+    sks = [K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0), persistent_solve=m).bind() for m in (0, 1)]
+    vd = cuda(v)
+    B = cuda(q.rhs(1, nrhs=2))
+    xs = []
+    for sk in sks:
+        sk.refactor(vd)
+        xs.append(sk.solve(B).cpu().numpy())
+        assert sk.refactor_status()[0] >= 0
+    assert np.array_equal(xs[0], xs[1])
+    for j in range(2):
+        assert np.isfinite(xs[1][j]).all()
 
 
 def test_deterministic_refactor_and_solve():
