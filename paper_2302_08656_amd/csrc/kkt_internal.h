@@ -41,7 +41,7 @@ int analyze_symbolic(int32_t n, const int64_t *rowptr, const int32_t *colind,
 // work item).  Panels never cross supernode boundaries.
 constexpr int kPanelMax = 32;
 // Width-1 panels of the triangular solves are packed this many to a 256-thread block.
-constexpr int kSolvePack = 32;
+constexpr int kSolvePack = 64;
 // Refactorization items whose panel and sources all have at most kSmallW columns and
 // kSmallR rows below run on 16 lanes with registers only; the others on 256 threads with
 // the source panel staged in LDS.  Targets sharing one source are grouped kGroup per item.
@@ -71,7 +71,9 @@ struct Schedule {
     // pair4[q] = {source panel, f_pair_pos, f_pair_rel (first index), target column}
     std::vector<int32_t> pan4, pair4;
     std::vector<int32_t> ldiag;         // slot of the diagonal of each column
-    // triangular solves: launch l runs items [x_lvl[l], x_lvl[l+1]); item = panel range
+    // triangular solves: launch l runs items [x_lvl[l], x_lvl[l+1]); an item is a wide
+    // panel (np = 1, pan = panel), a helper (np = 0, pan = panel) or a pack of -np width-1
+    // panels (pan = their rows)
     std::vector<int32_t> l_lvl, l_item_p0, l_item_np;
     std::vector<int32_t> u_lvl, u_item_p0, u_item_np;
     // level-sorted panel lists referenced by the solve items
@@ -79,8 +81,11 @@ struct Schedule {
     // hybrid solves: forward levels >= l_split and backward levels < u_split (the narrow top
     // of the tree, at most kPersistItems items per level) run in one persistent launch
     int32_t l_split = 0, u_split = 0;
-    // combined L+U in CSR for the row-oriented solves
-    std::vector<int32_t> csr_rowptr, csr_col, csr_src, csr_diag;
+    // combined L+U in CSR for the row-oriented solves.  Rows of wide panels list their L
+    // entries as [early | late | in-panel]: early columns belong to panels two or more
+    // forward levels below, and a helper item one level early sums them into a per-row
+    // partial sum (csr_early[i] = end of the early part, = csr_rowptr[i] when there is none).
+    std::vector<int32_t> csr_rowptr, csr_col, csr_src, csr_diag, csr_early;
     // value update: for each L+U slot, the CSR entry of A it receives (-1: fill)
     std::vector<int32_t> lu_src;
     // CSC view of A's pattern (positions into the CSR value array)

@@ -194,6 +194,21 @@ constexpr int kBlock = 256;   // threads of the elementwise, small-item and solv
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
+// Optional phase timestamps of the wide refactorization items (development builds only):
+// with KKT_PHASE_TRACE defined, thread 0 of each item records the constant-rate clock at
+// each phase boundary into kkt_phase_buf[item * 8 + phase].
+#ifdef KKT_PHASE_TRACE
+__device__ unsigned long long *kkt_phase_buf;
+#define KKT_PHASE(item, k)                                                             \
+    do {                                                                               \
+        if (threadIdx.x == 0 && kkt_phase_buf) kkt_phase_buf[(item) * 8 + (k)] = wall_clock64(); \
+    } while (0)
+#else
+#define KKT_PHASE(item, k) \
+    do {                   \
+    } while (0)
+#endif
+
 // pan[S] = {first column, width, rows below, 0}; pair[q] = {source panel, slot of the
 // source's first row in the target column, first index into rel, target column}
 struct RefArgs {
@@ -349,13 +364,15 @@ __global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, R
 // ----------------------------------------------------------------- 512-thread path
 
 constexpr int kBigThreads = 512;
-constexpr int kRChunk = 128;
+constexpr int kRChunk = 256;
 // LDS layout (bytes): Ld (source diagonal block, later the factored panel's U) | Ub (solved
 // rows per target) | Lr (a chunk of the source's L rows)
 constexpr int kOffLd = 0;
 constexpr int kOffUb = kOffLd + kPanelMax * kPanelMax * 8;
 constexpr int kOffLr = kOffUb + kPanelMax * kGroup * 8;
-constexpr int kLargeLds = kOffLr + kRChunk * kPanelMax * 8 + kPanelMax * 4;
+constexpr int kStagePairs = 256;
+constexpr int kOffPairs = kOffLr + kRChunk * kPanelMax * 8 + kPanelMax * 4;
+constexpr int kLargeLds = kOffPairs + kStagePairs * 16;
 
 // Dense LU without pivoting of a wide panel's block column: the diagonal block in the
 // registers of wavefront 0 (lane = row), then every row below on its own thread.
@@ -429,15 +446,25 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
     const int item = item0 + blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     constexpr int nw = kBigThreads / 64;
+    KKT_PHASE(item, 0);
     double *Ld = reinterpret_cast<double *>(sm + kOffLd);
     double *Ub = reinterpret_cast<double *>(sm + kOffUb);
     double *Lr = reinterpret_cast<double *>(sm + kOffLr);
     const int p1 = a.item_pair[item + 1];
     int *lds = reinterpret_cast<int *>(sm + kOffLr + kRChunk * kPanelMax * 8);   // diagonal slots
-    for (int g0 = a.item_pair[item], g1; g0 < p1; g0 = g1) {
-        const int S = a.pair[g0].x;
+    int4 *prs = reinterpret_cast<int4 *>(sm + kOffPairs);                          // staged pairs
+    const int pbeg = a.item_pair[item];
+    const int npr = p1 - pbeg;
+    const bool staged = npr <= kStagePairs;
+    if (staged)
+        for (int t = tid; t < npr; t += kBigThreads) prs[t] = a.pair[pbeg + t];
+    __syncthreads();
+    auto pr_at = [&](int q) { return staged ? prs[q - pbeg] : a.pair[q]; };
+    KKT_PHASE(item, 1);
+    for (int g0 = pbeg, g1; g0 < p1; g0 = g1) {
+        const int S = pr_at(g0).x;
         g1 = g0 + 1;
-        while (g1 < p1 && a.pair[g1].x == S) ++g1;
+        while (g1 < p1 && pr_at(g1).x == S) ++g1;
         const int4 pn = a.pan[S];
         const int s = pn.x, w = pn.y, r = pn.z;
         if (tid < w) lds[tid] = a.ldiag[s + tid];
@@ -447,20 +474,34 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
             if (i > j) Ld[j * kPanelMax + i] = a.lu[lds[j] + (i - j)];
         }
         __syncthreads();
-        // rows of S in each target: unit lower solve, one wavefront per target
-        for (int q = g0 + wv; q < g1; q += nw) {
-            const int ps = a.pair[q].y;
-            double u = lane < w ? a.lu[ps + lane] : 0.0;
-            for (int j = 0; j + 1 < w; ++j) {
-                const double uj = bcast(u, j);
-                if (lane > j && lane < w) u = fma(-Ld[j * kPanelMax + lane], uj, u);
+        KKT_PHASE(item, 2);
+        // rows of S in each target: unit lower solve with S's diagonal block, one lane per
+        // target (wavefront 0; groups hold at most kGroup targets); the lane keeps its
+        // target's rows in registers
+        if (wv == 0 && lane < g1 - g0) {
+            const int ps = pr_at(g0 + lane).y;
+            double u[kPanelMax];
+#pragma unroll
+            for (int j = 0; j < kPanelMax; ++j) u[j] = j < w ? a.lu[ps + j] : 0.0;
+#pragma unroll
+            for (int t = 1; t < kPanelMax; ++t) {
+                if (t < w) {
+                    double acc = u[t];
+#pragma unroll
+                    for (int j = 0; j < t; ++j) acc = fma(-Ld[j * kPanelMax + t], u[j], acc);
+                    u[t] = acc;
+                }
             }
-            if (lane < w) {
-                a.lu[ps + lane] = u;
-                Ub[(q - g0) * kPanelMax + lane] = u;
+#pragma unroll
+            for (int j = 0; j < kPanelMax; ++j) {
+                if (j < w) {
+                    a.lu[ps + j] = u[j];
+                    Ub[lane * kPanelMax + j] = u[j];
+                }
             }
         }
         __syncthreads();
+        KKT_PHASE(item, 3);
         // rows R of each target: chunks of S's L rows staged in LDS, precomputed slots
         for (int i0 = 0; i0 < r; i0 += kRChunk) {
             const int nr = min(kRChunk, r - i0);
@@ -487,7 +528,7 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
                         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
                     }
                     if (tb < m) {
-                        const int32_t *rel = a.rel + a.pair[g0 + tb].z + i0;
+                        const int32_t *rel = a.rel + pr_at(g0 + tb).z + i0;
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             const int i = ti * 16 + lk + 4 * v;
@@ -497,7 +538,7 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
                 }
             } else {
                 for (int q = g0 + wv; q < g1; q += nw) {
-                    const int32_t *rel = a.rel + a.pair[q].z + i0;
+                    const int32_t *rel = a.rel + pr_at(q).z + i0;
                     const double *ub = Ub + (q - g0) * kPanelMax;
                     for (int i = lane; i < nr; i += 64) {
                         double acc = 0.0;
@@ -510,23 +551,28 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
         }
         __threadfence_block();
         __syncthreads();
+        KKT_PHASE(item, 4);
     }
     const int T = a.item_panel[item];
     if (T >= 0) large_factor(a, T, sm, thresh);
+    KKT_PHASE(item, 5);
 }
 
 // ---------------------------------------------------------------------------------------
 // triangular solves: one 256-thread block per wide panel or per pack of kSolvePack
-// width-1 panels (8 lanes per row)
+// width-1 panels (kPackLanes lanes per row)
+
+constexpr int kPackLanes = kBlock / kSolvePack;
 
 struct SolveArgs {
     const int32_t *pan_start, *item_p0, *item_np, *pan;
-    const int32_t *rowptr, *col, *diag, *P, *Q;
+    const int32_t *rowptr, *col, *diag, *early, *P, *Q;
     const double *lucsr, *r, *c;
     const double *b;      // forward: right-hand side (original order)
     double *y;            // forward output / backward input (permuted)
     double *xt;           // backward output (permuted)
     double *x;            // backward output (original order)
+    double *psum;         // forward: partial sums of the early L columns of helped rows
 };
 
 // sum over q in [q0, q1) of lucsr[q] * v[col[q]] on a group of `width` lanes; four
@@ -545,55 +591,95 @@ __device__ __forceinline__ double row_dot(const SolveArgs &a, const double *v, i
     return group_sum((s0 + s1) + (s2 + s3), width);
 }
 
+// In-panel block of a wide panel staged in LDS by the whole block (one parallel round):
+// blk[t * kPanelMax + i] = entry (s + i, s + t) of L (t < i) or U (t > i); blk[i * 33] = U(i, i).
+__device__ __forceinline__ void stage_inpanel(const SolveArgs &a, int s, int w, double *blk) {
+    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+        const int i = e / w, t = e % w;
+        blk[t * kPanelMax + i] = a.lucsr[a.diag[s + i] + (t - i)];
+    }
+}
+
+// Forward substitution inside a panel of w <= kPanelMax rows (lane = row); yv enters as the
+// row's right-hand side minus its external part.
+__device__ __forceinline__ double inpanel_forward(const double *blk, int w, int lane, double yv) {
+    for (int t = 0; t + 1 < w; ++t) {
+        const double yt = bcast(yv, t);
+        if (lane > t && lane < w) yv = fma(-blk[t * kPanelMax + lane], yt, yv);
+    }
+    return yv;
+}
+
+// Backward substitution inside a panel (lane = row); val enters as y minus the external
+// part; returns the lane's unknown.
+__device__ __forceinline__ double inpanel_backward(const double *blk, int w, int lane, double val) {
+    double xv = 0.0;
+    for (int t = w - 1; t >= 0; --t) {
+        if (lane == t) xv = val / blk[t * kPanelMax + t];
+        const double xt = bcast(xv, t);
+        if (lane < t) val = fma(-blk[t * kPanelMax + lane], xt, val);
+    }
+    return xv;
+}
+
 __global__ __launch_bounds__(256) void k_lsolve_level(int item0, SolveArgs a) {
     __shared__ double ext[kPanelMax];
+    __shared__ double blk[kPanelMax * kPanelMax];
     const int item = item0 + blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const int np = a.item_np[item], p0 = a.item_p0[item];
     if (np < 0) {                                    // pack of width-1 panels, 8 lanes each
-        const int g = tid >> 3, gl = tid & 7;
+        const int g = tid / kPackLanes, gl = tid % kPackLanes;
         int i = -1, q0 = 0, q1 = 0;
         if (g < -np) {
-            i = a.pan_start[a.pan[p0 + g]];
+            i = a.pan[p0 + g];
             q0 = a.rowptr[i];
             q1 = a.diag[i];
         }
-        const double acc = row_dot(a, a.y, q0, q1, gl, 8);
+        const double acc = row_dot(a, a.y, q0, q1, gl, kPackLanes);
         if (i >= 0 && gl == 0) a.y[i] = a.r[a.P[i]] * a.b[a.P[i]] - acc;
         return;
     }
     const int T = a.pan[p0];
     const int s = a.pan_start[T], w = a.pan_start[T + 1] - s;
-    // external part of each row (columns left of the panel): 32 lanes per row, 8 rows at once
     const int g = tid >> 5, gl = tid & 31;
+    if (np == 0) {                                   // early partial sums of panel T's rows
+        for (int t = g; t < w; t += kBlock / 32) {
+            const int i = s + t;
+            const double acc = row_dot(a, a.y, a.rowptr[i], a.early[i], gl, 32);
+            if (gl == 0) a.psum[i] = acc;
+        }
+        return;
+    }
+    stage_inpanel(a, s, w, blk);
+    // late part of each row (columns left of the panel), 32 lanes per row, 8 rows at once
     for (int t = g; t < w; t += kBlock / 32) {
         const int i = s + t;
-        const double acc = row_dot(a, a.y, a.rowptr[i], a.diag[i] - t, gl, 32);
-        if (gl == 0) ext[t] = acc;
+        const int e = a.early[i];
+        double acc = row_dot(a, a.y, e, a.diag[i] - t, gl, 32);
+        if (gl == 0) ext[t] = e > a.rowptr[i] ? acc + a.psum[i] : acc;
     }
     __syncthreads();
     if (tid >= 64) return;
     double yv = 0.0;
     if (lane < w) yv = a.r[a.P[s + lane]] * a.b[a.P[s + lane]] - ext[lane];
-    for (int t = 0; t + 1 < w; ++t) {
-        const double yt = bcast(yv, t);
-        if (lane > t && lane < w) yv = fma(-a.lucsr[a.diag[s + lane] - (lane - t)], yt, yv);
-    }
+    yv = inpanel_forward(blk, w, lane, yv);
     if (lane < w) a.y[s + lane] = yv;
 }
 
 __global__ __launch_bounds__(256) void k_usolve_level(int item0, SolveArgs a) {
     __shared__ double ext[kPanelMax];
+    __shared__ double blk[kPanelMax * kPanelMax];
     const int item = item0 + blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const int np = a.item_np[item], p0 = a.item_p0[item];
     if (np < 0) {
-        const int g = tid >> 3, gl = tid & 7;
+        const int g = tid / kPackLanes, gl = tid % kPackLanes;
         int i = -1, q0 = 0, q1 = 0;
         if (g < -np) {
-            i = a.pan_start[a.pan[p0 + g]];
+            i = a.pan[p0 + g];
             q0 = a.diag[i] + 1;
             q1 = a.rowptr[i + 1];
         }
-        const double acc = row_dot(a, a.xt, q0, q1, gl, 8);
+        const double acc = row_dot(a, a.xt, q0, q1, gl, kPackLanes);
         if (i >= 0 && gl == 0) {
             const double xv = (a.y[i] - acc) / a.lucsr[a.diag[i]];
             a.xt[i] = xv;
@@ -604,6 +690,7 @@ __global__ __launch_bounds__(256) void k_usolve_level(int item0, SolveArgs a) {
     const int T = a.pan[p0];
     const int s = a.pan_start[T], w = a.pan_start[T + 1] - s;
     const int g = tid >> 5, gl = tid & 31;
+    stage_inpanel(a, s, w, blk);
     for (int t = g; t < w; t += kBlock / 32) {
         const int i = s + t;
         const double acc = row_dot(a, a.xt, a.diag[i] + (w - t), a.rowptr[i + 1], gl, 32);
@@ -611,13 +698,9 @@ __global__ __launch_bounds__(256) void k_usolve_level(int item0, SolveArgs a) {
     }
     __syncthreads();
     if (tid >= 64) return;
-    double val = 0.0, xv = 0.0;
+    double val = 0.0;
     if (lane < w) val = a.y[s + lane] - ext[lane];
-    for (int t = w - 1; t >= 0; --t) {
-        if (lane == t) xv = val / a.lucsr[a.diag[s + t]];
-        const double xt = bcast(xv, t);
-        if (lane < t) val = fma(-a.lucsr[a.diag[s + lane] + (t - lane)], xt, val);
-    }
+    const double xv = inpanel_backward(blk, w, lane, val);
     if (lane < w) {
         a.xt[s + lane] = xv;
         a.x[a.Q[s + lane]] = a.c[a.Q[s + lane]] * xv;
@@ -678,13 +761,15 @@ __device__ __forceinline__ double row_dot_wait(const SolveArgs &a, const double 
     return group_sum((s0 + s1) + (s2 + s3), width);
 }
 
-// y[:] = xt[:] = unset, work queues cleared
-__global__ void k_solve_reset(int n, double *__restrict__ y, double *__restrict__ xt, DevStatus *st) {
+// y[:] = xt[:] = psum[:] = unset, work queues cleared
+__global__ void k_solve_reset(int n, double *__restrict__ y, double *__restrict__ xt, double *__restrict__ psum,
+                              DevStatus *st) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const double u = __longlong_as_double((long long)kUnset);
     if (i < n) {
         y[i] = u;
         xt[i] = u;
+        psum[i] = u;
     }
     if (i < 4) st->queue[i] = 0;
 }
@@ -700,39 +785,47 @@ __device__ __forceinline__ int next_item(int *queue) {
 
 __global__ __launch_bounds__(256) void k_lsolve_persistent(int i0, int i1, SolveArgs a, int *queue, int *abort) {
     __shared__ double ext[kPanelMax];
+    __shared__ double blk[kPanelMax * kPanelMax];
     const int tid = threadIdx.x, lane = tid & 63;
     for (;;) {
         const int item = i0 + next_item(queue);
         if (item >= i1 || __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
         const int np = a.item_np[item], p0 = a.item_p0[item];
         if (np < 0) {                                    // pack of width-1 panels, 8 lanes each
-            const int g = tid >> 3, gl = tid & 7;
+            const int g = tid / kPackLanes, gl = tid % kPackLanes;
             int i = -1, q0 = 0, q1 = 0;
             if (g < -np) {
-                i = a.pan_start[a.pan[p0 + g]];
+                i = a.pan[p0 + g];
                 q0 = a.rowptr[i];
                 q1 = a.diag[i];
             }
-            const double acc = row_dot_wait(a, a.y, q0, q1, gl, 8, abort);
+            const double acc = row_dot_wait(a, a.y, q0, q1, gl, kPackLanes, abort);
             if (i >= 0 && gl == 0) publish(a.y + i, a.r[a.P[i]] * a.b[a.P[i]] - acc);
             continue;
         }
         const int T = a.pan[p0];
         const int s = a.pan_start[T], w = a.pan_start[T + 1] - s;
         const int g = tid >> 5, gl = tid & 31;
+        if (np == 0) {                                   // early partial sums of panel T's rows
+            for (int t = g; t < w; t += kBlock / 32) {
+                const int i = s + t;
+                const double acc = row_dot_wait(a, a.y, a.rowptr[i], a.early[i], gl, 32, abort);
+                if (gl == 0) publish(a.psum + i, acc);
+            }
+            continue;
+        }
+        stage_inpanel(a, s, w, blk);
         for (int t = g; t < w; t += kBlock / 32) {
             const int i = s + t;
-            const double acc = row_dot_wait(a, a.y, a.rowptr[i], a.diag[i] - t, gl, 32, abort);
-            if (gl == 0) ext[t] = acc;
+            const int e = a.early[i];
+            const double acc = row_dot_wait(a, a.y, e, a.diag[i] - t, gl, 32, abort);
+            if (gl == 0) ext[t] = e > a.rowptr[i] ? acc + wait_value(a.psum + i, abort) : acc;
         }
         __syncthreads();
         if (tid < 64) {
             double yv = 0.0;
             if (lane < w) yv = a.r[a.P[s + lane]] * a.b[a.P[s + lane]] - ext[lane];
-            for (int t = 0; t + 1 < w; ++t) {
-                const double yt = bcast(yv, t);
-                if (lane > t && lane < w) yv = fma(-a.lucsr[a.diag[s + lane] - (lane - t)], yt, yv);
-            }
+            yv = inpanel_forward(blk, w, lane, yv);
             if (lane < w) publish(a.y + s + lane, yv);
         }
         __syncthreads();
@@ -741,20 +834,21 @@ __global__ __launch_bounds__(256) void k_lsolve_persistent(int i0, int i1, Solve
 
 __global__ __launch_bounds__(256) void k_usolve_persistent(int i0, int i1, SolveArgs a, int *queue, int *abort) {
     __shared__ double ext[kPanelMax];
+    __shared__ double blk[kPanelMax * kPanelMax];
     const int tid = threadIdx.x, lane = tid & 63;
     for (;;) {
         const int item = i0 + next_item(queue);
         if (item >= i1 || __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
         const int np = a.item_np[item], p0 = a.item_p0[item];
         if (np < 0) {
-            const int g = tid >> 3, gl = tid & 7;
+            const int g = tid / kPackLanes, gl = tid % kPackLanes;
             int i = -1, q0 = 0, q1 = 0;
             if (g < -np) {
-                i = a.pan_start[a.pan[p0 + g]];
+                i = a.pan[p0 + g];
                 q0 = a.diag[i] + 1;
                 q1 = a.rowptr[i + 1];
             }
-            const double acc = row_dot_wait(a, a.xt, q0, q1, gl, 8, abort);
+            const double acc = row_dot_wait(a, a.xt, q0, q1, gl, kPackLanes, abort);
             if (i >= 0 && gl == 0) {
                 const double xv = (a.y[i] - acc) / a.lucsr[a.diag[i]];
                 a.x[a.Q[i]] = a.c[a.Q[i]] * xv;
@@ -765,6 +859,7 @@ __global__ __launch_bounds__(256) void k_usolve_persistent(int i0, int i1, Solve
         const int T = a.pan[p0];
         const int s = a.pan_start[T], w = a.pan_start[T + 1] - s;
         const int g = tid >> 5, gl = tid & 31;
+        stage_inpanel(a, s, w, blk);
         for (int t = g; t < w; t += kBlock / 32) {
             const int i = s + t;
             const double acc = row_dot_wait(a, a.xt, a.diag[i] + (w - t), a.rowptr[i + 1], gl, 32, abort);
@@ -772,13 +867,9 @@ __global__ __launch_bounds__(256) void k_usolve_persistent(int i0, int i1, Solve
         }
         __syncthreads();
         if (tid < 64) {
-            double val = 0.0, xv = 0.0;
+            double val = 0.0;
             if (lane < w) val = a.y[s + lane] - ext[lane];
-            for (int t = w - 1; t >= 0; --t) {
-                if (lane == t) xv = val / a.lucsr[a.diag[s + t]];
-                const double xt = bcast(xv, t);
-                if (lane < t) val = fma(-a.lucsr[a.diag[s + lane] + (t - lane)], xt, val);
-            }
+            const double xv = inpanel_backward(blk, w, lane, val);
             if (lane < w) {
                 a.x[a.Q[s + lane]] = a.c[a.Q[s + lane]] * xv;
                 publish(a.xt + s + lane, xv);

@@ -23,8 +23,8 @@ struct Dev {
     int4 *pan4, *pair4;
     unsigned long long *pcount;
     int32_t *l_item_p0, *l_item_np, *l_pan, *u_item_p0, *u_item_np, *u_pan;
-    int32_t *csr_rowptr, *csr_col, *csr_src, *csr_diag, *P, *Q;
-    double *r, *c, *lu, *lucsr, *y, *xt, *bsave;
+    int32_t *csr_rowptr, *csr_col, *csr_src, *csr_diag, *csr_early, *P, *Q;
+    double *r, *c, *lu, *lucsr, *y, *xt, *psum, *bsave;
     double *V, *Z, *w, *res, *part, *hbuf, *ybuf;
     DevStatus *st;
     ResNorms *rn;
@@ -104,6 +104,7 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.csr_col = c.take<int32_t>(nlu);
     d.csr_src = c.take<int32_t>(nlu);
     d.csr_diag = c.take<int32_t>(n);
+    d.csr_early = c.take<int32_t>(n);
     d.P = c.take<int32_t>(n);
     d.Q = c.take<int32_t>(n);
     d.r = c.take<double>(n);
@@ -112,6 +113,7 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.lucsr = c.take<double>(nlu);
     d.y = c.take<double>(n);
     d.xt = c.take<double>(n);
+    d.psum = c.take<double>(n);
     d.bsave = c.take<double>(n);
     d.V = c.take<double>((size_t)(m + 1) * n);
     d.Z = c.take<double>((size_t)m * n);
@@ -201,12 +203,12 @@ int enqueue_solve(kkt_handle *h, const double *b, double *x, hipStream_t s) {
     const Schedule &g = h->sch;
     const Dev &d = h->d;
     SolveArgs a{d.pan_start, d.l_item_p0, d.l_item_np, d.l_pan, d.csr_rowptr, d.csr_col, d.csr_diag,
-                d.P, d.Q, d.lucsr, d.r, d.c, b, d.y, d.xt, x};
+                d.csr_early, d.P, d.Q, d.lucsr, d.r, d.c, b, d.y, d.xt, x, d.psum};
     if (h->opts.persistent_solve) {
         // hybrid: level launches for the wide levels, one persistent launch for the narrow
         // levels at the top of the tree (last forward levels, first backward levels)
         const int n = h->sym.n;
-        timed(h, KKT_PROF_LSOLVE, s, [&] { k_solve_reset<<<blocks_for(n, 256), 256, 0, s>>>(n, d.y, d.xt, d.st); });
+        timed(h, KKT_PROF_LSOLVE, s, [&] { k_solve_reset<<<blocks_for(n, 256), 256, 0, s>>>(n, d.y, d.xt, d.psum, d.st); });
         for (int l = 0; l < g.l_split; ++l) {
             const int cnt = g.l_lvl[l + 1] - g.l_lvl[l];
             if (cnt) timed(h, KKT_PROF_LSOLVE, s, [&] { k_lsolve_level<<<cnt, kBlock, 0, s>>>(g.l_lvl[l], a); });
@@ -505,6 +507,8 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     HIPCHK(hipGetDevice(&dev));
     int ncu = 0;
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_refactor_large),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kLargeLds));
     h->resident_blocks = std::max(1, ncu) * 4;
     if (!h->h_small) HIPCHK(hipHostMalloc(&h->h_small, sizeof(double) * 4 * (kMaxRestart + 2) + 256));
     carve(h, static_cast<char *>(d_workspace), h->d, &need);
@@ -544,6 +548,7 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     rc |= upload(d.csr_col, g.csr_col, stream);
     rc |= upload(d.csr_src, g.csr_src, stream);
     rc |= upload(d.csr_diag, g.csr_diag, stream);
+    rc |= upload(d.csr_early, g.csr_early, stream);
     rc |= upload(d.P, s.P, stream);
     rc |= upload(d.Q, s.Q, stream);
     if (rc) return KKT_ERR_DEVICE;

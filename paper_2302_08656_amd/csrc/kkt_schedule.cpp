@@ -172,6 +172,12 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         });
         int32_t nlarge = 0;
         for (const auto &it : items) {
+            // the wide path solves one source's targets on the lanes of one wavefront
+            for (size_t q = 0, q1; q < it.pairs.size(); q = q1) {
+                q1 = q;
+                while (q1 < it.pairs.size() && it.pairs[q1].first == it.pairs[q].first) ++q1;
+                if (q1 - q > (size_t)kGroup) return KKT_ERR_PATTERN;
+            }
             nlarge += !it.small;
             g.f_item_panel.push_back(it.panel);
             for (const auto &pr : it.pairs) {
@@ -228,16 +234,35 @@ int build_schedule(const Symbolic &s, Schedule &g) {
             const int32_t T = pan_of[s.rowidx[p]], S = pan_of[j];
             if (T != S) ulev[T] = std::max(ulev[T], ulev[S] + 1);
         }
+    // forward-solve helpers: a wide panel T at level >= 2 with early columns gets a helper
+    // item at level llev[T] - 1
+    std::vector<char> has_helper(np, 0);
+    {
+        for (int32_t j = 0; j < n; ++j)
+            for (int64_t p = lbeg(j); p < s.colptr[j + 1]; ++p) {
+                const int32_t T = pan_of[s.rowidx[p]], S = pan_of[j];
+                if (T != S && pw(T) > 1 && llev[T] >= 2 && llev[S] <= llev[T] - 2) has_helper[T] = 1;
+            }
+    }
     auto build_solve = [&](const std::vector<int32_t> &lev, std::vector<int32_t> &lvl,
-                           std::vector<int32_t> &p0, std::vector<int32_t> &cnt, std::vector<int32_t> &pan) {
+                           std::vector<int32_t> &p0, std::vector<int32_t> &cnt, std::vector<int32_t> &pan,
+                           bool helpers) {
         const int32_t nl = np ? 1 + *std::max_element(lev.begin(), lev.end()) : 0;
-        std::vector<std::vector<int32_t>> at(nl);
-        for (int32_t p = 0; p < np; ++p) at[lev[p]].push_back(p);
+        std::vector<std::vector<int32_t>> at(nl), help(nl);
+        for (int32_t p = 0; p < np; ++p) {
+            at[lev[p]].push_back(p);
+            if (helpers && has_helper[p]) help[lev[p] - 1].push_back(p);
+        }
         lvl.assign(1, 0);
         p0.clear();
         cnt.clear();
         pan.clear();
         for (int32_t l = 0; l < nl; ++l) {
+            for (int32_t p : help[l]) {
+                p0.push_back((int32_t)pan.size());
+                cnt.push_back(0);      // zero: partial sums of the early columns of panel p
+                pan.push_back(p);
+            }
             std::vector<int32_t> wide, narrow;
             for (int32_t p : at[l]) (g.pan_start[p + 1] - g.pan_start[p] > 1 ? wide : narrow).push_back(p);
             std::stable_sort(wide.begin(), wide.end(), [&](int32_t a, int32_t b) {
@@ -252,13 +277,13 @@ int build_schedule(const Symbolic &s, Schedule &g) {
                 const int32_t c = (int32_t)std::min<size_t>(kSolvePack, narrow.size() - q);
                 p0.push_back((int32_t)pan.size());
                 cnt.push_back(-c);     // negative: a pack of width-1 panels
-                for (int32_t t = 0; t < c; ++t) pan.push_back(narrow[q + t]);
+                for (int32_t t = 0; t < c; ++t) pan.push_back(g.pan_start[narrow[q + t]]);   // rows
             }
             lvl.push_back((int32_t)p0.size());
         }
     };
-    build_solve(llev, g.l_lvl, g.l_item_p0, g.l_item_np, g.l_pan);
-    build_solve(ulev, g.u_lvl, g.u_item_p0, g.u_item_np, g.u_pan);
+    build_solve(llev, g.l_lvl, g.l_item_p0, g.l_item_np, g.l_pan, true);
+    build_solve(ulev, g.u_lvl, g.u_item_p0, g.u_item_np, g.u_pan, false);
     {
         const int32_t nl = (int32_t)g.l_lvl.size() - 1, nu = (int32_t)g.u_lvl.size() - 1;
         g.l_split = nl;
@@ -283,6 +308,33 @@ int build_schedule(const Symbolic &s, Schedule &g) {
                 g.csr_src[q] = (int32_t)p;
                 if (i == j) g.csr_diag[i] = q;
             }
+    }
+    // early | late | in-panel order of the L entries of rows of helped panels
+    g.csr_early.assign(g.csr_rowptr.begin(), g.csr_rowptr.end() - 1);
+    {
+        std::vector<int32_t> tc, ts;
+        for (int32_t T = 0; T < np; ++T) {
+            if (!has_helper[T]) continue;
+            const int32_t sp = g.pan_start[T];
+            for (int32_t i = sp; i < g.pan_start[T + 1]; ++i) {
+                const int32_t q0 = g.csr_rowptr[i], q1 = g.csr_diag[i] - (i - sp);   // external part
+                tc.clear();
+                ts.clear();
+                for (int pass = 0; pass < 2; ++pass)
+                    for (int32_t q = q0; q < q1; ++q) {
+                        const bool early = llev[pan_of[g.csr_col[q]]] <= llev[T] - 2;
+                        if (early == (pass == 0)) {
+                            tc.push_back(g.csr_col[q]);
+                            ts.push_back(g.csr_src[q]);
+                        }
+                    }
+                int32_t ne = 0;
+                for (int32_t q = q0; q < q1; ++q) ne += llev[pan_of[g.csr_col[q]]] <= llev[T] - 2;
+                std::copy(tc.begin(), tc.end(), g.csr_col.begin() + q0);
+                std::copy(ts.begin(), ts.end(), g.csr_src.begin() + q0);
+                g.csr_early[i] = q0 + ne;
+            }
+        }
     }
     // value update map and CSC view of A
     g.lu_src.assign(nlu, -1);
