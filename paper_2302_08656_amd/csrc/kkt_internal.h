@@ -66,10 +66,11 @@ struct Schedule {
     std::vector<int32_t> f_pair_pos;    // slot of the source's first row in the target column
     std::vector<int64_t> f_pair_rel;    // [npairs+1] range into f_rel
     std::vector<int32_t> f_rel;         // slot of each row R of the source in the target column
-    // packed records read by the refactorization kernels (4 x int32 each):
-    // pan4[S] = {first column, width, rows below, 0};
-    // pair4[q] = {source panel, f_pair_pos, f_pair_rel (first index), target column}
-    std::vector<int32_t> pan4, pair4;
+    // packed records read by the refactorization kernels (8 x int32 each):
+    // item8[i] = {panel to factor or -1, first pair, end pair, 0, s, w, r, ldiag[s]};
+    // pair8[q] = {source panel, f_pair_pos, f_pair_rel (first index), target column,
+    //             s, w, r, ldiag[s]}, with s, w, r the panel's first column, width, rows below
+    std::vector<int32_t> item8, pair8;
     std::vector<int32_t> ldiag;         // slot of the diagonal of each column
     // triangular solves: launch l runs items [x_lvl[l], x_lvl[l+1]); an item is a wide
     // panel (np = 1, pan = panel), a helper (np = 0, pan = panel) or a pack of -np width-1

@@ -201,7 +201,10 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 __device__ unsigned long long *kkt_phase_buf;
 #define KKT_PHASE(item, k)                                                             \
     do {                                                                               \
-        if (threadIdx.x == 0 && kkt_phase_buf) kkt_phase_buf[(item) * 8 + (k)] = wall_clock64(); \
+        if (threadIdx.x == 0 && kkt_phase_buf) {                                       \
+            kkt_phase_buf[(item) * 16 + (k)] = wall_clock64();                         \
+            if ((k) == 0 || (k) == 5) kkt_phase_buf[(item) * 16 + 14 + (k) / 5] = clock64(); \
+        }                                                                              \
     } while (0)
 #else
 #define KKT_PHASE(item, k) \
@@ -209,12 +212,15 @@ __device__ unsigned long long *kkt_phase_buf;
     } while (0)
 #endif
 
-// pan[S] = {first column, width, rows below, 0}; pair[q] = {source panel, slot of the
-// source's first row in the target column, first index into rel, target column}
+// Packed 32-byte records (two int4 each):
+//   item[2i]   = {panel to factor or -1, first pair, end of pairs, 0}
+//   item[2i+1] = {its first column s, width w, rows below r, slot of the diagonal of column s}
+//   pair[2q]   = {source panel, slot of the source's first row in the target column,
+//                 first index into rel, target column}
+//   pair[2q+1] = {source's first column, width, rows below, slot of its first diagonal}
 struct RefArgs {
     const int32_t *ldiag;      // slot of the diagonal of each column
-    const int4 *pan;
-    const int32_t *item_panel, *item_pair;
+    const int4 *item;
     const int4 *pair;
     const int32_t *rel;
     double *lu;
@@ -242,19 +248,34 @@ __device__ __forceinline__ double perturb(double p, double thresh, int &npert) {
 // Update of target column k by a narrow source panel S (w <= kSmallW, r <= kSmallR): rows
 // s..e-1 of column k (from slot ps on) become final U entries (unit lower solve with S's
 // diagonal block) and the rows R of S lose L(R, S) times them.
-__device__ __forceinline__ void small_pull(const RefArgs &a, int4 pr, int gl) {
-    const int4 pn = a.pan[pr.x];
-    const int s = pn.x, w = pn.y, r = pn.z, ps = pr.y;
-    const int32_t *rel = a.rel + pr.z;
-    // diagonal slots of the source's columns, one per lane, then shared by shuffles
-    const int ldg = gl < w ? a.ldiag[s + gl] : 0;
+__device__ __forceinline__ void small_pull(const RefArgs &a, int4 pa, int4 pb, int gl) {
+    const int ps = pa.y, s = pb.x, w = pb.y, r = pb.z;
+    const int32_t *rel = a.rel + pa.z;
+    // diagonal slots of the source's columns (the first comes with the record)
+    int ldg = pb.w;
+    if (w > 1 && gl > 0 && gl < w) ldg = a.ldiag[s + gl];
     int ld[kSmallW];
 #pragma unroll
     for (int j = 0; j < kSmallW; ++j) ld[j] = __shfl(ldg, j, 16);
+    // one round of independent loads: the target's rows of S, S's diagonal block and L rows,
+    // and the slots of those rows in the target
     double l_row[kSmallW - 1];   // L(s + gl, s + j) for j < gl
 #pragma unroll
     for (int j = 0; j < kSmallW - 1; ++j) l_row[j] = (j + 1 < w && gl > j && gl < w) ? a.lu[ld[j] + (gl - j)] : 0.0;
     double u = gl < w ? a.lu[ps + gl] : 0.0;
+    constexpr int kRows = kSmallR / 16;
+    double lr[kRows][kSmallW];
+    int pos[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int i = gl + 16 * k;
+        pos[k] = i < r ? rel[i] : 0;
+#pragma unroll
+        for (int j = 0; j < kSmallW; ++j) lr[k][j] = (i < r && j < w) ? a.lu[ld[j] + 1 + (w - 1 - j) + i] : 0.0;
+    }
+    double tv[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) tv[k] = gl + 16 * k < r ? a.lu[pos[k]] : 0.0;
 #pragma unroll
     for (int j = 0; j < kSmallW - 1; ++j) {
         const double uj = __shfl(u, j, 16);
@@ -262,35 +283,41 @@ __device__ __forceinline__ void small_pull(const RefArgs &a, int4 pr, int gl) {
     }
     if (gl < w) a.lu[ps + gl] = u;
     double uu[kSmallW];
-    int lb[kSmallW];
 #pragma unroll
-    for (int j = 0; j < kSmallW; ++j) {
-        uu[j] = __shfl(u, j, 16);
-        lb[j] = ld[j] + 1 + (w - 1 - j);
-    }
-    for (int i = gl; i < r; i += 16) {
-        const int pos = rel[i];
-        double acc = 0.0;
+    for (int j = 0; j < kSmallW; ++j) uu[j] = __shfl(u, j, 16);
 #pragma unroll
-        for (int j = 0; j < kSmallW; ++j)
-            if (j < w) acc = fma(a.lu[lb[j] + i], uu[j], acc);
-        a.lu[pos] -= acc;
+    for (int k = 0; k < kRows; ++k) {
+        if (gl + 16 * k < r) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < kSmallW; ++j)
+                if (j < w) acc = fma(lr[k][j], uu[j], acc);
+            a.lu[pos[k]] = tv[k] - acc;
+        }
     }
     __threadfence_block();   // a later source of the same column may read these rows
 }
 
 // Dense LU without pivoting of a narrow panel's block column (w <= kSmallW, r <= kSmallR).
-// Returns the number of replaced pivots (the same value on every lane of the group).
-__device__ __forceinline__ int small_factor(const RefArgs &a, int T, int gl, double thresh) {
-    const int4 pn = a.pan[T];
+// pn = {s, w, r, slot of the first diagonal}.  Returns the number of replaced pivots (the
+// same value on every lane of the group).
+__device__ __forceinline__ int small_factor(const RefArgs &a, int4 pn, int gl, double thresh) {
     const int s = pn.x, w = pn.y, r = pn.z;
-    const int ldg = gl < w ? a.ldiag[s + gl] : 0;
+    int ldg = pn.w;
+    if (w > 1 && gl > 0 && gl < w) ldg = a.ldiag[s + gl];
     int sg[kSmallW];
-    double d[kSmallW];          // lane gl < w: row gl of the diagonal block
 #pragma unroll
     for (int c = 0; c < kSmallW; ++c) sg[c] = __shfl(ldg, c, 16) - c;
+    // one round: the diagonal block (lane gl < w holds row gl) and this lane's rows below
+    double d[kSmallW];
 #pragma unroll
     for (int c = 0; c < kSmallW; ++c) d[c] = (c < w && gl < w) ? a.lu[sg[c] + gl] : 0.0;
+    constexpr int kRows = kSmallR / 16;
+    double x[kRows][kSmallW];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k)
+#pragma unroll
+        for (int c = 0; c < kSmallW; ++c) x[k][c] = (c < w && gl + 16 * k < r) ? a.lu[sg[c] + w + gl + 16 * k] : 0.0;
     int npert = 0, bad = 0;
     double U[kSmallW][kSmallW];   // final U of the diagonal block, known to every lane
 #pragma unroll
@@ -319,24 +346,24 @@ __device__ __forceinline__ int small_factor(const RefArgs &a, int T, int gl, dou
         for (int c = 0; c < kSmallW; ++c)
             if (c < w) a.lu[sg[c] + gl] = d[c];
     }
-    for (int i = gl; i < r; i += 16) {
-        double x[kSmallW];
 #pragma unroll
-        for (int c = 0; c < kSmallW; ++c) x[c] = c < w ? a.lu[sg[c] + w + i] : 0.0;
+    for (int k = 0; k < kRows; ++k) {
+        if (gl + 16 * k < r) {
 #pragma unroll
-        for (int jj = 0; jj < kSmallW; ++jj) {
-            if (jj < w) {
-                const double l = x[jj] / U[jj][jj];
-                bad |= !isfinite(l);
-                x[jj] = l;
+            for (int jj = 0; jj < kSmallW; ++jj) {
+                if (jj < w) {
+                    const double l = x[k][jj] / U[jj][jj];
+                    bad |= !isfinite(l);
+                    x[k][jj] = l;
 #pragma unroll
-                for (int c = jj + 1; c < kSmallW; ++c)
-                    if (c < w) x[c] = fma(-l, U[jj][c], x[c]);
+                    for (int c = jj + 1; c < kSmallW; ++c)
+                        if (c < w) x[k][c] = fma(-l, U[jj][c], x[k][c]);
+                }
             }
-        }
 #pragma unroll
-        for (int c = 0; c < kSmallW; ++c)
-            if (c < w) a.lu[sg[c] + w + i] = x[c];
+            for (int c = 0; c < kSmallW; ++c)
+                if (c < w) a.lu[sg[c] + w + gl + 16 * k] = x[k][c];
+        }
     }
     if (bad) atomicOr(&a.st->flags, kFlagNonfinite);
     return npert;
@@ -350,9 +377,9 @@ __global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, R
     int npert = 0;
     if (g < nsmall) {
         const int item = item0 + g;
-        for (int q = a.item_pair[item]; q < a.item_pair[item + 1]; ++q) small_pull(a, a.pair[q], gl);
-        const int T = a.item_panel[item];
-        if (T >= 0) npert = small_factor(a, T, gl, thresh);
+        const int4 ia = a.item[2 * item], ib = a.item[2 * item + 1];
+        for (int q = ia.y; q < ia.z; ++q) small_pull(a, a.pair[2 * q], a.pair[2 * q + 1], gl);
+        if (ia.x >= 0) npert = small_factor(a, ib, gl, thresh);
     }
     // one counter update per wavefront: group leaders contribute their count
     int c = gl == 0 ? npert : 0;
@@ -365,78 +392,153 @@ __global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, R
 
 constexpr int kBigThreads = 512;
 constexpr int kRChunk = 256;
-// LDS layout (bytes): Ld (source diagonal block, later the factored panel's U) | Ub (solved
-// rows per target) | Lr (a chunk of the source's L rows)
+constexpr int kStagePairs = 256;
+// LDS layout (bytes): Ls (the source's diagonal block, later the factored panel's U) | Ub
+// (solved rows per target) | Lr (a chunk of the source's L rows) | lds (the source's
+// diagonal slots) | sgs (slot of row s in each column of the panel to factor) | staged
+// pair records
 constexpr int kOffLd = 0;
 constexpr int kOffUb = kOffLd + kPanelMax * kPanelMax * 8;
 constexpr int kOffLr = kOffUb + kPanelMax * kGroup * 8;
-constexpr int kStagePairs = 256;
-constexpr int kOffPairs = kOffLr + kRChunk * kPanelMax * 8 + kPanelMax * 4;
-constexpr int kLargeLds = kOffPairs + kStagePairs * 16;
+constexpr int kOffLds = kOffLr + kRChunk * kPanelMax * 8;
+constexpr int kOffSgs = kOffLds + kPanelMax * 4;
+constexpr int kOffPairs = kOffSgs + kPanelMax * 4;
+constexpr int kLargeLds = kOffPairs + kStagePairs * 32;
+
+// Shifted sweeps.  A row of a panel of width w <= KW lives in registers x[0..KW-1] with
+// zeros past column w.  Step j of a triangular sweep consumes x[0] (column j) and moves
+// the remaining columns down by one while it applies the step's update, so each register
+// index is static while the loop over j stays rolled; the update of column c at step j is
+// the same FMA, in the same order, as in the unshifted form.
+// The row of multipliers (LDS, 16-byte aligned) is read into registers in one round before
+// the FMAs; otherwise the compiler interleaves one LDS round trip per pair of columns.
+template <int KW>
+__device__ __forceinline__ void load_lds_row(double (&rw)[kPanelMax], const double *row) {
+    const double2 *r2 = reinterpret_cast<const double2 *>(row);
+#pragma unroll
+    for (int c = 0; c < KW / 2; ++c) {
+        const double2 v = r2[c];
+        rw[2 * c] = v.x;
+        rw[2 * c + 1] = v.y;
+    }
+}
+
+template <int KW>
+__device__ __forceinline__ void shift_fma(double (&x)[kPanelMax], double l, const double (&rw)[kPanelMax]) {
+#pragma unroll
+    for (int c = 1; c < KW; ++c) x[c - 1] = fma(-l, rw[c], x[c]);
+    x[KW - 1] = 0.0;
+}
+
+// x[c] = lu[base[c] + off] for c < w, 0 beyond (every address in bounds)
+template <int KW>
+__device__ __forceinline__ void load_row(double (&x)[kPanelMax], const double *lu, const int *base,
+                                         int w, int off) {
+#pragma unroll
+    for (int c = 0; c < KW; ++c) {
+        const double v = lu[base[c < w ? c : 0] + off];
+        x[c] = c < w ? v : 0.0;
+    }
+}
 
 // Dense LU without pivoting of a wide panel's block column: the diagonal block in the
-// registers of wavefront 0 (lane = row), then every row below on its own thread.
-__device__ __forceinline__ void large_factor(const RefArgs &a, int T, char *sm, double thresh) {
+// registers of wavefront 0 (lane = row), every row below on its own thread.  The first
+// row below each thread is loaded before the diagonal block is factored.  sgs[c] = slot
+// of row s in column s + c (staged by the caller).  Us[j * kPanelMax + c] = U(j, j + c),
+// zero past the panel.
+template <int KW>
+__device__ __forceinline__ void large_factor_w(const RefArgs &a, int w, int r, char *sm, double thresh,
+                                               int item) {
     const int tid = threadIdx.x, lane = tid & 63;
-    const int4 pn = a.pan[T];
-    const int s = pn.x, w = pn.y, r = pn.z;
-    double *D = reinterpret_cast<double *>(sm + kOffLd);   // D[c * kPanelMax + row]
-    int *sgs = reinterpret_cast<int *>(sm + kOffUb);        // slot of row s in each column
-    if (tid < w) sgs[tid] = seg(a, s + tid, tid);
-    __syncthreads();
+    double *Us = reinterpret_cast<double *>(sm + kOffLd);
+    const int *sgs = reinterpret_cast<const int *>(sm + kOffSgs);
     int npert = 0, bad = 0;
+    double x[kPanelMax];
+    if (tid < r) load_row<KW>(x, a.lu, sgs, w, w + tid);
     if (tid < 64) {
         double d[kPanelMax];
+        load_row<KW>(d, a.lu, sgs, w, min(lane, w - 1));
+        if (lane >= w)
 #pragma unroll
-        for (int c = 0; c < kPanelMax; ++c) d[c] = (c < w && lane < w) ? a.lu[sgs[c] + lane] : 0.0;
+            for (int c = 0; c < KW; ++c) d[c] = 0.0;
+#pragma unroll 1
+        for (int j = 0; j < w; ++j) {
+            // lane j holds row j from column j on: it publishes the (perturbed) pivot and
+            // U(j, j + c) in LDS, and the wavefront reads the row back
+            if (lane == j) {
+                d[0] = perturb(d[0], thresh, npert);
+                double2 *o = reinterpret_cast<double2 *>(Us + j * kPanelMax);
 #pragma unroll
-        for (int jj = 0; jj < kPanelMax; ++jj) {
-            if (jj < w) {
-                const double p = perturb(bcast(d[jj], jj), thresh, npert);
-                bad |= !isfinite(p);
-                if (lane == jj) d[jj] = p;
-                const double l = d[jj] / p;
-                const bool below = lane > jj && lane < w;
-                if (below) d[jj] = l;
-#pragma unroll
-                for (int c = jj + 1; c < kPanelMax; ++c) {
-                    if (c < w) {
-                        const double ujc = bcast(d[c], jj);
-                        if (below) d[c] = fma(-l, ujc, d[c]);
-                    }
-                }
+                for (int c = 0; c < KW / 2; ++c) o[c] = double2{d[2 * c], d[2 * c + 1]};
             }
-        }
-#pragma unroll
-        for (int c = 0; c < kPanelMax; ++c) {
-            if (c < w && lane < w) {
-                a.lu[sgs[c] + lane] = d[c];
-                D[c * kPanelMax + lane] = d[c];
-            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            double rw[kPanelMax];
+            load_lds_row<KW>(rw, Us + j * kPanelMax);
+            __builtin_amdgcn_sched_barrier(0);
+            const double p = rw[0];
+            bad |= !isfinite(p);
+            const double l = d[0] / p;
+            if (lane > j && lane < w) a.lu[sgs[j] + lane] = l;
+            // rows below j; rows at or above j are complete and their registers unused
+            shift_fma<KW>(d, l, rw);
         }
     }
+    KKT_PHASE(item, 6);
     __syncthreads();
-    for (int i = tid; i < r; i += kBigThreads) {
-        double x[kPanelMax];
-#pragma unroll
-        for (int c = 0; c < kPanelMax; ++c) x[c] = c < w ? a.lu[sgs[c] + w + i] : 0.0;
-#pragma unroll
-        for (int jj = 0; jj < kPanelMax; ++jj) {
-            if (jj < w) {
-                const double l = x[jj] / D[jj * kPanelMax + jj];
-                bad |= !isfinite(l);
-                x[jj] = l;
-#pragma unroll
-                for (int c = jj + 1; c < kPanelMax; ++c)
-                    if (c < w) x[c] = fma(-l, D[c * kPanelMax + jj], x[c]);
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < kPanelMax; ++c)
-            if (c < w) a.lu[sgs[c] + w + i] = x[c];
+    KKT_PHASE(item, 7);
+    // U rows of the diagonal block (diagonal included) from LDS
+    for (int t = tid; t < w * KW; t += kBigThreads) {
+        const int j = t / KW, c = t % KW;
+        if (j + c < w) a.lu[sgs[j + c] + j] = Us[j * kPanelMax + c];
     }
-    if (tid == 0 && npert) atomicAdd(&a.pcount[blockIdx.x % kCountSlots], (unsigned long long)npert);
+    for (int i = tid; i < r; i += kBigThreads) {
+        if (i != tid) load_row<KW>(x, a.lu, sgs, w, w + i);
+#pragma unroll 1
+        for (int j = 0; j < w; ++j) {
+            double rw[kPanelMax];
+            load_lds_row<KW>(rw, Us + j * kPanelMax);
+            __builtin_amdgcn_sched_barrier(0);
+            const double l = x[0] / rw[0];
+            bad |= !isfinite(l);
+            a.lu[sgs[j] + w + i] = l;
+            shift_fma<KW>(x, l, rw);
+        }
+    }
+    if (npert) atomicAdd(&a.pcount[blockIdx.x % kCountSlots], (unsigned long long)npert);   // lane j counts pivot j
     if (__any(bad) && lane == 0) atomicOr(&a.st->flags, kFlagNonfinite);
+}
+
+__device__ __forceinline__ void large_factor(const RefArgs &a, int4 pn, char *sm, double thresh, int item) {
+    if (pn.y > 16) large_factor_w<32>(a, pn.y, pn.z, sm, thresh, item);
+    else if (pn.y > 8) large_factor_w<16>(a, pn.y, pn.z, sm, thresh, item);
+    else large_factor_w<8>(a, pn.y, pn.z, sm, thresh, item);
+}
+
+// Rows of the source panel (width w) in one target: unit lower solve with the source's
+// diagonal block Ls[j * kPanelMax + c] = L(j + c, j) (zero past the panel), in registers,
+// shifted; writes the solved rows to the factor and to ub.
+template <int KW>
+__device__ __forceinline__ void unit_lower_w(double *lu, int ps, int w, const double *Ls, double *ub, int item) {
+    double u[kPanelMax];
+#pragma unroll
+    for (int c = 0; c < KW; ++c) {
+        const double v = lu[ps + (c < w ? c : 0)];
+        u[c] = c < w ? v : 0.0;
+    }
+    KKT_PHASE(item, 8);
+#pragma unroll 1
+    for (int j = 0; j < w; ++j) {
+        double rw[kPanelMax];
+        load_lds_row<KW>(rw, Ls + j * kPanelMax);
+        __builtin_amdgcn_sched_barrier(0);
+        const double uj = u[0];
+        lu[ps + j] = uj;
+        ub[j] = uj;
+        shift_fma<KW>(u, uj, rw);
+    }
+    KKT_PHASE(item, 9);
 }
 
 // All pulls of one item with the source panel staged in LDS, then the panel factorization.
@@ -450,95 +552,116 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
     double *Ld = reinterpret_cast<double *>(sm + kOffLd);
     double *Ub = reinterpret_cast<double *>(sm + kOffUb);
     double *Lr = reinterpret_cast<double *>(sm + kOffLr);
-    const int p1 = a.item_pair[item + 1];
-    int *lds = reinterpret_cast<int *>(sm + kOffLr + kRChunk * kPanelMax * 8);   // diagonal slots
-    int4 *prs = reinterpret_cast<int4 *>(sm + kOffPairs);                          // staged pairs
-    const int pbeg = a.item_pair[item];
-    const int npr = p1 - pbeg;
+    int *lds = reinterpret_cast<int *>(sm + kOffLds);
+    int *sgs = reinterpret_cast<int *>(sm + kOffSgs);
+    int4 *prs = reinterpret_cast<int4 *>(sm + kOffPairs);
+    const int4 ia = a.item[2 * item], ib = a.item[2 * item + 1];
+    const int pbeg = ia.y, p1 = ia.z, npr = p1 - pbeg;
     const bool staged = npr <= kStagePairs;
+    // one round: the pair records and the slots of the panel to factor
     if (staged)
-        for (int t = tid; t < npr; t += kBigThreads) prs[t] = a.pair[pbeg + t];
+        for (int t = tid; t < 2 * npr; t += kBigThreads) prs[t] = a.pair[2 * pbeg + t];
+    if (ia.x >= 0 && tid < ib.y) sgs[tid] = a.ldiag[ib.x + tid] - tid;
     __syncthreads();
-    auto pr_at = [&](int q) { return staged ? prs[q - pbeg] : a.pair[q]; };
+    auto pra = [&](int q) { return staged ? prs[2 * (q - pbeg)] : a.pair[2 * q]; };
+    auto prb = [&](int q) { return staged ? prs[2 * (q - pbeg) + 1] : a.pair[2 * q + 1]; };
     KKT_PHASE(item, 1);
     for (int g0 = pbeg, g1; g0 < p1; g0 = g1) {
-        const int S = pr_at(g0).x;
+        const int S = pra(g0).x;
         g1 = g0 + 1;
-        while (g1 < p1 && pr_at(g1).x == S) ++g1;
-        const int4 pn = a.pan[S];
+        while (g1 < p1 && pra(g1).x == S) ++g1;
+        const int4 pn = prb(g0);
         const int s = pn.x, w = pn.y, r = pn.z;
-        if (tid < w) lds[tid] = a.ldiag[s + tid];
+        if (tid < w) lds[tid] = tid == 0 ? pn.w : a.ldiag[s + tid];
         __syncthreads();
-        for (int t = tid; t < w * w; t += kBigThreads) {
-            const int j = t / w, i = t % w;
-            if (i > j) Ld[j * kPanelMax + i] = a.lu[lds[j] + (i - j)];
+        // one round: S's diagonal block and the first chunk of its L rows
+        for (int t = tid; t < w * kPanelMax; t += kBigThreads) {
+            const int j = t / kPanelMax, c = t % kPanelMax;
+            Ld[t] = (c >= 1 && j + c < w) ? a.lu[lds[j] + c] : 0.0;
+        }
+        const int nr0 = min(kRChunk, r);
+        for (int t = tid; t < w * nr0; t += kBigThreads) {
+            const int j = t / nr0, i = t % nr0;
+            Lr[j * kRChunk + i] = a.lu[lds[j] + 1 + (w - 1 - j) + i];
         }
         __syncthreads();
         KKT_PHASE(item, 2);
         // rows of S in each target: unit lower solve with S's diagonal block, one lane per
-        // target (wavefront 0; groups hold at most kGroup targets); the lane keeps its
+        // target (wavefront 0; a group holds at most kGroup targets); the lane keeps its
         // target's rows in registers
         if (wv == 0 && lane < g1 - g0) {
-            const int ps = pr_at(g0 + lane).y;
-            double u[kPanelMax];
-#pragma unroll
-            for (int j = 0; j < kPanelMax; ++j) u[j] = j < w ? a.lu[ps + j] : 0.0;
-#pragma unroll
-            for (int t = 1; t < kPanelMax; ++t) {
-                if (t < w) {
-                    double acc = u[t];
-#pragma unroll
-                    for (int j = 0; j < t; ++j) acc = fma(-Ld[j * kPanelMax + t], u[j], acc);
-                    u[t] = acc;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < kPanelMax; ++j) {
-                if (j < w) {
-                    a.lu[ps + j] = u[j];
-                    Ub[lane * kPanelMax + j] = u[j];
-                }
-            }
+            const int ps = pra(g0 + lane).y;
+            double *ub = Ub + lane * kPanelMax;
+            if (w > 16) unit_lower_w<32>(a.lu, ps, w, Ld, ub, item);
+            else if (w > 8) unit_lower_w<16>(a.lu, ps, w, Ld, ub, item);
+            else unit_lower_w<8>(a.lu, ps, w, Ld, ub, item);
         }
         __syncthreads();
         KKT_PHASE(item, 3);
-        // rows R of each target: chunks of S's L rows staged in LDS, precomputed slots
+        // rows R of each target: chunks of S's L rows in LDS, precomputed slots
         for (int i0 = 0; i0 < r; i0 += kRChunk) {
             const int nr = min(kRChunk, r - i0);
-            for (int t = tid; t < w * nr; t += kBigThreads) {
-                const int j = t / nr, i = t % nr;
-                Lr[j * kRChunk + i] = a.lu[lds[j] + 1 + (w - 1 - j) + i0 + i];
+            if (i0 > 0) {
+                for (int t = tid; t < w * nr; t += kBigThreads) {
+                    const int j = t / nr, i = t % nr;
+                    Lr[j * kRChunk + i] = a.lu[lds[j] + 1 + (w - 1 - j) + i0 + i];
+                }
+                __syncthreads();
             }
-            __syncthreads();
             const int m = g1 - g0;
             if (a.use_mfma && m > 1) {
                 // update block Lr (nr x w) times the solved rows (w x m) on the matrix cores:
                 // 16x16 output tiles, k in steps of 4; lane holds A[lane % 16][lane / 16],
-                // B[lane / 16][lane % 16] and the four outputs D[lane / 16 + 4 v][lane % 16]
+                // B[lane / 16][lane % 16] and the four outputs D[lane / 16 + 4 v][lane % 16].
+                // Each wavefront computes up to kTiles tiles, then loads all their slots and
+                // current values in one round before writing them back.
+                constexpr int kTiles = 4;
                 const int mt = (nr + 15) >> 4, nt = (m + 15) >> 4;
                 const int li = lane & 15, lk = lane >> 4;
-                for (int tile = wv; tile < mt * nt; tile += nw) {
-                    const int ti = tile % mt, tt = tile / mt;
-                    const int ia = ti * 16 + li, tb = tt * 16 + li;
-                    double4_t acc = {0.0, 0.0, 0.0, 0.0};
-                    for (int k0 = 0; k0 < w; k0 += 4) {
-                        const int k = k0 + lk;
-                        const double av = (k < w && ia < nr) ? Lr[k * kRChunk + ia] : 0.0;
-                        const double bv = (k < w && tb < m) ? Ub[tb * kPanelMax + k] : 0.0;
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                for (int tile0 = wv * kTiles; tile0 < mt * nt; tile0 += nw * kTiles) {
+                    double4_t acc[kTiles];
+                    int slot[kTiles][4];
+                    double cur[kTiles][4];
+#pragma unroll
+                    for (int k = 0; k < kTiles; ++k) {
+                        const int tile = tile0 + k;
+                        acc[k] = double4_t{0.0, 0.0, 0.0, 0.0};
+                        if (tile < mt * nt) {
+                            const int ti = tile % mt, tt = tile / mt;
+                            const int ia2 = ti * 16 + li, tb = tt * 16 + li;
+                            for (int k0 = 0; k0 < w; k0 += 4) {
+                                const int kk = k0 + lk;
+                                const double av = (kk < w && ia2 < nr) ? Lr[kk * kRChunk + ia2] : 0.0;
+                                const double bv = (kk < w && tb < m) ? Ub[tb * kPanelMax + kk] : 0.0;
+                                acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[k], 0, 0, 0);
+                            }
+                        }
                     }
-                    if (tb < m) {
-                        const int32_t *rel = a.rel + pr_at(g0 + tb).z + i0;
+#pragma unroll
+                    for (int k = 0; k < kTiles; ++k) {
+                        const int tile = tile0 + k;
+                        const int ti = tile % mt, tt = tile / mt, tb = tt * 16 + li;
+                        const bool ok = tile < mt * nt && tb < m;
+                        const int32_t *rel = ok ? a.rel + pra(g0 + tb).z + i0 : a.rel;
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             const int i = ti * 16 + lk + 4 * v;
-                            if (i < nr) a.lu[rel[i]] -= acc[v];
+                            slot[k][v] = (ok && i < nr) ? rel[i] : -1;
                         }
                     }
+#pragma unroll
+                    for (int k = 0; k < kTiles; ++k)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) cur[k][v] = slot[k][v] >= 0 ? a.lu[slot[k][v]] : 0.0;
+#pragma unroll
+                    for (int k = 0; k < kTiles; ++k)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (slot[k][v] >= 0) a.lu[slot[k][v]] = cur[k][v] - acc[k][v];
                 }
             } else {
                 for (int q = g0 + wv; q < g1; q += nw) {
-                    const int32_t *rel = a.rel + pr_at(q).z + i0;
+                    const int32_t *rel = a.rel + pra(q).z + i0;
                     const double *ub = Ub + (q - g0) * kPanelMax;
                     for (int i = lane; i < nr; i += 64) {
                         double acc = 0.0;
@@ -553,8 +676,7 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
         __syncthreads();
         KKT_PHASE(item, 4);
     }
-    const int T = a.item_panel[item];
-    if (T >= 0) large_factor(a, T, sm, thresh);
+    if (ia.x >= 0) large_factor(a, ib, sm, thresh, item);
     KKT_PHASE(item, 5);
 }
 

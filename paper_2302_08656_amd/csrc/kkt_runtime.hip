@@ -19,8 +19,8 @@ namespace {
 struct Dev {
     int32_t *a_rowptr, *a_colind, *a_rowid, *a_cptr, *a_cpos, *lu_src;
     int32_t *colptr, *rowidx, *ulen, *pan_start, *pan_r;
-    int32_t *f_item_panel, *f_item_pair, *f_rel, *ldiag;
-    int4 *pan4, *pair4;
+    int32_t *f_rel, *ldiag;
+    int4 *item8, *pair8;
     unsigned long long *pcount;
     int32_t *l_item_p0, *l_item_np, *l_pan, *u_item_p0, *u_item_np, *u_pan;
     int32_t *csr_rowptr, *csr_col, *csr_src, *csr_diag, *csr_early, *P, *Q;
@@ -87,10 +87,8 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.ulen = c.take<int32_t>(n);
     d.pan_start = c.take<int32_t>(g.pan_start.size());
     d.pan_r = c.take<int32_t>(g.pan_r.size());
-    d.f_item_panel = c.take<int32_t>(g.f_item_panel.size());
-    d.f_item_pair = c.take<int32_t>(g.f_item_pair.size());
-    d.pair4 = c.take<int4>(std::max<size_t>(1, g.pair4.size() / 4));
-    d.pan4 = c.take<int4>(g.pan4.size() / 4);
+    d.item8 = c.take<int4>(std::max<size_t>(2, g.item8.size() / 4));
+    d.pair8 = c.take<int4>(std::max<size_t>(2, g.pair8.size() / 4));
     d.ldiag = c.take<int32_t>(n);
     d.f_rel = c.take<int32_t>(std::max<size_t>(1, g.f_rel.size()));
     d.pcount = c.take<unsigned long long>(kCountSlots);
@@ -269,7 +267,7 @@ int enqueue_refactor(kkt_handle *h, const double *v, hipStream_t s) {
     timed(h, KKT_PROF_UPDATE, s, [&] {
         k_gather_lu<<<blocks_for(nlu, 256), 256, 0, s>>>(nlu, d.lu_src, d.a_rowid, d.a_colind, v, d.r, d.c, d.lu);
     });
-    RefArgs a{d.ldiag, d.pan4, d.f_item_panel, d.f_item_pair, d.pair4, d.f_rel, d.lu, d.st, d.pcount,
+    RefArgs a{d.ldiag, d.item8, d.pair8, d.f_rel, d.lu, d.st, d.pcount,
               h->opts.tiny_pivot, h->opts.dense_mfma != 0};
     for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
         const int nl = g.f_nlarge[l], ns = g.f_lvl[l + 1] - g.f_lvl[l] - nl;
@@ -532,10 +530,8 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     rc |= upload(d.ulen, s.ulen, stream);
     rc |= upload(d.pan_start, g.pan_start, stream);
     rc |= upload(d.pan_r, g.pan_r, stream);
-    rc |= upload(d.f_item_panel, g.f_item_panel, stream);
-    rc |= upload(d.f_item_pair, g.f_item_pair, stream);
-    rc |= upload(reinterpret_cast<int32_t *>(d.pair4), g.pair4, stream);
-    rc |= upload(reinterpret_cast<int32_t *>(d.pan4), g.pan4, stream);
+    rc |= upload(reinterpret_cast<int32_t *>(d.item8), g.item8, stream);
+    rc |= upload(reinterpret_cast<int32_t *>(d.pair8), g.pair8, stream);
     rc |= upload(d.ldiag, g.ldiag, stream);
     rc |= upload(d.f_rel, g.f_rel, stream);
     rc |= upload(d.l_item_p0, g.l_item_p0, stream);

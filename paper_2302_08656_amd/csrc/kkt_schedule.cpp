@@ -207,20 +207,35 @@ int build_schedule(const Symbolic &s, Schedule &g) {
     if (g.f_rel.size() >= (size_t)INT32_MAX) return KKT_ERR_NOMEM;
     g.ldiag.resize(n);
     for (int32_t j = 0; j < n; ++j) g.ldiag[j] = (int32_t)(s.colptr[j] + s.ulen[j]);
-    g.pan4.resize(4 * (size_t)np);
-    for (int32_t p = 0; p < np; ++p) {
-        g.pan4[4 * p] = g.pan_start[p];
-        g.pan4[4 * p + 1] = pw(p);
-        g.pan4[4 * p + 2] = g.pan_r[p];
-        g.pan4[4 * p + 3] = 0;
+    // packed records (8 x int32 each): item i = {T, first pair, end pair, 0, s, w, r,
+    // ldiag[s]} with T the panel it factors (or -1) and s, w, r that panel's first column,
+    // width and rows below; pair q = {S, pos, rel, target column, s, w, r, ldiag[s]} with
+    // the source panel's geometry
+    auto geom = [&](int32_t *o, int32_t P) {
+        o[0] = P >= 0 ? g.pan_start[P] : 0;
+        o[1] = P >= 0 ? pw(P) : 0;
+        o[2] = P >= 0 ? g.pan_r[P] : 0;
+        o[3] = P >= 0 ? g.ldiag[g.pan_start[P]] : 0;
+    };
+    const size_t nitems = g.f_item_panel.size();
+    g.item8.resize(8 * nitems);
+    for (size_t i = 0; i < nitems; ++i) {
+        int32_t *o = &g.item8[8 * i];
+        o[0] = g.f_item_panel[i];
+        o[1] = g.f_item_pair[i];
+        o[2] = g.f_item_pair[i + 1];
+        o[3] = 0;
+        geom(o + 4, g.f_item_panel[i]);
     }
     const size_t npairs = g.f_pair_src.size();
-    g.pair4.resize(4 * npairs);
+    g.pair8.resize(8 * npairs);
     for (size_t q = 0; q < npairs; ++q) {
-        g.pair4[4 * q] = g.f_pair_src[q];
-        g.pair4[4 * q + 1] = g.f_pair_pos[q];
-        g.pair4[4 * q + 2] = (int32_t)g.f_pair_rel[q];
-        g.pair4[4 * q + 3] = g.f_pair_tgt[q];
+        int32_t *o = &g.pair8[8 * q];
+        o[0] = g.f_pair_src[q];
+        o[1] = g.f_pair_pos[q];
+        o[2] = (int32_t)g.f_pair_rel[q];
+        o[3] = g.f_pair_tgt[q];
+        geom(o + 4, g.f_pair_src[q]);
     }
     // solve levels
     std::vector<int32_t> llev(np, 0), ulev(np, 0);
