@@ -48,7 +48,20 @@ constexpr int kSolvePack = 64;
 constexpr int kSmallW = 4;
 constexpr int kSmallR = 64;
 constexpr int kGroup = 32;
-constexpr int kPersistItems = 64;
+// Solve levels with at most this many items run in the persistent launch (build-time
+// tunable).
+#ifndef KKT_PERSIST_ITEMS
+#define KKT_PERSIST_ITEMS (1 << 30)
+#endif
+constexpr int kPersistItems = KKT_PERSIST_ITEMS;
+// Solve helpers: a wide panel gets helper items kHelpAhead levels before it when one of
+// its rows has at least kHelpMin early entries (columns of panels more than kHelpAhead
+// levels below); each helper item sums the early entries of kHelpRows rows.
+constexpr int kHelpAhead = 2;
+constexpr int kHelpRows = 4;
+constexpr int kHelpMin = 32;
+// Solve panels of at most kPackW columns are packed whole, kSolvePack rows to an item.
+constexpr int kPackW = 4;
 
 // Device schedule, built on the host once per pattern and uploaded by kkt_bind.
 struct Schedule {
@@ -72,21 +85,28 @@ struct Schedule {
     //             s, w, r, ldiag[s]}, with s, w, r the panel's first column, width, rows below
     std::vector<int32_t> item8, pair8;
     std::vector<int32_t> ldiag;         // slot of the diagonal of each column
-    // triangular solves: launch l runs items [x_lvl[l], x_lvl[l+1]); an item is a wide
-    // panel (np = 1, pan = panel), a helper (np = 0, pan = panel) or a pack of -np width-1
-    // panels (pan = their rows)
-    std::vector<int32_t> l_lvl, l_item_p0, l_item_np;
-    std::vector<int32_t> u_lvl, u_item_p0, u_item_np;
-    // level-sorted panel lists referenced by the solve items
-    std::vector<int32_t> l_pan, u_pan;
-    // hybrid solves: forward levels >= l_split and backward levels < u_split (the narrow top
-    // of the tree, at most kPersistItems items per level) run in one persistent launch
+    // triangular solves: level l has items [x_lvl[l], x_lvl[l+1]), 4 x int32 each:
+    // {1, lanes, s, w}: wide panel of rows s..s+w-1; {0, t0, s, w}: helper summing the
+    // early columns of rows s+t0 .. s+t0+kHelpRows-1 of such a panel (kHelpAhead levels
+    // before it); {-c, p0, lanes, 0}: pack of c rows of whole panels of width <= kPackW
+    // whose row records are x_rows4[p0..] = {row, first external slot, end of external
+    // slots, t | w << 8} with t the row's offset in its panel of width w.  `lanes` = lanes
+    // per row for the external part (a power of two, 256 / lanes >= rows, at most 64).
+    std::vector<int32_t> l_lvl, u_lvl;
+    std::vector<int32_t> l_item4, u_item4, l_rows4, u_rows4;
+    // per-row records of the CSR copy: forward {first slot, first late slot, diagonal
+    // slot, end}; backward {diagonal slot, first early slot, end, 0}
+    std::vector<int32_t> rinfo4, urinfo4;
+    // forward levels >= l_split and backward levels < u_split run in one persistent launch
+    // (levels of at most kPersistItems items; the rest as one launch per level)
     int32_t l_split = 0, u_split = 0;
-    // combined L+U in CSR for the row-oriented solves.  Rows of wide panels list their L
-    // entries as [early | late | in-panel]: early columns belong to panels two or more
-    // forward levels below, and a helper item one level early sums them into a per-row
-    // partial sum (csr_early[i] = end of the early part, = csr_rowptr[i] when there is none).
-    std::vector<int32_t> csr_rowptr, csr_col, csr_src, csr_diag, csr_early;
+    // combined L+U in CSR for the row-oriented solves.  Rows of helped panels list their L
+    // entries as [early | late | in-panel] and their U entries as [in-panel | late | early]:
+    // early columns belong to panels more than kHelpAhead levels below in that triangle's
+    // order, and helper items kHelpAhead levels early sum them into per-row partial sums (csr_early[i] = end of
+    // the early L part, = csr_rowptr[i] when there is none; csr_uearly[i] = start of the
+    // early U part, = csr_rowptr[i + 1] when there is none).
+    std::vector<int32_t> csr_rowptr, csr_col, csr_src, csr_diag, csr_early, csr_uearly;
     // value update: for each L+U slot, the CSR entry of A it receives (-1: fill)
     std::vector<int32_t> lu_src;
     // CSC view of A's pattern (positions into the CSR value array)

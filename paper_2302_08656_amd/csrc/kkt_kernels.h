@@ -8,8 +8,8 @@
 namespace kkt {
 
 constexpr int kFlagNonfinite = 1;
-constexpr int kFlagInternal = 2;
-constexpr int kCountSlots = 1024;   // spread counter for replaced pivots   // a pull found no slot for a row (schedule bug)
+constexpr int kFlagInternal = 2;    // a schedule invariant failed on the device
+constexpr int kCountSlots = 1024;   // spread counter for replaced pivots
 
 // Scalars written by the kernels and read back by the host.
 struct DevStatus {
@@ -18,7 +18,6 @@ struct DevStatus {
     unsigned long long perturbed; // pivots replaced by the last refactorization
     int flags;                    // kFlagNonfinite
     int abort;                    // a persistent solve timed out waiting (sticky until refactor)
-    int queue[4];                 // work queues of the persistent solves
 };
 
 // Infinity norms of the last residual evaluation, read back by the host.

@@ -681,161 +681,37 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
 }
 
 // ---------------------------------------------------------------------------------------
-// triangular solves: one 256-thread block per wide panel or per pack of kSolvePack
-// width-1 panels (kPackLanes lanes per row)
+// triangular solves.  Items (one 256-thread block each): a pack of up to kSolvePack rows of
+// whole panels of at most kPackW columns (a group of lanes per row for the part outside
+// the panel, then the in-panel substitution in kPackW synchronised steps), a wide panel (a
+// group of lanes per row outside the panel, then a register substitution inside it on
+// wavefront 0), or a helper that sums the early columns of kHelpRows rows of a wide panel
+// kHelpAhead levels ahead.  Records:
+//   item {-c, p0, lanes, 0} pack of c rows listed at rows[p0..]; {1, lanes, s, w} wide
+//   panel of rows s..s+w-1; {0, t0, s, w} helper for rows s+t0 .. of that panel;
+//   pack row {i, first external slot, end of external slots, t | w << 8};
+//   rinfo[i] forward {first slot, first late slot, diagonal slot, end}, backward
+//   {diagonal slot, first early slot, end, 0}.
+//
+// Every item is written once for two execution modes: level launches (kWait = false: all
+// inputs were written by earlier launches) and one persistent launch per triangle (kWait =
+// true: an unknown is read with a device-coherent load and waited for while it still holds
+// the unset sentinel; results are published with device-coherent stores).  The arithmetic
+// is the same in both modes.
 
-constexpr int kPackLanes = kBlock / kSolvePack;
 
 struct SolveArgs {
-    const int32_t *pan_start, *item_p0, *item_np, *pan;
-    const int32_t *rowptr, *col, *diag, *early, *P, *Q;
-    const double *lucsr, *r, *c;
-    const double *b;      // forward: right-hand side (original order)
+    const int4 *item, *rows, *rinfo;
+    const int32_t *col, *Q;
+    const double *lucsr, *c;
+    const double *bp;     // forward right-hand side r[P[i]] * b[P[i]] (permuted order)
     double *y;            // forward output / backward input (permuted)
     double *xt;           // backward output (permuted)
     double *x;            // backward output (original order)
     double *psum;         // forward: partial sums of the early L columns of helped rows
+    double *usum;         // backward: partial sums of the early U columns of helped rows
+    int *abort;           // persistent mode: raised by a wait that timed out
 };
-
-// sum over q in [q0, q1) of lucsr[q] * v[col[q]] on a group of `width` lanes; four
-// independent gathers in flight per lane
-__device__ __forceinline__ double row_dot(const SolveArgs &a, const double *v, int q0, int q1, int gl, int width) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int q = q0 + gl;
-    for (; q + 3 * width < q1; q += 4 * width) {
-        const int c0 = a.col[q], c1 = a.col[q + width], c2 = a.col[q + 2 * width], c3 = a.col[q + 3 * width];
-        s0 = fma(a.lucsr[q], v[c0], s0);
-        s1 = fma(a.lucsr[q + width], v[c1], s1);
-        s2 = fma(a.lucsr[q + 2 * width], v[c2], s2);
-        s3 = fma(a.lucsr[q + 3 * width], v[c3], s3);
-    }
-    for (; q < q1; q += width) s0 = fma(a.lucsr[q], v[a.col[q]], s0);
-    return group_sum((s0 + s1) + (s2 + s3), width);
-}
-
-// In-panel block of a wide panel staged in LDS by the whole block (one parallel round):
-// blk[t * kPanelMax + i] = entry (s + i, s + t) of L (t < i) or U (t > i); blk[i * 33] = U(i, i).
-__device__ __forceinline__ void stage_inpanel(const SolveArgs &a, int s, int w, double *blk) {
-    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
-        const int i = e / w, t = e % w;
-        blk[t * kPanelMax + i] = a.lucsr[a.diag[s + i] + (t - i)];
-    }
-}
-
-// Forward substitution inside a panel of w <= kPanelMax rows (lane = row); yv enters as the
-// row's right-hand side minus its external part.
-__device__ __forceinline__ double inpanel_forward(const double *blk, int w, int lane, double yv) {
-    for (int t = 0; t + 1 < w; ++t) {
-        const double yt = bcast(yv, t);
-        if (lane > t && lane < w) yv = fma(-blk[t * kPanelMax + lane], yt, yv);
-    }
-    return yv;
-}
-
-// Backward substitution inside a panel (lane = row); val enters as y minus the external
-// part; returns the lane's unknown.
-__device__ __forceinline__ double inpanel_backward(const double *blk, int w, int lane, double val) {
-    double xv = 0.0;
-    for (int t = w - 1; t >= 0; --t) {
-        if (lane == t) xv = val / blk[t * kPanelMax + t];
-        const double xt = bcast(xv, t);
-        if (lane < t) val = fma(-blk[t * kPanelMax + lane], xt, val);
-    }
-    return xv;
-}
-
-__global__ __launch_bounds__(256) void k_lsolve_level(int item0, SolveArgs a) {
-    __shared__ double ext[kPanelMax];
-    __shared__ double blk[kPanelMax * kPanelMax];
-    const int item = item0 + blockIdx.x, tid = threadIdx.x, lane = tid & 63;
-    const int np = a.item_np[item], p0 = a.item_p0[item];
-    if (np < 0) {                                    // pack of width-1 panels, 8 lanes each
-        const int g = tid / kPackLanes, gl = tid % kPackLanes;
-        int i = -1, q0 = 0, q1 = 0;
-        if (g < -np) {
-            i = a.pan[p0 + g];
-            q0 = a.rowptr[i];
-            q1 = a.diag[i];
-        }
-        const double acc = row_dot(a, a.y, q0, q1, gl, kPackLanes);
-        if (i >= 0 && gl == 0) a.y[i] = a.r[a.P[i]] * a.b[a.P[i]] - acc;
-        return;
-    }
-    const int T = a.pan[p0];
-    const int s = a.pan_start[T], w = a.pan_start[T + 1] - s;
-    const int g = tid >> 5, gl = tid & 31;
-    if (np == 0) {                                   // early partial sums of panel T's rows
-        for (int t = g; t < w; t += kBlock / 32) {
-            const int i = s + t;
-            const double acc = row_dot(a, a.y, a.rowptr[i], a.early[i], gl, 32);
-            if (gl == 0) a.psum[i] = acc;
-        }
-        return;
-    }
-    stage_inpanel(a, s, w, blk);
-    // late part of each row (columns left of the panel), 32 lanes per row, 8 rows at once
-    for (int t = g; t < w; t += kBlock / 32) {
-        const int i = s + t;
-        const int e = a.early[i];
-        double acc = row_dot(a, a.y, e, a.diag[i] - t, gl, 32);
-        if (gl == 0) ext[t] = e > a.rowptr[i] ? acc + a.psum[i] : acc;
-    }
-    __syncthreads();
-    if (tid >= 64) return;
-    double yv = 0.0;
-    if (lane < w) yv = a.r[a.P[s + lane]] * a.b[a.P[s + lane]] - ext[lane];
-    yv = inpanel_forward(blk, w, lane, yv);
-    if (lane < w) a.y[s + lane] = yv;
-}
-
-__global__ __launch_bounds__(256) void k_usolve_level(int item0, SolveArgs a) {
-    __shared__ double ext[kPanelMax];
-    __shared__ double blk[kPanelMax * kPanelMax];
-    const int item = item0 + blockIdx.x, tid = threadIdx.x, lane = tid & 63;
-    const int np = a.item_np[item], p0 = a.item_p0[item];
-    if (np < 0) {
-        const int g = tid / kPackLanes, gl = tid % kPackLanes;
-        int i = -1, q0 = 0, q1 = 0;
-        if (g < -np) {
-            i = a.pan[p0 + g];
-            q0 = a.diag[i] + 1;
-            q1 = a.rowptr[i + 1];
-        }
-        const double acc = row_dot(a, a.xt, q0, q1, gl, kPackLanes);
-        if (i >= 0 && gl == 0) {
-            const double xv = (a.y[i] - acc) / a.lucsr[a.diag[i]];
-            a.xt[i] = xv;
-            a.x[a.Q[i]] = a.c[a.Q[i]] * xv;
-        }
-        return;
-    }
-    const int T = a.pan[p0];
-    const int s = a.pan_start[T], w = a.pan_start[T + 1] - s;
-    const int g = tid >> 5, gl = tid & 31;
-    stage_inpanel(a, s, w, blk);
-    for (int t = g; t < w; t += kBlock / 32) {
-        const int i = s + t;
-        const double acc = row_dot(a, a.xt, a.diag[i] + (w - t), a.rowptr[i + 1], gl, 32);
-        if (gl == 0) ext[t] = acc;
-    }
-    __syncthreads();
-    if (tid >= 64) return;
-    double val = 0.0;
-    if (lane < w) val = a.y[s + lane] - ext[lane];
-    const double xv = inpanel_backward(blk, w, lane, val);
-    if (lane < w) {
-        a.xt[s + lane] = xv;
-        a.x[a.Q[s + lane]] = a.c[a.Q[s + lane]] * xv;
-    }
-}
-
-// ---------------------------------------------------------------------------------------
-// persistent triangular solves (the narrow top of the tree): blocks take the solve items of
-// a range of levels from a queue in level order.
-// Every unknown starts as a signaling-NaN sentinel (arithmetic never produces one) and is
-// published by one 64-bit device-coherent store, so the value is its own ready flag.
-// A read of a not-yet-published unknown waits (bounded); items only depend on items that
-// were taken earlier, so the earliest unfinished item can always proceed.
 
 constexpr unsigned long long kUnset = 0x7ff4dead0badf00dULL;   // signaling NaN
 constexpr int kSpinLimit = 1 << 21;
@@ -845,159 +721,378 @@ __device__ __forceinline__ unsigned long long load_coherent(const double *p) {
                              __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void publish(double *p, double v) {
-    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// value of an unknown, waiting until it is published; on timeout or abort returns 0 and
-// raises *abort (the solve result is then invalid and reported as a device error)
-__device__ __forceinline__ double wait_value(const double *p, int *abort) {
-    unsigned long long b = load_coherent(p);
-    if (b != kUnset) return __longlong_as_double((long long)b);
+// waits until *p no longer holds the sentinel; on timeout or abort returns 0 and raises
+// *abort (the solve result is then invalid and reported as a device error)
+__device__ __noinline__ double wait_slow(const double *p, int *abort) {
     for (int it = 0; it < kSpinLimit; ++it) {
         __builtin_amdgcn_s_sleep(2);
-        b = load_coherent(p);
+        const unsigned long long b = load_coherent(p);
         if (b != kUnset) return __longlong_as_double((long long)b);
-        if ((it & 63) == 63 &&
-            __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            return 0.0;
+        if ((it & 63) == 63 && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return 0.0;
     }
     atomicOr(abort, 1);
     return 0.0;
 }
 
-// row_dot with waits; same summation order, so both solve modes give identical results
-__device__ __forceinline__ double row_dot_wait(const SolveArgs &a, const double *v, int q0, int q1, int gl,
-                                               int width, int *abort) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int q = q0 + gl;
-    for (; q + 3 * width < q1; q += 4 * width) {
-        const int c0 = a.col[q], c1 = a.col[q + width], c2 = a.col[q + 2 * width], c3 = a.col[q + 3 * width];
-        s0 = fma(a.lucsr[q], wait_value(v + c0, abort), s0);
-        s1 = fma(a.lucsr[q + width], wait_value(v + c1, abort), s1);
-        s2 = fma(a.lucsr[q + 2 * width], wait_value(v + c2, abort), s2);
-        s3 = fma(a.lucsr[q + 3 * width], wait_value(v + c3, abort), s3);
+// re-reads every still-unset entry of a batch together until none is left (bounded; on
+// timeout or abort the unset entries read as 0 and *abort is raised)
+template <int B>
+__device__ __forceinline__ void wait_batch(unsigned long long (&bb)[B], const double *v, const int (&cc)[B],
+                                           int *abort) {
+    bool pend = false;
+#pragma unroll
+    for (int k = 0; k < B; ++k) pend |= bb[k] == kUnset;
+    for (int it = 1; pend; ++it) {
+        __builtin_amdgcn_s_sleep(2);
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (bb[k] == kUnset) bb[k] = load_coherent(v + cc[k]);
+        pend = false;
+#pragma unroll
+        for (int k = 0; k < B; ++k) pend |= bb[k] == kUnset;
+        const bool stop = it >= kSpinLimit ||
+                          ((it & 63) == 0 && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (pend && stop) {
+            if (it >= kSpinLimit) atomicOr(abort, 1);
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                if (bb[k] == kUnset) bb[k] = 0ULL;
+            pend = false;
+        }
     }
-    for (; q < q1; q += width) s0 = fma(a.lucsr[q], wait_value(v + a.col[q], abort), s0);
+}
+
+template <bool kWait>
+__device__ __forceinline__ double get_value(const double *p, int *abort) {
+    if constexpr (kWait) {
+        const unsigned long long b = load_coherent(p);
+        return b != kUnset ? __longlong_as_double((long long)b) : wait_slow(p, abort);
+    } else {
+        return *p;
+    }
+}
+
+template <bool kWait>
+__device__ __forceinline__ void put_value(double *p, double v) {
+    if constexpr (kWait)
+        __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *p = v;
+}
+
+// sum over q in [q0, q1) of lucsr[q] * v[col[q]] on a group of `width` lanes.  A lane's
+// entries are taken four at a time into four accumulators, a remainder of fewer than four
+// into the first.  Loads go in batches of B entries per lane: the batch's indices and
+// factor values in one round, then its unknowns in one round.
+template <bool kWait, int B>
+__device__ __forceinline__ double sdot(const SolveArgs &a, const double *v, int q0, int q1, int gl, int width) {
+    static_assert(B % 4 == 0, "batch of whole groups of four");
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int q = q0 + gl; q < q1; q += B * width) {
+        const int rem = (q1 - q + width - 1) / width;
+        int cc[B];
+        double ll[B], vv[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const bool h = k < rem;
+            cc[k] = h ? a.col[q + k * width] : 0;
+            ll[k] = h ? a.lucsr[q + k * width] : 0.0;
+        }
+        if constexpr (kWait) {
+            unsigned long long bb[B];
+#pragma unroll
+            for (int k = 0; k < B; ++k) bb[k] = k < rem ? load_coherent(v + cc[k]) : 0ULL;
+            wait_batch<B>(bb, v, cc, a.abort);
+#pragma unroll
+            for (int k = 0; k < B; ++k) vv[k] = __longlong_as_double((long long)bb[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < B; ++k) vv[k] = k < rem ? v[cc[k]] : 0.0;
+        }
+#pragma unroll
+        for (int k0 = 0; k0 < B; k0 += 4) {
+            const int r4 = rem - k0;
+            if (r4 >= 4) {
+                s0 = fma(ll[k0], vv[k0], s0);
+                s1 = fma(ll[k0 + 1], vv[k0 + 1], s1);
+                s2 = fma(ll[k0 + 2], vv[k0 + 2], s2);
+                s3 = fma(ll[k0 + 3], vv[k0 + 3], s3);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    if (k < r4) s0 = fma(ll[k0 + k], vv[k0 + k], s0);
+            }
+        }
+    }
     return group_sum((s0 + s1) + (s2 + s3), width);
 }
 
-// y[:] = xt[:] = psum[:] = unset, work queues cleared
-__global__ void k_solve_reset(int n, double *__restrict__ y, double *__restrict__ xt, double *__restrict__ psum,
-                              DevStatus *st) {
+// Forward substitution inside a panel of w <= kPanelMax rows (lane = row): Lrow[t] =
+// L(lane, t) for t < lane, zero otherwise; yv enters as the row's right-hand side minus its
+// external part.
+__device__ __forceinline__ double inpanel_forward(const double (&Lrow)[kPanelMax], int w, int lane, double yv) {
+#pragma unroll
+    for (int t = 0; t + 1 < kPanelMax; ++t) {
+        if (t + 1 < w) {
+            const double yt = bcast(yv, t);
+            const double nv = fma(-Lrow[t], yt, yv);
+            yv = lane > t ? nv : yv;
+        }
+    }
+    return yv;
+}
+
+// Backward substitution inside a panel (lane = row): Urow[t] = U(lane, t) for t > lane,
+// dv = U(lane, lane); val enters as y minus the external part; returns the lane's unknown.
+__device__ __forceinline__ double inpanel_backward(const double (&Urow)[kPanelMax], double dv, int w, int lane,
+                                                   double val) {
+    double xv = 0.0;
+#pragma unroll
+    for (int t = kPanelMax - 1; t >= 0; --t) {
+        if (t < w) {
+            const double q = val / dv;          // final in lane t
+            const double xt = bcast(q, t);
+            xv = lane == t ? q : xv;
+            const double nv = fma(-Urow[t], xt, val);
+            val = lane < t ? nv : val;
+        }
+    }
+    return xv;
+}
+
+#ifdef KKT_PHASE_TRACE
+__device__ unsigned long long *kkt_phase_buf2;
+#define KKT_UPHASE(item, k)                                                             \
+    do {                                                                                \
+        if (kWait && threadIdx.x == 0 && kkt_phase_buf2) kkt_phase_buf2[(item) * 4 + (k)] = wall_clock64(); \
+    } while (0)
+#define KKT_SPHASE(item, k)                                                             \
+    do {                                                                                \
+        if (kWait && threadIdx.x == 0 && kkt_phase_buf) kkt_phase_buf[(item) * 4 + (k)] = wall_clock64(); \
+    } while (0)
+#else
+#define KKT_SPHASE(item, k) \
+    do {                    \
+    } while (0)
+#define KKT_UPHASE(item, k) \
+    do {                    \
+    } while (0)
+#endif
+
+template <bool kWait>
+__device__ __forceinline__ void lsolve_item(const SolveArgs &a, int item, double *ext, double *blk) {
+    const int4 it = a.item[item];
+    const int tid = threadIdx.x, lane = tid & 63;
+    KKT_SPHASE(item, 0);
+    if (it.x < 0) {                                     // pack of whole small panels
+        __shared__ double ys[kSolvePack];
+        const int lanes = it.z, g = tid / lanes, gl = tid % lanes;
+        const int4 rr = g < -it.x ? a.rows[it.y + g] : int4{-1, 0, 0, 0};
+        const int t = rr.w & 255;
+        const bool lead = rr.x >= 0 && gl == 0;
+        double bv = 0.0, Lp[kPackW - 1];
+#pragma unroll
+        for (int k = 0; k < kPackW - 1; ++k) Lp[k] = lead && k < t ? a.lucsr[rr.z + k] : 0.0;
+        if (lead) bv = a.bp[rr.x];
+        const double acc = sdot<kWait, 4>(a, a.y, rr.y, rr.z, gl, lanes);
+        double yv = bv - acc;
+        // in-panel substitution: step k solves the rows at offset k of their panels
+#pragma unroll
+        for (int k = 0; k < kPackW; ++k) {
+            if (lead && t == k) {
+#pragma unroll
+                for (int k2 = 0; k2 < k; ++k2) yv = fma(-Lp[k2], ys[g - k + k2], yv);
+                ys[g] = yv;
+                put_value<kWait>(a.y + rr.x, yv);
+            }
+            __syncthreads();
+        }
+        KKT_SPHASE(item, 3);
+        return;
+    }
+    const int s = it.z, w = it.w;
+    if (it.x == 0) {                                    // early partial sums, one wavefront per row
+        const int t = it.y + (tid >> 6);
+        if (t < w && t < it.y + kHelpRows) {
+            const int4 ri = a.rinfo[s + t];
+            const double acc = sdot<kWait, 8>(a, a.y, ri.x, ri.y, lane, 64);
+            if (lane == 0) put_value<kWait>(a.psum + s + t, acc);
+        }
+        KKT_SPHASE(item, 3);
+        return;
+    }
+    // wide panel: the in-panel rows are staged in LDS (blk[r * kPanelMax + t] = L(r, t),
+    // zero on and above the diagonal) alongside the first loads of the external part
+    {
+        const int lanes = it.y, t = tid / lanes, gl = tid % lanes;
+        const int4 ri = a.rinfo[s + min(t, w - 1)];
+        for (int e = tid; e < w * kPanelMax; e += kBlock) {
+            const int r = e / kPanelMax, c = e % kPanelMax;
+            const int d = a.rinfo[s + r].z;
+            blk[e] = c < r ? a.lucsr[d - r + c] : 0.0;
+        }
+        if (t < w) {
+            const double bv = gl == 0 ? a.bp[s + t] : 0.0;
+            const bool helped = ri.y > ri.x;
+            const double ps = helped && gl == 0 ? get_value<kWait>(a.psum + s + t, a.abort) : 0.0;
+            const double acc = sdot<kWait, 8>(a, a.y, ri.y, ri.z - t, gl, lanes);
+            if (gl == 0) ext[t] = bv - (helped ? acc + ps : acc);
+        }
+    }
+    KKT_SPHASE(item, 1);
+    __syncthreads();
+    KKT_SPHASE(item, 2);
+    if (tid < 64) {
+        double Lrow[kPanelMax];
+        load_lds_row<kPanelMax>(Lrow, blk + min(lane, kPanelMax - 1) * kPanelMax);
+        double yv = lane < w ? ext[lane] : 0.0;
+        yv = inpanel_forward(Lrow, w, lane, yv);
+        if (lane < w) put_value<kWait>(a.y + s + lane, yv);
+    }
+    KKT_SPHASE(item, 3);
+    __syncthreads();
+}
+
+template <bool kWait>
+__device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double *ext, double *blk) {
+    const int4 it = a.item[item];
+    const int tid = threadIdx.x, lane = tid & 63;
+    KKT_UPHASE(item, 0);
+    if (it.x < 0) {                                     // pack of whole small panels
+        __shared__ double xs[kSolvePack];
+        const int lanes = it.z, g = tid / lanes, gl = tid % lanes;
+        const int4 rr = g < -it.x ? a.rows[it.y + g] : int4{-1, 0, 0, 0};
+        const int t = rr.w & 255, w = rr.w >> 8;
+        const int e = w - 1 - t;                        // in-panel entries right of the diagonal
+        const bool lead = rr.x >= 0 && gl == 0;
+        double yv = 0.0, dd = 1.0, ci = 0.0, Up[kPackW - 1];
+        int qi = 0;
+        const int d = rr.y - (w - t);                   // diagonal slot
+#pragma unroll
+        for (int k = 0; k < kPackW - 1; ++k) Up[k] = lead && k < e ? a.lucsr[d + 1 + k] : 0.0;
+        if (lead) {
+            yv = a.y[rr.x];
+            dd = a.lucsr[d];
+            qi = a.Q[rr.x];
+            ci = a.c[qi];
+        }
+        const double acc = sdot<kWait, 4>(a, a.xt, rr.y, rr.z, gl, lanes);
+        double val = yv - acc;
+        // step k solves the rows k places before the end of their panels; the row's
+        // in-panel terms are taken from the right
+#pragma unroll
+        for (int k = 0; k < kPackW; ++k) {
+            if (lead && e == k) {
+#pragma unroll
+                for (int k2 = k - 1; k2 >= 0; --k2) val = fma(-Up[k2], xs[g + 1 + k2], val);
+                const double xv = val / dd;
+                xs[g] = xv;
+                a.x[qi] = ci * xv;
+                put_value<kWait>(a.xt + rr.x, xv);
+            }
+            __syncthreads();
+        }
+        KKT_UPHASE(item, 3);
+        return;
+    }
+    const int s = it.z, w = it.w;
+    if (it.x == 0) {                                    // early partial sums, one wavefront per row
+        const int t = it.y + (tid >> 6);
+        if (t < w && t < it.y + kHelpRows) {
+            const int4 ri = a.rinfo[s + t];
+            const double acc = sdot<kWait, 8>(a, a.xt, ri.y, ri.z, lane, 64);
+            if (lane == 0) put_value<kWait>(a.usum + s + t, acc);
+        }
+        KKT_UPHASE(item, 3);
+        return;
+    }
+    // in-panel rows staged in LDS: blk[r * kPanelMax + t] = U(r, t) for t > r, else zero
+    double dv = 1.0, yv = 0.0, ci = 0.0;
+    int qi = 0;
+    {
+        for (int e = tid; e < w * kPanelMax; e += kBlock) {
+            const int r = e / kPanelMax, c = e % kPanelMax;
+            const int d = a.rinfo[s + r].x;
+            blk[e] = c > r && c < w ? a.lucsr[d + (c - r)] : 0.0;
+        }
+        if (tid < w) {
+            const int i = s + tid;
+            dv = a.lucsr[a.rinfo[i].x];
+            yv = a.y[i];
+            qi = a.Q[i];
+            ci = a.c[qi];
+        }
+        const int lanes = it.y, t = tid / lanes, gl = tid % lanes;
+        if (t < w) {
+            const int4 ri = a.rinfo[s + t];
+            const bool helped = ri.y < ri.z;
+            const double us = helped && gl == 0 ? get_value<kWait>(a.usum + s + t, a.abort) : 0.0;
+            const double acc = sdot<kWait, 8>(a, a.xt, ri.x + (w - t), ri.y, gl, lanes);
+            if (gl == 0) ext[t] = helped ? acc + us : acc;
+        }
+    }
+    KKT_UPHASE(item, 1);
+    __syncthreads();
+    KKT_UPHASE(item, 2);
+    if (tid < 64) {
+        double Urow[kPanelMax];
+        load_lds_row<kPanelMax>(Urow, blk + min(lane, kPanelMax - 1) * kPanelMax);
+        const double val = lane < w ? yv - ext[lane] : 0.0;
+        const double xv = inpanel_backward(Urow, dv, w, lane, val);
+        if (lane < w) {
+            a.x[qi] = ci * xv;
+            put_value<kWait>(a.xt + s + lane, xv);
+        }
+    }
+    KKT_UPHASE(item, 3);
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_lsolve_level(int item0, SolveArgs a) {
+    __shared__ double ext[kPanelMax];
+    __shared__ __align__(16) double blk[kPanelMax * kPanelMax];
+    lsolve_item<false>(a, item0 + blockIdx.x, ext, blk);
+}
+
+__global__ __launch_bounds__(256) void k_usolve_level(int item0, SolveArgs a) {
+    __shared__ double ext[kPanelMax];
+    __shared__ __align__(16) double blk[kPanelMax * kPanelMax];
+    usolve_item<false>(a, item0 + blockIdx.x, ext, blk);
+}
+
+// Persistent solves: the items of levels [i0, i1) in level order, item i0 + k on block
+// k % gridDim.x, each block in increasing order.  An item only reads unknowns of items of
+// lower levels, i.e. of smaller index, so the unfinished item of smallest index can always
+// proceed: with every block resident (cooperative launch) the launch always drains.
+__global__ __launch_bounds__(256) void k_lsolve_persistent(int i0, int i1, SolveArgs a) {
+    __shared__ double ext[kPanelMax];
+    __shared__ __align__(16) double blk[kPanelMax * kPanelMax];
+    for (int item = i0 + blockIdx.x; item < i1; item += gridDim.x) lsolve_item<true>(a, item, ext, blk);
+}
+
+__global__ __launch_bounds__(256) void k_usolve_persistent(int i0, int i1, SolveArgs a) {
+    __shared__ double ext[kPanelMax];
+    __shared__ __align__(16) double blk[kPanelMax * kPanelMax];
+    for (int item = i0 + blockIdx.x; item < i1; item += gridDim.x) usolve_item<true>(a, item, ext, blk);
+}
+
+// bp = r[P] .* b[P]; with mark, every unknown of the persistent mode starts unset
+__global__ void k_solve_reset(int n, const double *__restrict__ b, const double *__restrict__ r,
+                              const int32_t *__restrict__ P, double *__restrict__ bp, double *__restrict__ y,
+                              double *__restrict__ xt, double *__restrict__ psum, double *__restrict__ usum,
+                              int mark) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const double u = __longlong_as_double((long long)kUnset);
     if (i < n) {
-        y[i] = u;
-        xt[i] = u;
-        psum[i] = u;
-    }
-    if (i < 4) st->queue[i] = 0;
-}
-
-__device__ __forceinline__ int next_item(int *queue) {
-    __shared__ int s_item;
-    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
-    __syncthreads();
-    const int item = s_item;
-    __syncthreads();
-    return item;
-}
-
-__global__ __launch_bounds__(256) void k_lsolve_persistent(int i0, int i1, SolveArgs a, int *queue, int *abort) {
-    __shared__ double ext[kPanelMax];
-    __shared__ double blk[kPanelMax * kPanelMax];
-    const int tid = threadIdx.x, lane = tid & 63;
-    for (;;) {
-        const int item = i0 + next_item(queue);
-        if (item >= i1 || __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-        const int np = a.item_np[item], p0 = a.item_p0[item];
-        if (np < 0) {                                    // pack of width-1 panels, 8 lanes each
-            const int g = tid / kPackLanes, gl = tid % kPackLanes;
-            int i = -1, q0 = 0, q1 = 0;
-            if (g < -np) {
-                i = a.pan[p0 + g];
-                q0 = a.rowptr[i];
-                q1 = a.diag[i];
-            }
-            const double acc = row_dot_wait(a, a.y, q0, q1, gl, kPackLanes, abort);
-            if (i >= 0 && gl == 0) publish(a.y + i, a.r[a.P[i]] * a.b[a.P[i]] - acc);
-            continue;
+        const int pi = P[i];
+        bp[i] = r[pi] * b[pi];
+        if (mark) {
+            const double u = __longlong_as_double((long long)kUnset);
+            y[i] = u;
+            xt[i] = u;
+            psum[i] = u;
+            usum[i] = u;
         }
-        const int T = a.pan[p0];
-        const int s = a.pan_start[T], w = a.pan_start[T + 1] - s;
-        const int g = tid >> 5, gl = tid & 31;
-        if (np == 0) {                                   // early partial sums of panel T's rows
-            for (int t = g; t < w; t += kBlock / 32) {
-                const int i = s + t;
-                const double acc = row_dot_wait(a, a.y, a.rowptr[i], a.early[i], gl, 32, abort);
-                if (gl == 0) publish(a.psum + i, acc);
-            }
-            continue;
-        }
-        stage_inpanel(a, s, w, blk);
-        for (int t = g; t < w; t += kBlock / 32) {
-            const int i = s + t;
-            const int e = a.early[i];
-            const double acc = row_dot_wait(a, a.y, e, a.diag[i] - t, gl, 32, abort);
-            if (gl == 0) ext[t] = e > a.rowptr[i] ? acc + wait_value(a.psum + i, abort) : acc;
-        }
-        __syncthreads();
-        if (tid < 64) {
-            double yv = 0.0;
-            if (lane < w) yv = a.r[a.P[s + lane]] * a.b[a.P[s + lane]] - ext[lane];
-            yv = inpanel_forward(blk, w, lane, yv);
-            if (lane < w) publish(a.y + s + lane, yv);
-        }
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(256) void k_usolve_persistent(int i0, int i1, SolveArgs a, int *queue, int *abort) {
-    __shared__ double ext[kPanelMax];
-    __shared__ double blk[kPanelMax * kPanelMax];
-    const int tid = threadIdx.x, lane = tid & 63;
-    for (;;) {
-        const int item = i0 + next_item(queue);
-        if (item >= i1 || __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-        const int np = a.item_np[item], p0 = a.item_p0[item];
-        if (np < 0) {
-            const int g = tid / kPackLanes, gl = tid % kPackLanes;
-            int i = -1, q0 = 0, q1 = 0;
-            if (g < -np) {
-                i = a.pan[p0 + g];
-                q0 = a.diag[i] + 1;
-                q1 = a.rowptr[i + 1];
-            }
-            const double acc = row_dot_wait(a, a.xt, q0, q1, gl, kPackLanes, abort);
-            if (i >= 0 && gl == 0) {
-                const double xv = (a.y[i] - acc) / a.lucsr[a.diag[i]];
-                a.x[a.Q[i]] = a.c[a.Q[i]] * xv;
-                publish(a.xt + i, xv);
-            }
-            continue;
-        }
-        const int T = a.pan[p0];
-        const int s = a.pan_start[T], w = a.pan_start[T + 1] - s;
-        const int g = tid >> 5, gl = tid & 31;
-        stage_inpanel(a, s, w, blk);
-        for (int t = g; t < w; t += kBlock / 32) {
-            const int i = s + t;
-            const double acc = row_dot_wait(a, a.xt, a.diag[i] + (w - t), a.rowptr[i + 1], gl, 32, abort);
-            if (gl == 0) ext[t] = acc;
-        }
-        __syncthreads();
-        if (tid < 64) {
-            double val = 0.0;
-            if (lane < w) val = a.y[s + lane] - ext[lane];
-            const double xv = inpanel_backward(blk, w, lane, val);
-            if (lane < w) {
-                a.x[a.Q[s + lane]] = a.c[a.Q[s + lane]] * xv;
-                publish(a.xt + s + lane, xv);
-            }
-        }
-        __syncthreads();
     }
 }
 

@@ -22,9 +22,9 @@ struct Dev {
     int32_t *f_rel, *ldiag;
     int4 *item8, *pair8;
     unsigned long long *pcount;
-    int32_t *l_item_p0, *l_item_np, *l_pan, *u_item_p0, *u_item_np, *u_pan;
-    int32_t *csr_rowptr, *csr_col, *csr_src, *csr_diag, *csr_early, *P, *Q;
-    double *r, *c, *lu, *lucsr, *y, *xt, *psum, *bsave;
+    int4 *l_item4, *u_item4, *l_rows4, *u_rows4, *rinfo4, *urinfo4;
+    int32_t *csr_col, *csr_src, *P, *Q;
+    double *r, *c, *lu, *lucsr, *y, *xt, *psum, *usum, *bp, *bsave;
     double *V, *Z, *w, *res, *part, *hbuf, *ybuf;
     DevStatus *st;
     ResNorms *rn;
@@ -60,7 +60,7 @@ struct kkt_handle {
     Dev d{};
     const double *d_values = nullptr;
     double *h_small = nullptr;   // pinned host staging for small read-backs
-    int resident_blocks = 1024;  // grid of the persistent solves (blocks of 256 threads)
+    int grid_l = 1, grid_u = 1;  // co-resident blocks of the persistent solve kernels
     // launch profiler
     bool prof = false;
     kkt_profile acc{};
@@ -92,17 +92,14 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.ldiag = c.take<int32_t>(n);
     d.f_rel = c.take<int32_t>(std::max<size_t>(1, g.f_rel.size()));
     d.pcount = c.take<unsigned long long>(kCountSlots);
-    d.l_item_p0 = c.take<int32_t>(g.l_item_p0.size());
-    d.l_item_np = c.take<int32_t>(g.l_item_np.size());
-    d.l_pan = c.take<int32_t>(g.l_pan.size());
-    d.u_item_p0 = c.take<int32_t>(g.u_item_p0.size());
-    d.u_item_np = c.take<int32_t>(g.u_item_np.size());
-    d.u_pan = c.take<int32_t>(g.u_pan.size());
-    d.csr_rowptr = c.take<int32_t>(n + 1);
+    d.l_item4 = c.take<int4>(std::max<size_t>(1, g.l_item4.size() / 4));
+    d.u_item4 = c.take<int4>(std::max<size_t>(1, g.u_item4.size() / 4));
+    d.l_rows4 = c.take<int4>(std::max<size_t>(1, g.l_rows4.size() / 4));
+    d.u_rows4 = c.take<int4>(std::max<size_t>(1, g.u_rows4.size() / 4));
+    d.rinfo4 = c.take<int4>(n);
+    d.urinfo4 = c.take<int4>(n);
     d.csr_col = c.take<int32_t>(nlu);
     d.csr_src = c.take<int32_t>(nlu);
-    d.csr_diag = c.take<int32_t>(n);
-    d.csr_early = c.take<int32_t>(n);
     d.P = c.take<int32_t>(n);
     d.Q = c.take<int32_t>(n);
     d.r = c.take<double>(n);
@@ -112,6 +109,8 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.y = c.take<double>(n);
     d.xt = c.take<double>(n);
     d.psum = c.take<double>(n);
+    d.usum = c.take<double>(n);
+    d.bp = c.take<double>(n);
     d.bsave = c.take<double>(n);
     d.V = c.take<double>((size_t)(m + 1) * n);
     d.Z = c.take<double>((size_t)m * n);
@@ -197,50 +196,50 @@ int upload(T *dst, const std::vector<T> &src, hipStream_t s) {
 }
 
 // x = Q C (L U)^-1 P R b for one column (both in original order)
+// One cooperative launch of a persistent solve kernel over items [i0, i1).
+template <class K>
+hipError_t launch_persistent(K kernel, int grid, int i0, int i1, SolveArgs &a, hipStream_t s) {
+    void *args[] = {&i0, &i1, &a};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kernel), dim3(grid), dim3(kBlock), args, 0, s);
+}
+
 int enqueue_solve(kkt_handle *h, const double *b, double *x, hipStream_t s) {
     const Schedule &g = h->sch;
     const Dev &d = h->d;
-    SolveArgs a{d.pan_start, d.l_item_p0, d.l_item_np, d.l_pan, d.csr_rowptr, d.csr_col, d.csr_diag,
-                d.csr_early, d.P, d.Q, d.lucsr, d.r, d.c, b, d.y, d.xt, x, d.psum};
-    if (h->opts.persistent_solve) {
-        // hybrid: level launches for the wide levels, one persistent launch for the narrow
-        // levels at the top of the tree (last forward levels, first backward levels)
-        const int n = h->sym.n;
-        timed(h, KKT_PROF_LSOLVE, s, [&] { k_solve_reset<<<blocks_for(n, 256), 256, 0, s>>>(n, d.y, d.xt, d.psum, d.st); });
-        for (int l = 0; l < g.l_split; ++l) {
-            const int cnt = g.l_lvl[l + 1] - g.l_lvl[l];
-            if (cnt) timed(h, KKT_PROF_LSOLVE, s, [&] { k_lsolve_level<<<cnt, kBlock, 0, s>>>(g.l_lvl[l], a); });
-        }
-        const int li0 = g.l_lvl[g.l_split], li1 = g.l_lvl.back();
-        if (li1 > li0)
-            timed(h, KKT_PROF_LSOLVE, s, [&] {
-                k_lsolve_persistent<<<std::min(li1 - li0, h->resident_blocks), kBlock, 0, s>>>(
-                    li0, li1, a, &d.st->queue[0], &d.st->abort);
-            });
-        a.item_p0 = d.u_item_p0;
-        a.item_np = d.u_item_np;
-        a.pan = d.u_pan;
-        const int ui1 = g.u_lvl[g.u_split];
-        if (ui1 > 0)
-            timed(h, KKT_PROF_USOLVE, s, [&] {
-                k_usolve_persistent<<<std::min(ui1, h->resident_blocks), kBlock, 0, s>>>(0, ui1, a, &d.st->queue[1],
-                                                                                       &d.st->abort);
-            });
-        for (size_t l = g.u_split; l + 1 < g.u_lvl.size(); ++l) {
-            const int cnt = g.u_lvl[l + 1] - g.u_lvl[l];
-            if (cnt) timed(h, KKT_PROF_USOLVE, s, [&] { k_usolve_level<<<cnt, kBlock, 0, s>>>(g.u_lvl[l], a); });
-        }
-        HIPCHK(hipGetLastError());
-        return KKT_OK;
-    }
-    for (size_t l = 0; l + 1 < g.l_lvl.size(); ++l) {
+    const int n = h->sym.n;
+    const bool pers = h->opts.persistent_solve != 0;
+    SolveArgs a{d.l_item4, d.l_rows4, d.rinfo4, d.csr_col, d.Q, d.lucsr, d.c, d.bp, d.y, d.xt, x, d.psum, d.usum,
+                &d.st->abort};
+    timed(h, KKT_PROF_LSOLVE, s, [&] {
+        k_solve_reset<<<blocks_for(n, 256), 256, 0, s>>>(n, b, d.r, d.P, d.bp, d.y, d.xt, d.psum, d.usum,
+                                                         pers ? 1 : 0);
+    });
+    // forward: level launches below l_split, then the persistent launch
+    const int lsplit = pers ? g.l_split : (int)g.l_lvl.size() - 1;
+    for (int l = 0; l < lsplit; ++l) {
         const int cnt = g.l_lvl[l + 1] - g.l_lvl[l];
         if (cnt) timed(h, KKT_PROF_LSOLVE, s, [&] { k_lsolve_level<<<cnt, kBlock, 0, s>>>(g.l_lvl[l], a); });
     }
-    a.item_p0 = d.u_item_p0;
-    a.item_np = d.u_item_np;
-    a.pan = d.u_pan;
-    for (size_t l = 0; l + 1 < g.u_lvl.size(); ++l) {
+    const int li0 = g.l_lvl[lsplit], li1 = g.l_lvl.back();
+    if (li1 > li0) {
+        hipError_t e = hipSuccess;
+        timed(h, KKT_PROF_LSOLVE, s,
+              [&] { e = launch_persistent(k_lsolve_persistent, std::min(li1 - li0, h->grid_l), li0, li1, a, s); });
+        HIPCHK(e);
+    }
+    // backward: the persistent launch for levels below u_split, then level launches
+    a.item = d.u_item4;
+    a.rows = d.u_rows4;
+    a.rinfo = d.urinfo4;
+    const int usplit = pers ? g.u_split : 0;
+    const int ui1 = g.u_lvl[usplit];
+    if (ui1 > 0) {
+        hipError_t e = hipSuccess;
+        timed(h, KKT_PROF_USOLVE, s,
+              [&] { e = launch_persistent(k_usolve_persistent, std::min(ui1, h->grid_u), 0, ui1, a, s); });
+        HIPCHK(e);
+    }
+    for (size_t l = usplit; l + 1 < g.u_lvl.size(); ++l) {
         const int cnt = g.u_lvl[l + 1] - g.u_lvl[l];
         if (cnt) timed(h, KKT_PROF_USOLVE, s, [&] { k_usolve_level<<<cnt, kBlock, 0, s>>>(g.u_lvl[l], a); });
     }
@@ -460,8 +459,9 @@ int kkt_get_stats(const kkt_handle *h, kkt_stats *out) {
     out->gpu_levels_f = (int32_t)h->sch.f_lvl.size() - 1;
     out->gpu_levels_l = (int32_t)h->sch.l_lvl.size() - 1;
     out->gpu_levels_u = (int32_t)h->sch.u_lvl.size() - 1;
-    out->persistent_levels_l = out->gpu_levels_l - h->sch.l_split;
-    out->persistent_levels_u = h->sch.u_split;
+    const bool pers = h->opts.persistent_solve != 0;
+    out->persistent_levels_l = pers ? out->gpu_levels_l - h->sch.l_split : 0;
+    out->persistent_levels_u = pers ? h->sch.u_split : 0;
     out->flops_refactor = h->sch.flops;
     return KKT_OK;
 }
@@ -507,7 +507,17 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_refactor_large),
                                hipFuncAttributeMaxDynamicSharedMemorySize, kLargeLds));
-    h->resident_blocks = std::max(1, ncu) * 4;
+    {
+        int coop = 0, bl = 0, bu = 0;
+        HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        if (!coop && h->opts.persistent_solve) return KKT_ERR_DEVICE;
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bl, reinterpret_cast<const void *>(&k_lsolve_persistent),
+                                                            kBlock, 0));
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bu, reinterpret_cast<const void *>(&k_usolve_persistent),
+                                                            kBlock, 0));
+        h->grid_l = std::max(1, bl) * std::max(1, ncu);
+        h->grid_u = std::max(1, bu) * std::max(1, ncu);
+    }
     if (!h->h_small) HIPCHK(hipHostMalloc(&h->h_small, sizeof(double) * 4 * (kMaxRestart + 2) + 256));
     carve(h, static_cast<char *>(d_workspace), h->d, &need);
     const Symbolic &s = h->sym;
@@ -534,17 +544,14 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     rc |= upload(reinterpret_cast<int32_t *>(d.pair8), g.pair8, stream);
     rc |= upload(d.ldiag, g.ldiag, stream);
     rc |= upload(d.f_rel, g.f_rel, stream);
-    rc |= upload(d.l_item_p0, g.l_item_p0, stream);
-    rc |= upload(d.l_item_np, g.l_item_np, stream);
-    rc |= upload(d.l_pan, g.l_pan, stream);
-    rc |= upload(d.u_item_p0, g.u_item_p0, stream);
-    rc |= upload(d.u_item_np, g.u_item_np, stream);
-    rc |= upload(d.u_pan, g.u_pan, stream);
-    rc |= upload(d.csr_rowptr, g.csr_rowptr, stream);
+    rc |= upload(reinterpret_cast<int32_t *>(d.l_item4), g.l_item4, stream);
+    rc |= upload(reinterpret_cast<int32_t *>(d.u_item4), g.u_item4, stream);
+    rc |= upload(reinterpret_cast<int32_t *>(d.l_rows4), g.l_rows4, stream);
+    rc |= upload(reinterpret_cast<int32_t *>(d.u_rows4), g.u_rows4, stream);
+    rc |= upload(reinterpret_cast<int32_t *>(d.rinfo4), g.rinfo4, stream);
+    rc |= upload(reinterpret_cast<int32_t *>(d.urinfo4), g.urinfo4, stream);
     rc |= upload(d.csr_col, g.csr_col, stream);
     rc |= upload(d.csr_src, g.csr_src, stream);
-    rc |= upload(d.csr_diag, g.csr_diag, stream);
-    rc |= upload(d.csr_early, g.csr_early, stream);
     rc |= upload(d.P, s.P, stream);
     rc |= upload(d.Q, s.Q, stream);
     if (rc) return KKT_ERR_DEVICE;

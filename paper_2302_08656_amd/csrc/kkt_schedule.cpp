@@ -249,56 +249,80 @@ int build_schedule(const Symbolic &s, Schedule &g) {
             const int32_t T = pan_of[s.rowidx[p]], S = pan_of[j];
             if (T != S) ulev[T] = std::max(ulev[T], ulev[S] + 1);
         }
-    // forward-solve helpers: a wide panel T at level >= 2 with early columns gets a helper
-    // item at level llev[T] - 1
-    std::vector<char> has_helper(np, 0);
+    // solve helpers: a wide panel T (more than kPackW columns) of a triangle with a row of at
+    // least kHelpMin early entries (external entries in panels more than kHelpAhead levels
+    // below T) gets helper items at level lev[T] - kHelpAhead that sum those entries
+    std::vector<char> has_lhelp(np, 0), has_uhelp(np, 0);
     {
-        for (int32_t j = 0; j < n; ++j)
+        std::vector<int32_t> lcnt(n, 0), ucnt(n, 0);
+        for (int32_t j = 0; j < n; ++j) {
+            const int32_t S = pan_of[j];
             for (int64_t p = lbeg(j); p < s.colptr[j + 1]; ++p) {
-                const int32_t T = pan_of[s.rowidx[p]], S = pan_of[j];
-                if (T != S && pw(T) > 1 && llev[T] >= 2 && llev[S] <= llev[T] - 2) has_helper[T] = 1;
+                const int32_t i = s.rowidx[p], T = pan_of[i];
+                if (T != S && pw(T) > kPackW && llev[S] < llev[T] - kHelpAhead) lcnt[i]++;
             }
+            for (int64_t p = s.colptr[j]; p < s.colptr[j] + s.ulen[j]; ++p) {
+                const int32_t i = s.rowidx[p], T = pan_of[i];
+                if (T != S && pw(T) > kPackW && ulev[S] < ulev[T] - kHelpAhead) ucnt[i]++;
+            }
+        }
+        for (int32_t i = 0; i < n; ++i) {
+            if (lcnt[i] >= kHelpMin) has_lhelp[pan_of[i]] = 1;
+            if (ucnt[i] >= kHelpMin) has_uhelp[pan_of[i]] = 1;
+        }
     }
-    auto build_solve = [&](const std::vector<int32_t> &lev, std::vector<int32_t> &lvl,
-                           std::vector<int32_t> &p0, std::vector<int32_t> &cnt, std::vector<int32_t> &pan,
-                           bool helpers) {
+    // solve items; pack rows hold the row index only until the CSR copy exists
+    auto build_solve = [&](const std::vector<int32_t> &lev, std::vector<int32_t> &lvl, std::vector<int32_t> &item4,
+                           std::vector<int32_t> &rows4, const std::vector<char> &has_helper) {
         const int32_t nl = np ? 1 + *std::max_element(lev.begin(), lev.end()) : 0;
         std::vector<std::vector<int32_t>> at(nl), help(nl);
         for (int32_t p = 0; p < np; ++p) {
             at[lev[p]].push_back(p);
-            if (helpers && has_helper[p]) help[lev[p] - 1].push_back(p);
+            if (has_helper[p]) help[lev[p] - kHelpAhead].push_back(p);
         }
         lvl.assign(1, 0);
-        p0.clear();
-        cnt.clear();
-        pan.clear();
+        item4.clear();
+        rows4.clear();
+        auto push = [&](int32_t a, int32_t b, int32_t c, int32_t d) {
+            item4.push_back(a);
+            item4.push_back(b);
+            item4.push_back(c);
+            item4.push_back(d);
+        };
         for (int32_t l = 0; l < nl; ++l) {
-            for (int32_t p : help[l]) {
-                p0.push_back((int32_t)pan.size());
-                cnt.push_back(0);      // zero: partial sums of the early columns of panel p
-                pan.push_back(p);
+            for (int32_t p : help[l])
+                for (int32_t t0 = 0; t0 < pw(p); t0 += kHelpRows) push(0, t0, g.pan_start[p], pw(p));
+            std::vector<int32_t> wide, small;
+            for (int32_t p : at[l]) (pw(p) > kPackW ? wide : small).push_back(p);
+            std::stable_sort(wide.begin(), wide.end(), [&](int32_t a, int32_t b) { return pw(a) > pw(b); });
+            // lanes per row: the largest power of two that fits the item's rows in 256 threads,
+            // at most one wavefront
+            auto lanes_for = [](int32_t rows) {
+                int32_t l = 64;
+                while (l * rows > 256) l >>= 1;
+                return l;
+            };
+            for (int32_t p : wide) push(1, lanes_for(pw(p)), g.pan_start[p], pw(p));
+            // whole small panels, at most kSolvePack rows per pack
+            for (size_t q = 0; q < small.size();) {
+                const int32_t off = (int32_t)(rows4.size() / 4);
+                int32_t c = 0;
+                while (q < small.size() && c + pw(small[q]) <= kSolvePack) {
+                    const int32_t p = small[q++];
+                    for (int32_t t = 0; t < pw(p); ++t, ++c) {
+                        rows4.push_back(g.pan_start[p] + t);
+                        rows4.push_back(0);
+                        rows4.push_back(0);
+                        rows4.push_back(t | pw(p) << 8);
+                    }
+                }
+                push(-c, off, lanes_for(c), 0);
             }
-            std::vector<int32_t> wide, narrow;
-            for (int32_t p : at[l]) (g.pan_start[p + 1] - g.pan_start[p] > 1 ? wide : narrow).push_back(p);
-            std::stable_sort(wide.begin(), wide.end(), [&](int32_t a, int32_t b) {
-                return g.pan_start[a + 1] - g.pan_start[a] > g.pan_start[b + 1] - g.pan_start[b];
-            });
-            for (int32_t p : wide) {
-                p0.push_back((int32_t)pan.size());
-                cnt.push_back(1);
-                pan.push_back(p);
-            }
-            for (size_t q = 0; q < narrow.size(); q += kSolvePack) {
-                const int32_t c = (int32_t)std::min<size_t>(kSolvePack, narrow.size() - q);
-                p0.push_back((int32_t)pan.size());
-                cnt.push_back(-c);     // negative: a pack of width-1 panels
-                for (int32_t t = 0; t < c; ++t) pan.push_back(g.pan_start[narrow[q + t]]);   // rows
-            }
-            lvl.push_back((int32_t)p0.size());
+            lvl.push_back((int32_t)(item4.size() / 4));
         }
     };
-    build_solve(llev, g.l_lvl, g.l_item_p0, g.l_item_np, g.l_pan, true);
-    build_solve(ulev, g.u_lvl, g.u_item_p0, g.u_item_np, g.u_pan, false);
+    build_solve(llev, g.l_lvl, g.l_item4, g.l_rows4, has_lhelp);
+    build_solve(ulev, g.u_lvl, g.u_item4, g.u_rows4, has_uhelp);
     {
         const int32_t nl = (int32_t)g.l_lvl.size() - 1, nu = (int32_t)g.u_lvl.size() - 1;
         g.l_split = nl;
@@ -324,32 +348,66 @@ int build_schedule(const Symbolic &s, Schedule &g) {
                 if (i == j) g.csr_diag[i] = q;
             }
     }
-    // early | late | in-panel order of the L entries of rows of helped panels
+    // rows of helped panels list their external L entries as [early | late] (before the
+    // in-panel part) and their external U entries as [late | early] (after it)
     g.csr_early.assign(g.csr_rowptr.begin(), g.csr_rowptr.end() - 1);
+    g.csr_uearly.assign(g.csr_rowptr.begin() + 1, g.csr_rowptr.end());
     {
         std::vector<int32_t> tc, ts;
-        for (int32_t T = 0; T < np; ++T) {
-            if (!has_helper[T]) continue;
-            const int32_t sp = g.pan_start[T];
-            for (int32_t i = sp; i < g.pan_start[T + 1]; ++i) {
-                const int32_t q0 = g.csr_rowptr[i], q1 = g.csr_diag[i] - (i - sp);   // external part
-                tc.clear();
-                ts.clear();
-                for (int pass = 0; pass < 2; ++pass)
-                    for (int32_t q = q0; q < q1; ++q) {
-                        const bool early = llev[pan_of[g.csr_col[q]]] <= llev[T] - 2;
-                        if (early == (pass == 0)) {
-                            tc.push_back(g.csr_col[q]);
-                            ts.push_back(g.csr_src[q]);
-                        }
+        auto split = [&](int32_t q0, int32_t q1, int32_t T, const std::vector<int32_t> &lev, bool early_first) {
+            tc.clear();
+            ts.clear();
+            int32_t ne = 0;
+            for (int pass = 0; pass < 2; ++pass)
+                for (int32_t q = q0; q < q1; ++q) {
+                    const bool early = lev[pan_of[g.csr_col[q]]] < lev[T] - kHelpAhead;
+                    ne += pass == 0 && early;
+                    if (early == ((pass == 0) == early_first)) {
+                        tc.push_back(g.csr_col[q]);
+                        ts.push_back(g.csr_src[q]);
                     }
-                int32_t ne = 0;
-                for (int32_t q = q0; q < q1; ++q) ne += llev[pan_of[g.csr_col[q]]] <= llev[T] - 2;
-                std::copy(tc.begin(), tc.end(), g.csr_col.begin() + q0);
-                std::copy(ts.begin(), ts.end(), g.csr_src.begin() + q0);
-                g.csr_early[i] = q0 + ne;
+                }
+            std::copy(tc.begin(), tc.end(), g.csr_col.begin() + q0);
+            std::copy(ts.begin(), ts.end(), g.csr_src.begin() + q0);
+            return ne;
+        };
+        for (int32_t T = 0; T < np; ++T) {
+            const int32_t sp = g.pan_start[T], w = pw(T);
+            for (int32_t i = sp; i < sp + w; ++i) {
+                const int32_t t = i - sp;
+                if (has_lhelp[T]) {
+                    const int32_t q0 = g.csr_rowptr[i], q1 = g.csr_diag[i] - t;
+                    g.csr_early[i] = q0 + split(q0, q1, T, llev, true);
+                }
+                if (has_uhelp[T]) {
+                    const int32_t q0 = g.csr_diag[i] + (w - t), q1 = g.csr_rowptr[i + 1];
+                    g.csr_uearly[i] = q1 - split(q0, q1, T, ulev, false);
+                }
             }
         }
+    }
+    // per-row records and the external ranges of pack rows
+    g.rinfo4.resize(4 * (size_t)n);
+    g.urinfo4.resize(4 * (size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        g.rinfo4[4 * (size_t)i] = g.csr_rowptr[i];
+        g.rinfo4[4 * (size_t)i + 1] = g.csr_early[i];
+        g.rinfo4[4 * (size_t)i + 2] = g.csr_diag[i];
+        g.rinfo4[4 * (size_t)i + 3] = g.csr_rowptr[i + 1];
+        g.urinfo4[4 * (size_t)i] = g.csr_diag[i];
+        g.urinfo4[4 * (size_t)i + 1] = g.csr_uearly[i];
+        g.urinfo4[4 * (size_t)i + 2] = g.csr_rowptr[i + 1];
+        g.urinfo4[4 * (size_t)i + 3] = 0;
+    }
+    for (size_t k = 0; k < g.l_rows4.size(); k += 4) {
+        const int32_t i = g.l_rows4[k], t = g.l_rows4[k + 3] & 255;
+        g.l_rows4[k + 1] = g.csr_rowptr[i];
+        g.l_rows4[k + 2] = g.csr_diag[i] - t;
+    }
+    for (size_t k = 0; k < g.u_rows4.size(); k += 4) {
+        const int32_t i = g.u_rows4[k], t = g.u_rows4[k + 3] & 255, w = g.u_rows4[k + 3] >> 8;
+        g.u_rows4[k + 1] = g.csr_diag[i] + (w - t);
+        g.u_rows4[k + 2] = g.csr_rowptr[i + 1];
     }
     // value update map and CSC view of A
     g.lu_src.assign(nlu, -1);
