@@ -132,7 +132,10 @@ int kkt_workspace_bytes(const kkt_handle *h, int32_t max_nrhs, size_t *bytes);
 
 /* Setup (Algorithm 1, set up the GPU refactorization): uploads the symbolic structure and
  * schedules into d_workspace (device, >= kkt_workspace_bytes, 256-byte aligned) on stream
- * and records the device.  Waits for the upload.  Errors: ARG, NOMEM (too small), DEVICE. */
+ * and records the device; the first bind also creates the handle's internal second stream
+ * (used inside kkt_refactor, always joined back into the caller's stream).  A handle stays
+ * on its first device: binding again on another one returns STATE.  Waits for the upload.
+ * Errors: ARG, NOMEM (too small), STATE, DEVICE. */
 int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs,
              hipStream_t stream);
 

@@ -441,48 +441,62 @@ __device__ __forceinline__ void load_row(double (&x)[kPanelMax], const double *l
     }
 }
 
-// Dense LU without pivoting of a wide panel's block column: the diagonal block in the
-// registers of wavefront 0 (lane = row), every row below on its own thread.  The first
-// row below each thread is loaded before the diagonal block is factored.  sgs[c] = slot
-// of row s in column s + c (staged by the caller).  Us[j * kPanelMax + c] = U(j, j + c),
-// zero past the panel.
+// One step j of the panel sweep on a row (shifted, KW columns): the pivot row's entries
+// U(j, j + c) are read from LDS in one round; the row's multiplier is stored.
+template <int KW>
+__device__ __forceinline__ void sweep_step(double (&x)[kPanelMax], const double *urow, double *dst, int &bad) {
+    double rw[kPanelMax];
+    load_lds_row<KW>(rw, urow);
+    __builtin_amdgcn_sched_barrier(0);
+    const double l = x[0] / rw[0];
+    bad |= !isfinite(l);
+    *dst = l;
+    shift_fma<KW>(x, l, rw);
+}
+
+// Dense LU without pivoting of a wide panel's block column (w + r rows, w columns).  Thread
+// t owns panel row t (t < w: the diagonal block; below: the L rows) for t < kBigThreads;
+// step j: the owner of row j perturbs its pivot and publishes U(j, j..) in LDS
+// (Us[j * kPanelMax + c] = U(j, j + c), zero past the panel), then after one barrier every
+// later row takes its multiplier and update from it.  The sweep narrows from KW to
+// KW / 2 register columns once no more than KW / 2 columns remain.  Rows beyond the
+// first kBigThreads are eliminated afterwards from the finished Us.  sgs[c] = slot of row s
+// in column s + c (staged by the caller); row t of the panel is at slot sgs[c] + t.
 template <int KW>
 __device__ __forceinline__ void large_factor_w(const RefArgs &a, int w, int r, char *sm, double thresh,
                                                int item) {
     const int tid = threadIdx.x, lane = tid & 63;
     double *Us = reinterpret_cast<double *>(sm + kOffLd);
     const int *sgs = reinterpret_cast<const int *>(sm + kOffSgs);
+    const int nrow = w + r;
     int npert = 0, bad = 0;
     double x[kPanelMax];
-    if (tid < r) load_row<KW>(x, a.lu, sgs, w, w + tid);
-    if (tid < 64) {
-        double d[kPanelMax];
-        load_row<KW>(d, a.lu, sgs, w, min(lane, w - 1));
-        if (lane >= w)
 #pragma unroll
-            for (int c = 0; c < KW; ++c) d[c] = 0.0;
+    for (int c = 0; c < kPanelMax; ++c) x[c] = 0.0;
+    if (tid < nrow) load_row<KW>(x, a.lu, sgs, w, tid);
+    constexpr int KH = KW / 2;
+    const int jsplit = max(0, w - KH);          // steps with more than KH columns left
 #pragma unroll 1
-        for (int j = 0; j < w; ++j) {
-            // lane j holds row j from column j on: it publishes the (perturbed) pivot and
-            // U(j, j + c) in LDS, and the wavefront reads the row back
-            if (lane == j) {
-                d[0] = perturb(d[0], thresh, npert);
-                double2 *o = reinterpret_cast<double2 *>(Us + j * kPanelMax);
+    for (int j = 0; j < w; ++j) {
+        if (tid == j) {
+            x[0] = perturb(x[0], thresh, npert);
+            double2 *o = reinterpret_cast<double2 *>(Us + j * kPanelMax);
+            if (j < jsplit) {
 #pragma unroll
-                for (int c = 0; c < KW / 2; ++c) o[c] = double2{d[2 * c], d[2 * c + 1]};
+                for (int c = 0; c < KW / 2; ++c) o[c] = double2{x[2 * c], x[2 * c + 1]};
+            } else {
+#pragma unroll
+                for (int c = 0; c < KH / 2; ++c) o[c] = double2{x[2 * c], x[2 * c + 1]};
+#pragma unroll
+                for (int c = KH / 2; c < KW / 2; ++c) o[c] = double2{0.0, 0.0};
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            double rw[kPanelMax];
-            load_lds_row<KW>(rw, Us + j * kPanelMax);
-            __builtin_amdgcn_sched_barrier(0);
-            const double p = rw[0];
-            bad |= !isfinite(p);
-            const double l = d[0] / p;
-            if (lane > j && lane < w) a.lu[sgs[j] + lane] = l;
-            // rows below j; rows at or above j are complete and their registers unused
-            shift_fma<KW>(d, l, rw);
+        }
+        __syncthreads();
+        if (tid == 0) bad |= !isfinite(Us[j * kPanelMax]);
+        if (tid > j && tid < nrow) {
+            double *dst = a.lu + sgs[j] + tid;
+            if (j < jsplit) sweep_step<KW>(x, Us + j * kPanelMax, dst, bad);
+            else sweep_step<KH>(x, Us + j * kPanelMax, dst, bad);
         }
     }
     KKT_PHASE(item, 6);
@@ -493,20 +507,13 @@ __device__ __forceinline__ void large_factor_w(const RefArgs &a, int w, int r, c
         const int j = t / KW, c = t % KW;
         if (j + c < w) a.lu[sgs[j + c] + j] = Us[j * kPanelMax + c];
     }
-    for (int i = tid; i < r; i += kBigThreads) {
-        if (i != tid) load_row<KW>(x, a.lu, sgs, w, w + i);
+    // rows beyond the threads of the block
+    for (int i = tid + kBigThreads; i < nrow; i += kBigThreads) {
+        load_row<KW>(x, a.lu, sgs, w, i);
 #pragma unroll 1
-        for (int j = 0; j < w; ++j) {
-            double rw[kPanelMax];
-            load_lds_row<KW>(rw, Us + j * kPanelMax);
-            __builtin_amdgcn_sched_barrier(0);
-            const double l = x[0] / rw[0];
-            bad |= !isfinite(l);
-            a.lu[sgs[j] + w + i] = l;
-            shift_fma<KW>(x, l, rw);
-        }
+        for (int j = 0; j < w; ++j) sweep_step<KW>(x, Us + j * kPanelMax, a.lu + sgs[j] + i, bad);
     }
-    if (npert) atomicAdd(&a.pcount[blockIdx.x % kCountSlots], (unsigned long long)npert);   // lane j counts pivot j
+    if (npert) atomicAdd(&a.pcount[blockIdx.x % kCountSlots], (unsigned long long)npert);   // row j counts pivot j
     if (__any(bad) && lane == 0) atomicOr(&a.st->flags, kFlagNonfinite);
 }
 

@@ -61,6 +61,10 @@ struct kkt_handle {
     const double *d_values = nullptr;
     double *h_small = nullptr;   // pinned host staging for small read-backs
     int grid_l = 1, grid_u = 1;  // co-resident blocks of the persistent solve kernels
+    // second stream of the refactorization: the narrow and the wide items of one level run
+    // concurrently, joined by a pair of events per level
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // launch profiler
     bool prof = false;
     kkt_profile acc{};
@@ -270,12 +274,24 @@ int enqueue_refactor(kkt_handle *h, const double *v, hipStream_t s) {
               h->opts.tiny_pivot, h->opts.dense_mfma != 0};
     for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
         const int nl = g.f_nlarge[l], ns = g.f_lvl[l + 1] - g.f_lvl[l] - nl;
+        // the two kinds of items of a level touch disjoint target columns: with both present
+        // the narrow ones run on the side stream, forked after and joined before the level
+        const bool both = nl && ns;
+        hipStream_t ss = both ? h->side : s;
+        if (both) {
+            HIPCHK(hipEventRecord(h->ev_fork, s));
+            HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+        }
         if (nl)
             timed(h, KKT_PROF_REFACTOR_LARGE, s, [&] { k_refactor_large<<<nl, kBigThreads, kLargeLds, s>>>(g.f_lvl[l], a); });
         if (ns)
-            timed(h, KKT_PROF_REFACTOR_SMALL, s, [&] {
-                k_refactor_small<<<blocks_for(ns, kBlock / 16), kBlock, 0, s>>>(g.f_lvl[l] + nl, ns, a);
+            timed(h, KKT_PROF_REFACTOR_SMALL, ss, [&] {
+                k_refactor_small<<<blocks_for(ns, kBlock / 16), kBlock, 0, ss>>>(g.f_lvl[l] + nl, ns, a);
             });
+        if (both) {
+            HIPCHK(hipEventRecord(h->ev_join, h->side));
+            HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
+        }
     }
     timed(h, KKT_PROF_TO_CSR, s, [&] { k_to_csr<<<blocks_for(nlu, 256), 256, 0, s>>>(nlu, d.csr_src, d.lu, d.lucsr); });
     timed(h, KKT_PROF_UPDATE, s, [&] { k_sum_counts<<<1, 256, 0, s>>>(d.pcount, &d.st->perturbed); });
@@ -519,6 +535,12 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
         h->grid_u = std::max(1, bu) * std::max(1, ncu);
     }
     if (!h->h_small) HIPCHK(hipHostMalloc(&h->h_small, sizeof(double) * 4 * (kMaxRestart + 2) + 256));
+    if (h->side && h->device != dev) return KKT_ERR_STATE;   // rebinding keeps the device
+    if (!h->side) {
+        HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    }
     carve(h, static_cast<char *>(d_workspace), h->d, &need);
     const Symbolic &s = h->sym;
     const Schedule &g = h->sch;
@@ -665,6 +687,13 @@ int kkt_profile_read(kkt_handle *h, kkt_profile *out, hipStream_t stream) {
 void kkt_destroy(kkt_handle *h) {
     if (!h) return;
     if (h->h_small) (void)hipHostFree(h->h_small);
+    if (h->side) {
+        DeviceGuard g(h->device);
+        (void)hipStreamSynchronize(h->side);
+        (void)hipStreamDestroy(h->side);
+        (void)hipEventDestroy(h->ev_fork);
+        (void)hipEventDestroy(h->ev_join);
+    }
     for (auto &pe : h->ev_pending) h->ev_free.push_back(pe.second);
     for (auto &ev : h->ev_free) {
         (void)hipEventDestroy(ev.first);
