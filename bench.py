@@ -127,29 +127,34 @@ def main():
     cols = np.repeat(np.arange(q.n), np.diff(sym["colptr"]))
     nnz_l = int(np.count_nonzero(sym["rowidx"] > cols))
     nnz_u = st["nnz_lu"] - q.n - nnz_l
-    # algorithmic bytes per unit of each class (int32 indices, FP64 values)
+    # algorithmic bytes per unit of work of each kernel class (int32 indices, FP64 values):
+    # refactorization: every factor value of the columns a class factors read and written
+    # once; solves: factor values + column indices, pointers and the vectors they touch;
+    # value update: A's values and map, the factor written, scale vectors; CSR copy: read
+    # slot index, read and write the value
     per_unit = {
-        "refactor_large": None, "refactor_small": None,
-        "refactor": 16 * st["nnz_lu"] * nprof,                       # every factor value read + written once
-        "lsolve": (12 * nnz_l + 48 * q.n) * solves,                  # L values + columns, pointers, b, r, P, y
-        "usolve": (12 * (nnz_u + q.n) + 48 * q.n) * solves,          # U values + columns, pointers, y, x, c, Q
+        "refactor_large": 16 * st["nnz_lu_wide"] * nprof,
+        "refactor_small": 16 * (st["nnz_lu"] - st["nnz_lu_wide"]) * nprof,
+        "lsolve": (12 * nnz_l + 48 * q.n) * solves,
+        "usolve": (12 * (nnz_u + q.n) + 48 * q.n) * solves,
         "to_csr": 20 * st["nnz_lu"] * nprof,
         "update": (12 * q.nnz + 12 * st["nnz_lu"] + 40 * q.n) * nprof,
     }
-    prof["refactor"] = (prof["refactor_large"][0] + prof["refactor_small"][0],
-                        prof["refactor_large"][1] + prof["refactor_small"][1])
-    ranked = sorted((v[1], k) for k, v in prof.items() if k not in ("refactor_large", "refactor_small"))
+    kernel_of = {"refactor_large": "k_refactor_large", "refactor_small": "k_refactor_small",
+                 "lsolve": "k_lsolve_persistent", "usolve": "k_usolve_persistent", "to_csr": "k_to_csr",
+                 "update": "k_row_scale..k_gather_lu", "residual": "k_residual/k_spmv", "krylov": "krylov"}
+    ranked = sorted((v[1], k) for k, v in prof.items())
     dom = ranked[-1][1]
     launches, ms = prof[dom]
-    if per_unit.get(dom):
+    if per_unit.get(dom) and launches:
         ach = per_unit[dom] / (ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(ach, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 6), "traffic": None,
-                    "kernel": dom, "launches": launches, "avg_launch_us": round(ms / launches * 1e3, 3),
+                    "kernel": kernel_of[dom], "launches": launches, "avg_launch_us": round(ms / launches * 1e3, 3),
                     "bytes_per_launch": per_unit[dom] // launches}
     else:
         roofline = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
-                    "traffic": None, "kernel": dom}
+                    "traffic": None, "kernel": kernel_of.get(dom, dom)}
     breakdown = {k: {"launches_per_unit": round(v[0] / nprof, 2), "ms_per_unit": round(v[1] / nprof, 4)}
                  for k, v in prof.items()}
 

@@ -101,6 +101,7 @@ typedef struct {
     int32_t persistent_levels_l; /* forward levels run by the persistent launch */
     int32_t persistent_levels_u; /* backward levels run by the persistent launch */
     double flops_refactor;      /* sum_k 2 |L(:,k)| |U(k,:)| + |L(:,k)| */
+    int64_t nnz_lu_wide;        /* L+U entries of the columns factored by wide-panel items */
 } kkt_stats;
 
 /* Fills *o with the defaults listed in kkt_opts. */

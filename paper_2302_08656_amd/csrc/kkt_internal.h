@@ -112,6 +112,7 @@ struct Schedule {
     // CSC view of A's pattern (positions into the CSR value array)
     std::vector<int32_t> a_cptr, a_cpos, a_rowid;
     double flops = 0.0;
+    int64_t nnz_lu_wide = 0;            // L+U entries of columns factored by wide-path items
 };
 
 int build_schedule(const Symbolic &s, Schedule &g);

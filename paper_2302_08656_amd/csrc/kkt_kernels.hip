@@ -593,10 +593,42 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
         }
         __syncthreads();
         KKT_PHASE(item, 2);
+        // Update of the rows R of each target by S on the matrix cores (more than one target):
+        // the block Lr (nr x w) times the solved rows (w x m) in 16x16 output tiles, k in steps
+        // of 4; lane holds A[lane % 16][lane / 16], B[lane / 16][lane % 16] and the four outputs
+        // D[lane / 16 + 4 v][lane % 16].  Wavefronts 1.. own the tiles, kTiles at a time; for
+        // the first pass of the first chunk they load the destination slots and current values
+        // while wavefront 0 solves the targets' rows of S.
+        constexpr int kTiles = 4;
+        const int m = g1 - g0;
+        const bool mf = a.use_mfma && m > 1;
+        const int nt = (m + 15) >> 4;
+        const int li = lane & 15, lk = lane >> 4;
+        auto tile_slots = [&](int tile, int mt, int nr, int i0, int (&sl)[4]) {
+            const int ti = tile % mt, tt = tile / mt, tb = tt * 16 + li;
+            const bool ok = tile < mt * nt && tb < m;
+            const int32_t *rel = ok ? a.rel + pra(g0 + tb).z + i0 : a.rel;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = ti * 16 + lk + 4 * v;
+                sl[v] = (ok && i < nr) ? rel[i] : -1;
+            }
+        };
+        int pslot[kTiles][4];
+        double pcur[kTiles][4];
+        const int mt0 = (min(kRChunk, r) + 15) >> 4;
+        if (mf && wv > 0) {
+#pragma unroll
+            for (int k = 0; k < kTiles; ++k) tile_slots((wv - 1) * kTiles + k, mt0, min(kRChunk, r), 0, pslot[k]);
+#pragma unroll
+            for (int k = 0; k < kTiles; ++k)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) pcur[k][v] = pslot[k][v] >= 0 ? a.lu[pslot[k][v]] : 0.0;
+        }
         // rows of S in each target: unit lower solve with S's diagonal block, one lane per
         // target (wavefront 0; a group holds at most kGroup targets); the lane keeps its
         // target's rows in registers
-        if (wv == 0 && lane < g1 - g0) {
+        if (wv == 0 && lane < m) {
             const int ps = pra(g0 + lane).y;
             double *ub = Ub + lane * kPanelMax;
             if (w > 16) unit_lower_w<32>(a.lu, ps, w, Ld, ub, item);
@@ -615,56 +647,54 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
                 }
                 __syncthreads();
             }
-            const int m = g1 - g0;
-            if (a.use_mfma && m > 1) {
-                // update block Lr (nr x w) times the solved rows (w x m) on the matrix cores:
-                // 16x16 output tiles, k in steps of 4; lane holds A[lane % 16][lane / 16],
-                // B[lane / 16][lane % 16] and the four outputs D[lane / 16 + 4 v][lane % 16].
-                // Each wavefront computes up to kTiles tiles, then loads all their slots and
-                // current values in one round before writing them back.
-                constexpr int kTiles = 4;
-                const int mt = (nr + 15) >> 4, nt = (m + 15) >> 4;
-                const int li = lane & 15, lk = lane >> 4;
-                for (int tile0 = wv * kTiles; tile0 < mt * nt; tile0 += nw * kTiles) {
-                    double4_t acc[kTiles];
-                    int slot[kTiles][4];
-                    double cur[kTiles][4];
+            if (mf) {
+                const int mt = (nr + 15) >> 4;
+                if (wv > 0) {
+                    for (int tile0 = (wv - 1) * kTiles, pass = 0; tile0 < mt * nt;
+                         tile0 += (nw - 1) * kTiles, ++pass) {
+                        double4_t acc[kTiles];
 #pragma unroll
-                    for (int k = 0; k < kTiles; ++k) {
-                        const int tile = tile0 + k;
-                        acc[k] = double4_t{0.0, 0.0, 0.0, 0.0};
-                        if (tile < mt * nt) {
-                            const int ti = tile % mt, tt = tile / mt;
-                            const int ia2 = ti * 16 + li, tb = tt * 16 + li;
-                            for (int k0 = 0; k0 < w; k0 += 4) {
-                                const int kk = k0 + lk;
-                                const double av = (kk < w && ia2 < nr) ? Lr[kk * kRChunk + ia2] : 0.0;
-                                const double bv = (kk < w && tb < m) ? Ub[tb * kPanelMax + kk] : 0.0;
-                                acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[k], 0, 0, 0);
+                        for (int k = 0; k < kTiles; ++k) acc[k] = double4_t{0.0, 0.0, 0.0, 0.0};
+                        for (int k0 = 0; k0 < w; k0 += 4) {
+                            const int kk = k0 + lk;
+                            double av[kTiles], bv[kTiles];
+#pragma unroll
+                            for (int k = 0; k < kTiles; ++k) {
+                                const int tile = tile0 + k;
+                                const int ti = tile % mt, tt = tile / mt;
+                                const int ia2 = ti * 16 + li, tb = tt * 16 + li;
+                                const bool ok = tile < mt * nt && kk < w;
+                                av[k] = (ok && ia2 < nr) ? Lr[kk * kRChunk + ia2] : 0.0;
+                                bv[k] = (ok && tb < m) ? Ub[tb * kPanelMax + kk] : 0.0;
                             }
+#pragma unroll
+                            for (int k = 0; k < kTiles; ++k)
+                                acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[k], bv[k], acc[k], 0, 0, 0);
                         }
-                    }
+                        int slot[kTiles][4];
+                        double cur[kTiles][4];
+                        if (i0 == 0 && pass == 0) {
 #pragma unroll
-                    for (int k = 0; k < kTiles; ++k) {
-                        const int tile = tile0 + k;
-                        const int ti = tile % mt, tt = tile / mt, tb = tt * 16 + li;
-                        const bool ok = tile < mt * nt && tb < m;
-                        const int32_t *rel = ok ? a.rel + pra(g0 + tb).z + i0 : a.rel;
+                            for (int k = 0; k < kTiles; ++k)
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int i = ti * 16 + lk + 4 * v;
-                            slot[k][v] = (ok && i < nr) ? rel[i] : -1;
+                                for (int v = 0; v < 4; ++v) {
+                                    slot[k][v] = pslot[k][v];
+                                    cur[k][v] = pcur[k][v];
+                                }
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < kTiles; ++k) tile_slots(tile0 + k, mt, nr, i0, slot[k]);
+#pragma unroll
+                            for (int k = 0; k < kTiles; ++k)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) cur[k][v] = slot[k][v] >= 0 ? a.lu[slot[k][v]] : 0.0;
                         }
+#pragma unroll
+                        for (int k = 0; k < kTiles; ++k)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v)
+                                if (slot[k][v] >= 0) a.lu[slot[k][v]] = cur[k][v] - acc[k][v];
                     }
-#pragma unroll
-                    for (int k = 0; k < kTiles; ++k)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) cur[k][v] = slot[k][v] >= 0 ? a.lu[slot[k][v]] : 0.0;
-#pragma unroll
-                    for (int k = 0; k < kTiles; ++k)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            if (slot[k][v] >= 0) a.lu[slot[k][v]] = cur[k][v] - acc[k][v];
                 }
             } else {
                 for (int q = g0 + wv; q < g1; q += nw) {

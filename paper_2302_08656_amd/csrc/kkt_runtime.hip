@@ -479,6 +479,7 @@ int kkt_get_stats(const kkt_handle *h, kkt_stats *out) {
     out->persistent_levels_l = pers ? out->gpu_levels_l - h->sch.l_split : 0;
     out->persistent_levels_u = pers ? h->sch.u_split : 0;
     out->flops_refactor = h->sch.flops;
+    out->nnz_lu_wide = h->sch.nnz_lu_wide;
     return KKT_OK;
 }
 

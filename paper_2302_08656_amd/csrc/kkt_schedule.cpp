@@ -436,6 +436,12 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         fl += 2.0 * lk * (double)urow[k] + lk;
     }
     g.flops = fl;
+    g.nnz_lu_wide = 0;
+    for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l)
+        for (int32_t it = g.f_lvl[l]; it < g.f_lvl[l] + g.f_nlarge[l]; ++it) {
+            const int32_t P = g.f_item_panel[it];
+            if (P >= 0) g.nnz_lu_wide += s.colptr[g.pan_start[P + 1]] - s.colptr[g.pan_start[P]];
+        }
     return KKT_OK;
 }
 
