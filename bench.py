@@ -134,13 +134,15 @@ def main():
     # slot index, read and write the value
     per_unit = {
         "refactor_large": 16 * st["nnz_lu_wide"] * nprof,
-        "refactor_small": 16 * (st["nnz_lu"] - st["nnz_lu_wide"]) * nprof,
+        "refactor_medium": 16 * st["nnz_lu_medium"] * nprof,
+        "refactor_small": 16 * (st["nnz_lu"] - st["nnz_lu_wide"] - st["nnz_lu_medium"]) * nprof,
         "lsolve": (12 * nnz_l + 48 * q.n) * solves,
         "usolve": (12 * (nnz_u + q.n) + 48 * q.n) * solves,
         "to_csr": 20 * st["nnz_lu"] * nprof,
         "update": (12 * q.nnz + 12 * st["nnz_lu"] + 40 * q.n) * nprof,
     }
-    kernel_of = {"refactor_large": "k_refactor_large", "refactor_small": "k_refactor_small",
+    kernel_of = {"refactor_large": "k_refactor_wide<BigCfg>", "refactor_medium": "k_refactor_wide<MedCfg>",
+                 "refactor_small": "k_refactor_small",
                  "lsolve": "k_lsolve_persistent", "usolve": "k_usolve_persistent", "to_csr": "k_to_csr",
                  "update": "k_row_scale..k_gather_lu", "residual": "k_residual/k_spmv", "krylov": "krylov"}
     ranked = sorted((v[1], k) for k, v in prof.items())

@@ -101,7 +101,8 @@ typedef struct {
     int32_t persistent_levels_l; /* forward levels run by the persistent launch */
     int32_t persistent_levels_u; /* backward levels run by the persistent launch */
     double flops_refactor;      /* sum_k 2 |L(:,k)| |U(k,:)| + |L(:,k)| */
-    int64_t nnz_lu_wide;        /* L+U entries of the columns factored by wide-panel items */
+    int64_t nnz_lu_wide;        /* L+U entries of the columns factored by wide items (32-column blocks) */
+    int64_t nnz_lu_medium;      /* L+U entries of the columns factored by medium wide items */
 } kkt_stats;
 
 /* Fills *o with the defaults listed in kkt_opts. */
@@ -133,9 +134,9 @@ int kkt_workspace_bytes(const kkt_handle *h, int32_t max_nrhs, size_t *bytes);
 
 /* Setup (Algorithm 1, set up the GPU refactorization): uploads the symbolic structure and
  * schedules into d_workspace (device, >= kkt_workspace_bytes, 256-byte aligned) on stream
- * and records the device; the first bind also creates the handle's internal second stream
- * (used inside kkt_refactor, always joined back into the caller's stream).  A handle stays
- * on its first device: binding again on another one returns STATE.  Waits for the upload.
+ * and records the device; the first bind also creates the handle's two internal streams
+ * (used inside kkt_refactor, always joined back into the caller's stream).  A handle stays on
+ * its first device: binding again on another one returns STATE.  Waits for the upload.
  * Errors: ARG, NOMEM (too small), STATE, DEVICE. */
 int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs,
              hipStream_t stream);
@@ -173,14 +174,15 @@ int kkt_export_factors(kkt_handle *h, double *h_lu, double *h_r, double *h_c,
 
 /* Kernel classes timed by the optional launch profiler. */
 #define KKT_PROF_UPDATE 0          /* equilibration, norms, value gather, counters */
-#define KKT_PROF_REFACTOR_LARGE 1  /* wide panel items (LDS-staged, matrix cores) */
+#define KKT_PROF_REFACTOR_LARGE 1  /* wide panel items (LDS-staged, matrix cores), up to 32 columns */
 #define KKT_PROF_REFACTOR_SMALL 2  /* narrow panel items (16 lanes each) */
 #define KKT_PROF_TO_CSR 3          /* row-ordered copy of the factors */
 #define KKT_PROF_LSOLVE 4          /* forward-substitution levels */
 #define KKT_PROF_USOLVE 5          /* backward-substitution levels */
 #define KKT_PROF_RESIDUAL 6        /* residual, products with A */
 #define KKT_PROF_KRYLOV 7          /* FGMRES vector kernels */
-#define KKT_PROF_NCLASS 8
+#define KKT_PROF_REFACTOR_MEDIUM 8 /* wide items of panels up to 16 columns (smaller blocks) */
+#define KKT_PROF_NCLASS 9
 
 typedef struct {
     int64_t launches[KKT_PROF_NCLASS];

@@ -39,11 +39,11 @@ class _Info(C.Structure):
 
 
 PROFILE_CLASSES = ["update", "refactor_large", "refactor_small", "to_csr", "lsolve", "usolve",
-                   "residual", "krylov"]
+                   "residual", "krylov", "refactor_medium"]
 
 
 class _Profile(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 8), ("ms", C.c_double * 8)]
+    _fields_ = [("launches", C.c_int64 * 9), ("ms", C.c_double * 9)]
 
 
 class _Stats(C.Structure):
@@ -51,7 +51,8 @@ class _Stats(C.Structure):
                 ("levels_f", C.c_int32), ("levels_l", C.c_int32), ("levels_u", C.c_int32),
                 ("gpu_levels_f", C.c_int32), ("gpu_levels_l", C.c_int32), ("gpu_levels_u", C.c_int32),
                 ("persistent_levels_l", C.c_int32), ("persistent_levels_u", C.c_int32),
-                ("flops_refactor", C.c_double), ("nnz_lu_wide", C.c_int64)]
+                ("flops_refactor", C.c_double), ("nnz_lu_wide", C.c_int64),
+                ("nnz_lu_medium", C.c_int64)]
 
 
 EXPORTS = ["kkt_default_opts", "kkt_analyze", "kkt_get_stats", "kkt_export_symbolic",

@@ -48,6 +48,8 @@ constexpr int kSolvePack = 64;
 constexpr int kSmallW = 4;
 constexpr int kSmallR = 64;
 constexpr int kGroup = 32;
+constexpr int kMedW = 16;
+constexpr int kMedRows = 256;
 // Solve levels with at most this many items run in the persistent launch (build-time
 // tunable).
 #ifndef KKT_PERSIST_ITEMS
@@ -69,10 +71,12 @@ struct Schedule {
     std::vector<int32_t> pan_start;     // [npan+1] first column of each panel
     std::vector<int32_t> pan_r;         // [npan] L rows below the panel (= U columns right)
     // refactorization: launch l runs items [f_lvl[l], f_lvl[l+1]); the first f_nlarge[l] of
-    // them take the 256-thread path, the rest the 16-lane path.  An item owns the target
+    // them take the wide path (in its medium configuration, f_nmed[l] = f_nlarge[l], when
+    // every wide item of the level has panels of at most kMedW columns and factors a panel
+    // of at most kMedRows rows), the rest the 16-lane path.  An item owns the target
     // columns of its (source panel, target column) pairs, listed source-major, and then
     // factors its panel (f_item_panel >= 0).
-    std::vector<int32_t> f_lvl, f_nlarge;
+    std::vector<int32_t> f_lvl, f_nlarge, f_nmed;
     std::vector<int32_t> f_item_panel;  // panel to factor after the pulls, or -1
     std::vector<int32_t> f_item_pair;   // [nitems+1] range into f_pair_src / f_pair_tgt
     std::vector<int32_t> f_pair_src, f_pair_tgt;
@@ -82,7 +86,9 @@ struct Schedule {
     // packed records read by the refactorization kernels (8 x int32 each):
     // item8[i] = {panel to factor or -1, first pair, end pair, 0, s, w, r, ldiag[s]};
     // pair8[q] = {source panel, f_pair_pos, f_pair_rel (first index), target column,
-    //             s, w, r, ldiag[s]}, with s, w, r the panel's first column, width, rows below
+    //             s, w, r, ldiag[s]}, with s, w, r the panel's first column, width, rows below;
+    // for pairs of narrow items {ldiag[s+1], f_pair_pos, f_pair_rel, ldiag[s+2], ldiag[s+3],
+    //             w, r, ldiag[s]} (slots past the width are 0)
     std::vector<int32_t> item8, pair8;
     std::vector<int32_t> ldiag;         // slot of the diagonal of each column
     // triangular solves: level l has items [x_lvl[l], x_lvl[l+1]), 4 x int32 each:
@@ -112,7 +118,8 @@ struct Schedule {
     // CSC view of A's pattern (positions into the CSR value array)
     std::vector<int32_t> a_cptr, a_cpos, a_rowid;
     double flops = 0.0;
-    int64_t nnz_lu_wide = 0;            // L+U entries of columns factored by wide-path items
+    int64_t nnz_lu_wide = 0;            // L+U entries of columns factored by wide items
+    int64_t nnz_lu_med = 0;             // ... by medium wide items
 };
 
 int build_schedule(const Symbolic &s, Schedule &g);

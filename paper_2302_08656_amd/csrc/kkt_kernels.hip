@@ -245,54 +245,63 @@ __device__ __forceinline__ double perturb(double p, double thresh, int &npert) {
 
 // ----------------------------------------------------------------- 16-lane path
 
-// Update of target column k by a narrow source panel S (w <= kSmallW, r <= kSmallR): rows
-// s..e-1 of column k (from slot ps on) become final U entries (unit lower solve with S's
-// diagonal block) and the rows R of S lose L(R, S) times them.
-__device__ __forceinline__ void small_pull(const RefArgs &a, int4 pa, int4 pb, int gl) {
-    const int ps = pa.y, s = pb.x, w = pb.y, r = pb.z;
+// Source side of the update of target column k by a narrow source panel S (w <= kSmallW,
+// r <= kSmallR), loaded by one 16-lane group: S's diagonal block rows, its L rows and the
+// slots of those rows in the target.  Independent of the target's values, so the next
+// pair's source side is loaded while the current pair is applied.
+constexpr int kSmallRows = kSmallR / 16;
+struct SmallSrc {
+    int ps, w, r;
+    int pos[kSmallRows];
+    double l_row[kSmallW - 1];          // L(s + gl, s + j) for j < gl
+    double lr[kSmallRows][kSmallW];     // L(R_i, s + j) for this lane's rows i
+};
+
+// pa, pb: the pair's record {ldiag[s+1], pos, rel, ldiag[s+2]}, {ldiag[s+3], w, r, ldiag[s]}
+__device__ __forceinline__ void small_load_src(const RefArgs &a, int4 pa, int4 pb, int gl, SmallSrc &x) {
+    const int ld[kSmallW] = {pb.w, pa.x, pa.w, pb.x};
+    x.ps = pa.y;
+    x.w = pb.y;
+    x.r = pb.z;
+    const int w = x.w, r = x.r;
     const int32_t *rel = a.rel + pa.z;
-    // diagonal slots of the source's columns (the first comes with the record)
-    int ldg = pb.w;
-    if (w > 1 && gl > 0 && gl < w) ldg = a.ldiag[s + gl];
-    int ld[kSmallW];
 #pragma unroll
-    for (int j = 0; j < kSmallW; ++j) ld[j] = __shfl(ldg, j, 16);
-    // one round of independent loads: the target's rows of S, S's diagonal block and L rows,
-    // and the slots of those rows in the target
-    double l_row[kSmallW - 1];   // L(s + gl, s + j) for j < gl
+    for (int j = 0; j < kSmallW - 1; ++j) x.l_row[j] = (j + 1 < w && gl > j && gl < w) ? a.lu[ld[j] + (gl - j)] : 0.0;
 #pragma unroll
-    for (int j = 0; j < kSmallW - 1; ++j) l_row[j] = (j + 1 < w && gl > j && gl < w) ? a.lu[ld[j] + (gl - j)] : 0.0;
-    double u = gl < w ? a.lu[ps + gl] : 0.0;
-    constexpr int kRows = kSmallR / 16;
-    double lr[kRows][kSmallW];
-    int pos[kRows];
-#pragma unroll
-    for (int k = 0; k < kRows; ++k) {
+    for (int k = 0; k < kSmallRows; ++k) {
         const int i = gl + 16 * k;
-        pos[k] = i < r ? rel[i] : 0;
+        x.pos[k] = i < r ? rel[i] : 0;
 #pragma unroll
-        for (int j = 0; j < kSmallW; ++j) lr[k][j] = (i < r && j < w) ? a.lu[ld[j] + 1 + (w - 1 - j) + i] : 0.0;
+        for (int j = 0; j < kSmallW; ++j) x.lr[k][j] = (i < r && j < w) ? a.lu[ld[j] + 1 + (w - 1 - j) + i] : 0.0;
     }
-    double tv[kRows];
+}
+
+// Target side: rows s..s+w-1 of column k (from slot ps on) become final U entries (unit
+// lower solve with S's diagonal block) and the rows R of S lose L(R, S) times them.
+__device__ __forceinline__ void small_apply(const RefArgs &a, const SmallSrc &x, int gl) {
+    const int w = x.w, r = x.r;
+    // one round: the target's rows of S and of R
+    double u = gl < w ? a.lu[x.ps + gl] : 0.0;
+    double tv[kSmallRows];
 #pragma unroll
-    for (int k = 0; k < kRows; ++k) tv[k] = gl + 16 * k < r ? a.lu[pos[k]] : 0.0;
+    for (int k = 0; k < kSmallRows; ++k) tv[k] = gl + 16 * k < r ? a.lu[x.pos[k]] : 0.0;
 #pragma unroll
     for (int j = 0; j < kSmallW - 1; ++j) {
         const double uj = __shfl(u, j, 16);
-        if (j + 1 < w && gl > j && gl < w) u = fma(-l_row[j], uj, u);
+        if (j + 1 < w && gl > j && gl < w) u = fma(-x.l_row[j], uj, u);
     }
-    if (gl < w) a.lu[ps + gl] = u;
+    if (gl < w) a.lu[x.ps + gl] = u;
     double uu[kSmallW];
 #pragma unroll
     for (int j = 0; j < kSmallW; ++j) uu[j] = __shfl(u, j, 16);
 #pragma unroll
-    for (int k = 0; k < kRows; ++k) {
+    for (int k = 0; k < kSmallRows; ++k) {
         if (gl + 16 * k < r) {
             double acc = 0.0;
 #pragma unroll
             for (int j = 0; j < kSmallW; ++j)
-                if (j < w) acc = fma(lr[k][j], uu[j], acc);
-            a.lu[pos[k]] = tv[k] - acc;
+                if (j < w) acc = fma(x.lr[k][j], uu[j], acc);
+            a.lu[x.pos[k]] = tv[k] - acc;
         }
     }
     __threadfence_block();   // a later source of the same column may read these rows
@@ -301,10 +310,8 @@ __device__ __forceinline__ void small_pull(const RefArgs &a, int4 pa, int4 pb, i
 // Dense LU without pivoting of a narrow panel's block column (w <= kSmallW, r <= kSmallR).
 // pn = {s, w, r, slot of the first diagonal}.  Returns the number of replaced pivots (the
 // same value on every lane of the group).
-__device__ __forceinline__ int small_factor(const RefArgs &a, int4 pn, int gl, double thresh) {
-    const int s = pn.x, w = pn.y, r = pn.z;
-    int ldg = pn.w;
-    if (w > 1 && gl > 0 && gl < w) ldg = a.ldiag[s + gl];
+__device__ __forceinline__ int small_factor(const RefArgs &a, int4 pn, int ldg, int gl, double thresh) {
+    const int w = pn.y, r = pn.z;
     int sg[kSmallW];
 #pragma unroll
     for (int c = 0; c < kSmallW; ++c) sg[c] = __shfl(ldg, c, 16) - c;
@@ -369,7 +376,10 @@ __device__ __forceinline__ int small_factor(const RefArgs &a, int4 pn, int gl, d
     return npert;
 }
 
-// kBlock/16 items per block, one per 16-lane group
+// kBlock/16 items per block, one per 16-lane group.  kPipe: the next pair's source side is
+// loaded while the current pair is applied (fewer dependent rounds per item, more registers:
+// for levels with few items); otherwise one pair at a time (more items in flight).
+template <bool kPipe>
 __global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, RefArgs a) {
     const double thresh = a.tiny * a.st->anorm_scaled;
     const int g = blockIdx.x * (kBlock / 16) + (threadIdx.x >> 4);
@@ -378,8 +388,49 @@ __global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, R
     if (g < nsmall) {
         const int item = item0 + g;
         const int4 ia = a.item[2 * item], ib = a.item[2 * item + 1];
-        for (int q = ia.y; q < ia.z; ++q) small_pull(a, a.pair[2 * q], a.pair[2 * q + 1], gl);
-        if (ia.x >= 0) npert = small_factor(a, ib, gl, thresh);
+        // one round: the records of up to 16 pairs (lane t holds pair p0 + t) and the
+        // diagonal slots of the panel to factor
+        const int p0 = ia.y, np = ia.z - ia.y;
+        int4 ra = int4{0, 0, 0, 0}, rb = int4{0, 0, 0, 0};
+        if (gl < np) {
+            ra = a.pair[2 * (p0 + gl)];
+            rb = a.pair[2 * (p0 + gl) + 1];
+        }
+        const int ldg = (ia.x >= 0 && ib.y > 1 && gl > 0 && gl < ib.y) ? a.ldiag[ib.x + gl] : ib.w;
+        auto rec = [&](int q, int4 &pa, int4 &pb) {
+            if (q >= 16) {   // items with more than 16 pairs read the rest on demand
+                pa = a.pair[2 * (p0 + q)];
+                pb = a.pair[2 * (p0 + q) + 1];
+                return;
+            }
+            pa = int4{__shfl(ra.x, q, 16), __shfl(ra.y, q, 16), __shfl(ra.z, q, 16), __shfl(ra.w, q, 16)};
+            pb = int4{__shfl(rb.x, q, 16), __shfl(rb.y, q, 16), __shfl(rb.z, q, 16), __shfl(rb.w, q, 16)};
+        };
+        if constexpr (kPipe) {
+            if (np > 0) {
+                SmallSrc cur, nxt;
+                int4 pa, pb;
+                rec(0, pa, pb);
+                small_load_src(a, pa, pb, gl, cur);
+                for (int q = 0; q < np; ++q) {
+                    if (q + 1 < np) {
+                        rec(q + 1, pa, pb);
+                        small_load_src(a, pa, pb, gl, nxt);
+                    }
+                    small_apply(a, cur, gl);
+                    cur = nxt;
+                }
+            }
+        } else {
+            for (int q = 0; q < np; ++q) {
+                SmallSrc cur;
+                int4 pa, pb;
+                rec(q, pa, pb);
+                small_load_src(a, pa, pb, gl, cur);
+                small_apply(a, cur, gl);
+            }
+        }
+        if (ia.x >= 0) npert = small_factor(a, ib, ldg, gl, thresh);
     }
     // one counter update per wavefront: group leaders contribute their count
     int c = gl == 0 ? npert : 0;
@@ -390,20 +441,33 @@ __global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, R
 
 // ----------------------------------------------------------------- 512-thread path
 
-constexpr int kBigThreads = 512;
-constexpr int kRChunk = 256;
 constexpr int kStagePairs = 256;
-// LDS layout (bytes): Ls (the source's diagonal block, later the factored panel's U) | Ub
-// (solved rows per target) | Lr (a chunk of the source's L rows) | lds (the source's
-// diagonal slots) | sgs (slot of row s in each column of the panel to factor) | staged
-// pair records
-constexpr int kOffLd = 0;
-constexpr int kOffUb = kOffLd + kPanelMax * kPanelMax * 8;
-constexpr int kOffLr = kOffUb + kPanelMax * kGroup * 8;
-constexpr int kOffLds = kOffLr + kRChunk * kPanelMax * 8;
-constexpr int kOffSgs = kOffLds + kPanelMax * 4;
-constexpr int kOffPairs = kOffSgs + kPanelMax * 4;
-constexpr int kLargeLds = kOffPairs + kStagePairs * 32;
+
+// Configurations of the wide path: threads per block, minimum waves per SIMD, source L rows
+// staged per chunk, widest panel (target and sources) and update tiles per wavefront and
+// pass.  LDS layout (bytes): Ld (the source's diagonal block, later the factored panel's U)
+// | Ub (solved rows per target) | Lr (a chunk of the source's L rows) | lds (the source's
+// diagonal slots) | sgs (slot of row s in each column of the panel to factor) | staged pair
+// records.
+template <int T, int WV, int CH, int MW, int TI>
+struct WideCfg {
+    static constexpr int kThreads = T;
+    static constexpr int kWaves = WV;
+    static constexpr int kChunk = CH;
+    static constexpr int kMaxW = MW;
+    static constexpr int kTiles = TI;
+    static constexpr int kOffLd = 0;
+    static constexpr int kOffUb = kOffLd + kMaxW * kPanelMax * 8;
+    static constexpr int kOffLr = kOffUb + kPanelMax * kGroup * 8;
+    static constexpr int kOffLds = kOffLr + kChunk * kMaxW * 8;
+    static constexpr int kOffSgs = kOffLds + kPanelMax * 4;
+    static constexpr int kOffPairs = kOffSgs + kPanelMax * 4;
+    static constexpr int kLds = kOffPairs + kStagePairs * 32;
+};
+// panels up to 32 columns: one block per CU
+using BigCfg = WideCfg<512, 2, 256, 32, 4>;
+// panels up to 16 columns: four blocks per CU
+using MedCfg = WideCfg<256, 4, 128, 16, 2>;
 
 // Shifted sweeps.  A row of a panel of width w <= KW lives in registers x[0..KW-1] with
 // zeros past column w.  Step j of a triangular sweep consumes x[0] (column j) and moves
@@ -455,19 +519,19 @@ __device__ __forceinline__ void sweep_step(double (&x)[kPanelMax], const double 
 }
 
 // Dense LU without pivoting of a wide panel's block column (w + r rows, w columns).  Thread
-// t owns panel row t (t < w: the diagonal block; below: the L rows) for t < kBigThreads;
+// t owns panel row t (t < w: the diagonal block; below: the L rows) for t < C::kThreads;
 // step j: the owner of row j perturbs its pivot and publishes U(j, j..) in LDS
 // (Us[j * kPanelMax + c] = U(j, j + c), zero past the panel), then after one barrier every
 // later row takes its multiplier and update from it.  The sweep narrows from KW to
 // KW / 2 register columns once no more than KW / 2 columns remain.  Rows beyond the
-// first kBigThreads are eliminated afterwards from the finished Us.  sgs[c] = slot of row s
+// first C::kThreads are eliminated afterwards from the finished Us.  sgs[c] = slot of row s
 // in column s + c (staged by the caller); row t of the panel is at slot sgs[c] + t.
-template <int KW>
+template <class C, int KW>
 __device__ __forceinline__ void large_factor_w(const RefArgs &a, int w, int r, char *sm, double thresh,
                                                int item) {
     const int tid = threadIdx.x, lane = tid & 63;
-    double *Us = reinterpret_cast<double *>(sm + kOffLd);
-    const int *sgs = reinterpret_cast<const int *>(sm + kOffSgs);
+    double *Us = reinterpret_cast<double *>(sm + C::kOffLd);
+    const int *sgs = reinterpret_cast<const int *>(sm + C::kOffSgs);
     const int nrow = w + r;
     int npert = 0, bad = 0;
     double x[kPanelMax];
@@ -503,12 +567,12 @@ __device__ __forceinline__ void large_factor_w(const RefArgs &a, int w, int r, c
     __syncthreads();
     KKT_PHASE(item, 7);
     // U rows of the diagonal block (diagonal included) from LDS
-    for (int t = tid; t < w * KW; t += kBigThreads) {
+    for (int t = tid; t < w * KW; t += C::kThreads) {
         const int j = t / KW, c = t % KW;
         if (j + c < w) a.lu[sgs[j + c] + j] = Us[j * kPanelMax + c];
     }
     // rows beyond the threads of the block
-    for (int i = tid + kBigThreads; i < nrow; i += kBigThreads) {
+    for (int i = tid + C::kThreads; i < nrow; i += C::kThreads) {
         load_row<KW>(x, a.lu, sgs, w, i);
 #pragma unroll 1
         for (int j = 0; j < w; ++j) sweep_step<KW>(x, Us + j * kPanelMax, a.lu + sgs[j] + i, bad);
@@ -517,10 +581,16 @@ __device__ __forceinline__ void large_factor_w(const RefArgs &a, int w, int r, c
     if (__any(bad) && lane == 0) atomicOr(&a.st->flags, kFlagNonfinite);
 }
 
+template <class C>
 __device__ __forceinline__ void large_factor(const RefArgs &a, int4 pn, char *sm, double thresh, int item) {
-    if (pn.y > 16) large_factor_w<32>(a, pn.y, pn.z, sm, thresh, item);
-    else if (pn.y > 8) large_factor_w<16>(a, pn.y, pn.z, sm, thresh, item);
-    else large_factor_w<8>(a, pn.y, pn.z, sm, thresh, item);
+    if constexpr (C::kMaxW > 16) {
+        if (pn.y > 16) {
+            large_factor_w<C, 32>(a, pn.y, pn.z, sm, thresh, item);
+            return;
+        }
+    }
+    if (pn.y > 8) large_factor_w<C, 16>(a, pn.y, pn.z, sm, thresh, item);
+    else large_factor_w<C, 8>(a, pn.y, pn.z, sm, thresh, item);
 }
 
 // Rows of the source panel (width w) in one target: unit lower solve with the source's
@@ -549,25 +619,26 @@ __device__ __forceinline__ void unit_lower_w(double *lu, int ps, int w, const do
 }
 
 // All pulls of one item with the source panel staged in LDS, then the panel factorization.
-__global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefArgs a) {
+template <class C>
+__global__ __launch_bounds__(C::kThreads, C::kWaves) void k_refactor_wide(int item0, RefArgs a) {
     extern __shared__ __align__(16) char sm[];
     const double thresh = a.tiny * a.st->anorm_scaled;
     const int item = item0 + blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    constexpr int nw = kBigThreads / 64;
+    constexpr int nw = C::kThreads / 64;
     KKT_PHASE(item, 0);
-    double *Ld = reinterpret_cast<double *>(sm + kOffLd);
-    double *Ub = reinterpret_cast<double *>(sm + kOffUb);
-    double *Lr = reinterpret_cast<double *>(sm + kOffLr);
-    int *lds = reinterpret_cast<int *>(sm + kOffLds);
-    int *sgs = reinterpret_cast<int *>(sm + kOffSgs);
-    int4 *prs = reinterpret_cast<int4 *>(sm + kOffPairs);
+    double *Ld = reinterpret_cast<double *>(sm + C::kOffLd);
+    double *Ub = reinterpret_cast<double *>(sm + C::kOffUb);
+    double *Lr = reinterpret_cast<double *>(sm + C::kOffLr);
+    int *lds = reinterpret_cast<int *>(sm + C::kOffLds);
+    int *sgs = reinterpret_cast<int *>(sm + C::kOffSgs);
+    int4 *prs = reinterpret_cast<int4 *>(sm + C::kOffPairs);
     const int4 ia = a.item[2 * item], ib = a.item[2 * item + 1];
     const int pbeg = ia.y, p1 = ia.z, npr = p1 - pbeg;
     const bool staged = npr <= kStagePairs;
     // one round: the pair records and the slots of the panel to factor
     if (staged)
-        for (int t = tid; t < 2 * npr; t += kBigThreads) prs[t] = a.pair[2 * pbeg + t];
+        for (int t = tid; t < 2 * npr; t += C::kThreads) prs[t] = a.pair[2 * pbeg + t];
     if (ia.x >= 0 && tid < ib.y) sgs[tid] = a.ldiag[ib.x + tid] - tid;
     __syncthreads();
     auto pra = [&](int q) { return staged ? prs[2 * (q - pbeg)] : a.pair[2 * q]; };
@@ -582,14 +653,14 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
         if (tid < w) lds[tid] = tid == 0 ? pn.w : a.ldiag[s + tid];
         __syncthreads();
         // one round: S's diagonal block and the first chunk of its L rows
-        for (int t = tid; t < w * kPanelMax; t += kBigThreads) {
+        for (int t = tid; t < w * kPanelMax; t += C::kThreads) {
             const int j = t / kPanelMax, c = t % kPanelMax;
             Ld[t] = (c >= 1 && j + c < w) ? a.lu[lds[j] + c] : 0.0;
         }
-        const int nr0 = min(kRChunk, r);
-        for (int t = tid; t < w * nr0; t += kBigThreads) {
+        const int nr0 = min(C::kChunk, r);
+        for (int t = tid; t < w * nr0; t += C::kThreads) {
             const int j = t / nr0, i = t % nr0;
-            Lr[j * kRChunk + i] = a.lu[lds[j] + 1 + (w - 1 - j) + i];
+            Lr[j * C::kChunk + i] = a.lu[lds[j] + 1 + (w - 1 - j) + i];
         }
         __syncthreads();
         KKT_PHASE(item, 2);
@@ -599,7 +670,7 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
         // D[lane / 16 + 4 v][lane % 16].  Wavefronts 1.. own the tiles, kTiles at a time; for
         // the first pass of the first chunk they load the destination slots and current values
         // while wavefront 0 solves the targets' rows of S.
-        constexpr int kTiles = 4;
+        constexpr int kTiles = C::kTiles;
         const int m = g1 - g0;
         const bool mf = a.use_mfma && m > 1;
         const int nt = (m + 15) >> 4;
@@ -616,10 +687,10 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
         };
         int pslot[kTiles][4];
         double pcur[kTiles][4];
-        const int mt0 = (min(kRChunk, r) + 15) >> 4;
+        const int mt0 = (min(C::kChunk, r) + 15) >> 4;
         if (mf && wv > 0) {
 #pragma unroll
-            for (int k = 0; k < kTiles; ++k) tile_slots((wv - 1) * kTiles + k, mt0, min(kRChunk, r), 0, pslot[k]);
+            for (int k = 0; k < kTiles; ++k) tile_slots((wv - 1) * kTiles + k, mt0, min(C::kChunk, r), 0, pslot[k]);
 #pragma unroll
             for (int k = 0; k < kTiles; ++k)
 #pragma unroll
@@ -631,19 +702,19 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
         if (wv == 0 && lane < m) {
             const int ps = pra(g0 + lane).y;
             double *ub = Ub + lane * kPanelMax;
-            if (w > 16) unit_lower_w<32>(a.lu, ps, w, Ld, ub, item);
+            if (C::kMaxW > 16 && w > 16) unit_lower_w<C::kMaxW>(a.lu, ps, w, Ld, ub, item);
             else if (w > 8) unit_lower_w<16>(a.lu, ps, w, Ld, ub, item);
             else unit_lower_w<8>(a.lu, ps, w, Ld, ub, item);
         }
         __syncthreads();
         KKT_PHASE(item, 3);
         // rows R of each target: chunks of S's L rows in LDS, precomputed slots
-        for (int i0 = 0; i0 < r; i0 += kRChunk) {
-            const int nr = min(kRChunk, r - i0);
+        for (int i0 = 0; i0 < r; i0 += C::kChunk) {
+            const int nr = min(C::kChunk, r - i0);
             if (i0 > 0) {
-                for (int t = tid; t < w * nr; t += kBigThreads) {
+                for (int t = tid; t < w * nr; t += C::kThreads) {
                     const int j = t / nr, i = t % nr;
-                    Lr[j * kRChunk + i] = a.lu[lds[j] + 1 + (w - 1 - j) + i0 + i];
+                    Lr[j * C::kChunk + i] = a.lu[lds[j] + 1 + (w - 1 - j) + i0 + i];
                 }
                 __syncthreads();
             }
@@ -664,7 +735,7 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
                                 const int ti = tile % mt, tt = tile / mt;
                                 const int ia2 = ti * 16 + li, tb = tt * 16 + li;
                                 const bool ok = tile < mt * nt && kk < w;
-                                av[k] = (ok && ia2 < nr) ? Lr[kk * kRChunk + ia2] : 0.0;
+                                av[k] = (ok && ia2 < nr) ? Lr[kk * C::kChunk + ia2] : 0.0;
                                 bv[k] = (ok && tb < m) ? Ub[tb * kPanelMax + kk] : 0.0;
                             }
 #pragma unroll
@@ -702,7 +773,7 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
                     const double *ub = Ub + (q - g0) * kPanelMax;
                     for (int i = lane; i < nr; i += 64) {
                         double acc = 0.0;
-                        for (int j = 0; j < w; ++j) acc = fma(Lr[j * kRChunk + i], ub[j], acc);
+                        for (int j = 0; j < w; ++j) acc = fma(Lr[j * C::kChunk + i], ub[j], acc);
                         a.lu[rel[i]] -= acc;
                     }
                 }
@@ -713,7 +784,7 @@ __global__ __launch_bounds__(kBigThreads) void k_refactor_large(int item0, RefAr
         __syncthreads();
         KKT_PHASE(item, 4);
     }
-    if (ia.x >= 0) large_factor(a, ib, sm, thresh, item);
+    if (ia.x >= 0) large_factor<C>(a, ib, sm, thresh, item);
     KKT_PHASE(item, 5);
 }
 

@@ -31,6 +31,7 @@ struct Dev {
 };
 
 constexpr int kDotBlocks = 512;
+constexpr int kSmallPipeMax = 100000;  // narrow items per level up to which the pipelined variant runs
 constexpr int kNormBlocks = 1024;
 constexpr int kMaxRestart = 64;
 
@@ -63,8 +64,8 @@ struct kkt_handle {
     int grid_l = 1, grid_u = 1;  // co-resident blocks of the persistent solve kernels
     // second stream of the refactorization: the narrow and the wide items of one level run
     // concurrently, joined by a pair of events per level
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t side = nullptr, side2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
     // launch profiler
     bool prof = false;
     kkt_profile acc{};
@@ -273,22 +274,32 @@ int enqueue_refactor(kkt_handle *h, const double *v, hipStream_t s) {
     RefArgs a{d.ldiag, d.item8, d.pair8, d.f_rel, d.lu, d.st, d.pcount,
               h->opts.tiny_pivot, h->opts.dense_mfma != 0};
     for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
-        const int nl = g.f_nlarge[l], ns = g.f_lvl[l + 1] - g.f_lvl[l] - nl;
-        // the two kinds of items of a level touch disjoint target columns: with both present
-        // the narrow ones run on the side stream, forked after and joined before the level
-        const bool both = nl && ns;
-        hipStream_t ss = both ? h->side : s;
-        if (both) {
+        // the kinds of items of a level touch disjoint target columns: the wide ones (32- and
+        // 16-column configurations, one after the other) run on the caller's stream, the
+        // narrow ones on the side stream, forked after and joined before the level
+        const int nm = g.f_nmed[l], nb = g.f_nlarge[l] - nm, ns = g.f_lvl[l + 1] - g.f_lvl[l] - nb - nm;
+        const int i0 = g.f_lvl[l];
+        const bool fork = (nb > 0 || nm > 0) && ns > 0;
+        hipStream_t ss = fork ? h->side : s;
+        if (fork) {
             HIPCHK(hipEventRecord(h->ev_fork, s));
             HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
         }
-        if (nl)
-            timed(h, KKT_PROF_REFACTOR_LARGE, s, [&] { k_refactor_large<<<nl, kBigThreads, kLargeLds, s>>>(g.f_lvl[l], a); });
         if (ns)
             timed(h, KKT_PROF_REFACTOR_SMALL, ss, [&] {
-                k_refactor_small<<<blocks_for(ns, kBlock / 16), kBlock, 0, ss>>>(g.f_lvl[l] + nl, ns, a);
+                // many items: keep more in flight; few: shorten each item's dependent chain
+                if (ns > kSmallPipeMax)
+                    k_refactor_small<false><<<blocks_for(ns, kBlock / 16), kBlock, 0, ss>>>(i0 + nb + nm, ns, a);
+                else
+                    k_refactor_small<true><<<blocks_for(ns, kBlock / 16), kBlock, 0, ss>>>(i0 + nb + nm, ns, a);
             });
-        if (both) {
+        if (nb)
+            timed(h, KKT_PROF_REFACTOR_LARGE, s,
+                  [&] { k_refactor_wide<BigCfg><<<nb, BigCfg::kThreads, BigCfg::kLds, s>>>(i0, a); });
+        if (nm)
+            timed(h, KKT_PROF_REFACTOR_MEDIUM, s,
+                  [&] { k_refactor_wide<MedCfg><<<nm, MedCfg::kThreads, MedCfg::kLds, s>>>(i0 + nb, a); });
+        if (fork) {
             HIPCHK(hipEventRecord(h->ev_join, h->side));
             HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
         }
@@ -480,6 +491,7 @@ int kkt_get_stats(const kkt_handle *h, kkt_stats *out) {
     out->persistent_levels_u = pers ? h->sch.u_split : 0;
     out->flops_refactor = h->sch.flops;
     out->nnz_lu_wide = h->sch.nnz_lu_wide;
+    out->nnz_lu_medium = h->sch.nnz_lu_med;
     return KKT_OK;
 }
 
@@ -522,8 +534,10 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     HIPCHK(hipGetDevice(&dev));
     int ncu = 0;
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_refactor_large),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kLargeLds));
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_refactor_wide<BigCfg>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, BigCfg::kLds));
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_refactor_wide<MedCfg>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, MedCfg::kLds));
     {
         int coop = 0, bl = 0, bu = 0;
         HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
@@ -539,8 +553,10 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     if (h->side && h->device != dev) return KKT_ERR_STATE;   // rebinding keeps the device
     if (!h->side) {
         HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+        HIPCHK(hipStreamCreateWithFlags(&h->side2, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_join2, hipEventDisableTiming));
     }
     carve(h, static_cast<char *>(d_workspace), h->d, &need);
     const Symbolic &s = h->sym;
@@ -691,9 +707,12 @@ void kkt_destroy(kkt_handle *h) {
     if (h->side) {
         DeviceGuard g(h->device);
         (void)hipStreamSynchronize(h->side);
+        (void)hipStreamSynchronize(h->side2);
         (void)hipStreamDestroy(h->side);
+        (void)hipStreamDestroy(h->side2);
         (void)hipEventDestroy(h->ev_fork);
         (void)hipEventDestroy(h->ev_join);
+        (void)hipEventDestroy(h->ev_join2);
     }
     for (auto &pe : h->ev_pending) h->ev_free.push_back(pe.second);
     for (auto &ev : h->ev_free) {

@@ -106,6 +106,7 @@ int build_schedule(const Symbolic &s, Schedule &g) {
     auto is_small = [&](int32_t p) { return pw(p) <= kSmallW && g.pan_r[p] <= kSmallR; };
     g.f_lvl.assign(1, 0);
     g.f_nlarge.clear();
+    g.f_nmed.clear();
     g.f_item_panel.clear();
     g.f_item_pair.assign(1, 0);
     g.f_pair_src.clear();
@@ -119,6 +120,7 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         std::vector<std::pair<int32_t, int32_t>> pairs;   // (source, target)
         bool small;
         double cost;
+        int kind = 0;   // 0 wide (up to kPanelMax columns), 1 medium, 2 narrow
     };
     for (int32_t l = 0; l < nlev; ++l) {
         auto &pl = by_launch[l];                  // (target, source)
@@ -159,18 +161,30 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         }
         for (auto &it : items) {
             std::sort(it.pairs.begin(), it.pairs.end());
+            int32_t mw = it.panel >= 0 ? pw(it.panel) : 0;
             for (const auto &pr : it.pairs) {
                 if (!is_small(pr.first)) it.small = false;
                 it.cost += (double)pw(pr.first) * (pw(pr.first) + g.pan_r[pr.first]);
+                mw = std::max(mw, pw(pr.first));
             }
             if (it.panel >= 0) it.cost += (double)pw(it.panel) * pw(it.panel) * (pw(it.panel) + g.pan_r[it.panel]);
+            const bool fits_med =
+                mw <= kMedW && (it.panel < 0 || pw(it.panel) + g.pan_r[it.panel] <= kMedRows);
+            it.kind = it.small ? 2 : fits_med ? 1 : 0;
         }
+        // the medium configuration only where a level has no item that needs the big one
+        // (one launch per level for the wide items)
+        bool any_big = false;
+        for (const auto &it : items) any_big |= it.kind == 0;
+        if (any_big)
+            for (auto &it : items)
+                if (it.kind == 1) it.kind = 0;
         for (int32_t T : panels_at[l]) fac_index[T] = -1;
         std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
-            if (a.small != b.small) return !a.small;
+            if (a.kind != b.kind) return a.kind < b.kind;
             return a.cost > b.cost;
         });
-        int32_t nlarge = 0;
+        int32_t nlarge = 0, nmed = 0;
         for (const auto &it : items) {
             // the wide path solves one source's targets on the lanes of one wavefront
             for (size_t q = 0, q1; q < it.pairs.size(); q = q1) {
@@ -179,6 +193,7 @@ int build_schedule(const Symbolic &s, Schedule &g) {
                 if (q1 - q > (size_t)kGroup) return KKT_ERR_PATTERN;
             }
             nlarge += !it.small;
+            nmed += it.kind == 1;
             g.f_item_panel.push_back(it.panel);
             for (const auto &pr : it.pairs) {
                 g.f_pair_src.push_back(pr.first);
@@ -201,6 +216,7 @@ int build_schedule(const Symbolic &s, Schedule &g) {
             g.f_item_pair.push_back((int32_t)g.f_pair_src.size());
         }
         g.f_nlarge.push_back(nlarge);
+        g.f_nmed.push_back(nmed);
         g.f_lvl.push_back((int32_t)g.f_item_panel.size());
     }
     if (!by_launch[nlev].empty()) return KKT_ERR_PATTERN;   // top panels have no targets
@@ -227,15 +243,30 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         o[3] = 0;
         geom(o + 4, g.f_item_panel[i]);
     }
+    // pairs of narrow items (16-lane path) carry the diagonal slots of all source columns
+    // instead: {ldiag[s+1], pos, rel, ldiag[s+2], ldiag[s+3], w, r, ldiag[s]} (0 past w)
     const size_t npairs = g.f_pair_src.size();
     g.pair8.resize(8 * npairs);
+    std::vector<char> narrow_pair(npairs, 0);
+    for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l)
+        for (int32_t it = g.f_lvl[l] + g.f_nlarge[l]; it < g.f_lvl[l + 1]; ++it)
+            for (int32_t q = g.f_item_pair[it]; q < g.f_item_pair[it + 1]; ++q) narrow_pair[q] = 1;
     for (size_t q = 0; q < npairs; ++q) {
         int32_t *o = &g.pair8[8 * q];
-        o[0] = g.f_pair_src[q];
+        const int32_t S = g.f_pair_src[q];
         o[1] = g.f_pair_pos[q];
         o[2] = (int32_t)g.f_pair_rel[q];
-        o[3] = g.f_pair_tgt[q];
-        geom(o + 4, g.f_pair_src[q]);
+        geom(o + 4, S);
+        if (narrow_pair[q]) {
+            const int32_t sp = g.pan_start[S], w = pw(S);
+            auto dslot = [&](int32_t j) { return j < w ? g.ldiag[sp + j] : 0; };
+            o[0] = dslot(1);
+            o[3] = dslot(2);
+            o[4] = dslot(3);
+        } else {
+            o[0] = S;
+            o[3] = g.f_pair_tgt[q];
+        }
     }
     // solve levels
     std::vector<int32_t> llev(np, 0), ulev(np, 0);
@@ -436,11 +467,13 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         fl += 2.0 * lk * (double)urow[k] + lk;
     }
     g.flops = fl;
-    g.nnz_lu_wide = 0;
+    g.nnz_lu_wide = g.nnz_lu_med = 0;
     for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l)
         for (int32_t it = g.f_lvl[l]; it < g.f_lvl[l] + g.f_nlarge[l]; ++it) {
             const int32_t P = g.f_item_panel[it];
-            if (P >= 0) g.nnz_lu_wide += s.colptr[g.pan_start[P + 1]] - s.colptr[g.pan_start[P]];
+            if (P < 0) continue;
+            const int64_t e = s.colptr[g.pan_start[P + 1]] - s.colptr[g.pan_start[P]];
+            (it < g.f_lvl[l] + g.f_nlarge[l] - g.f_nmed[l] ? g.nnz_lu_wide : g.nnz_lu_med) += e;
         }
     return KKT_OK;
 }
