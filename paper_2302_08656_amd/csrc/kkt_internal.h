@@ -113,10 +113,10 @@ struct Schedule {
     // the early L part, = csr_rowptr[i] when there is none; csr_uearly[i] = start of the
     // early U part, = csr_rowptr[i + 1] when there is none).
     std::vector<int32_t> csr_rowptr, csr_col, csr_src, csr_diag, csr_early, csr_uearly;
-    // value update: for each L+U slot, the CSR entry of A it receives (-1: fill)
-    std::vector<int32_t> lu_src;
-    // CSC view of A's pattern (positions into the CSR value array)
-    std::vector<int32_t> a_cptr, a_cpos, a_rowid;
+    // value update: the L+U slot of each entry of A (CSR order) and the fill-in slots
+    std::vector<int32_t> a_map, lu_fill;
+    // CSC view of A's pattern (positions into the CSR value array, rows)
+    std::vector<int32_t> a_cptr, a_cpos, a_crow;
     double flops = 0.0;
     int64_t nnz_lu_wide = 0;            // L+U entries of columns factored by wide items
     int64_t nnz_lu_med = 0;             // ... by medium wide items

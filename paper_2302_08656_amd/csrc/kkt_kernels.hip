@@ -75,36 +75,60 @@ __global__ __launch_bounds__(256) void k_row_scale(int n, const int32_t *__restr
     }
 }
 
-// c_j from the row-scaled matrix, 8 lanes per column of the CSC view
+// c_j from the row-scaled matrix, 8 lanes per column of the CSC view (crow: row of each
+// CSC entry, cpos: its position in the CSR value array)
 __global__ __launch_bounds__(256) void k_col_scale(int n, const int32_t *__restrict__ cptr,
                                                    const int32_t *__restrict__ cpos,
-                                                   const int32_t *__restrict__ rowid,
+                                                   const int32_t *__restrict__ crow,
                                                    const double *__restrict__ v, const double *__restrict__ r,
                                                    int scale, double *__restrict__ c) {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = gid >> 3, gl = gid & 7;
     double m = 0.0;
     if (j < n)
-        for (int t = cptr[j] + gl; t < cptr[j + 1]; t += 8) {
-            const int p = cpos[t];
-            m = fmax(m, fabs(r[rowid[p]] * v[p]));
-        }
+        for (int t = cptr[j] + gl; t < cptr[j + 1]; t += 8) m = fmax(m, fabs(r[crow[t]] * v[cpos[t]]));
     for (int o = 4; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 8));
     if (j < n && gl == 0) c[j] = scale ? inv_pow2_floor_log2(m) : 1.0;
 }
 
-// ||A||_inf and ||R A C||_inf (row sums in CSR order): block maxima into part[2 * block]
-__global__ __launch_bounds__(256) void k_norms(int n, const int32_t *__restrict__ rowptr,
-                                               const int32_t *__restrict__ col, const double *__restrict__ v,
-                                               const double *__restrict__ r, const double *__restrict__ c,
-                                               double *__restrict__ part) {
+// Scaled values into the factor, lu[map[p]] = (r_i a_ip) c_j, and the row sums of |A| and
+// |R A C| in CSR order (one thread per row, entries loaded eight at a time), block maxima
+// into part[2 * block]; then the fill-in slots of the factor are set to zero.
+__global__ __launch_bounds__(256) void k_scatter_norms(int n, const int32_t *__restrict__ rowptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const double *__restrict__ v, const double *__restrict__ r,
+                                                       const double *__restrict__ c,
+                                                       const int32_t *__restrict__ map, int64_t nfill,
+                                                       const int32_t *__restrict__ fill, double *__restrict__ lu,
+                                                       double *__restrict__ part) {
     __shared__ double red[2][4];
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
     double s = 0.0, a = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (int i = gid; i < n; i += stride) {
+        const int p0 = rowptr[i], p1 = rowptr[i + 1];
+        const double ri = r[i];
         double si = 0.0, ai = 0.0;
-        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-            ai = ai + fabs(v[p]);
-            si = si + fabs((r[i] * v[p]) * c[col[p]]);
+        for (int p = p0; p < p1; p += 8) {
+            int cc[8], mm[8];
+            double vv[8], cj[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const bool h = p + k < p1;
+                cc[k] = h ? col[p + k] : 0;
+                mm[k] = h ? map[p + k] : 0;
+                vv[k] = h ? v[p + k] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) cj[k] = p + k < p1 ? c[cc[k]] : 0.0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (p + k < p1) {
+                    const double t = (ri * vv[k]) * cj[k];
+                    lu[mm[k]] = t;
+                    ai = ai + fabs(vv[k]);
+                    si = si + fabs(t);
+                }
+            }
         }
         s = fmax(s, si);
         a = fmax(a, ai);
@@ -122,6 +146,7 @@ __global__ __launch_bounds__(256) void k_norms(int n, const int32_t *__restrict_
         part[2 * blockIdx.x] = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
         part[2 * blockIdx.x + 1] = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
     }
+    for (int64_t k = gid; k < nfill; k += stride) lu[fill[k]] = 0.0;
 }
 
 // dst[j] = max over blocks b of part[nfield * b + j] (NaN propagates), j < nfield
@@ -147,16 +172,6 @@ __global__ __launch_bounds__(256) void k_max_parts(int nblk, int nfield, const d
         }
         __syncthreads();
     }
-}
-
-__global__ void k_gather_lu(int64_t nlu, const int32_t *__restrict__ src, const int32_t *__restrict__ rowid,
-                            const int32_t *__restrict__ col, const double *__restrict__ v,
-                            const double *__restrict__ r, const double *__restrict__ c,
-                            double *__restrict__ lu) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nlu) return;
-    const int e = src[p];
-    lu[p] = e < 0 ? 0.0 : (r[rowid[e]] * v[e]) * c[col[e]];
 }
 
 // st->perturbed = sum of the spread counter slots

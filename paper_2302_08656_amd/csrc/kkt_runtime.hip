@@ -17,7 +17,7 @@ namespace {
 
 // device pointers carved out of the caller's workspace
 struct Dev {
-    int32_t *a_rowptr, *a_colind, *a_rowid, *a_cptr, *a_cpos, *lu_src;
+    int32_t *a_rowptr, *a_colind, *a_crow, *a_cptr, *a_cpos, *a_map, *lu_fill;
     int32_t *colptr, *rowidx, *ulen, *pan_start, *pan_r;
     int32_t *f_rel, *ldiag;
     int4 *item8, *pair8;
@@ -83,10 +83,11 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     Carver c{base};
     d.a_rowptr = c.take<int32_t>(n + 1);
     d.a_colind = c.take<int32_t>(na);
-    d.a_rowid = c.take<int32_t>(na);
+    d.a_crow = c.take<int32_t>(na);
     d.a_cptr = c.take<int32_t>(n + 1);
     d.a_cpos = c.take<int32_t>(na);
-    d.lu_src = c.take<int32_t>(nlu);
+    d.a_map = c.take<int32_t>(na);
+    d.lu_fill = c.take<int32_t>(std::max<size_t>(1, g.lu_fill.size()));
     d.colptr = c.take<int32_t>(n + 1);
     d.rowidx = c.take<int32_t>(nlu);
     d.ulen = c.take<int32_t>(n);
@@ -262,15 +263,13 @@ int enqueue_refactor(kkt_handle *h, const double *v, hipStream_t s) {
         k_row_scale<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_rowptr, v, eq, d.r, d.st, d.pcount);
     });
     timed(h, KKT_PROF_UPDATE, s, [&] {
-        k_col_scale<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_cptr, d.a_cpos, d.a_rowid, v, d.r, eq, d.c);
+        k_col_scale<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_cptr, d.a_cpos, d.a_crow, v, d.r, eq, d.c);
     });
     timed(h, KKT_PROF_UPDATE, s, [&] {
-        k_norms<<<kNormBlocks, 256, 0, s>>>(n, d.a_rowptr, d.a_colind, v, d.r, d.c, d.part);
+        k_scatter_norms<<<kNormBlocks, 256, 0, s>>>(n, d.a_rowptr, d.a_colind, v, d.r, d.c, d.a_map,
+                                                   (int64_t)g.lu_fill.size(), d.lu_fill, d.lu, d.part);
     });
     timed(h, KKT_PROF_UPDATE, s, [&] { k_max_parts<<<1, 256, 0, s>>>(kNormBlocks, 2, d.part, &d.st->anorm_scaled); });
-    timed(h, KKT_PROF_UPDATE, s, [&] {
-        k_gather_lu<<<blocks_for(nlu, 256), 256, 0, s>>>(nlu, d.lu_src, d.a_rowid, d.a_colind, v, d.r, d.c, d.lu);
-    });
     RefArgs a{d.ldiag, d.item8, d.pair8, d.f_rel, d.lu, d.st, d.pcount,
               h->opts.tiny_pivot, h->opts.dense_mfma != 0};
     for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
@@ -570,10 +569,11 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     int rc = KKT_OK;
     rc |= upload(d.a_rowptr, rp32, stream);
     rc |= upload(d.a_colind, s.a_colind, stream);
-    rc |= upload(d.a_rowid, g.a_rowid, stream);
+    rc |= upload(d.a_crow, g.a_crow, stream);
     rc |= upload(d.a_cptr, g.a_cptr, stream);
     rc |= upload(d.a_cpos, g.a_cpos, stream);
-    rc |= upload(d.lu_src, g.lu_src, stream);
+    rc |= upload(d.a_map, g.a_map, stream);
+    rc |= upload(d.lu_fill, g.lu_fill, stream);
     rc |= upload(d.colptr, cp32, stream);
     rc |= upload(d.rowidx, s.rowidx, stream);
     rc |= upload(d.ulen, s.ulen, stream);

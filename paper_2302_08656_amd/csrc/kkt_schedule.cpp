@@ -440,22 +440,33 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         g.u_rows4[k + 1] = g.csr_diag[i] + (w - t);
         g.u_rows4[k + 2] = g.csr_rowptr[i + 1];
     }
-    // value update map and CSC view of A
-    g.lu_src.assign(nlu, -1);
-    for (int64_t e = 0; e < s.nnz_a; ++e) g.lu_src[s.map[e]] = (int32_t)e;
-    g.a_cptr.assign(n + 1, 0);
-    g.a_rowid.resize(s.nnz_a);
-    for (int32_t i = 0; i < n; ++i)
-        for (int64_t p = s.a_rowptr[i]; p < s.a_rowptr[i + 1]; ++p) {
-            g.a_rowid[p] = i;
-            g.a_cptr[s.a_colind[p] + 1]++;
+    // value update: the factor slot of each entry of A (CSR order), the fill-in slots, and
+    // the CSC view of A (position in the CSR value array and row of each entry)
+    g.a_map.resize(s.nnz_a);
+    {
+        std::vector<char> hit(nlu, 0);
+        for (int64_t e = 0; e < s.nnz_a; ++e) {
+            g.a_map[e] = (int32_t)s.map[e];
+            hit[s.map[e]] = 1;
         }
+        g.lu_fill.clear();
+        for (int64_t p = 0; p < nlu; ++p)
+            if (!hit[p]) g.lu_fill.push_back((int32_t)p);
+    }
+    g.a_cptr.assign(n + 1, 0);
+    for (int32_t i = 0; i < n; ++i)
+        for (int64_t p = s.a_rowptr[i]; p < s.a_rowptr[i + 1]; ++p) g.a_cptr[s.a_colind[p] + 1]++;
     for (int32_t j = 0; j < n; ++j) g.a_cptr[j + 1] += g.a_cptr[j];
     g.a_cpos.resize(s.nnz_a);
+    g.a_crow.resize(s.nnz_a);
     {
         std::vector<int32_t> nxt(g.a_cptr.begin(), g.a_cptr.end() - 1);
         for (int32_t i = 0; i < n; ++i)
-            for (int64_t p = s.a_rowptr[i]; p < s.a_rowptr[i + 1]; ++p) g.a_cpos[nxt[s.a_colind[p]]++] = (int32_t)p;
+            for (int64_t p = s.a_rowptr[i]; p < s.a_rowptr[i + 1]; ++p) {
+                const int32_t t = nxt[s.a_colind[p]]++;
+                g.a_cpos[t] = (int32_t)p;
+                g.a_crow[t] = i;
+            }
     }
     // refactor flops: sum_k 2 |L(:,k)| |U(k,:)| + |L(:,k)|
     std::vector<int64_t> urow(n, 0);
