@@ -462,8 +462,8 @@ constexpr int kStagePairs = 256;
 // staged per chunk, widest panel (target and sources) and update tiles per wavefront and
 // pass.  LDS layout (bytes): Ld (the source's diagonal block, later the factored panel's U)
 // | Ub (solved rows per target) | Lr (a chunk of the source's L rows) | lds (the source's
-// diagonal slots) | sgs (slot of row s in each column of the panel to factor) | staged pair
-// records.
+// diagonal slots) | sgs (slot of row s in each column of the panel to factor) | flg (pivot
+// rows published by the panel sweep) | staged pair records.
 template <int T, int WV, int CH, int MW, int TI>
 struct WideCfg {
     static constexpr int kThreads = T;
@@ -476,7 +476,8 @@ struct WideCfg {
     static constexpr int kOffLr = kOffUb + kPanelMax * kGroup * 8;
     static constexpr int kOffLds = kOffLr + kChunk * kMaxW * 8;
     static constexpr int kOffSgs = kOffLds + kPanelMax * 4;
-    static constexpr int kOffPairs = kOffSgs + kPanelMax * 4;
+    static constexpr int kOffFlg = kOffSgs + kPanelMax * 4;
+    static constexpr int kOffPairs = kOffFlg + kPanelMax * 4;
     static constexpr int kLds = kOffPairs + kStagePairs * 32;
 };
 // panels up to 32 columns: one block per CU
@@ -534,48 +535,72 @@ __device__ __forceinline__ void sweep_step(double (&x)[kPanelMax], const double 
 }
 
 // Dense LU without pivoting of a wide panel's block column (w + r rows, w columns).  Thread
-// t owns panel row t (t < w: the diagonal block; below: the L rows) for t < C::kThreads;
-// step j: the owner of row j perturbs its pivot and publishes U(j, j..) in LDS
-// (Us[j * kPanelMax + c] = U(j, j + c), zero past the panel), then after one barrier every
-// later row takes its multiplier and update from it.  The sweep narrows from KW to
-// KW / 2 register columns once no more than KW / 2 columns remain.  Rows beyond the
-// first C::kThreads are eliminated afterwards from the finished Us.  sgs[c] = slot of row s
-// in column s + c (staged by the caller); row t of the panel is at slot sgs[c] + t.
+// t owns panel row t (t < w: the diagonal block; below: the L rows) for t < C::kThreads.
+// All pivot rows are in wavefront 0, which runs the whole sweep without waiting: at step j
+// lane j perturbs its pivot if tiny, publishes U(j, j..) in LDS (Us[j * kPanelMax + c] =
+// U(j, j + c), zero past the panel) and raises flg[j]; every later row of the wavefront
+// takes its multiplier and update from it.  The other wavefronts follow, waiting (bounded)
+// on flg[j] before step j.  The sweep narrows from KW to KW / 2 register columns once no
+// more than KW / 2 columns remain.  Rows beyond the first C::kThreads are eliminated
+// afterwards from the finished Us.  sgs[c] = slot of row s in column s + c (staged by the
+// caller); row t of the panel is at slot sgs[c] + t.
+constexpr int kSweepSpin = 1 << 22;
+
 template <class C, int KW>
 __device__ __forceinline__ void large_factor_w(const RefArgs &a, int w, int r, char *sm, double thresh,
                                                int item) {
     const int tid = threadIdx.x, lane = tid & 63;
     double *Us = reinterpret_cast<double *>(sm + C::kOffLd);
     const int *sgs = reinterpret_cast<const int *>(sm + C::kOffSgs);
+    int *flg = reinterpret_cast<int *>(sm + C::kOffFlg);
     const int nrow = w + r;
     int npert = 0, bad = 0;
     double x[kPanelMax];
 #pragma unroll
     for (int c = 0; c < kPanelMax; ++c) x[c] = 0.0;
     if (tid < nrow) load_row<KW>(x, a.lu, sgs, w, tid);
+    if (tid < kPanelMax) flg[tid] = 0;
+    __syncthreads();
     constexpr int KH = KW / 2;
     const int jsplit = max(0, w - KH);          // steps with more than KH columns left
+    if (tid < 64) {
 #pragma unroll 1
-    for (int j = 0; j < w; ++j) {
-        if (tid == j) {
-            x[0] = perturb(x[0], thresh, npert);
-            double2 *o = reinterpret_cast<double2 *>(Us + j * kPanelMax);
-            if (j < jsplit) {
+        for (int j = 0; j < w; ++j) {
+            // the window past the panel's remaining columns holds zeros (shifted in, and
+            // untouched by the narrowed sweep), so the whole window is published as it is
+            if (tid == j) {
+                x[0] = perturb(x[0], thresh, npert);
+                bad |= !isfinite(x[0]);
+                double2 *o = reinterpret_cast<double2 *>(Us + j * kPanelMax);
 #pragma unroll
                 for (int c = 0; c < KW / 2; ++c) o[c] = double2{x[2 * c], x[2 * c + 1]};
-            } else {
-#pragma unroll
-                for (int c = 0; c < KH / 2; ++c) o[c] = double2{x[2 * c], x[2 * c + 1]};
-#pragma unroll
-                for (int c = KH / 2; c < KW / 2; ++c) o[c] = double2{0.0, 0.0};
             }
+            __builtin_amdgcn_wave_barrier();
+            if (tid > j && tid < nrow) {
+                double *dst = a.lu + sgs[j] + tid;
+                if (j < jsplit) sweep_step<KW>(x, Us + j * kPanelMax, dst, bad);
+                else sweep_step<KH>(x, Us + j * kPanelMax, dst, bad);
+            }
+            // the other wavefronts may read row j once it is complete in LDS
+            if (tid == j) __hip_atomic_store(flg + j, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        __syncthreads();
-        if (tid == 0) bad |= !isfinite(Us[j * kPanelMax]);
-        if (tid > j && tid < nrow) {
-            double *dst = a.lu + sgs[j] + tid;
-            if (j < jsplit) sweep_step<KW>(x, Us + j * kPanelMax, dst, bad);
-            else sweep_step<KH>(x, Us + j * kPanelMax, dst, bad);
+    } else if (tid - lane < nrow) {             // a wavefront with rows to eliminate
+#pragma unroll 1
+        for (int j = 0; j < w; ++j) {
+            int spin = 0;
+            while (__hip_atomic_load(flg + j, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
+                if (++spin > kSweepSpin) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (spin > kSweepSpin) {
+                if (lane == 0) atomicOr(&a.st->flags, kFlagInternal);
+                break;
+            }
+            if (tid < nrow) {
+                double *dst = a.lu + sgs[j] + tid;
+                if (j < jsplit) sweep_step<KW>(x, Us + j * kPanelMax, dst, bad);
+                else sweep_step<KH>(x, Us + j * kPanelMax, dst, bad);
+            }
         }
     }
     KKT_PHASE(item, 6);
