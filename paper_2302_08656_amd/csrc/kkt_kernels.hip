@@ -645,8 +645,11 @@ __device__ __forceinline__ void unit_lower_w(double *lu, int ps, int w, const do
         u[c] = c < w ? v : 0.0;
     }
     KKT_PHASE(item, 8);
+    // the window narrows to KW / 2 columns once no more remain (the rest are zeros)
+    constexpr int KH = KW / 2;
+    const int jsplit = max(0, w - KH);
 #pragma unroll 1
-    for (int j = 0; j < w; ++j) {
+    for (int j = 0; j < jsplit; ++j) {
         double rw[kPanelMax];
         load_lds_row<KW>(rw, Ls + j * kPanelMax);
         __builtin_amdgcn_sched_barrier(0);
@@ -654,6 +657,16 @@ __device__ __forceinline__ void unit_lower_w(double *lu, int ps, int w, const do
         lu[ps + j] = uj;
         ub[j] = uj;
         shift_fma<KW>(u, uj, rw);
+    }
+#pragma unroll 1
+    for (int j = jsplit; j < w; ++j) {
+        double rw[kPanelMax];
+        load_lds_row<KH>(rw, Ls + j * kPanelMax);
+        __builtin_amdgcn_sched_barrier(0);
+        const double uj = u[0];
+        lu[ps + j] = uj;
+        ub[j] = uj;
+        shift_fma<KH>(u, uj, rw);
     }
     KKT_PHASE(item, 9);
 }
