@@ -32,6 +32,8 @@ def parse():
     ap.add_argument("--config", type=int, default=2, help="workload index: 0 grid200, 1 grid25k, 2 grid70k")
     ap.add_argument("--cpu-sample", type=int, default=8, help="oracle units timed for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain MIB-MiB device copy (counter scaling reference) and exit")
     return ap.parse_args()
 
 
@@ -41,17 +43,54 @@ def nearest_rank(xs, p):
     return s[k - 1]
 
 
-def algorithmic_bytes(n, nnz_a, nnz_lu):
-    """Compulsory HBM bytes of one refactorization (value update, panel factorization and
-    the row-ordered copy) and of one triangular solve, with int32 indices and FP64 values.
-    refactor: read values + map (12 nnz_a), read/write every factor value once and its row
-    index (20 nnz_lu), scale factors and pointers (16 n), CSR copy (read slot index, read
-    and write value: 20 nnz_lu); solve: values + column index (12 nnz_lu) plus vectors and
-    pointers (48 n)."""
-    refactor = 12 * nnz_a + 20 * nnz_lu + 16 * n + 20 * nnz_lu
-    solve = 12 * nnz_lu + 48 * n
-    spmv = 12 * nnz_a + 28 * n
-    return refactor, solve, spmv
+def unit_bytes(n, nnz_a, nnz_lu, k):
+    """Compulsory HBM bytes of one unit with k FGMRES iterations (int32 indices, FP64
+    values): the refactorization reads A's values and map and writes every factor value
+    once, each solve reads the factor once, each residual/product reads A once, and
+    Arnoldi step j reads and writes j+2 basis-length vectors."""
+    b_ref = 12 * nnz_a + 12 * nnz_lu + 16 * n
+    b_solve = 12 * nnz_lu + 48 * n
+    b_spmv = 12 * nnz_a + 28 * n
+    b_orth = sum(32 * (j + 2) * n + 8 * n for j in range(1, k + 1))
+    return b_ref + (k + 2) * b_spmv + (k + 1) * b_solve + b_orth + 16 * n
+
+
+def copy_calibration(mib):
+    """Runs a plain device-to-device copy of MIB MiB five times: the reference against which
+    the HBM byte counters (FETCH_SIZE, WRITE_SIZE) of the path's kernels are scaled."""
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    n = mib * (1 << 20) // 8
+    x = torch.rand(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 8, "copies": 5, "check": bool(torch.equal(x, y))}))
+
+
+def kernel_source_digest():
+    """SHA-256 of the kernel source, which ties a stored counter reading to the kernels it
+    was taken from."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2302_08656_amd", "csrc", "kkt_kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of KERNEL from the stored counter summary (FETCH_SIZE + WRITE_SIZE,
+    scaled by the same counters on a plain copy), or None when there is no reading for this
+    kernel or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "kkt_grid70k_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic-record: "):
+            rec = json.loads(line[len("traffic-record: "):])
+            if rec.get("kernel") == kernel and rec.get("source_sha256") == kernel_source_digest():
+                return rec["bytes_per_launch"]
+    return None
 
 
 def main():
@@ -60,6 +99,9 @@ def main():
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU design is described but not built)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import numpy as np
     import torch
 
@@ -141,22 +183,26 @@ def main():
         "to_csr": 20 * st["nnz_lu"] * nprof,
         "update": (12 * q.nnz + 12 * st["nnz_lu"] + 40 * q.n) * nprof,
     }
-    kernel_of = {"refactor_large": "k_refactor_wide<BigCfg>", "refactor_medium": "k_refactor_wide<MedCfg>",
+    kernel_of = {"refactor_large": "k_refactor_wide<WideCfg<512, 2, 256, 32, 4> >",
+                 "refactor_medium": "k_refactor_wide<WideCfg<256, 4, 128, 16, 2> >",
                  "refactor_small": "k_refactor_small",
                  "lsolve": "k_lsolve_persistent", "usolve": "k_usolve_persistent", "to_csr": "k_to_csr",
-                 "update": "k_row_scale..k_gather_lu", "residual": "k_residual/k_spmv", "krylov": "krylov"}
+                 "update": "k_row_scale..k_max_parts", "residual": "k_residual/k_spmv", "krylov": "krylov"}
     ranked = sorted((v[1], k) for k, v in prof.items())
     dom = ranked[-1][1]
     launches, ms = prof[dom]
     if per_unit.get(dom) and launches:
         ach = per_unit[dom] / (ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(ach, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 6), "traffic": None,
+                    "frac": round(ach / HBM_PEAK_GBS, 6), "traffic": stored_traffic(kernel_of[dom]),
                     "kernel": kernel_of[dom], "launches": launches, "avg_launch_us": round(ms / launches * 1e3, 3),
                     "bytes_per_launch": per_unit[dom] // launches}
     else:
         roofline = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
                     "traffic": None, "kernel": kernel_of.get(dom, dom)}
+    b_unit = sum(unit_bytes(q.n, q.nnz, st["nnz_lu"], k) for k in iters) / len(iters)
+    whole = {"bytes_per_unit": int(b_unit), "achieved": round(b_unit * value / 1e9, 3), "unit": "GB/s",
+             "frac": round(b_unit * value / 1e9 / HBM_PEAK_GBS, 6)}
     breakdown = {k: {"launches_per_unit": round(v[0] / nprof, 2), "ms_per_unit": round(v[1] / nprof, 4)}
                  for k, v in prof.items()}
 
@@ -172,6 +218,7 @@ def main():
         "failures": fails, "fgmres_iters_mean": round(float(np.mean(iters)), 3),
         "berr_max": float(np.max(berrs)),
         "roofline": roofline,
+        "whole_unit_bytes": whole,
         "kernel_breakdown": breakdown,
     }
     if not args.no_cpu_baseline:
