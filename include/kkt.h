@@ -78,6 +78,12 @@ typedef struct {
      * which blocks take work items in dependency order and wait, bounded, for the unknowns
      * they read; 0 = one launch per dependency level throughout. */
     int32_t persistent_solve;
+    /* 1 = the refactorization's per-level launches (everything after the value update) are
+     * recorded into a HIP graph at the first kkt_refactor after kkt_bind and replayed by
+     * later calls on the caller's stream (default); they are launched one by one while the
+     * launch profiler is on, when the caller's stream is itself being captured, or when
+     * recording fails.  0 = always one by one.  Results are bitwise identical either way. */
+    int32_t graph_refactor;
 } kkt_opts;
 
 typedef struct {
@@ -135,8 +141,10 @@ int kkt_workspace_bytes(const kkt_handle *h, int32_t max_nrhs, size_t *bytes);
 /* Setup (Algorithm 1, set up the GPU refactorization): uploads the symbolic structure and
  * schedules into d_workspace (device, >= kkt_workspace_bytes, 256-byte aligned) on stream
  * and records the device; the first bind also creates the handle's two internal streams
- * (used inside kkt_refactor, always joined back into the caller's stream).  A handle stays on
- * its first device: binding again on another one returns STATE.  Waits for the upload.
+ * (one runs narrow refactorization items beside the wide ones and is always joined back
+ * into the caller's stream; the other only records the refactorization graph).  Binding
+ * again drops the recorded graph.  A handle stays on its first device: binding again on
+ * another one returns STATE.  Waits for the upload.
  * Errors: ARG, NOMEM (too small), STATE, DEVICE. */
 int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs,
              hipStream_t stream);
@@ -144,8 +152,12 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs,
 /* Value update and refactorization without pivoting (Algorithm 1, update the factor
  * object with the new values, refactor).  d_values: device FP64[nnz_a] in the analysed
  * CSR order, BORROWED until the next kkt_refactor or kkt_destroy (kkt_refine reads it for
- * residuals).  Asynchronous.  Errors: ARG, STATE (not bound), DEVICE.  Tiny pivots and
- * non-finite factors are reported by kkt_refine / kkt_refactor_status. */
+ * residuals).  Asynchronous: the value update is launched on stream, then the level
+ * launches, replayed from the graph recorded at the first call after kkt_bind when
+ * opts.graph_refactor is set (the first call also records it, which takes longer).  Calls
+ * on one handle must be ordered by the caller (they share the workspace).  Errors: ARG,
+ * STATE (not bound), DEVICE.  Tiny pivots and non-finite factors are reported by
+ * kkt_refine / kkt_refactor_status. */
 int kkt_refactor(kkt_handle *h, const double *d_values, hipStream_t stream);
 
 /* Waits for the last refactorization; *perturbed = replaced pivots.  Returns OK,

@@ -64,8 +64,13 @@ struct kkt_handle {
     int grid_l = 1, grid_u = 1;  // co-resident blocks of the persistent solve kernels
     // second stream of the refactorization: the narrow and the wide items of one level run
     // concurrently, joined by a pair of events per level
-    hipStream_t side = nullptr, side2 = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // the refactorization's per-level launches, recorded once per bind on the capture stream
+    // and replayed on the caller's stream
+    hipStream_t cap = nullptr;
+    hipGraphExec_t levels = nullptr;
+    bool levels_failed = false;
     // launch profiler
     bool prof = false;
     kkt_profile acc{};
@@ -253,11 +258,11 @@ int enqueue_solve(kkt_handle *h, const double *b, double *x, hipStream_t s) {
     return KKT_OK;
 }
 
-int enqueue_refactor(kkt_handle *h, const double *v, hipStream_t s) {
+// value update: scale factors, scaled values scattered into the factor, norms
+int enqueue_update(kkt_handle *h, const double *v, hipStream_t s) {
     const Schedule &g = h->sch;
     const Dev &d = h->d;
     const int n = h->sym.n;
-    const int64_t nlu = h->sym.nnz_lu();
     const int eq = h->opts.equilibrate != 0;
     timed(h, KKT_PROF_UPDATE, s, [&] {
         k_row_scale<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_rowptr, v, eq, d.r, d.st, d.pcount);
@@ -270,6 +275,16 @@ int enqueue_refactor(kkt_handle *h, const double *v, hipStream_t s) {
                                                    (int64_t)g.lu_fill.size(), d.lu_fill, d.lu, d.part);
     });
     timed(h, KKT_PROF_UPDATE, s, [&] { k_max_parts<<<1, 256, 0, s>>>(kNormBlocks, 2, d.part, &d.st->anorm_scaled); });
+    HIPCHK(hipGetLastError());
+    return KKT_OK;
+}
+
+// the level launches of the refactorization, the row-ordered copy and the pivot count; they
+// read only workspace buffers, so one recording serves every later call
+int enqueue_levels(kkt_handle *h, hipStream_t s) {
+    const Schedule &g = h->sch;
+    const Dev &d = h->d;
+    const int64_t nlu = h->sym.nnz_lu();
     RefArgs a{d.ldiag, d.item8, d.pair8, d.f_rel, d.lu, d.st, d.pcount,
               h->opts.tiny_pivot, h->opts.dense_mfma != 0};
     for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
@@ -439,6 +454,7 @@ void kkt_default_opts(kkt_opts *o) {
     o->fixed_q = nullptr;
     o->dense_mfma = 1;
     o->persistent_solve = 1;
+    o->graph_refactor = 1;
 }
 
 int kkt_analyze(int32_t n, const int64_t *rowptr, const int32_t *colind, const double *values_k1,
@@ -550,12 +566,17 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     }
     if (!h->h_small) HIPCHK(hipHostMalloc(&h->h_small, sizeof(double) * 4 * (kMaxRestart + 2) + 256));
     if (h->side && h->device != dev) return KKT_ERR_STATE;   // rebinding keeps the device
+    if (h->levels) {   // recorded with the previous workspace's addresses
+        HIPCHK(hipStreamSynchronize(h->cap));
+        HIPCHK(hipGraphExecDestroy(h->levels));
+        h->levels = nullptr;
+    }
+    h->levels_failed = false;
     if (!h->side) {
         HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
-        HIPCHK(hipStreamCreateWithFlags(&h->side2, hipStreamNonBlocking));
+        HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
-        HIPCHK(hipEventCreateWithFlags(&h->ev_join2, hipEventDisableTiming));
     }
     carve(h, static_cast<char *>(d_workspace), h->d, &need);
     const Symbolic &s = h->sym;
@@ -605,12 +626,52 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     return KKT_OK;
 }
 
+namespace {
+
+// records the level launches on the capture stream into h->levels; on any failure the
+// calls fall back to launching them one by one
+void record_levels(kkt_handle *h) {
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        h->levels_failed = true;
+        return;
+    }
+    const int rc = enqueue_levels(h, h->cap);
+    const hipError_t e = hipStreamEndCapture(h->cap, &graph);
+    if (rc != KKT_OK || e != hipSuccess || !graph ||
+        hipGraphInstantiate(&h->levels, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        h->levels = nullptr;
+        h->levels_failed = true;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+}
+
+int run_levels(kkt_handle *h, hipStream_t s) {
+    if (h->opts.graph_refactor && !h->prof && !h->levels_failed) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIPCHK(hipStreamIsCapturing(s, &cs));
+        if (cs == hipStreamCaptureStatusNone) {
+            if (!h->levels) record_levels(h);
+            if (h->levels) {
+                HIPCHK(hipGraphLaunch(h->levels, s));
+                return KKT_OK;
+            }
+        }
+    }
+    return enqueue_levels(h, s);
+}
+
+}  // namespace
+
 int kkt_refactor(kkt_handle *h, const double *d_values, hipStream_t stream) {
     if (!h || !d_values) return KKT_ERR_ARG;
     if (!h->bound) return KKT_ERR_STATE;
     DeviceGuard dg(h->device);
     if (!dg.ok) return KKT_ERR_DEVICE;
-    int rc = enqueue_refactor(h, d_values, stream);
+    int rc = enqueue_update(h, d_values, stream);
+    if (!rc) rc = run_levels(h, stream);
     if (rc) return rc;
     h->d_values = d_values;
     h->factored = true;
@@ -707,12 +768,12 @@ void kkt_destroy(kkt_handle *h) {
     if (h->side) {
         DeviceGuard g(h->device);
         (void)hipStreamSynchronize(h->side);
-        (void)hipStreamSynchronize(h->side2);
+        (void)hipStreamSynchronize(h->cap);
+        if (h->levels) (void)hipGraphExecDestroy(h->levels);
         (void)hipStreamDestroy(h->side);
-        (void)hipStreamDestroy(h->side2);
+        (void)hipStreamDestroy(h->cap);
         (void)hipEventDestroy(h->ev_fork);
         (void)hipEventDestroy(h->ev_join);
-        (void)hipEventDestroy(h->ev_join2);
     }
     for (auto &pe : h->ev_pending) h->ev_free.push_back(pe.second);
     for (auto &ev : h->ev_free) {

@@ -152,6 +152,32 @@ def test_persistent_and_level_solves_agree_bitwise():
         assert np.isfinite(xs[1][j]).all()
 
 
+def test_graph_replayed_refactor_matches_one_by_one():
+    print("[gpu] graph-replayed vs one-by-one refactorization", flush=True)
+    q = kktgen.make_sequence(kktgen.small(3000, config_id=149, steps=4))
+    sg = K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0), graph_refactor=1).bind()
+    se = K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0), graph_refactor=0).bind()
+    assert sg.stats["gpu_levels_f"] > 1
+
+    def both(t):
+        vd = cuda(q.values(t))
+        se.refactor(vd)                     # eager work between the replays
+        lu_e, r_e, c_e = se.export_factors()
+        sg.refactor(vd)
+        lu_g, r_g, c_g = sg.export_factors()
+        assert np.array_equal(lu_e, lu_g) and np.array_equal(r_e, r_g) and np.array_equal(c_e, c_g)
+        assert sg.refactor_status() == se.refactor_status()
+
+    for t in range(4):
+        both(t)
+    sg.profile(True)                        # launched one by one while profiling
+    both(1)
+    sg.profile(False)
+    sg.bind()                               # a new workspace drops the recording
+    both(2)
+    both(3)
+
+
 def test_deterministic_refactor_and_solve():
     print("[gpu] determinism", flush=True)
     q = kktgen.make_sequence(kktgen.small(500, config_id=144))
