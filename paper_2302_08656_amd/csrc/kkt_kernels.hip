@@ -458,6 +458,11 @@ __global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, R
 
 constexpr int kStagePairs = 256;
 
+// LDS row stride (doubles) of per-lane rows that the lanes of a wavefront read or write at
+// the same column at once: rows start four banks apart, so 16 consecutive lanes touch
+// distinct banks, and 16-byte alignment is kept for paired reads
+constexpr int kRowLd = kPanelMax + 2;
+
 // Configurations of the wide path: threads per block, minimum waves per SIMD, source L rows
 // staged per chunk, widest panel (target and sources) and update tiles per wavefront and
 // pass.  LDS layout (bytes): Ld (the source's diagonal block, later the factored panel's U)
@@ -473,7 +478,7 @@ struct WideCfg {
     static constexpr int kTiles = TI;
     static constexpr int kOffLd = 0;
     static constexpr int kOffUb = kOffLd + kMaxW * kPanelMax * 8;
-    static constexpr int kOffLr = kOffUb + kPanelMax * kGroup * 8;
+    static constexpr int kOffLr = kOffUb + kRowLd * kGroup * 8;
     static constexpr int kOffLds = kOffLr + kChunk * kMaxW * 8;
     static constexpr int kOffSgs = kOffLds + kPanelMax * 4;
     static constexpr int kOffFlg = kOffSgs + kPanelMax * 4;
@@ -754,7 +759,7 @@ __global__ __launch_bounds__(C::kThreads, C::kWaves) void k_refactor_wide(int it
         // target's rows in registers
         if (wv == 0 && lane < m) {
             const int ps = pra(g0 + lane).y;
-            double *ub = Ub + lane * kPanelMax;
+            double *ub = Ub + lane * kRowLd;
             if (C::kMaxW > 16 && w > 16) unit_lower_w<C::kMaxW>(a.lu, ps, w, Ld, ub, item);
             else if (w > 8) unit_lower_w<16>(a.lu, ps, w, Ld, ub, item);
             else unit_lower_w<8>(a.lu, ps, w, Ld, ub, item);
@@ -789,7 +794,7 @@ __global__ __launch_bounds__(C::kThreads, C::kWaves) void k_refactor_wide(int it
                                 const int ia2 = ti * 16 + li, tb = tt * 16 + li;
                                 const bool ok = tile < mt * nt && kk < w;
                                 av[k] = (ok && ia2 < nr) ? Lr[kk * C::kChunk + ia2] : 0.0;
-                                bv[k] = (ok && tb < m) ? Ub[tb * kPanelMax + kk] : 0.0;
+                                bv[k] = (ok && tb < m) ? Ub[tb * kRowLd + kk] : 0.0;
                             }
 #pragma unroll
                             for (int k = 0; k < kTiles; ++k)
@@ -823,7 +828,7 @@ __global__ __launch_bounds__(C::kThreads, C::kWaves) void k_refactor_wide(int it
             } else {
                 for (int q = g0 + wv; q < g1; q += nw) {
                     const int32_t *rel = a.rel + pra(q).z + i0;
-                    const double *ub = Ub + (q - g0) * kPanelMax;
+                    const double *ub = Ub + (q - g0) * kRowLd;
                     for (int i = lane; i < nr; i += 64) {
                         double acc = 0.0;
                         for (int j = 0; j < w; ++j) acc = fma(Lr[j * C::kChunk + i], ub[j], acc);
@@ -1083,7 +1088,7 @@ __device__ __forceinline__ void lsolve_item(const SolveArgs &a, int item, double
         KKT_SPHASE(item, 3);
         return;
     }
-    // wide panel: the in-panel rows are staged in LDS (blk[r * kPanelMax + t] = L(r, t),
+    // wide panel: the in-panel rows are staged in LDS (blk[r * kRowLd + t] = L(r, t),
     // zero on and above the diagonal) alongside the first loads of the external part
     {
         const int lanes = it.y, t = tid / lanes, gl = tid % lanes;
@@ -1091,7 +1096,7 @@ __device__ __forceinline__ void lsolve_item(const SolveArgs &a, int item, double
         for (int e = tid; e < w * kPanelMax; e += kBlock) {
             const int r = e / kPanelMax, c = e % kPanelMax;
             const int d = a.rinfo[s + r].z;
-            blk[e] = c < r ? a.lucsr[d - r + c] : 0.0;
+            blk[r * kRowLd + c] = c < r ? a.lucsr[d - r + c] : 0.0;
         }
         if (t < w) {
             const double bv = gl == 0 ? a.bp[s + t] : 0.0;
@@ -1106,7 +1111,7 @@ __device__ __forceinline__ void lsolve_item(const SolveArgs &a, int item, double
     KKT_SPHASE(item, 2);
     if (tid < 64) {
         double Lrow[kPanelMax];
-        load_lds_row<kPanelMax>(Lrow, blk + min(lane, kPanelMax - 1) * kPanelMax);
+        load_lds_row<kPanelMax>(Lrow, blk + min(lane, kPanelMax - 1) * kRowLd);
         double yv = lane < w ? ext[lane] : 0.0;
         yv = inpanel_forward(Lrow, w, lane, yv);
         if (lane < w) put_value<kWait>(a.y + s + lane, yv);
@@ -1168,14 +1173,14 @@ __device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double
         KKT_UPHASE(item, 3);
         return;
     }
-    // in-panel rows staged in LDS: blk[r * kPanelMax + t] = U(r, t) for t > r, else zero
+    // in-panel rows staged in LDS: blk[r * kRowLd + t] = U(r, t) for t > r, else zero
     double dv = 1.0, yv = 0.0, ci = 0.0;
     int qi = 0;
     {
         for (int e = tid; e < w * kPanelMax; e += kBlock) {
             const int r = e / kPanelMax, c = e % kPanelMax;
             const int d = a.rinfo[s + r].x;
-            blk[e] = c > r && c < w ? a.lucsr[d + (c - r)] : 0.0;
+            blk[r * kRowLd + c] = c > r && c < w ? a.lucsr[d + (c - r)] : 0.0;
         }
         if (tid < w) {
             const int i = s + tid;
@@ -1198,7 +1203,7 @@ __device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double
     KKT_UPHASE(item, 2);
     if (tid < 64) {
         double Urow[kPanelMax];
-        load_lds_row<kPanelMax>(Urow, blk + min(lane, kPanelMax - 1) * kPanelMax);
+        load_lds_row<kPanelMax>(Urow, blk + min(lane, kPanelMax - 1) * kRowLd);
         const double val = lane < w ? yv - ext[lane] : 0.0;
         const double xv = inpanel_backward(Urow, dv, w, lane, val);
         if (lane < w) {
@@ -1212,13 +1217,13 @@ __device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double
 
 __global__ __launch_bounds__(256) void k_lsolve_level(int item0, SolveArgs a) {
     __shared__ double ext[kPanelMax];
-    __shared__ __align__(16) double blk[kPanelMax * kPanelMax];
+    __shared__ __align__(16) double blk[kPanelMax * kRowLd];
     lsolve_item<false>(a, item0 + blockIdx.x, ext, blk);
 }
 
 __global__ __launch_bounds__(256) void k_usolve_level(int item0, SolveArgs a) {
     __shared__ double ext[kPanelMax];
-    __shared__ __align__(16) double blk[kPanelMax * kPanelMax];
+    __shared__ __align__(16) double blk[kPanelMax * kRowLd];
     usolve_item<false>(a, item0 + blockIdx.x, ext, blk);
 }
 
@@ -1228,13 +1233,13 @@ __global__ __launch_bounds__(256) void k_usolve_level(int item0, SolveArgs a) {
 // proceed: with every block resident (cooperative launch) the launch always drains.
 __global__ __launch_bounds__(256) void k_lsolve_persistent(int i0, int i1, SolveArgs a) {
     __shared__ double ext[kPanelMax];
-    __shared__ __align__(16) double blk[kPanelMax * kPanelMax];
+    __shared__ __align__(16) double blk[kPanelMax * kRowLd];
     for (int item = i0 + blockIdx.x; item < i1; item += gridDim.x) lsolve_item<true>(a, item, ext, blk);
 }
 
 __global__ __launch_bounds__(256) void k_usolve_persistent(int i0, int i1, SolveArgs a) {
     __shared__ double ext[kPanelMax];
-    __shared__ __align__(16) double blk[kPanelMax * kPanelMax];
+    __shared__ __align__(16) double blk[kPanelMax * kRowLd];
     for (int item = i0 + blockIdx.x; item < i1; item += gridDim.x) usolve_item<true>(a, item, ext, blk);
 }
 
