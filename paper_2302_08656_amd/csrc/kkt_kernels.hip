@@ -394,10 +394,12 @@ __device__ __forceinline__ int small_factor(const RefArgs &a, int4 pn, int ldg, 
 // kBlock/16 items per block, one per 16-lane group.  kPipe: the next pair's source side is
 // loaded while the current pair is applied (fewer dependent rounds per item, more registers:
 // for levels with few items); otherwise one pair at a time (more items in flight).
+// Group g (16 lanes) runs narrow item item0 + g when g < nsmall; the wavefront's perturbed
+// pivots go to counter slot `slot`.  No block-wide synchronisation: the groups of a block
+// are independent.
 template <bool kPipe>
-__global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, RefArgs a) {
+__device__ __forceinline__ void small_group(int item0, int nsmall, const RefArgs &a, int g, int slot) {
     const double thresh = a.tiny * a.st->anorm_scaled;
-    const int g = blockIdx.x * (kBlock / 16) + (threadIdx.x >> 4);
     const int gl = threadIdx.x & 15;
     int npert = 0;
     if (g < nsmall) {
@@ -450,8 +452,13 @@ __global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, R
     // one counter update per wavefront: group leaders contribute their count
     int c = gl == 0 ? npert : 0;
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-    if ((threadIdx.x & 63) == 0 && c)
-        atomicAdd(&a.pcount[(blockIdx.x * 4 + (threadIdx.x >> 6)) % kCountSlots], (unsigned long long)c);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&a.pcount[slot % kCountSlots], (unsigned long long)c);
+}
+
+template <bool kPipe>
+__global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, RefArgs a) {
+    small_group<kPipe>(item0, nsmall, a, blockIdx.x * (kBlock / 16) + (threadIdx.x >> 4),
+                       blockIdx.x * 4 + (threadIdx.x >> 6));
 }
 
 // ----------------------------------------------------------------- 512-thread path
@@ -678,10 +685,8 @@ __device__ __forceinline__ void unit_lower_w(double *lu, int ps, int w, const do
 
 // All pulls of one item with the source panel staged in LDS, then the panel factorization.
 template <class C>
-__global__ __launch_bounds__(C::kThreads, C::kWaves) void k_refactor_wide(int item0, RefArgs a) {
-    extern __shared__ __align__(16) char sm[];
+__device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char *sm) {
     const double thresh = a.tiny * a.st->anorm_scaled;
-    const int item = item0 + blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     constexpr int nw = C::kThreads / 64;
     KKT_PHASE(item, 0);
@@ -844,6 +849,22 @@ __global__ __launch_bounds__(C::kThreads, C::kWaves) void k_refactor_wide(int it
     }
     if (ia.x >= 0) large_factor<C>(a, ib, sm, thresh, item);
     KKT_PHASE(item, 5);
+}
+
+// One launch per level: block b < nwide runs wide item item0 + b; the blocks after it run
+// the level's narrow items small0 .. small0 + nsmall - 1, C::kThreads / 16 to a block (they
+// touch other columns than the wide items, so one launch needs no ordering between them).
+template <class C>
+__global__ __launch_bounds__(C::kThreads, C::kWaves) void k_refactor_wide(int item0, RefArgs a, int nwide, int small0,
+                                                                         int nsmall) {
+    extern __shared__ __align__(16) char sm[];
+    if ((int)blockIdx.x >= nwide) {
+        const int b = blockIdx.x - nwide;
+        small_group<(C::kMaxW > 16)>(small0, nsmall, a, b * (C::kThreads / 16) + (threadIdx.x >> 4),
+                                     b * (C::kThreads / 64) + (threadIdx.x >> 6));
+        return;
+    }
+    wide_item<C>(item0 + blockIdx.x, a, sm);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -32,6 +32,9 @@ struct Dev {
 
 constexpr int kDotBlocks = 512;
 constexpr int kSmallPipeMax = 100000;  // narrow items per level up to which the pipelined variant runs
+// narrow items per level up to which they run as extra blocks of the level's wide launch
+// instead of a concurrent launch on the second stream, whose fork and join cost more
+constexpr int kMergeSmall = 20000;
 constexpr int kNormBlocks = 1024;
 constexpr int kMaxRestart = 64;
 
@@ -293,13 +296,14 @@ int enqueue_levels(kkt_handle *h, hipStream_t s) {
         // narrow ones on the side stream, forked after and joined before the level
         const int nm = g.f_nmed[l], nb = g.f_nlarge[l] - nm, ns = g.f_lvl[l + 1] - g.f_lvl[l] - nb - nm;
         const int i0 = g.f_lvl[l];
-        const bool fork = (nb > 0 || nm > 0) && ns > 0;
+        const bool merge = (nb > 0 || nm > 0) && ns > 0 && ns <= kMergeSmall;
+        const bool fork = (nb > 0 || nm > 0) && ns > 0 && !merge;
         hipStream_t ss = fork ? h->side : s;
         if (fork) {
             HIPCHK(hipEventRecord(h->ev_fork, s));
             HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
         }
-        if (ns)
+        if (ns && !merge)
             timed(h, KKT_PROF_REFACTOR_SMALL, ss, [&] {
                 // many items: keep more in flight; few: shorten each item's dependent chain
                 if (ns > kSmallPipeMax)
@@ -307,12 +311,18 @@ int enqueue_levels(kkt_handle *h, hipStream_t s) {
                 else
                     k_refactor_small<true><<<blocks_for(ns, kBlock / 16), kBlock, 0, ss>>>(i0 + nb + nm, ns, a);
             });
+        // merged narrow items go with the level's first wide launch
+        const int s0 = i0 + nb + nm, mb = merge && nb ? ns : 0, mm = merge && !nb ? ns : 0;
         if (nb)
-            timed(h, KKT_PROF_REFACTOR_LARGE, s,
-                  [&] { k_refactor_wide<BigCfg><<<nb, BigCfg::kThreads, BigCfg::kLds, s>>>(i0, a); });
+            timed(h, KKT_PROF_REFACTOR_LARGE, s, [&] {
+                const int g = nb + (int)blocks_for(mb, BigCfg::kThreads / 16);
+                k_refactor_wide<BigCfg><<<g, BigCfg::kThreads, BigCfg::kLds, s>>>(i0, a, nb, s0, mb);
+            });
         if (nm)
-            timed(h, KKT_PROF_REFACTOR_MEDIUM, s,
-                  [&] { k_refactor_wide<MedCfg><<<nm, MedCfg::kThreads, MedCfg::kLds, s>>>(i0 + nb, a); });
+            timed(h, KKT_PROF_REFACTOR_MEDIUM, s, [&] {
+                const int g = nm + (int)blocks_for(mm, MedCfg::kThreads / 16);
+                k_refactor_wide<MedCfg><<<g, MedCfg::kThreads, MedCfg::kLds, s>>>(i0 + nb, a, nm, s0, mm);
+            });
         if (fork) {
             HIPCHK(hipEventRecord(h->ev_join, h->side));
             HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
