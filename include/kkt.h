@@ -107,8 +107,9 @@ typedef struct {
     int32_t persistent_levels_l; /* forward levels run by the persistent launch */
     int32_t persistent_levels_u; /* backward levels run by the persistent launch */
     double flops_refactor;      /* sum_k 2 |L(:,k)| |U(k,:)| + |L(:,k)| */
-    int64_t nnz_lu_wide;        /* L+U entries of the columns factored by wide items (32-column blocks) */
-    int64_t nnz_lu_medium;      /* L+U entries of the columns factored by medium wide items */
+    int64_t nnz_lu_wide;        /* L+U entries of the columns factored by the 512-thread launches
+                                 * (their wide items and the narrow items that ride with them) */
+    int64_t nnz_lu_medium;      /* L+U entries of the columns factored by the 256-thread launches */
 } kkt_stats;
 
 /* Fills *o with the defaults listed in kkt_opts. */
@@ -140,10 +141,8 @@ int kkt_workspace_bytes(const kkt_handle *h, int32_t max_nrhs, size_t *bytes);
 
 /* Setup (Algorithm 1, set up the GPU refactorization): uploads the symbolic structure and
  * schedules into d_workspace (device, >= kkt_workspace_bytes, 256-byte aligned) on stream
- * and records the device; the first bind also creates the handle's two internal streams
- * (one runs narrow refactorization items beside the wide ones and is always joined back
- * into the caller's stream; the other only records the refactorization graph).  Binding
- * again drops the recorded graph.  A handle stays on its first device: binding again on
+ * and records the device; the first bind also creates the handle's internal stream, which
+ * only records the refactorization graph.  Binding again drops the recorded graph.  A handle stays on its first device: binding again on
  * another one returns STATE.  Waits for the upload.
  * Errors: ARG, NOMEM (too small), STATE, DEVICE. */
 int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs,

@@ -73,7 +73,8 @@ struct Schedule {
     // refactorization: launch l runs items [f_lvl[l], f_lvl[l+1]); the first f_nlarge[l] of
     // them take the wide path (in its medium configuration, f_nmed[l] = f_nlarge[l], when
     // every wide item of the level has panels of at most kMedW columns and factors a panel
-    // of at most kMedRows rows), the rest the 16-lane path.  An item owns the target
+    // of at most kMedRows rows), the rest the 16-lane path (as extra blocks of the level's
+    // wide launch, or as a launch of their own on a level without wide items).  An item owns the target
     // columns of its (source panel, target column) pairs, listed source-major, and then
     // factors its panel (f_item_panel >= 0).
     std::vector<int32_t> f_lvl, f_nlarge, f_nmed;
@@ -118,8 +119,8 @@ struct Schedule {
     // CSC view of A's pattern (positions into the CSR value array, rows)
     std::vector<int32_t> a_cptr, a_cpos, a_crow;
     double flops = 0.0;
-    int64_t nnz_lu_wide = 0;            // L+U entries of columns factored by wide items
-    int64_t nnz_lu_med = 0;             // ... by medium wide items
+    int64_t nnz_lu_wide = 0;            // L+U entries of columns factored by 512-thread launches
+    int64_t nnz_lu_med = 0;             // ... by 256-thread launches
 };
 
 int build_schedule(const Symbolic &s, Schedule &g);

@@ -32,9 +32,6 @@ struct Dev {
 
 constexpr int kDotBlocks = 512;
 constexpr int kSmallPipeMax = 100000;  // narrow items per level up to which the pipelined variant runs
-// narrow items per level up to which they run as extra blocks of the level's wide launch
-// instead of a concurrent launch on the second stream, whose fork and join cost more
-constexpr int kMergeSmall = 20000;
 constexpr int kNormBlocks = 1024;
 constexpr int kMaxRestart = 64;
 
@@ -65,12 +62,8 @@ struct kkt_handle {
     const double *d_values = nullptr;
     double *h_small = nullptr;   // pinned host staging for small read-backs
     int grid_l = 1, grid_u = 1;  // co-resident blocks of the persistent solve kernels
-    // second stream of the refactorization: the narrow and the wide items of one level run
-    // concurrently, joined by a pair of events per level
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // the refactorization's per-level launches, recorded once per bind on the capture stream
-    // and replayed on the caller's stream
+    // (created at the first bind) and replayed on the caller's stream
     hipStream_t cap = nullptr;
     hipGraphExec_t levels = nullptr;
     bool levels_failed = false;
@@ -291,28 +284,21 @@ int enqueue_levels(kkt_handle *h, hipStream_t s) {
     RefArgs a{d.ldiag, d.item8, d.pair8, d.f_rel, d.lu, d.st, d.pcount,
               h->opts.tiny_pivot, h->opts.dense_mfma != 0};
     for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
-        // the kinds of items of a level touch disjoint target columns: the wide ones (32- and
-        // 16-column configurations, one after the other) run on the caller's stream, the
-        // narrow ones on the side stream, forked after and joined before the level
+        // the kinds of items of a level touch disjoint target columns, so one launch runs the
+        // wide items (32- or 16-column configuration) and the narrow ones together; a level
+        // without wide items has a launch of the narrow kernel
         const int nm = g.f_nmed[l], nb = g.f_nlarge[l] - nm, ns = g.f_lvl[l + 1] - g.f_lvl[l] - nb - nm;
         const int i0 = g.f_lvl[l];
-        const bool merge = (nb > 0 || nm > 0) && ns > 0 && ns <= kMergeSmall;
-        const bool fork = (nb > 0 || nm > 0) && ns > 0 && !merge;
-        hipStream_t ss = fork ? h->side : s;
-        if (fork) {
-            HIPCHK(hipEventRecord(h->ev_fork, s));
-            HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-        }
-        if (ns && !merge)
-            timed(h, KKT_PROF_REFACTOR_SMALL, ss, [&] {
+        if (ns && !nb && !nm)
+            timed(h, KKT_PROF_REFACTOR_SMALL, s, [&] {
                 // many items: keep more in flight; few: shorten each item's dependent chain
                 if (ns > kSmallPipeMax)
-                    k_refactor_small<false><<<blocks_for(ns, kBlock / 16), kBlock, 0, ss>>>(i0 + nb + nm, ns, a);
+                    k_refactor_small<false><<<blocks_for(ns, kBlock / 16), kBlock, 0, s>>>(i0, ns, a);
                 else
-                    k_refactor_small<true><<<blocks_for(ns, kBlock / 16), kBlock, 0, ss>>>(i0 + nb + nm, ns, a);
+                    k_refactor_small<true><<<blocks_for(ns, kBlock / 16), kBlock, 0, s>>>(i0, ns, a);
             });
-        // merged narrow items go with the level's first wide launch
-        const int s0 = i0 + nb + nm, mb = merge && nb ? ns : 0, mm = merge && !nb ? ns : 0;
+        // otherwise the narrow items are extra blocks of the level's first wide launch
+        const int s0 = i0 + nb + nm, mb = nb ? ns : 0, mm = nb ? 0 : ns;
         if (nb)
             timed(h, KKT_PROF_REFACTOR_LARGE, s, [&] {
                 const int g = nb + (int)blocks_for(mb, BigCfg::kThreads / 16);
@@ -323,10 +309,6 @@ int enqueue_levels(kkt_handle *h, hipStream_t s) {
                 const int g = nm + (int)blocks_for(mm, MedCfg::kThreads / 16);
                 k_refactor_wide<MedCfg><<<g, MedCfg::kThreads, MedCfg::kLds, s>>>(i0 + nb, a, nm, s0, mm);
             });
-        if (fork) {
-            HIPCHK(hipEventRecord(h->ev_join, h->side));
-            HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
-        }
     }
     timed(h, KKT_PROF_TO_CSR, s, [&] { k_to_csr<<<blocks_for(nlu, 256), 256, 0, s>>>(nlu, d.csr_src, d.lu, d.lucsr); });
     timed(h, KKT_PROF_UPDATE, s, [&] { k_sum_counts<<<1, 256, 0, s>>>(d.pcount, &d.st->perturbed); });
@@ -575,19 +557,14 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
         h->grid_u = std::max(1, bu) * std::max(1, ncu);
     }
     if (!h->h_small) HIPCHK(hipHostMalloc(&h->h_small, sizeof(double) * 4 * (kMaxRestart + 2) + 256));
-    if (h->side && h->device != dev) return KKT_ERR_STATE;   // rebinding keeps the device
+    if (h->cap && h->device != dev) return KKT_ERR_STATE;   // rebinding keeps the device
     if (h->levels) {   // recorded with the previous workspace's addresses
         HIPCHK(hipStreamSynchronize(h->cap));
         HIPCHK(hipGraphExecDestroy(h->levels));
         h->levels = nullptr;
     }
     h->levels_failed = false;
-    if (!h->side) {
-        HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
-        HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
-        HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-        HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
-    }
+    if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
     carve(h, static_cast<char *>(d_workspace), h->d, &need);
     const Symbolic &s = h->sym;
     const Schedule &g = h->sch;
@@ -775,15 +752,11 @@ int kkt_profile_read(kkt_handle *h, kkt_profile *out, hipStream_t stream) {
 void kkt_destroy(kkt_handle *h) {
     if (!h) return;
     if (h->h_small) (void)hipHostFree(h->h_small);
-    if (h->side) {
+    if (h->cap) {
         DeviceGuard g(h->device);
-        (void)hipStreamSynchronize(h->side);
         (void)hipStreamSynchronize(h->cap);
         if (h->levels) (void)hipGraphExecDestroy(h->levels);
-        (void)hipStreamDestroy(h->side);
         (void)hipStreamDestroy(h->cap);
-        (void)hipEventDestroy(h->ev_fork);
-        (void)hipEventDestroy(h->ev_join);
     }
     for (auto &pe : h->ev_pending) h->ev_free.push_back(pe.second);
     for (auto &ev : h->ev_free) {

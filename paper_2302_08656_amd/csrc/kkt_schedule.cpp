@@ -478,14 +478,21 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         fl += 2.0 * lk * (double)urow[k] + lk;
     }
     g.flops = fl;
+    // per launch kind: the 512-thread launch of a level factors its wide items and its narrow
+    // ones, the 256-thread launch its medium items and (with no 512-thread launch) the narrow
+    // ones; levels without wide items have a narrow launch
     g.nnz_lu_wide = g.nnz_lu_med = 0;
-    for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l)
-        for (int32_t it = g.f_lvl[l]; it < g.f_lvl[l] + g.f_nlarge[l]; ++it) {
+    for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
+        const int32_t nm = g.f_nmed[l], nb = g.f_nlarge[l] - nm;
+        for (int32_t it = g.f_lvl[l]; it < g.f_lvl[l + 1]; ++it) {
             const int32_t P = g.f_item_panel[it];
             if (P < 0) continue;
             const int64_t e = s.colptr[g.pan_start[P + 1]] - s.colptr[g.pan_start[P]];
-            (it < g.f_lvl[l] + g.f_nlarge[l] - g.f_nmed[l] ? g.nnz_lu_wide : g.nnz_lu_med) += e;
+            const bool med = (it >= g.f_lvl[l] + nb && it < g.f_lvl[l] + nb + nm) || (nb == 0 && nm > 0);
+            if (nb > 0 && !med) g.nnz_lu_wide += e;
+            else if (med) g.nnz_lu_med += e;
         }
+    }
     return KKT_OK;
 }
 
