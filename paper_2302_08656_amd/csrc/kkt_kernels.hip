@@ -1031,14 +1031,15 @@ __device__ __forceinline__ double inpanel_forward(const double (&Lrow)[kPanelMax
 }
 
 // Backward substitution inside a panel (lane = row): Urow[t] = U(lane, t) for t > lane,
-// dv = U(lane, lane); val enters as y minus the external part; returns the lane's unknown.
-__device__ __forceinline__ double inpanel_backward(const double (&Urow)[kPanelMax], double dv, int w, int lane,
+// rdv = 1 / U(lane, lane), taken before the substitution so that no division sits on its
+// dependency chain; val enters as y minus the external part; returns the lane's unknown.
+__device__ __forceinline__ double inpanel_backward(const double (&Urow)[kPanelMax], double rdv, int w, int lane,
                                                    double val) {
     double xv = 0.0;
 #pragma unroll
     for (int t = kPanelMax - 1; t >= 0; --t) {
         if (t < w) {
-            const double q = val / dv;          // final in lane t
+            const double q = val * rdv;         // final in lane t
             const double xt = bcast(q, t);
             xv = lane == t ? q : xv;
             const double nv = fma(-Urow[t], xt, val);
@@ -1164,6 +1165,7 @@ __device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double
             qi = a.Q[rr.x];
             ci = a.c[qi];
         }
+        const double rdd = 1.0 / dd;                    // off the substitution's chain
         const double acc = sdot<kWait, 4>(a, a.xt, rr.y, rr.z, gl, lanes);
         double val = yv - acc;
         // step k solves the rows k places before the end of their panels; the row's
@@ -1173,7 +1175,7 @@ __device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double
             if (lead && e == k) {
 #pragma unroll
                 for (int k2 = k - 1; k2 >= 0; --k2) val = fma(-Up[k2], xs[g + 1 + k2], val);
-                const double xv = val / dd;
+                const double xv = val * rdd;
                 xs[g] = xv;
                 a.x[qi] = ci * xv;
                 put_value<kWait>(a.xt + rr.x, xv);
@@ -1226,7 +1228,7 @@ __device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double
         double Urow[kPanelMax];
         load_lds_row<kPanelMax>(Urow, blk + min(lane, kPanelMax - 1) * kRowLd);
         const double val = lane < w ? yv - ext[lane] : 0.0;
-        const double xv = inpanel_backward(Urow, dv, w, lane, val);
+        const double xv = inpanel_backward(Urow, 1.0 / dv, w, lane, val);
         if (lane < w) {
             a.x[qi] = ci * xv;
             put_value<kWait>(a.xt + s + lane, xv);
