@@ -32,7 +32,7 @@ struct Dev {
 
 constexpr int kDotBlocks = 512;
 constexpr int kSmallPipeMax = 100000;  // narrow items per level up to which the pipelined variant runs
-constexpr int kNormBlocks = 1024;
+constexpr int kNormBlocks = 4096;
 constexpr int kMaxRestart = 64;
 
 struct Carver {
