@@ -84,6 +84,12 @@ typedef struct {
      * launch profiler is on, when the caller's stream is itself being captured, or when
      * recording fails.  0 = always one by one.  Results are bitwise identical either way. */
     int32_t graph_refactor;
+    /* 0 = every preconditioner application inside kkt_refine is an exact triangular solve
+     * (default).  k in 1..1024 = the applications inside the FGMRES iterations use k Jacobi
+     * sweeps per triangle instead (L from y = the permuted scaled right-hand side, U from
+     * D^-1 y), fully parallel but approximate; the first solve of kkt_refine and kkt_solve
+     * stay exact, and FGMRES, being flexible, accepts the varying preconditioner. */
+    int32_t approx_sweeps;
 } kkt_opts;
 
 typedef struct {

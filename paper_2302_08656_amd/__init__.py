@@ -31,7 +31,7 @@ class _Opts(C.Structure):
                 ("gmres_restart", C.c_int32), ("max_iters", C.c_int32), ("berr_tol", C.c_double),
                 ("sn_max_width", C.c_int32), ("fixed_p", C.c_void_p), ("fixed_q", C.c_void_p),
                 ("dense_mfma", C.c_int32), ("persistent_solve", C.c_int32),
-                ("graph_refactor", C.c_int32)]
+                ("graph_refactor", C.c_int32), ("approx_sweeps", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -130,7 +130,7 @@ class KKTSolver:
     def __init__(self, n, rowptr, colind, values_k1, *, pivot_tau=None, tiny_pivot=None,
                  equilibrate=None, gmres_restart=None, max_iters=None, berr_tol=None,
                  sn_max_width=None, fixed_p=None, fixed_q=None, dense_mfma=None, persistent_solve=None,
-                 graph_refactor=None):
+                 graph_refactor=None, approx_sweeps=None):
         L = _lib()
         self.n = int(n)
         rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
@@ -141,7 +141,8 @@ class KKTSolver:
         for name, val in (("pivot_tau", pivot_tau), ("tiny_pivot", tiny_pivot), ("equilibrate", equilibrate),
                           ("gmres_restart", gmres_restart), ("max_iters", max_iters), ("berr_tol", berr_tol),
                           ("sn_max_width", sn_max_width), ("dense_mfma", dense_mfma),
-                          ("persistent_solve", persistent_solve), ("graph_refactor", graph_refactor)):
+                          ("persistent_solve", persistent_solve), ("graph_refactor", graph_refactor),
+                          ("approx_sweeps", approx_sweeps)):
             if val is not None:
                 setattr(o, name, val)
         fp = None if fixed_p is None else np.ascontiguousarray(fixed_p, dtype=np.int32)

@@ -33,6 +33,7 @@ struct Dev {
 constexpr int kDotBlocks = 512;
 constexpr int kSmallPipeMax = 100000;  // narrow items per level up to which the pipelined variant runs
 constexpr int kNormBlocks = 4096;
+constexpr int kMaxSweeps = 1024;       // largest approx_sweeps accepted
 constexpr int kMaxRestart = 64;
 
 struct Carver {
@@ -346,6 +347,41 @@ int residual_berr(kkt_handle *h, const double *x, const double *b, double *berr,
     return KKT_OK;
 }
 
+// Preconditioner application inside refinement with `sweeps` Jacobi sweeps per triangle
+// instead of the exact solves: L from y = bp, U from x = D^-1 y.  The exact solve's helper
+// sums (psum, usum) serve as the second iterate buffers.
+int enqueue_approx_solve(kkt_handle *h, const double *b, double *x, int sweeps, hipStream_t s) {
+    const Dev &d = h->d;
+    const int n = h->sym.n;
+    const unsigned nb8 = blocks_for((int64_t)n * 8, 256), nb = blocks_for(n, 256);
+    timed(h, KKT_PROF_LSOLVE, s, [&] {
+        k_solve_reset<<<nb, 256, 0, s>>>(n, b, d.r, d.P, d.bp, d.y, d.xt, d.psum, d.usum, 0);
+    });
+    const double *yin = d.bp;
+    double *ybuf[2] = {d.psum, d.y};
+    for (int k = 0; k < sweeps; ++k) {
+        double *yout = ybuf[k & 1];
+        timed(h, KKT_PROF_LSOLVE, s, [&] {
+            k_jacobi_l<<<nb8, 256, 0, s>>>(n, d.rinfo4, d.csr_col, d.lucsr, d.bp,
+                                           yin, yout);
+        });
+        yin = yout;
+    }
+    const double *xin = nullptr;
+    double *xbuf[2] = {d.xt, d.usum};
+    for (int k = 0; k < sweeps; ++k) {
+        double *xout = xbuf[k & 1];
+        timed(h, KKT_PROF_USOLVE, s, [&] {
+            k_jacobi_u<<<nb8, 256, 0, s>>>(n, d.urinfo4, d.csr_col, d.lucsr, yin,
+                                           xin, xout, k == 0 ? 1 : 0);
+        });
+        xin = xout;
+    }
+    timed(h, KKT_PROF_USOLVE, s, [&] { k_unpermute<<<nb, 256, 0, s>>>(n, d.Q, d.c, xin, x); });
+    HIPCHK(hipGetLastError());
+    return KKT_OK;
+}
+
 int fgmres_column(kkt_handle *h, const double *b, double *x, kkt_info *info, hipStream_t s) {
     const Dev &d = h->d;
     const int n = h->sym.n;
@@ -371,7 +407,8 @@ int fgmres_column(kkt_handle *h, const double *b, double *x, kkt_info *info, hip
         int jend = -1;
         for (int j = 0; j < m; ++j) {
             double *vj = d.V + (size_t)j * n, *zj = d.Z + (size_t)j * n;
-            rc = enqueue_solve(h, vj, zj, s);
+            rc = h->opts.approx_sweeps > 0 ? enqueue_approx_solve(h, vj, zj, h->opts.approx_sweeps, s)
+                                           : enqueue_solve(h, vj, zj, s);
             if (rc) return rc;
             timed(h, KKT_PROF_RESIDUAL, s, [&] {
                 k_spmv<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_rowptr, d.a_colind, h->d_values, zj, d.w);
@@ -447,6 +484,7 @@ void kkt_default_opts(kkt_opts *o) {
     o->dense_mfma = 1;
     o->persistent_solve = 1;
     o->graph_refactor = 1;
+    o->approx_sweeps = 0;
 }
 
 int kkt_analyze(int32_t n, const int64_t *rowptr, const int32_t *colind, const double *values_k1,
@@ -457,7 +495,7 @@ int kkt_analyze(int32_t n, const int64_t *rowptr, const int32_t *colind, const d
     kkt_default_opts(&o);
     if (opts) o = *opts;
     if (o.gmres_restart < 1 || o.gmres_restart > kMaxRestart || o.max_iters < 0 || !(o.berr_tol >= 0.0) ||
-        !(o.tiny_pivot >= 0.0))
+        !(o.tiny_pivot >= 0.0) || o.approx_sweeps < 0 || o.approx_sweeps > kMaxSweeps)
         return KKT_ERR_ARG;
     kkt_handle *h = new (std::nothrow) kkt_handle;
     if (!h) return KKT_ERR_NOMEM;

@@ -178,6 +178,47 @@ def test_graph_replayed_refactor_matches_one_by_one():
     both(3)
 
 
+@pytest.mark.parametrize("spec,sweeps,converges", [(kktgen.config(0), 4, True),
+                                                   (kktgen.small(2000, config_id=151, steps=2), 8, False)],
+                         ids=["grid200_sweeps4", "grid2000_sweeps8"])
+def test_refine_with_jacobi_sweeps(spec, sweeps, converges):
+    # a few sweeps are a weak preconditioner for these factors: the 200-bus grid still reaches
+    # the target, the 2,000-bus grid stalls above it; either way the result is finite, the
+    # status is a warning at worst and the reported backward error is the true one
+    print(f"[gpu] refine with {sweeps} Jacobi sweeps per triangle", flush=True)
+    q = kktgen.make_sequence(spec)
+    sk = K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0), approx_sweeps=sweeps, max_iters=60).bind()
+    for t in range(min(q.steps, 4)):
+        v, b = q.values(t), q.rhs(t)
+        sk.refactor(cuda(v))
+        x, info = sk.refine(cuda(b))
+        xh = x.cpu().numpy()
+        _, berr = oracle.residual(q.n, q.rowptr, q.colind, v, xh, b)
+        assert np.isfinite(xh).all() and info[0].status in (K.OK, K.WARN_NOT_CONVERGED), (t, info)
+        assert abs(info[0].berr - berr) <= 1e-6 * berr + 1e-20, (t, berr, info)
+        if converges:
+            assert info[0].status == K.OK and berr <= 1e-10, (t, berr, info)
+
+
+def test_jacobi_sweeps_past_the_depth_match_exact_solves():
+    # Jacobi sweeps on a triangle are exact once they outnumber its row levels (the strictly
+    # triangular part is nilpotent), so refinement then takes the exact path's steps
+    print("[gpu] Jacobi sweeps past the triangle depth", flush=True)
+    q = kktgen.make_sequence(kktgen.small(300, config_id=152, steps=4))
+    se = K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0)).bind()
+    deep = max(se.stats["levels_l"], se.stats["levels_u"]) + 1
+    sj = K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0), approx_sweeps=deep).bind()
+    for t in range(q.steps):
+        v, b = cuda(q.values(t)), cuda(q.rhs(t))
+        its = []
+        for sk in (se, sj):
+            sk.refactor(v)
+            _, info = sk.refine(b)
+            assert info[0].status == K.OK
+            its.append(info[0].iters)
+        assert abs(its[0] - its[1]) <= 1, its
+
+
 def test_deterministic_refactor_and_solve():
     print("[gpu] determinism", flush=True)
     q = kktgen.make_sequence(kktgen.small(500, config_id=144))

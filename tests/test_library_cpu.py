@@ -41,6 +41,7 @@ def test_default_options():
     assert o["tiny_pivot"] == oracle.EPS
     assert o["sn_max_width"] == oracle.SN_MAX
     assert o["berr_tol"] == 1e-10 and o["gmres_restart"] == 30 and o["max_iters"] == 100
+    assert o["graph_refactor"] == 1 and o["approx_sweeps"] == 0
 
 
 def compare_symbolic(n, rowptr, colind, values, **kw):
@@ -127,6 +128,12 @@ def test_analyze_errors_match_oracle():
     with pytest.raises(K.KKTError) as e:
         K.KKTSolver(3, rowptr, colind, vals, fixed_p=np.arange(3))
     assert e.value.code == K.ERR_ARG
+    for bad in (-1, 1025):
+        with pytest.raises(K.KKTError) as e:
+            K.KKTSolver(3, rowptr, colind, vals, approx_sweeps=bad)
+        assert e.value.code == K.ERR_ARG
+    diag = K.KKTSolver(3, np.arange(4), np.arange(3, dtype=np.int32), np.array([1.0, 2.0, 3.0]), approx_sweeps=1024)
+    assert diag.opts["approx_sweeps"] == 1024
 
 
 def test_call_order_errors_without_device():
