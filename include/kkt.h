@@ -191,14 +191,16 @@ int kkt_export_factors(kkt_handle *h, double *h_lu, double *h_r, double *h_c,
 
 /* Kernel classes timed by the optional launch profiler. */
 #define KKT_PROF_UPDATE 0          /* equilibration, norms, value gather, counters */
-#define KKT_PROF_REFACTOR_LARGE 1  /* wide panel items (LDS-staged, matrix cores), up to 32 columns */
-#define KKT_PROF_REFACTOR_SMALL 2  /* narrow panel items (16 lanes each) */
+#define KKT_PROF_REFACTOR_LARGE 1  /* 512-thread level launches: wide panel items up to 32 columns
+                                    * (LDS-staged, matrix cores) and the level's narrow items */
+#define KKT_PROF_REFACTOR_SMALL 2  /* narrow-only level launches (16 lanes per item) */
 #define KKT_PROF_TO_CSR 3          /* row-ordered copy of the factors */
-#define KKT_PROF_LSOLVE 4          /* forward-substitution levels */
-#define KKT_PROF_USOLVE 5          /* backward-substitution levels */
+#define KKT_PROF_LSOLVE 4          /* forward substitution (and its Jacobi sweeps) */
+#define KKT_PROF_USOLVE 5          /* backward substitution (and its Jacobi sweeps) */
 #define KKT_PROF_RESIDUAL 6        /* residual, products with A */
 #define KKT_PROF_KRYLOV 7          /* FGMRES vector kernels */
-#define KKT_PROF_REFACTOR_MEDIUM 8 /* wide items of panels up to 16 columns (smaller blocks) */
+#define KKT_PROF_REFACTOR_MEDIUM 8 /* 256-thread level launches: wide items of panels up to 16
+                                    * columns and the level's narrow items */
 #define KKT_PROF_NCLASS 9
 
 typedef struct {
@@ -207,8 +209,9 @@ typedef struct {
 } kkt_profile;
 
 /* Test and benchmark hook: on = 1 resets the counters and records a pair of HIP events
- * around every later kernel launch of the handle (on the caller's stream); on = 0 stops.
- * Adds a few microseconds per launch while on. */
+ * around every later kernel launch of the handle (on the caller's stream); the
+ * refactorization's levels are then launched one by one instead of from the recorded graph.
+ * on = 0 stops.  Adds a few microseconds per launch while on. */
 int kkt_profile_enable(kkt_handle *h, int32_t on);
 
 /* Waits for the stream and returns the accumulated launch counts and times. */
