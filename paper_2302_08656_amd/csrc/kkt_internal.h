@@ -64,6 +64,10 @@ constexpr int kHelpRows = 4;
 constexpr int kHelpMin = 32;
 // Solve panels of at most kPackW columns are packed whole, kSolvePack rows to an item.
 constexpr int kPackW = 4;
+// The row-ordered copy of the factor rides with up to kCopyLaunches of the top refactor
+// levels that have at most kCopyItems items each.
+constexpr int kCopyItems = 16;
+constexpr int kCopyLaunches = 4;
 
 // Device schedule, built on the host once per pattern and uploaded by kkt_bind.
 struct Schedule {
@@ -78,6 +82,10 @@ struct Schedule {
     // columns of its (source panel, target column) pairs, listed source-major, and then
     // factors its panel (f_item_panel >= 0).
     std::vector<int32_t> f_lvl, f_nlarge, f_nmed;
+    // row-ordered copy: copy_k lists CSR positions; launch copy_lvl + c (c < copy_ptr.size()
+    // - 1) copies copy_k[copy_ptr[c] .. copy_ptr[c+1]), the copy after the last level the rest
+    int32_t copy_lvl = 0;
+    std::vector<int32_t> copy_k, copy_ptr;
     std::vector<int32_t> f_item_panel;  // panel to factor after the pulls, or -1
     std::vector<int32_t> f_item_pair;   // [nitems+1] range into f_pair_src / f_pair_tgt
     std::vector<int32_t> f_pair_src, f_pair_tgt;

@@ -186,10 +186,14 @@ __global__ __launch_bounds__(256) void k_sum_counts(const unsigned long long *__
     if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
 }
 
-__global__ void k_to_csr(int64_t nlu, const int32_t *__restrict__ csr_src, const double *__restrict__ lu,
-                         double *__restrict__ lucsr) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < nlu) lucsr[q] = lu[csr_src[q]];
+// lucsr[k] = lu[csr_src[k]] for k = copy_k[q], q in [q0, q1)
+__global__ void k_to_csr(int q0, int q1, const int32_t *__restrict__ copy_k, const int32_t *__restrict__ csr_src,
+                         const double *__restrict__ lu, double *__restrict__ lucsr) {
+    const int q = q0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < q1) {
+        const int k = copy_k[q];
+        lucsr[k] = lu[csr_src[k]];
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -243,6 +247,11 @@ struct RefArgs {
     unsigned long long *pcount;   // replaced-pivot counter, spread over kCountSlots slots
     double tiny;
     int use_mfma;                 // dense update blocks on the matrix cores
+    // row-ordered copy of the factor: lucsr[k] = lu[csr_src[k]] for the CSR positions k listed
+    // in copy_k
+    const int32_t *copy_k;
+    const int32_t *csr_src;
+    double *lucsr;
 };
 
 // slot of the first L entry (row j+1 or below) of column j
@@ -853,11 +862,22 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char
 
 // One launch per level: block b < nwide runs wide item item0 + b; the blocks after it run
 // the level's narrow items small0 .. small0 + nsmall - 1, C::kThreads / 16 to a block (they
-// touch other columns than the wide items, so one launch needs no ordering between them).
+// touch other columns than the wide items, so one launch needs no ordering between them);
+// any blocks after those copy copy_k[c0 .. c1) of the row-ordered factor (columns that no
+// launch from this one on writes).
 template <class C>
 __global__ __launch_bounds__(C::kThreads, C::kWaves) void k_refactor_wide(int item0, RefArgs a, int nwide, int small0,
-                                                                         int nsmall) {
+                                                                         int nsmall, int c0, int c1) {
     extern __shared__ __align__(16) char sm[];
+    const int nsb = (nsmall + C::kThreads / 16 - 1) / (C::kThreads / 16);
+    if ((int)blockIdx.x >= nwide + nsb) {
+        const int b = blockIdx.x - nwide - nsb, nbc = gridDim.x - nwide - nsb;
+        for (int q = c0 + b * C::kThreads + threadIdx.x; q < c1; q += nbc * C::kThreads) {
+            const int k = a.copy_k[q];
+            a.lucsr[k] = a.lu[a.csr_src[k]];
+        }
+        return;
+    }
     if ((int)blockIdx.x >= nwide) {
         const int b = blockIdx.x - nwide;
         small_group<(C::kMaxW > 16)>(small0, nsmall, a, b * (C::kThreads / 16) + (threadIdx.x >> 4),

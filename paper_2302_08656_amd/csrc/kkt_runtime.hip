@@ -23,7 +23,7 @@ struct Dev {
     int4 *item8, *pair8;
     unsigned long long *pcount;
     int4 *l_item4, *u_item4, *l_rows4, *u_rows4, *rinfo4, *urinfo4;
-    int32_t *csr_col, *csr_src, *P, *Q;
+    int32_t *csr_col, *csr_src, *copy_k, *P, *Q;
     double *r, *c, *lu, *lucsr, *y, *xt, *psum, *usum, *bp, *bsave;
     double *V, *Z, *w, *res, *part, *hbuf, *ybuf;
     DevStatus *st;
@@ -63,6 +63,7 @@ struct kkt_handle {
     const double *d_values = nullptr;
     double *h_small = nullptr;   // pinned host staging for small read-backs
     int grid_l = 1, grid_u = 1;  // co-resident blocks of the persistent solve kernels
+    int ncu = 1;                 // compute units of the bound device
     // the refactorization's per-level launches, recorded once per bind on the capture stream
     // (created at the first bind) and replayed on the caller's stream
     hipStream_t cap = nullptr;
@@ -108,6 +109,7 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.urinfo4 = c.take<int4>(n);
     d.csr_col = c.take<int32_t>(nlu);
     d.csr_src = c.take<int32_t>(nlu);
+    d.copy_k = c.take<int32_t>(std::max<size_t>(1, g.copy_k.size()));
     d.P = c.take<int32_t>(n);
     d.Q = c.take<int32_t>(n);
     d.r = c.take<double>(n);
@@ -281,9 +283,9 @@ int enqueue_update(kkt_handle *h, const double *v, hipStream_t s) {
 int enqueue_levels(kkt_handle *h, hipStream_t s) {
     const Schedule &g = h->sch;
     const Dev &d = h->d;
-    const int64_t nlu = h->sym.nnz_lu();
     RefArgs a{d.ldiag, d.item8, d.pair8, d.f_rel, d.lu, d.st, d.pcount,
-              h->opts.tiny_pivot, h->opts.dense_mfma != 0};
+              h->opts.tiny_pivot, h->opts.dense_mfma != 0, d.copy_k, d.csr_src, d.lucsr};
+    const int ncopy = (int)g.copy_ptr.size() - 1;   // launches that carry a chunk of the copy
     for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
         // the kinds of items of a level touch disjoint target columns, so one launch runs the
         // wide items (32- or 16-column configuration) and the narrow ones together; a level
@@ -298,20 +300,33 @@ int enqueue_levels(kkt_handle *h, hipStream_t s) {
                 else
                     k_refactor_small<true><<<blocks_for(ns, kBlock / 16), kBlock, 0, s>>>(i0, ns, a);
             });
-        // otherwise the narrow items are extra blocks of the level's first wide launch
+        // otherwise the narrow items are extra blocks of the level's first wide launch, and so
+        // is a chunk of the row-ordered copy on the top levels (columns already final)
         const int s0 = i0 + nb + nm, mb = nb ? ns : 0, mm = nb ? 0 : ns;
+        const int cc = (int)l - g.copy_lvl;
+        const bool copy = cc >= 0 && cc < ncopy && (nb || nm);
+        const int c0 = copy ? g.copy_ptr[cc] : 0, c1 = copy ? g.copy_ptr[cc + 1] : 0;
+        const int cb = c1 > c0 ? h->ncu : 0;
         if (nb)
             timed(h, KKT_PROF_REFACTOR_LARGE, s, [&] {
-                const int g = nb + (int)blocks_for(mb, BigCfg::kThreads / 16);
-                k_refactor_wide<BigCfg><<<g, BigCfg::kThreads, BigCfg::kLds, s>>>(i0, a, nb, s0, mb);
+                const int g = nb + (int)blocks_for(mb, BigCfg::kThreads / 16) + cb;
+                k_refactor_wide<BigCfg><<<g, BigCfg::kThreads, BigCfg::kLds, s>>>(i0, a, nb, s0, mb, c0, c1);
             });
         if (nm)
             timed(h, KKT_PROF_REFACTOR_MEDIUM, s, [&] {
-                const int g = nm + (int)blocks_for(mm, MedCfg::kThreads / 16);
-                k_refactor_wide<MedCfg><<<g, MedCfg::kThreads, MedCfg::kLds, s>>>(i0 + nb, a, nm, s0, mm);
+                const int c = nb ? 0 : cb;
+                const int g = nm + (int)blocks_for(mm, MedCfg::kThreads / 16) + c;
+                k_refactor_wide<MedCfg><<<g, MedCfg::kThreads, MedCfg::kLds, s>>>(i0 + nb, a, nm, s0, mm,
+                                                                                 nb ? 0 : c0, nb ? 0 : c1);
             });
     }
-    timed(h, KKT_PROF_TO_CSR, s, [&] { k_to_csr<<<blocks_for(nlu, 256), 256, 0, s>>>(nlu, d.csr_src, d.lu, d.lucsr); });
+    {
+        // the rest of the copy: the columns of the top levels (all of it without such levels)
+        const int q0 = ncopy > 0 ? g.copy_ptr.back() : 0, q1 = (int)g.copy_k.size();
+        if (q1 > q0)
+            timed(h, KKT_PROF_TO_CSR, s,
+                  [&] { k_to_csr<<<blocks_for(q1 - q0, 256), 256, 0, s>>>(q0, q1, d.copy_k, d.csr_src, d.lu, d.lucsr); });
+    }
     timed(h, KKT_PROF_UPDATE, s, [&] { k_sum_counts<<<1, 256, 0, s>>>(d.pcount, &d.st->perturbed); });
     HIPCHK(hipGetLastError());
     return KKT_OK;
@@ -593,6 +608,7 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
                                                             kBlock, 0));
         h->grid_l = std::max(1, bl) * std::max(1, ncu);
         h->grid_u = std::max(1, bu) * std::max(1, ncu);
+        h->ncu = std::max(1, ncu);
     }
     if (!h->h_small) HIPCHK(hipHostMalloc(&h->h_small, sizeof(double) * 4 * (kMaxRestart + 2) + 256));
     if (h->cap && h->device != dev) return KKT_ERR_STATE;   // rebinding keeps the device
@@ -637,6 +653,7 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     rc |= upload(reinterpret_cast<int32_t *>(d.urinfo4), g.urinfo4, stream);
     rc |= upload(d.csr_col, g.csr_col, stream);
     rc |= upload(d.csr_src, g.csr_src, stream);
+    rc |= upload(d.copy_k, g.copy_k, stream);
     rc |= upload(d.P, s.P, stream);
     rc |= upload(d.Q, s.Q, stream);
     if (rc) return KKT_ERR_DEVICE;

@@ -478,6 +478,26 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         fl += 2.0 * lk * (double)urow[k] + lk;
     }
     g.flops = fl;
+    // the row-ordered copy of the factor: an entry can be copied once its column is final,
+    // i.e. after the launch that factors the column's panel.  The top levels have few items
+    // and leave most of the GPU idle, so the entries of every column final before the first
+    // of them are copied by extra blocks of up to kCopyLaunches of those launches (in
+    // consecutive chunks); the rest after the last level
+    {
+        const int32_t nlev = (int32_t)g.f_lvl.size() - 1;
+        int32_t win = nlev;
+        while (win > 0 && g.f_lvl[win] - g.f_lvl[win - 1] <= kCopyItems && g.f_nlarge[win - 1] > 0) --win;
+        const int32_t nwin = std::min<int32_t>(kCopyLaunches, nlev - win);
+        g.copy_lvl = win;
+        g.copy_k.clear();
+        g.copy_ptr.assign(1, 0);
+        std::vector<int32_t> late;
+        for (int64_t q = 0; q < nlu; ++q)
+            (nwin > 0 && plev[pan_of[g.csr_col[q]]] < win ? g.copy_k : late).push_back((int32_t)q);
+        const int64_t ne = (int64_t)g.copy_k.size();
+        for (int32_t c = 1; c <= nwin; ++c) g.copy_ptr.push_back((int32_t)(ne * c / nwin));
+        g.copy_k.insert(g.copy_k.end(), late.begin(), late.end());
+    }
     // per launch kind: the 512-thread launch of a level factors its wide items and its narrow
     // ones, the 256-thread launch its medium items and (with no 512-thread launch) the narrow
     // ones; levels without wide items have a narrow launch
