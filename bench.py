@@ -173,16 +173,17 @@ def main():
     nnz_u = st["nnz_lu"] - q.n - nnz_l
     # algorithmic bytes per unit of work of each kernel class (int32 indices, FP64 values):
     # refactorization: every factor value of the columns a class factors read and written
-    # once; solves: factor values + column indices, pointers and the vectors they touch;
-    # value update: A's values and map, the factor written, scale vectors; CSR copy: read
-    # slot index, read and write the value
+    # once, plus 20 bytes per entry of the row-ordered copy that its launches carry (read
+    # slot index, read and write the value); solves: factor values + column indices, pointers
+    # and the vectors they touch; value update: A's values and map, the factor written, scale
+    # vectors; CSR copy after the last level: 20 bytes per remaining entry
     per_unit = {
-        "refactor_large": 16 * st["nnz_lu_wide"] * nprof,
+        "refactor_large": (16 * st["nnz_lu_wide"] + 20 * st["copy_in_levels"]) * nprof,
         "refactor_medium": 16 * st["nnz_lu_medium"] * nprof,
         "refactor_small": 16 * (st["nnz_lu"] - st["nnz_lu_wide"] - st["nnz_lu_medium"]) * nprof,
         "lsolve": (12 * nnz_l + 48 * q.n) * solves,
         "usolve": (12 * (nnz_u + q.n) + 48 * q.n) * solves,
-        "to_csr": 20 * st["nnz_lu"] * nprof,
+        "to_csr": 20 * (st["nnz_lu"] - st["copy_in_levels"]) * nprof,
         "update": (12 * q.nnz + 12 * st["nnz_lu"] + 40 * q.n) * nprof,
     }
     kernel_of = {"refactor_large": "k_refactor_wide<WideCfg<512, 2, 256, 32, 4> >",

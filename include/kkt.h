@@ -116,6 +116,8 @@ typedef struct {
     int64_t nnz_lu_wide;        /* L+U entries of the columns factored by the 512-thread launches
                                  * (their wide items and the narrow items that ride with them) */
     int64_t nnz_lu_medium;      /* L+U entries of the columns factored by the 256-thread launches */
+    int64_t copy_in_levels;     /* entries of the row-ordered factor copy done by the level
+                                 * launches (the rest by a copy after the last level) */
 } kkt_stats;
 
 /* Fills *o with the defaults listed in kkt_opts. */

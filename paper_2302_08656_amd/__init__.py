@@ -53,7 +53,7 @@ class _Stats(C.Structure):
                 ("gpu_levels_f", C.c_int32), ("gpu_levels_l", C.c_int32), ("gpu_levels_u", C.c_int32),
                 ("persistent_levels_l", C.c_int32), ("persistent_levels_u", C.c_int32),
                 ("flops_refactor", C.c_double), ("nnz_lu_wide", C.c_int64),
-                ("nnz_lu_medium", C.c_int64)]
+                ("nnz_lu_medium", C.c_int64), ("copy_in_levels", C.c_int64)]
 
 
 EXPORTS = ["kkt_default_opts", "kkt_analyze", "kkt_get_stats", "kkt_export_symbolic",

@@ -552,6 +552,7 @@ int kkt_get_stats(const kkt_handle *h, kkt_stats *out) {
     out->flops_refactor = h->sch.flops;
     out->nnz_lu_wide = h->sch.nnz_lu_wide;
     out->nnz_lu_medium = h->sch.nnz_lu_med;
+    out->copy_in_levels = h->sch.copy_ptr.empty() ? 0 : h->sch.copy_ptr.back();
     return KKT_OK;
 }
 
