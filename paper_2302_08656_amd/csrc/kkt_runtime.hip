@@ -309,15 +309,14 @@ int enqueue_levels(kkt_handle *h, hipStream_t s) {
         const int cb = c1 > c0 ? h->ncu : 0;
         if (nb)
             timed(h, KKT_PROF_REFACTOR_LARGE, s, [&] {
-                const int g = nb + (int)blocks_for(mb, BigCfg::kThreads / 16) + cb;
-                k_refactor_wide<BigCfg><<<g, BigCfg::kThreads, BigCfg::kLds, s>>>(i0, a, nb, s0, mb, c0, c1);
+                const int grid = nb + (int)blocks_for(mb, BigCfg::kThreads / 16) + cb;
+                k_refactor_wide<BigCfg><<<grid, BigCfg::kThreads, BigCfg::kLds, s>>>(i0, a, nb, s0, mb, c0, c1);
             });
         if (nm)
             timed(h, KKT_PROF_REFACTOR_MEDIUM, s, [&] {
-                const int c = nb ? 0 : cb;
-                const int g = nm + (int)blocks_for(mm, MedCfg::kThreads / 16) + c;
-                k_refactor_wide<MedCfg><<<g, MedCfg::kThreads, MedCfg::kLds, s>>>(i0 + nb, a, nm, s0, mm,
-                                                                                 nb ? 0 : c0, nb ? 0 : c1);
+                const int grid = nm + (int)blocks_for(mm, MedCfg::kThreads / 16) + (nb ? 0 : cb);
+                k_refactor_wide<MedCfg><<<grid, MedCfg::kThreads, MedCfg::kLds, s>>>(i0 + nb, a, nm, s0, mm,
+                                                                                    nb ? 0 : c0, nb ? 0 : c1);
             });
     }
     {
