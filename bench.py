@@ -39,6 +39,29 @@ def parse():
     return ap.parse_args()
 
 
+def coprime_stride(T):
+    """A stride near 0.35 T that is coprime to T: the timed order t_i = i * stride mod T
+    visits every system once per T units and spreads any prefix over the whole sequence
+    (the D range widens along it)."""
+    import math
+    st = max(1, int(round(0.35 * T)))
+    while math.gcd(st, T) != 1:
+        st += 1
+    return st
+
+
+def host_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return os.cpu_count(), model
+
+
 def nearest_rank(xs, p):
     s = sorted(xs)
     k = max(1, int(-(-p * len(s) // 100)))
@@ -139,18 +162,21 @@ def main():
         _, info = sk.refine(drhs[t], x)
         return info[0]
 
+    stride = coprime_stride(T)
+    order = [(i * stride) % T for i in range(max(args.steps, args.warmup, 1))]
     for i in range(args.warmup):
-        unit(i % T)
+        unit(order[i])
     torch.cuda.synchronize()
-    lat, iters, fails, berrs = [], [], 0, []
+    lat, iters, fails, berrs, perts = [], [], 0, [], []
     t_start = time.perf_counter()
     for i in range(args.steps):
-        t = i % T
+        t = order[i]
         a = time.perf_counter()
         inf = unit(t)
         lat.append((time.perf_counter() - a) * 1e3)
         iters.append(inf.iters)
         berrs.append(inf.berr)
+        perts.append(inf.perturbed_pivots)
         if inf.status != K.OK or not (inf.berr <= 1e-10):
             fails += 1
     torch.cuda.synchronize()
@@ -159,38 +185,38 @@ def main():
     value = ok_units / elapsed
 
     # per-kernel-class launch timing with HIP events on the library's stream (torch's
-    # current stream), over a second pass of the same workload
-    nprof = min(args.steps, 50)
+    # current stream), over a second pass of the same units in the same order
+    nprof = min(args.steps, T)
     sk.profile(True)
     solves = 0
     for i in range(nprof):
-        solves += 1 + unit(i % T).iters
+        solves += 1 + unit(order[i]).iters
     prof = sk.profile_read()
     sk.profile(False)
     sym = sk.export_symbolic()
     cols = np.repeat(np.arange(q.n), np.diff(sym["colptr"]))
     nnz_l = int(np.count_nonzero(sym["rowidx"] > cols))
     nnz_u = st["nnz_lu"] - q.n - nnz_l
-    # algorithmic bytes per unit of work of each kernel class (int32 indices, FP64 values):
-    # refactorization: every factor value of the columns a class factors read and written
-    # once, plus 20 bytes per entry of the row-ordered copy that its launches carry (read
-    # slot index, read and write the value); solves: factor values + column indices, pointers
-    # and the vectors they touch; value update: A's values and map, the factor written, scale
-    # vectors; CSR copy after the last level: 20 bytes per remaining entry
+    # algorithmic bytes per unit of work of each kernel class, from the compulsory-traffic
+    # definitions (int32 indices, FP64 values): a refactorization class writes each factor
+    # entry of the columns it factors once and reads its structure once (12 bytes per
+    # entry); solves read each factor entry and its column index once plus the vectors;
+    # the value update reads A's values and map and writes the factor; the row-ordered copy
+    # of the factor is this design's own layout conversion and is reported apart
+    # (layout_copy_bytes), not priced into any class
     per_unit = {
-        "refactor_large": (16 * st["nnz_lu_wide"] + 20 * st["copy_in_levels"]) * nprof,
-        "refactor_medium": 16 * st["nnz_lu_medium"] * nprof,
-        "refactor_small": 16 * (st["nnz_lu"] - st["nnz_lu_wide"] - st["nnz_lu_medium"]) * nprof,
+        "refactor_large": 12 * st["nnz_lu_wide"] * nprof,
+        "refactor_medium": 12 * st["nnz_lu_medium"] * nprof,
+        "refactor_small": 12 * (st["nnz_lu"] - st["nnz_lu_wide"] - st["nnz_lu_medium"]) * nprof,
         "lsolve": (12 * nnz_l + 48 * q.n) * solves,
         "usolve": (12 * (nnz_u + q.n) + 48 * q.n) * solves,
-        "to_csr": 20 * (st["nnz_lu"] - st["copy_in_levels"]) * nprof,
         "update": (12 * q.nnz + 12 * st["nnz_lu"] + 40 * q.n) * nprof,
     }
     kernel_of = {"refactor_large": "k_refactor_wide<WideCfg<512, 2, 256, 32, 4> >",
                  "refactor_medium": "k_refactor_wide<WideCfg<256, 4, 128, 16, 2> >",
                  "refactor_small": "k_refactor_small",
                  "lsolve": "k_lsolve_persistent", "usolve": "k_usolve_persistent", "to_csr": "k_to_csr",
-                 "update": "k_row_scale..k_max_parts", "residual": "k_residual/k_spmv", "krylov": "krylov"}
+                 "update": "k_clear_status..k_max_parts", "residual": "k_residual/k_spmv", "krylov": "krylov"}
     ranked = sorted((v[1], k) for k, v in prof.items())
     dom = ranked[-1][1]
     launches, ms = prof[dom]
@@ -199,7 +225,9 @@ def main():
         roofline = {"bound": "hbm", "achieved": round(ach, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 6), "traffic": stored_traffic(kernel_of[dom]),
                     "kernel": kernel_of[dom], "launches": launches, "avg_launch_us": round(ms / launches * 1e3, 3),
-                    "bytes_per_launch": per_unit[dom] // launches}
+                    "bytes_per_launch": per_unit[dom] // launches,
+                    "bytes_rule": "12 B per factor entry of the columns the launches factor",
+                    "layout_copy_bytes_per_unit": 20 * st["nnz_lu"]}
     else:
         roofline = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
                     "traffic": None, "kernel": kernel_of.get(dom, dom)}
@@ -208,6 +236,8 @@ def main():
              "frac": round(b_unit * value / 1e9 / HBM_PEAK_GBS, 6)}
     breakdown = {k: {"launches_per_unit": round(v[0] / nprof, 2), "ms_per_unit": round(v[1] / nprof, 4)}
                  for k, v in prof.items()}
+    nproc, cpu_model = host_info()
+    timed = sorted(set(order[:args.steps]))
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "units/s", "n_gpus": 1,
@@ -216,31 +246,41 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{spec.name}: {spec.buses}-bus-shaped KKT sequence, N={q.n}, "
                                f"nnz={q.nnz}, {T} systems, 1 rhs each",
-                   "nnz_lu": st["nnz_lu"], "analyze_s": round(t_analyze, 3),
+                   "nnz_lu": st["nnz_lu"], "pivot_tau": sk.opts["pivot_tau"],
+                   "offdiag_pivots": int(np.count_nonzero(sym["P"] != sym["Q"])),
+                   "timed_order": f"system (i * {stride}) mod {T} for unit i = 0..{args.steps - 1}",
+                   "timed_systems": (f"all {T}" if len(timed) == T else timed),
                    "refinement_preconditioner": (f"{args.approx_sweeps} Jacobi sweeps per triangle"
                                                  if args.approx_sweeps else "exact triangular solves")},
         "p50_ms": round(nearest_rank(lat, 50), 4), "p99_ms": round(nearest_rank(lat, 99), 4),
         "failures": fails, "fgmres_iters_mean": round(float(np.mean(iters)), 3),
         "berr_max": float(np.max(berrs)),
+        "perturbed_pivots_per_unit": round(float(np.mean(perts)), 2),
+        "workspace_bytes": sk.workspace_bytes(1),
+        "analyze_s": round(t_analyze, 3),
+        "analyze_amortized_ms_per_unit": round(t_analyze / T * 1e3, 3),
         "roofline": roofline,
         "whole_unit_bytes": whole,
         "kernel_breakdown": breakdown,
     }
+    sk.close()
+    del dvals, drhs, x
+    torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         import oracle
         t0 = time.perf_counter()
         so = oracle.Symbolic(q.n, q.rowptr, q.colind, vals[0])
         t_oa = time.perf_counter() - t0
-        sample = [int(round(i * (T - 1) / max(1, args.cpu_sample - 1))) for i in range(args.cpu_sample)]
+        sample = order[:max(1, min(args.cpu_sample, args.steps))]
         t0 = time.perf_counter()
         for t in sample:
             lu, r, c, _, _ = so.refactor(vals[t])
             so.fgmres(vals[t], lu, r, c, rhs[t])
         t_cpu = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": round(len(sample) / t_cpu, 4), "unit": "units/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"{len(sample)} units (steps {sample}) of the same sequence, "
-                                         f"single-threaded C oracle; oracle analyze {t_oa:.1f}s"}
+                               "kind": "oracle", "nproc": nproc, "cpu_model": cpu_model,
+                               "sample": f"the first {len(sample)} timed units (systems {sample}) of the same "
+                                         f"order, single-threaded C oracle; oracle analyze {t_oa:.1f}s"}
     print(json.dumps(out))
 
 

@@ -40,13 +40,16 @@ typedef struct ihipStream_t *hipStream_t;   /* identical to HIP's own typedef */
 #define KKT_OK 0
 #define KKT_WARN_PIVOT_PERTURBED 1  /* a refactor replaced tiny pivots (kkt_info) */
 #define KKT_WARN_NOT_CONVERGED 2    /* refinement stopped at max_iters above berr_tol */
-#define KKT_ERR_ARG (-1)            /* null pointer, bad size, bad option */
+#define KKT_ERR_ARG (-1)            /* null pointer, bad size, bad option, a size beyond the int32
+                                     * indices of the device structures */
 #define KKT_ERR_PATTERN (-2)        /* non-square, unsorted, duplicate, out of range, no diagonal */
 #define KKT_ERR_SINGULAR (-3)       /* analyze found a pivot step with no nonzero candidate */
 #define KKT_ERR_NONFINITE (-4)      /* NaN/Inf in values or factors */
 #define KKT_ERR_STATE (-5)          /* call order: refactor before bind, solve before refactor */
 #define KKT_ERR_NOMEM (-6)          /* host allocation failed or workspace too small */
 #define KKT_ERR_DEVICE (-7)         /* a HIP call failed */
+#define KKT_ERR_SCHEDULE (-8)       /* the analysed structure broke an internal invariant or limit of
+                                     * the GPU schedule (a library fault, not a property of the input) */
 
 typedef struct kkt_handle kkt_handle;
 

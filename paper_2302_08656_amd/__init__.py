@@ -6,9 +6,11 @@ PyTorch supplies device memory (the workspace and vectors) and the current strea
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import dataclasses
 import os
+import weakref
 
 import numpy as np
 
@@ -16,7 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkkt.so")
 
 OK, WARN_PIVOT_PERTURBED, WARN_NOT_CONVERGED = 0, 1, 2
-ERR_ARG, ERR_PATTERN, ERR_SINGULAR, ERR_NONFINITE, ERR_STATE, ERR_NOMEM, ERR_DEVICE = -1, -2, -3, -4, -5, -6, -7
+ERR_ARG, ERR_PATTERN, ERR_SINGULAR, ERR_NONFINITE, ERR_STATE, ERR_NOMEM, ERR_DEVICE, ERR_SCHEDULE = \
+    -1, -2, -3, -4, -5, -6, -7, -8
 
 
 class KKTError(RuntimeError):
@@ -62,6 +65,14 @@ EXPORTS = ["kkt_default_opts", "kkt_analyze", "kkt_get_stats", "kkt_export_symbo
            "kkt_destroy", "kkt_strerror"]
 
 _LIB = None
+# handles still open; destroyed at interpreter exit before the HIP runtime is torn down
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for sk in list(_LIVE):
+        sk.close()
 
 
 def _lib():
@@ -154,6 +165,7 @@ class KKTSolver:
         if rc != OK:
             raise KKTError(rc, "kkt_analyze")
         self._h = h
+        _LIVE.add(self)
         self.opts = {f: getattr(o, f) for f, _ in _Opts._fields_ if f not in ("fixed_p", "fixed_q")}
         st = _Stats()
         L.kkt_get_stats(h, C.byref(st))
@@ -191,12 +203,14 @@ class KKTSolver:
         dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         nbytes = self.workspace_bytes(max_nrhs)
         with torch.cuda.device(dev):
-            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
-            base = self._ws.data_ptr()
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+            base = ws.data_ptr()
             off = (-base) % 256
             rc = _lib().kkt_bind(self._h, C.c_void_p(base + off), nbytes, int(max_nrhs), _stream_ptr(stream))
         if rc != OK:
+            # the handle may still use the previous workspace: keep it alive
             raise KKTError(rc, "kkt_bind")
+        self._ws = ws          # the previous workspace is released only now
         self.device = dev
         return self
 

@@ -50,12 +50,6 @@ constexpr int kSmallR = 64;
 constexpr int kGroup = 32;
 constexpr int kMedW = 16;
 constexpr int kMedRows = 256;
-// Solve levels with at most this many items run in the persistent launch (build-time
-// tunable).
-#ifndef KKT_PERSIST_ITEMS
-#define KKT_PERSIST_ITEMS (1 << 30)
-#endif
-constexpr int kPersistItems = KKT_PERSIST_ITEMS;
 // Solve helpers: a wide panel gets helper items kHelpAhead levels before it when one of
 // its rows has at least kHelpMin early entries (columns of panels more than kHelpAhead
 // levels below); each helper item sums the early entries of kHelpRows rows.
@@ -113,7 +107,7 @@ struct Schedule {
     // slot, end}; backward {diagonal slot, first early slot, end, 0}
     std::vector<int32_t> rinfo4, urinfo4;
     // forward levels >= l_split and backward levels < u_split run in one persistent launch
-    // (levels of at most kPersistItems items; the rest as one launch per level)
+    // (with the persistent mode on, every level: l_split = 0, u_split = number of levels)
     int32_t l_split = 0, u_split = 0;
     // combined L+U in CSR for the row-oriented solves.  Rows of helped panels list their L
     // entries as [early | late | in-panel] and their U entries as [in-panel | late | early]:

@@ -41,21 +41,24 @@ __device__ __forceinline__ double group_sum(double v, int width) {
 // ---------------------------------------------------------------------------------------
 // value update
 
-// r_i = 2^-floor(log2 max_j |a_ij|), 8 lanes per row; also clears the status words
-__global__ __launch_bounds__(256) void k_row_scale(int n, const int32_t *__restrict__ rowptr,
-                                                   const double *__restrict__ v, int scale,
-                                                   double *__restrict__ r, DevStatus *st,
-                                                   unsigned long long *pcount) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid == 0) {
+// Clears the status words and the replaced-pivot counter slots of a refactorization (one
+// block, launched before k_row_scale, whose blocks may raise the non-finite flag).
+__global__ __launch_bounds__(256) void k_clear_status(DevStatus *st, unsigned long long *pcount) {
+    if (threadIdx.x == 0) {
         st->anorm_scaled = 0.0;
         st->anorm = 0.0;
         st->perturbed = 0;
         st->flags = 0;
         st->abort = 0;
     }
-    if (blockIdx.x == 0)
-        for (int t = threadIdx.x; t < kCountSlots; t += blockDim.x) pcount[t] = 0;
+    for (int t = threadIdx.x; t < kCountSlots; t += blockDim.x) pcount[t] = 0;
+}
+
+// r_i = 2^-floor(log2 max_j |a_ij|), 8 lanes per row; a non-finite value raises the flag
+__global__ __launch_bounds__(256) void k_row_scale(int n, const int32_t *__restrict__ rowptr,
+                                                   const double *__restrict__ v, int scale,
+                                                   double *__restrict__ r, DevStatus *st) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = gid >> 3, gl = gid & 7;
     double m = 0.0;
     int bad = 0;
@@ -212,24 +215,6 @@ __device__ __forceinline__ int lower_bound_row(const int32_t *__restrict__ rowid
 constexpr int kBlock = 256;   // threads of the elementwise, small-item and solve blocks
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
-
-// Optional phase timestamps of the wide refactorization items (development builds only):
-// with KKT_PHASE_TRACE defined, thread 0 of each item records the constant-rate clock at
-// each phase boundary into kkt_phase_buf[item * 8 + phase].
-#ifdef KKT_PHASE_TRACE
-__device__ unsigned long long *kkt_phase_buf;
-#define KKT_PHASE(item, k)                                                             \
-    do {                                                                               \
-        if (threadIdx.x == 0 && kkt_phase_buf) {                                       \
-            kkt_phase_buf[(item) * 16 + (k)] = wall_clock64();                         \
-            if ((k) == 0 || (k) == 5) kkt_phase_buf[(item) * 16 + 14 + (k) / 5] = clock64(); \
-        }                                                                              \
-    } while (0)
-#else
-#define KKT_PHASE(item, k) \
-    do {                   \
-    } while (0)
-#endif
 
 // Packed 32-byte records (two int4 each):
 //   item[2i]   = {panel to factor or -1, first pair, end of pairs, 0}
@@ -568,8 +553,7 @@ __device__ __forceinline__ void sweep_step(double (&x)[kPanelMax], const double 
 constexpr int kSweepSpin = 1 << 22;
 
 template <class C, int KW>
-__device__ __forceinline__ void large_factor_w(const RefArgs &a, int w, int r, char *sm, double thresh,
-                                               int item) {
+__device__ __forceinline__ void large_factor_w(const RefArgs &a, int w, int r, char *sm, double thresh) {
     const int tid = threadIdx.x, lane = tid & 63;
     double *Us = reinterpret_cast<double *>(sm + C::kOffLd);
     const int *sgs = reinterpret_cast<const int *>(sm + C::kOffSgs);
@@ -624,9 +608,7 @@ __device__ __forceinline__ void large_factor_w(const RefArgs &a, int w, int r, c
             }
         }
     }
-    KKT_PHASE(item, 6);
     __syncthreads();
-    KKT_PHASE(item, 7);
     // U rows of the diagonal block (diagonal included) from LDS
     for (int t = tid; t < w * KW; t += C::kThreads) {
         const int j = t / KW, c = t % KW;
@@ -643,29 +625,28 @@ __device__ __forceinline__ void large_factor_w(const RefArgs &a, int w, int r, c
 }
 
 template <class C>
-__device__ __forceinline__ void large_factor(const RefArgs &a, int4 pn, char *sm, double thresh, int item) {
+__device__ __forceinline__ void large_factor(const RefArgs &a, int4 pn, char *sm, double thresh) {
     if constexpr (C::kMaxW > 16) {
         if (pn.y > 16) {
-            large_factor_w<C, 32>(a, pn.y, pn.z, sm, thresh, item);
+            large_factor_w<C, 32>(a, pn.y, pn.z, sm, thresh);
             return;
         }
     }
-    if (pn.y > 8) large_factor_w<C, 16>(a, pn.y, pn.z, sm, thresh, item);
-    else large_factor_w<C, 8>(a, pn.y, pn.z, sm, thresh, item);
+    if (pn.y > 8) large_factor_w<C, 16>(a, pn.y, pn.z, sm, thresh);
+    else large_factor_w<C, 8>(a, pn.y, pn.z, sm, thresh);
 }
 
 // Rows of the source panel (width w) in one target: unit lower solve with the source's
 // diagonal block Ls[j * kPanelMax + c] = L(j + c, j) (zero past the panel), in registers,
 // shifted; writes the solved rows to the factor and to ub.
 template <int KW>
-__device__ __forceinline__ void unit_lower_w(double *lu, int ps, int w, const double *Ls, double *ub, int item) {
+__device__ __forceinline__ void unit_lower_w(double *lu, int ps, int w, const double *Ls, double *ub) {
     double u[kPanelMax];
 #pragma unroll
     for (int c = 0; c < KW; ++c) {
         const double v = lu[ps + (c < w ? c : 0)];
         u[c] = c < w ? v : 0.0;
     }
-    KKT_PHASE(item, 8);
     // the window narrows to KW / 2 columns once no more remain (the rest are zeros)
     constexpr int KH = KW / 2;
     const int jsplit = max(0, w - KH);
@@ -689,7 +670,6 @@ __device__ __forceinline__ void unit_lower_w(double *lu, int ps, int w, const do
         ub[j] = uj;
         shift_fma<KH>(u, uj, rw);
     }
-    KKT_PHASE(item, 9);
 }
 
 // All pulls of one item with the source panel staged in LDS, then the panel factorization.
@@ -698,7 +678,6 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char
     const double thresh = a.tiny * a.st->anorm_scaled;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     constexpr int nw = C::kThreads / 64;
-    KKT_PHASE(item, 0);
     double *Ld = reinterpret_cast<double *>(sm + C::kOffLd);
     double *Ub = reinterpret_cast<double *>(sm + C::kOffUb);
     double *Lr = reinterpret_cast<double *>(sm + C::kOffLr);
@@ -715,7 +694,6 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char
     __syncthreads();
     auto pra = [&](int q) { return staged ? prs[2 * (q - pbeg)] : a.pair[2 * q]; };
     auto prb = [&](int q) { return staged ? prs[2 * (q - pbeg) + 1] : a.pair[2 * q + 1]; };
-    KKT_PHASE(item, 1);
     for (int g0 = pbeg, g1; g0 < p1; g0 = g1) {
         const int S = pra(g0).x;
         g1 = g0 + 1;
@@ -735,7 +713,6 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char
             Lr[j * C::kChunk + i] = a.lu[lds[j] + 1 + (w - 1 - j) + i];
         }
         __syncthreads();
-        KKT_PHASE(item, 2);
         // Update of the rows R of each target by S on the matrix cores (more than one target):
         // the block Lr (nr x w) times the solved rows (w x m) in 16x16 output tiles, k in steps
         // of 4; lane holds A[lane % 16][lane / 16], B[lane / 16][lane % 16] and the four outputs
@@ -774,12 +751,11 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char
         if (wv == 0 && lane < m) {
             const int ps = pra(g0 + lane).y;
             double *ub = Ub + lane * kRowLd;
-            if (C::kMaxW > 16 && w > 16) unit_lower_w<C::kMaxW>(a.lu, ps, w, Ld, ub, item);
-            else if (w > 8) unit_lower_w<16>(a.lu, ps, w, Ld, ub, item);
-            else unit_lower_w<8>(a.lu, ps, w, Ld, ub, item);
+            if (C::kMaxW > 16 && w > 16) unit_lower_w<C::kMaxW>(a.lu, ps, w, Ld, ub);
+            else if (w > 8) unit_lower_w<16>(a.lu, ps, w, Ld, ub);
+            else unit_lower_w<8>(a.lu, ps, w, Ld, ub);
         }
         __syncthreads();
-        KKT_PHASE(item, 3);
         // rows R of each target: chunks of S's L rows in LDS, precomputed slots
         for (int i0 = 0; i0 < r; i0 += C::kChunk) {
             const int nr = min(C::kChunk, r - i0);
@@ -854,10 +830,8 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char
         }
         __threadfence_block();
         __syncthreads();
-        KKT_PHASE(item, 4);
     }
-    if (ia.x >= 0) large_factor<C>(a, ib, sm, thresh, item);
-    KKT_PHASE(item, 5);
+    if (ia.x >= 0) large_factor<C>(a, ib, sm, thresh);
 }
 
 // One launch per level: block b < nwide runs wide item item0 + b; the blocks after it run
@@ -1069,30 +1043,10 @@ __device__ __forceinline__ double inpanel_backward(const double (&Urow)[kPanelMa
     return xv;
 }
 
-#ifdef KKT_PHASE_TRACE
-__device__ unsigned long long *kkt_phase_buf2;
-#define KKT_UPHASE(item, k)                                                             \
-    do {                                                                                \
-        if (kWait && threadIdx.x == 0 && kkt_phase_buf2) kkt_phase_buf2[(item) * 4 + (k)] = wall_clock64(); \
-    } while (0)
-#define KKT_SPHASE(item, k)                                                             \
-    do {                                                                                \
-        if (kWait && threadIdx.x == 0 && kkt_phase_buf) kkt_phase_buf[(item) * 4 + (k)] = wall_clock64(); \
-    } while (0)
-#else
-#define KKT_SPHASE(item, k) \
-    do {                    \
-    } while (0)
-#define KKT_UPHASE(item, k) \
-    do {                    \
-    } while (0)
-#endif
-
 template <bool kWait>
 __device__ __forceinline__ void lsolve_item(const SolveArgs &a, int item, double *ext, double *blk) {
     const int4 it = a.item[item];
     const int tid = threadIdx.x, lane = tid & 63;
-    KKT_SPHASE(item, 0);
     if (it.x < 0) {                                     // pack of whole small panels
         __shared__ double ys[kSolvePack];
         const int lanes = it.z, g = tid / lanes, gl = tid % lanes;
@@ -1116,7 +1070,6 @@ __device__ __forceinline__ void lsolve_item(const SolveArgs &a, int item, double
             }
             __syncthreads();
         }
-        KKT_SPHASE(item, 3);
         return;
     }
     const int s = it.z, w = it.w;
@@ -1127,7 +1080,6 @@ __device__ __forceinline__ void lsolve_item(const SolveArgs &a, int item, double
             const double acc = sdot<kWait, 8>(a, a.y, ri.x, ri.y, lane, 64);
             if (lane == 0) put_value<kWait>(a.psum + s + t, acc);
         }
-        KKT_SPHASE(item, 3);
         return;
     }
     // wide panel: the in-panel rows are staged in LDS (blk[r * kRowLd + t] = L(r, t),
@@ -1148,9 +1100,7 @@ __device__ __forceinline__ void lsolve_item(const SolveArgs &a, int item, double
             if (gl == 0) ext[t] = bv - (helped ? acc + ps : acc);
         }
     }
-    KKT_SPHASE(item, 1);
     __syncthreads();
-    KKT_SPHASE(item, 2);
     if (tid < 64) {
         double Lrow[kPanelMax];
         load_lds_row<kPanelMax>(Lrow, blk + min(lane, kPanelMax - 1) * kRowLd);
@@ -1158,7 +1108,6 @@ __device__ __forceinline__ void lsolve_item(const SolveArgs &a, int item, double
         yv = inpanel_forward(Lrow, w, lane, yv);
         if (lane < w) put_value<kWait>(a.y + s + lane, yv);
     }
-    KKT_SPHASE(item, 3);
     __syncthreads();
 }
 
@@ -1166,7 +1115,6 @@ template <bool kWait>
 __device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double *ext, double *blk) {
     const int4 it = a.item[item];
     const int tid = threadIdx.x, lane = tid & 63;
-    KKT_UPHASE(item, 0);
     if (it.x < 0) {                                     // pack of whole small panels
         __shared__ double xs[kSolvePack];
         const int lanes = it.z, g = tid / lanes, gl = tid % lanes;
@@ -1202,7 +1150,6 @@ __device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double
             }
             __syncthreads();
         }
-        KKT_UPHASE(item, 3);
         return;
     }
     const int s = it.z, w = it.w;
@@ -1213,7 +1160,6 @@ __device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double
             const double acc = sdot<kWait, 8>(a, a.xt, ri.y, ri.z, lane, 64);
             if (lane == 0) put_value<kWait>(a.usum + s + t, acc);
         }
-        KKT_UPHASE(item, 3);
         return;
     }
     // in-panel rows staged in LDS: blk[r * kRowLd + t] = U(r, t) for t > r, else zero
@@ -1241,9 +1187,7 @@ __device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double
             if (gl == 0) ext[t] = helped ? acc + us : acc;
         }
     }
-    KKT_UPHASE(item, 1);
     __syncthreads();
-    KKT_UPHASE(item, 2);
     if (tid < 64) {
         double Urow[kPanelMax];
         load_lds_row<kPanelMax>(Urow, blk + min(lane, kPanelMax - 1) * kRowLd);
@@ -1254,7 +1198,6 @@ __device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double
             put_value<kWait>(a.xt + s + lane, xv);
         }
     }
-    KKT_UPHASE(item, 3);
     __syncthreads();
 }
 

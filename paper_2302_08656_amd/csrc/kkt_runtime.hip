@@ -68,6 +68,7 @@ struct kkt_handle {
     // (created at the first bind) and replayed on the caller's stream
     hipStream_t cap = nullptr;
     hipGraphExec_t levels = nullptr;
+    hipEvent_t levels_done = nullptr;   // recorded after every replay, on the caller's stream
     bool levels_failed = false;
     // launch profiler
     bool prof = false;
@@ -263,8 +264,9 @@ int enqueue_update(kkt_handle *h, const double *v, hipStream_t s) {
     const Dev &d = h->d;
     const int n = h->sym.n;
     const int eq = h->opts.equilibrate != 0;
+    timed(h, KKT_PROF_UPDATE, s, [&] { k_clear_status<<<1, 256, 0, s>>>(d.st, d.pcount); });
     timed(h, KKT_PROF_UPDATE, s, [&] {
-        k_row_scale<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_rowptr, v, eq, d.r, d.st, d.pcount);
+        k_row_scale<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_rowptr, v, eq, d.r, d.st);
     });
     timed(h, KKT_PROF_UPDATE, s, [&] {
         k_col_scale<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_cptr, d.a_cpos, d.a_crow, v, d.r, eq, d.c);
@@ -610,15 +612,19 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
         h->grid_u = std::max(1, bu) * std::max(1, ncu);
         h->ncu = std::max(1, ncu);
     }
+    if (h->device >= 0 && h->device != dev) return KKT_ERR_STATE;   // rebinding keeps the device
+    h->device = dev;
+    h->bound = false;      // until the new workspace holds the structure
+    h->factored = false;
     if (!h->h_small) HIPCHK(hipHostMalloc(&h->h_small, sizeof(double) * 4 * (kMaxRestart + 2) + 256));
-    if (h->cap && h->device != dev) return KKT_ERR_STATE;   // rebinding keeps the device
-    if (h->levels) {   // recorded with the previous workspace's addresses
-        HIPCHK(hipStreamSynchronize(h->cap));
+    if (h->levels) {   // recorded with the previous workspace's addresses; the last replay
+        HIPCHK(hipEventSynchronize(h->levels_done));   // may still run on a caller's stream
         HIPCHK(hipGraphExecDestroy(h->levels));
         h->levels = nullptr;
     }
     h->levels_failed = false;
     if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    if (!h->levels_done) HIPCHK(hipEventCreateWithFlags(&h->levels_done, hipEventDisableTiming));
     carve(h, static_cast<char *>(d_workspace), h->d, &need);
     const Symbolic &s = h->sym;
     const Schedule &g = h->sch;
@@ -659,7 +665,6 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     if (rc) return KKT_ERR_DEVICE;
     HIPCHK(hipMemsetAsync(d.st, 0, sizeof(DevStatus), stream));
     HIPCHK(hipStreamSynchronize(stream));
-    h->device = dev;
     h->ws = static_cast<char *>(d_workspace);
     h->ws_bytes = bytes;
     h->max_nrhs = max_nrhs;
@@ -698,6 +703,7 @@ int run_levels(kkt_handle *h, hipStream_t s) {
             if (!h->levels) record_levels(h);
             if (h->levels) {
                 HIPCHK(hipGraphLaunch(h->levels, s));
+                HIPCHK(hipEventRecord(h->levels_done, s));
                 return KKT_OK;
             }
         }
@@ -806,18 +812,23 @@ int kkt_profile_read(kkt_handle *h, kkt_profile *out, hipStream_t stream) {
 
 void kkt_destroy(kkt_handle *h) {
     if (!h) return;
-    if (h->h_small) (void)hipHostFree(h->h_small);
-    if (h->cap) {
+    // order: wait for the last replay and for every profiled launch, then release the graph,
+    // the capture stream, the events and last the pinned staging buffer
+    if (h->device >= 0) {
         DeviceGuard g(h->device);
-        (void)hipStreamSynchronize(h->cap);
+        if (h->levels_done) (void)hipEventSynchronize(h->levels_done);
+        for (auto &pe : h->ev_pending) (void)hipEventSynchronize(pe.second.second);
+        if (h->cap) (void)hipStreamSynchronize(h->cap);
         if (h->levels) (void)hipGraphExecDestroy(h->levels);
-        (void)hipStreamDestroy(h->cap);
+        if (h->cap) (void)hipStreamDestroy(h->cap);
+        if (h->levels_done) (void)hipEventDestroy(h->levels_done);
+        for (auto &pe : h->ev_pending) h->ev_free.push_back(pe.second);
+        for (auto &ev : h->ev_free) {
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
     }
-    for (auto &pe : h->ev_pending) h->ev_free.push_back(pe.second);
-    for (auto &ev : h->ev_free) {
-        (void)hipEventDestroy(ev.first);
-        (void)hipEventDestroy(ev.second);
-    }
+    if (h->h_small) (void)hipHostFree(h->h_small);
     delete h;
 }
 
@@ -833,6 +844,7 @@ const char *kkt_strerror(int status) {
         case KKT_ERR_STATE: return "call out of order";
         case KKT_ERR_NOMEM: return "out of memory or workspace too small";
         case KKT_ERR_DEVICE: return "HIP runtime error";
+        case KKT_ERR_SCHEDULE: return "internal GPU schedule invariant or limit violated";
         default: return "unknown status";
     }
 }

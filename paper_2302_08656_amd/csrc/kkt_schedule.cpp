@@ -30,7 +30,7 @@ namespace kkt {
 int build_schedule(const Symbolic &s, Schedule &g) {
     const int32_t n = s.n;
     const int64_t nlu = s.nnz_lu();
-    if (nlu >= INT32_MAX || s.nnz_a >= INT32_MAX) return KKT_ERR_NOMEM;
+    if (nlu >= INT32_MAX || s.nnz_a >= INT32_MAX) return KKT_ERR_ARG;   // int32 slots on the device
     // panels
     g.pan_start.clear();
     for (int32_t t = 0; t + 1 < (int32_t)s.sn_start.size(); ++t) {
@@ -52,16 +52,16 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         const int64_t r0 = lbeg(e - 1);
         for (int32_t j = sp; j < e; ++j) {
             const int64_t l = lbeg(j);
-            if (s.colptr[j + 1] - l != (e - 1 - j) + g.pan_r[p]) return KKT_ERR_PATTERN;
+            if (s.colptr[j + 1] - l != (e - 1 - j) + g.pan_r[p]) return KKT_ERR_SCHEDULE;
             for (int32_t t = 0; t < e - 1 - j; ++t)
-                if (s.rowidx[l + t] != j + 1 + t) return KKT_ERR_PATTERN;
+                if (s.rowidx[l + t] != j + 1 + t) return KKT_ERR_SCHEDULE;
             if (!std::equal(s.rowidx.begin() + l + (e - 1 - j), s.rowidx.begin() + s.colptr[j + 1],
                             s.rowidx.begin() + r0))
-                return KKT_ERR_PATTERN;
+                return KKT_ERR_SCHEDULE;
             // U rows s..j-1 directly above the diagonal
-            if (s.ulen[j] < j - sp) return KKT_ERR_PATTERN;
+            if (s.ulen[j] < j - sp) return KKT_ERR_SCHEDULE;
             for (int32_t t = 0; t < j - sp; ++t)
-                if (s.rowidx[s.colptr[j] + s.ulen[j] - (j - sp) + t] != sp + t) return KKT_ERR_PATTERN;
+                if (s.rowidx[s.colptr[j] + s.ulen[j] - (j - sp) + t] != sp + t) return KKT_ERR_SCHEDULE;
         }
     }
     // refactor levels of panels and (source, target) pairs.  A panel T waits for every
@@ -92,9 +92,9 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         const int32_t sp = g.pan_start[S], e = g.pan_start[S + 1];
         const auto b = s.rowidx.begin() + s.colptr[k], en = s.rowidx.begin() + s.colptr[k] + s.ulen[k];
         const auto it = std::lower_bound(b, en, sp);
-        if (en - it < e - sp) return KKT_ERR_PATTERN;
+        if (en - it < e - sp) return KKT_ERR_SCHEDULE;
         for (int32_t t = 0; t < e - sp; ++t)
-            if (it[t] != sp + t) return KKT_ERR_PATTERN;
+            if (it[t] != sp + t) return KKT_ERR_SCHEDULE;
     }
     const int32_t nlev = np ? 1 + *std::max_element(plev.begin(), plev.end()) : 0;
     // group pairs by launch (= source level + 1), then target column, then source
@@ -190,7 +190,7 @@ int build_schedule(const Symbolic &s, Schedule &g) {
             for (size_t q = 0, q1; q < it.pairs.size(); q = q1) {
                 q1 = q;
                 while (q1 < it.pairs.size() && it.pairs[q1].first == it.pairs[q].first) ++q1;
-                if (q1 - q > (size_t)kGroup) return KKT_ERR_PATTERN;
+                if (q1 - q > (size_t)kGroup) return KKT_ERR_SCHEDULE;
             }
             nlarge += !it.small;
             nmed += it.kind == 1;
@@ -208,7 +208,7 @@ int build_schedule(const Symbolic &s, Schedule &g) {
                 for (int64_t t = lbeg(e - 1); t < s.colptr[e]; ++t) {
                     const int32_t row = s.rowidx[t];
                     while (p < pend && s.rowidx[p] < row) ++p;
-                    if (p == pend || s.rowidx[p] != row) return KKT_ERR_PATTERN;
+                    if (p == pend || s.rowidx[p] != row) return KKT_ERR_SCHEDULE;
                     g.f_rel.push_back((int32_t)p);
                 }
                 g.f_pair_rel.push_back((int64_t)g.f_rel.size());
@@ -219,8 +219,8 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         g.f_nmed.push_back(nmed);
         g.f_lvl.push_back((int32_t)g.f_item_panel.size());
     }
-    if (!by_launch[nlev].empty()) return KKT_ERR_PATTERN;   // top panels have no targets
-    if (g.f_rel.size() >= (size_t)INT32_MAX) return KKT_ERR_NOMEM;
+    if (!by_launch[nlev].empty()) return KKT_ERR_SCHEDULE;   // top panels have no targets
+    if (g.f_rel.size() >= (size_t)INT32_MAX) return KKT_ERR_ARG;
     g.ldiag.resize(n);
     for (int32_t j = 0; j < n; ++j) g.ldiag[j] = (int32_t)(s.colptr[j] + s.ulen[j]);
     // packed records (8 x int32 each): item i = {T, first pair, end pair, 0, s, w, r,
@@ -354,13 +354,9 @@ int build_schedule(const Symbolic &s, Schedule &g) {
     };
     build_solve(llev, g.l_lvl, g.l_item4, g.l_rows4, has_lhelp);
     build_solve(ulev, g.u_lvl, g.u_item4, g.u_rows4, has_uhelp);
-    {
-        const int32_t nl = (int32_t)g.l_lvl.size() - 1, nu = (int32_t)g.u_lvl.size() - 1;
-        g.l_split = nl;
-        while (g.l_split > 0 && g.l_lvl[g.l_split] - g.l_lvl[g.l_split - 1] <= kPersistItems) --g.l_split;
-        g.u_split = 0;
-        while (g.u_split < nu && g.u_lvl[g.u_split + 1] - g.u_lvl[g.u_split] <= kPersistItems) ++g.u_split;
-    }
+    // with the persistent mode on, one launch per triangle covers every level
+    g.l_split = 0;
+    g.u_split = (int32_t)g.u_lvl.size() - 1;
     // combined L+U in CSR: row i lists (i, j) by ascending j, csr_src = CSC slot
     g.csr_rowptr.assign(n + 1, 0);
     for (int64_t p = 0; p < nlu; ++p) g.csr_rowptr[s.rowidx[p] + 1]++;

@@ -1,3 +1,4 @@
+import gc
 import os
 import sys
 
@@ -11,3 +12,11 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: CPU test that takes tens of seconds")
+
+
+@pytest.fixture(autouse=True)
+def _release_handles():
+    """Destroys the solver handles a test left behind (their device work is finished by
+    then) before the next test starts."""
+    yield
+    gc.collect()

@@ -57,6 +57,33 @@ def check_factor_parity(so, lu_g, lu_o, npert, thresh):
     assert np.all(excess <= (2 * thresh if npert else 0.0)), f"diagonal excess {excess.max():.3e}"
 
 
+def check_solve_componentwise(so, lu_g, r, c, b, x):
+    """One triangular-solve application x = Q C (L^U^)^-1 P R b with the GPU's own factors:
+    with x~ = C^-1 Q^T x and b~ = P R b (both exact, power-of-two scaling), the forward and
+    backward substitutions satisfy (L^ + dL) y = b~, (U^ + dU) x~ = y with |dL| <= gL |L^|,
+    |dU| <= gU |U^| (gL = gamma of the longest L row plus its subtraction; gU also counts
+    the reciprocal of the diagonal and its product), hence
+    |b~ - L^ U^ x~| <= (gL + gU + gL gU) |L^| |U^| |x~|.  The residual is formed in extended
+    precision so that the host's own rounding stays far below the bound."""
+    n = so.n
+    cols = np.repeat(np.arange(n), np.diff(so.colptr))
+    low = so.rowidx > cols
+    kL = np.bincount(so.rowidx[low], minlength=n)
+    kU = np.bincount(so.rowidx[~low], minlength=n) - 1
+    gam = lambda m: m * U_RND / (1 - m * U_RND)
+    gL, gU = gam(kL.max() + 1), gam(kU.max() + 3)
+    Lg, Ug = factors(n, so.colptr, so.rowidx, lu_g)
+    xt = x[so.Q] / c[so.Q]
+    bt = r[so.P] * b[so.P]
+    assert np.isfinite(xt).all()
+    L128, U128 = Lg.astype(np.longdouble), Ug.astype(np.longdouble)
+    res = np.abs(bt.astype(np.longdouble) - L128 @ (U128 @ xt.astype(np.longdouble))).astype(np.float64)
+    bound = (gL + gU + gL * gU) * (abs(Lg) @ (abs(Ug) @ np.abs(xt))) * (1 + 1e-12)
+    worst = np.max(res / np.maximum(bound, 1e-300))
+    assert np.all(res <= bound), f"solve residual exceeds its bound by {worst:.3e}x"
+    return worst
+
+
 def setup(q, t0=0, **kw):
     v0 = q.values(t0)
     so = oracle.Symbolic(q.n, q.rowptr, q.colind, v0, **{k: v for k, v in kw.items() if k == "tau"})
@@ -74,6 +101,8 @@ CASES = [
     ("grid2000_vector_fma", kktgen.small(2000, config_id=147, steps=2), {"dense_mfma": 0}),
     ("grid2000_mfma", kktgen.small(2000, config_id=147, steps=2), {}),
     ("grid2000_level_solves", kktgen.small(2000, config_id=147, steps=2), {"persistent_solve": 0}),
+    # threshold pivoting at analysis: 6,030 off-diagonal pivots, 377 panel levels
+    ("grid2000_tau1e-3", kktgen.small(2000, config_id=147, steps=2), {"tau": 1e-3}),
 ]
 
 
@@ -95,6 +124,8 @@ def test_refactor_parity(name, spec, kw):
         At = sp.diags(r_o) @ A @ sp.diags(c_o)
         thresh = oracle.EPS * abs(At).sum(axis=1).max()
         check_factor_parity(so, lu_g, lu_o, np_o, thresh)
+        b = q.rhs(t)
+        check_solve_componentwise(so, lu_g, r_g, c_g, b, sk.solve(cuda(b)).cpu().numpy())
 
 
 @pytest.mark.parametrize("name,spec,kw", CASES, ids=[c[0] for c in CASES])
@@ -234,12 +265,17 @@ def test_deterministic_refactor_and_solve():
     assert np.array_equal(lu1, lu2) and np.array_equal(x1, x2)
 
 
-def test_nonfinite_values_reported():
-    print("[gpu] non-finite values", flush=True)
-    q = kktgen.make_sequence(kktgen.small(30, config_id=145))
+@pytest.mark.parametrize("where,bad", [("first_block", np.nan), ("last_row", np.nan), ("last_row", np.inf),
+                                       ("middle", -np.inf)])
+def test_nonfinite_values_reported(where, bad):
+    # the status words are cleared by a launch of their own before the row pass, so a flag
+    # raised by any block of the row pass survives (a 2,000-bus grid has 76 row blocks)
+    print(f"[gpu] non-finite values {where} {bad}", flush=True)
+    q = kktgen.make_sequence(kktgen.small(30 if where == "first_block" else 2000, config_id=145))
     so, sk = setup(q)
     v = q.values(1)
-    v[5] = np.nan
+    pos = {"first_block": 5, "last_row": q.nnz - 1, "middle": q.nnz // 2}[where]
+    v[pos] = bad
     vd = cuda(v)
     sk.refactor(vd)
     with pytest.raises(K.KKTError) as e:
@@ -285,7 +321,9 @@ def test_not_converged_is_reported():
 @pytest.mark.parametrize("cid,steps", [(1, (0, 1, 29)), (2, (0, 1, 49))], ids=["grid25k", "grid70k"])
 def test_full_size_grids(cid, steps):
     """Full-size parity: scale factors bit-exact, equal perturbation counts, factors within
-    the bound above, and backward error <= 1e-10 after refinement."""
+    the bound above, one triangular-solve application within its componentwise bound (this
+    reaches the wide-panel and helper items of the solves), backward error <= 1e-10 after
+    refinement, and as many FGMRES steps as the oracle's run of the same algorithm (+-1)."""
     print(f"[gpu] full size config {cid}", flush=True)
     q = kktgen.make_sequence(kktgen.config(cid))
     so, sk = setup(q)
@@ -302,6 +340,11 @@ def test_full_size_grids(cid, steps):
         assert np_g == np_o
         At = sp.diags(r_o) @ q.scipy(t) @ sp.diags(c_o)
         check_factor_parity(so, lu_g, lu_o, np_o, oracle.EPS * abs(At).sum(axis=1).max())
+        x0 = sk.solve(cuda(b)).cpu().numpy()
+        worst = check_solve_componentwise(so, lu_g, r_g, c_g, b, x0)
         x, info = sk.refine(cuda(b))
         _, berr = oracle.residual(q.n, q.rowptr, q.colind, v, x.cpu().numpy(), b)
         assert info[0].status == K.OK and berr <= 1e-10, (t, berr, info)
+        _, it_o, berr_o, st_o = so.fgmres(v, lu_o, r_o, c_o, b)
+        print(f"[gpu]   solve bound use {worst:.2e}; fgmres steps gpu {info[0].iters} oracle {it_o}", flush=True)
+        assert st_o == oracle.OK and abs(info[0].iters - it_o) <= 1, (t, info[0].iters, it_o)

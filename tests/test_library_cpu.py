@@ -103,9 +103,12 @@ def test_symbolic_bit_exact_random_unsymmetric(seed):
 
 
 @pytest.mark.slow
-def test_symbolic_bit_exact_25k_grid():
-    q = kktgen.make_sequence(kktgen.config(1))
-    compare_symbolic(q.n, q.rowptr, q.colind, q.values(0))
+@pytest.mark.parametrize("cid", [1, 2], ids=["grid25k", "grid70k"])
+def test_symbolic_bit_exact_full_size_grids(cid):
+    q = kktgen.make_sequence(kktgen.config(cid))
+    sk, so = compare_symbolic(q.n, q.rowptr, q.colind, q.values(0))
+    # the default static diagonal pivoting keeps every diagonal on these grids
+    assert np.array_equal(so.P, so.Q)
 
 
 def test_analyze_errors_match_oracle():

@@ -284,6 +284,111 @@ def test_threshold_pivot_invariant():
         assert abs(colk[0]) >= tau * m * (1 - 1e-9)
 
 
+def pivot_rule_replay(At, P, Q, tau):
+    """Replays the analysis pivot sequence by dense right-looking elimination of A~(:, Q)
+    (rows kept in original index) and checks every step's choice against the rule:
+    the diagonal row Q[k] is taken exactly when it is a non-pivotal row with a nonzero value
+    and |x_diag| >= tau * max|x_candidates|; otherwise the largest candidate, lowest row on
+    ties.  Steps whose decision lies within rounding of the threshold or of a tie are not
+    asserted.  Returns (asserted steps, steps where the diagonal won without being the
+    largest candidate, steps that took an off-diagonal row)."""
+    n = At.shape[0]
+    M = At[:, Q].copy()
+    pivotal = np.zeros(n, dtype=bool)
+    rows = np.arange(n)
+    checked = diag_not_max = offdiag = 0
+    for k in range(n):
+        cand = ~pivotal
+        x = np.where(cand, M[:, k], 0.0)
+        ax = np.abs(x)
+        m = ax.max()
+        assert m > 0.0, k
+        d = Q[k]
+        diag_ok = bool(cand[d] and x[d] != 0.0 and ax[d] >= tau * m)
+        near_thr = cand[d] and x[d] != 0.0 and abs(ax[d] - tau * m) <= 1e-11 * m
+        win = np.flatnonzero(cand & (ax >= m * (1 - 1e-9)))
+        exact_tie = np.all(ax[win] == m)
+        if not near_thr:
+            if diag_ok:
+                assert P[k] == d, (k, P[k], d)
+                diag_not_max += int(ax[d] < m)
+            else:
+                assert P[k] != d or not cand[d] or x[d] == 0.0, k
+                if len(win) == 1 or exact_tie:
+                    assert P[k] == win.min(), (k, P[k], win)
+                else:
+                    assert P[k] in win, (k, P[k], win)
+                offdiag += int(P[k] != d)
+            checked += 1
+        piv = P[k]
+        assert cand[piv], k
+        el = cand & (rows != piv)
+        M[el, k + 1:] -= np.outer(M[el, k] / M[piv, k], M[piv, k + 1:])
+        pivotal[piv] = True
+    return checked, diag_not_max, offdiag
+
+
+@pytest.mark.parametrize("tau", [0.0, 1e-3, 0.1])
+def test_pivot_rule_dense_replay_kkt(tau):
+    """The diagonal preference of the analysis pivot rule, replayed densely on a KKT grid.
+    At tau = 0 every nonzero diagonal is kept, also where another candidate is larger, so
+    an oracle that always took the largest candidate fails here."""
+    q = kktgen.make_sequence(kktgen.small(14, config_id=109, steps=1, schedule="fixed"))
+    v = q.values(0)
+    s = oracle.Symbolic(q.n, q.rowptr, q.colind, v, tau=tau)
+    r, c = oracle.equilibrate(q.n, q.rowptr, q.colind, v)
+    At = (r[:, None] * q.scipy(0).toarray()) * c[None, :]
+    checked, diag_not_max, offdiag = pivot_rule_replay(At, s.P, s.Q, tau)
+    assert checked >= q.n - 2
+    assert diag_not_max > 0
+    if tau == 0.0:
+        assert np.array_equal(s.P, s.Q)
+
+
+@pytest.mark.parametrize("seed,tau", [(0, 0.0), (1, 1e-3), (2, 0.1), (3, 0.1), (4, 0.5)])
+def test_pivot_rule_dense_replay_random_unsymmetric(seed, tau):
+    rng = np.random.default_rng(300 + seed)
+    n = 48
+    M = (rng.random((n, n)) < 0.12) * rng.standard_normal((n, n))
+    M[np.arange(n), np.arange(n)] = rng.standard_normal(n) * (rng.random(n) < 0.8)
+    rp, ci, v = dense_to_csr(M, force_diag=True)
+    try:
+        s = oracle.Symbolic(n, rp, ci, v, tau=tau)
+    except oracle.OracleError:
+        pytest.skip("structurally singular draw")
+    r, c = oracle.equilibrate(n, rp, ci, v)
+    A = np.zeros((n, n))
+    A[np.repeat(np.arange(n), np.diff(rp)), ci] = v
+    At = (r[:, None] * A) * c[None, :]
+    checked, diag_not_max, offdiag = pivot_rule_replay(At, s.P, s.Q, tau)
+    assert checked >= n - 2
+    if tau <= 0.1:
+        assert diag_not_max > 0
+    if tau > 0.0:
+        assert offdiag > 0
+
+
+def test_pivot_rule_hand_built_3x3():
+    """Q = I, no scaling; column 0 holds (0.5, 2, 0) or (0.5, 2, -2) or (0, 2, -2)."""
+    def piv0(col0, tau):
+        M = np.array([[col0[0], 1.0, 0.0], [col0[1], 1.0, 1.0], [col0[2], 1.0, 3.0]])
+        rp, ci, v = dense_to_csr(M)
+        s = oracle.Symbolic(3, rp, ci, v, tau=tau, scale=False, fixed_q=np.arange(3))
+        return int(s.P[0])
+    # diagonal between tau*max and max: kept although row 1 is larger
+    assert piv0((0.5, 2.0, 0.0), 0.1) == 0
+    assert piv0((0.5, 2.0, 0.0), 0.25) == 0          # exactly tau * max: kept
+    assert piv0((0.5, 2.0, 0.0), 0.0) == 0
+    # diagonal below tau*max: the largest candidate
+    assert piv0((0.5, 2.0, 0.0), 0.5) == 1
+    # tie in magnitude: the lowest row
+    assert piv0((0.5, 2.0, -2.0), 0.5) == 1
+    assert piv0((0.5, -2.0, 2.0), 0.5) == 1
+    # zero diagonal is never kept, even at tau = 0
+    assert piv0((0.0, 2.0, -2.0), 0.0) == 1
+    assert piv0((0.0, -1.0, 3.0), 0.0) == 2
+
+
 def test_closed_form_2x2_saddle():
     a, b, cc = 3.0, 2.0, 0.5
     M = np.array([[a, b], [b, -cc]])
