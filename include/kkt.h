@@ -159,6 +159,25 @@ int kkt_workspace_bytes(const kkt_handle *h, int32_t max_nrhs, size_t *bytes);
 int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs,
              hipStream_t stream);
 
+/* Size of the library's static device scratch array used by kkt_bind_scratch (64 MiB per
+ * device; enough for the workspace of a KKT system of about 5,000 buses). */
+#define KKT_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): kkt_bind with the workspace taken from
+ * the library's own static device array of KKT_SCRATCH_BYTES bytes instead of caller
+ * memory.  This call allocates nothing (no device or pinned host memory, no stream, event
+ * or graph); later calls on the handle allocate nothing either: its refactorizations launch
+ * their levels one by one instead of recording a graph, and small read-backs go through a
+ * host array inside the handle.  Every device holds one such array, kept until the process
+ * ends, and at most one handle is bound to it: binding another handle on the same device
+ * unbinds the previous one (its later calls return STATE) and overwrites the array, so
+ * calls of handles that use it must not overlap in time (they race on one array); the
+ * caller orders them.  Results are bitwise identical to the same handle bound by kkt_bind.
+ * Waits for the upload.  Errors: ARG, NOMEM (kkt_workspace_bytes exceeds KKT_SCRATCH_BYTES),
+ * STATE (handle already on another device), DEVICE. */
+int kkt_bind_scratch(kkt_handle *h, int32_t max_nrhs, hipStream_t stream);
+
 /* Value update and refactorization without pivoting (Algorithm 1, update the factor
  * object with the new values, refactor).  d_values: device FP64[nnz_a] in the analysed
  * CSR order, BORROWED until the next kkt_refactor or kkt_destroy (kkt_refine reads it for

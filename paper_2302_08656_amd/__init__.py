@@ -18,6 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkkt.so")
 
 OK, WARN_PIVOT_PERTURBED, WARN_NOT_CONVERGED = 0, 1, 2
+# bytes of the static device array behind KKTSolver.bind_scratch (KKT_SCRATCH_BYTES)
+SCRATCH_BYTES = 64 << 20
 ERR_ARG, ERR_PATTERN, ERR_SINGULAR, ERR_NONFINITE, ERR_STATE, ERR_NOMEM, ERR_DEVICE, ERR_SCHEDULE = \
     -1, -2, -3, -4, -5, -6, -7, -8
 
@@ -60,7 +62,7 @@ class _Stats(C.Structure):
 
 
 EXPORTS = ["kkt_default_opts", "kkt_analyze", "kkt_get_stats", "kkt_export_symbolic",
-           "kkt_workspace_bytes", "kkt_bind", "kkt_refactor", "kkt_refactor_status", "kkt_solve",
+           "kkt_workspace_bytes", "kkt_bind", "kkt_bind_scratch", "kkt_refactor", "kkt_refactor_status", "kkt_solve",
            "kkt_refine", "kkt_export_factors", "kkt_profile_enable", "kkt_profile_read",
            "kkt_destroy", "kkt_strerror"]
 
@@ -91,6 +93,7 @@ def _lib():
         L.kkt_export_symbolic.argtypes = [p] * 11
         L.kkt_workspace_bytes.argtypes = [p, C.c_int32, C.POINTER(C.c_size_t)]
         L.kkt_bind.argtypes = [p, p, C.c_size_t, C.c_int32, p]
+        L.kkt_bind_scratch.argtypes = [p, C.c_int32, p]
         L.kkt_refactor.argtypes = [p, p, p]
         L.kkt_refactor_status.argtypes = [p, C.POINTER(C.c_int64), p]
         L.kkt_solve.argtypes = [p, p, p, C.c_int32, C.c_int64, p]
@@ -211,6 +214,19 @@ class KKTSolver:
             # the handle may still use the previous workspace: keep it alive
             raise KKTError(rc, "kkt_bind")
         self._ws = ws          # the previous workspace is released only now
+        self.device = dev
+        return self
+
+    def bind_scratch(self, device=None, max_nrhs=1, stream=None):
+        """Binds to the library's static device scratch array (kkt_bind_scratch): no
+        device memory is allocated, here or by later calls on this handle."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        with torch.cuda.device(dev):
+            rc = _lib().kkt_bind_scratch(self._h, int(max_nrhs), _stream_ptr(stream))
+        if rc != OK:
+            raise KKTError(rc, "kkt_bind_scratch")
+        self._ws = None
         self.device = dev
         return self
 

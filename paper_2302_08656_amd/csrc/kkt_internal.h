@@ -116,6 +116,8 @@ struct Schedule {
     // the early L part, = csr_rowptr[i] when there is none; csr_uearly[i] = start of the
     // early U part, = csr_rowptr[i + 1] when there is none).
     std::vector<int32_t> csr_rowptr, csr_col, csr_src, csr_diag, csr_early, csr_uearly;
+    // int32 row pointers of A and column pointers of L+U, as uploaded
+    std::vector<int32_t> a_rowptr32, colptr32;
     // value update: the L+U slot of each entry of A (CSR order) and the fill-in slots
     std::vector<int32_t> a_map, lu_fill;
     // CSC view of A's pattern (positions into the CSR value array, rows)

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -61,7 +62,14 @@ struct kkt_handle {
     int32_t max_nrhs = 1;
     Dev d{};
     const double *d_values = nullptr;
-    double *h_small = nullptr;   // pinned host staging for small read-backs
+    // host staging for small read-backs: the pinned buffer made by kkt_bind, or the handle's
+    // own array (pageable) for a handle bound by kkt_bind_scratch that never had one
+    double *h_small = nullptr;
+    double *h_pinned = nullptr;
+    double h_stage[4 * (kMaxRestart + 2) + 32] = {};
+    // bound to the library's static scratch array: nothing is allocated after the bind (no
+    // graph is recorded; the level launches go one by one)
+    bool on_scratch = false;
     int grid_l = 1, grid_u = 1;  // co-resident blocks of the persistent solve kernels
     int ncu = 1;                 // compute units of the bound device
     // the refactorization's per-level launches, recorded once per bind on the capture stream
@@ -580,17 +588,39 @@ int kkt_export_symbolic(const kkt_handle *h, int32_t *P, int32_t *Q, int64_t *co
 
 int kkt_workspace_bytes(const kkt_handle *h, int32_t max_nrhs, size_t *bytes) {
     if (!h || !bytes || max_nrhs < 1) return KKT_ERR_ARG;
-    Dev scratch{};
-    carve(h, nullptr, scratch, bytes);
+    Dev probe{};
+    carve(h, nullptr, probe, bytes);
     return KKT_OK;
 }
 
-int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, hipStream_t stream) {
-    if (!h || !d_workspace || max_nrhs < 1) return KKT_ERR_ARG;
-    if (reinterpret_cast<uintptr_t>(d_workspace) % 256) return KKT_ERR_ARG;
+}  // extern "C"
+
+// Static device scratch of kkt_bind_scratch, one copy per device (each holds it until the
+// process ends).  Host code never passes `scratch` itself to the device: its device address
+// is taken once per device with hipGetSymbolAddress and kept in g_scratch_ptr.
+static __device__ __align__(256) char scratch[KKT_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+kkt_handle *g_scratch_owner[kMaxDevices] = {};   // the handle bound to that device's scratch
+
+// drops h's claim on its device's scratch array (the caller holds g_scratch_mu)
+void release_scratch_locked(kkt_handle *h) {
+    if (h->on_scratch && h->device >= 0 && h->device < kMaxDevices && g_scratch_owner[h->device] == h)
+        g_scratch_owner[h->device] = nullptr;
+    h->on_scratch = false;
+}
+
+// Common part of kkt_bind and kkt_bind_scratch: checks the size, records the device,
+// uploads the structure into ws and waits.  no_alloc: take no pinned buffer, create no
+// stream, event or graph (the level launches then go one by one).
+int bind_common(kkt_handle *h, char *ws, size_t bytes, int32_t max_nrhs, hipStream_t stream, bool no_alloc) {
     size_t need = 0;
-    Dev scratch{};
-    carve(h, nullptr, scratch, &need);
+    Dev probe{};
+    carve(h, nullptr, probe, &need);
     if (bytes < need) return KKT_ERR_NOMEM;
     int dev = -1;
     HIPCHK(hipGetDevice(&dev));
@@ -616,33 +646,32 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     h->device = dev;
     h->bound = false;      // until the new workspace holds the structure
     h->factored = false;
-    if (!h->h_small) HIPCHK(hipHostMalloc(&h->h_small, sizeof(double) * 4 * (kMaxRestart + 2) + 256));
+    if (!h->h_pinned && !no_alloc)
+        HIPCHK(hipHostMalloc(&h->h_pinned, sizeof(double) * 4 * (kMaxRestart + 2) + 256));
+    h->h_small = h->h_pinned ? h->h_pinned : h->h_stage;
     if (h->levels) {   // recorded with the previous workspace's addresses; the last replay
         HIPCHK(hipEventSynchronize(h->levels_done));   // may still run on a caller's stream
         HIPCHK(hipGraphExecDestroy(h->levels));
         h->levels = nullptr;
     }
     h->levels_failed = false;
-    if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
-    if (!h->levels_done) HIPCHK(hipEventCreateWithFlags(&h->levels_done, hipEventDisableTiming));
-    carve(h, static_cast<char *>(d_workspace), h->d, &need);
+    if (!no_alloc) {
+        if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        if (!h->levels_done) HIPCHK(hipEventCreateWithFlags(&h->levels_done, hipEventDisableTiming));
+    }
+    carve(h, ws, h->d, &need);
     const Symbolic &s = h->sym;
     const Schedule &g = h->sch;
     const Dev &d = h->d;
-    std::vector<int32_t> rp32(s.n + 1), cp32(s.n + 1);
-    for (int32_t i = 0; i <= s.n; ++i) {
-        rp32[i] = (int32_t)s.a_rowptr[i];
-        cp32[i] = (int32_t)s.colptr[i];
-    }
     int rc = KKT_OK;
-    rc |= upload(d.a_rowptr, rp32, stream);
+    rc |= upload(d.a_rowptr, g.a_rowptr32, stream);
     rc |= upload(d.a_colind, s.a_colind, stream);
     rc |= upload(d.a_crow, g.a_crow, stream);
     rc |= upload(d.a_cptr, g.a_cptr, stream);
     rc |= upload(d.a_cpos, g.a_cpos, stream);
     rc |= upload(d.a_map, g.a_map, stream);
     rc |= upload(d.lu_fill, g.lu_fill, stream);
-    rc |= upload(d.colptr, cp32, stream);
+    rc |= upload(d.colptr, g.colptr32, stream);
     rc |= upload(d.rowidx, s.rowidx, stream);
     rc |= upload(d.ulen, s.ulen, stream);
     rc |= upload(d.pan_start, g.pan_start, stream);
@@ -665,12 +694,57 @@ int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, h
     if (rc) return KKT_ERR_DEVICE;
     HIPCHK(hipMemsetAsync(d.st, 0, sizeof(DevStatus), stream));
     HIPCHK(hipStreamSynchronize(stream));
-    h->ws = static_cast<char *>(d_workspace);
+    h->ws = ws;
     h->ws_bytes = bytes;
     h->max_nrhs = max_nrhs;
+    h->on_scratch = no_alloc;
     h->bound = true;
     h->factored = false;
     return KKT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kkt_bind(kkt_handle *h, void *d_workspace, size_t bytes, int32_t max_nrhs, hipStream_t stream) {
+    if (!h || !d_workspace || max_nrhs < 1) return KKT_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256) return KKT_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    release_scratch_locked(h);
+    return bind_common(h, static_cast<char *>(d_workspace), bytes, max_nrhs, stream, false);
+}
+
+int kkt_bind_scratch(kkt_handle *h, int32_t max_nrhs, hipStream_t stream) {
+    if (!h || max_nrhs < 1) return KKT_ERR_ARG;
+    size_t need = 0;
+    Dev probe{};
+    carve(h, nullptr, probe, &need);
+    if (need > KKT_SCRATCH_BYTES) return KKT_ERR_NOMEM;   // beyond the static array
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return KKT_ERR_DEVICE;
+    if (h->device >= 0 && h->device != dev) return KKT_ERR_STATE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {   // once per device, with that device current
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return KKT_ERR_DEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    // the previous holder of this device's array loses its binding (its structure and
+    // factors are about to be overwritten)
+    kkt_handle *prev = g_scratch_owner[dev];
+    if (prev && prev != h) {
+        prev->bound = false;
+        prev->factored = false;
+        prev->on_scratch = false;
+    }
+    g_scratch_owner[dev] = nullptr;
+    h->on_scratch = false;
+    const int rc = bind_common(h, static_cast<char *>(g_scratch_ptr[dev]), KKT_SCRATCH_BYTES, max_nrhs, stream, true);
+    if (rc == KKT_OK) g_scratch_owner[dev] = h;
+    return rc;
 }
 
 namespace {
@@ -696,7 +770,7 @@ void record_levels(kkt_handle *h) {
 }
 
 int run_levels(kkt_handle *h, hipStream_t s) {
-    if (h->opts.graph_refactor && !h->prof && !h->levels_failed) {
+    if (h->opts.graph_refactor && !h->prof && !h->levels_failed && !h->on_scratch) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         HIPCHK(hipStreamIsCapturing(s, &cs));
         if (cs == hipStreamCaptureStatusNone) {
@@ -812,6 +886,10 @@ int kkt_profile_read(kkt_handle *h, kkt_profile *out, hipStream_t stream) {
 
 void kkt_destroy(kkt_handle *h) {
     if (!h) return;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        release_scratch_locked(h);
+    }
     // order: wait for the last replay and for every profiled launch, then release the graph,
     // the capture stream, the events and last the pinned staging buffer
     if (h->device >= 0) {
@@ -828,7 +906,7 @@ void kkt_destroy(kkt_handle *h) {
             (void)hipEventDestroy(ev.second);
         }
     }
-    if (h->h_small) (void)hipHostFree(h->h_small);
+    if (h->h_pinned) (void)hipHostFree(h->h_pinned);
     delete h;
 }
 

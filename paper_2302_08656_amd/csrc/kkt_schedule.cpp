@@ -39,6 +39,13 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         for (int32_t q = 0; q < m; ++q) g.pan_start.push_back(a + (int32_t)((int64_t)w * q / m));
     }
     g.pan_start.push_back(n);
+    // int32 copies of the pointer arrays that the device reads (uploaded as they are)
+    g.a_rowptr32.resize(n + 1);
+    g.colptr32.resize(n + 1);
+    for (int32_t i = 0; i <= n; ++i) {
+        g.a_rowptr32[i] = (int32_t)s.a_rowptr[i];
+        g.colptr32[i] = (int32_t)s.colptr[i];
+    }
     const int32_t np = g.npan = (int32_t)g.pan_start.size() - 1;
     std::vector<int32_t> pan_of(n);
     for (int32_t p = 0; p < np; ++p)

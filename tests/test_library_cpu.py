@@ -153,3 +153,22 @@ def test_call_order_errors_without_device():
     assert L.kkt_bind(sk._h, ctypes.c_void_p(257), 1 << 30, 1, None) == K.ERR_ARG
     assert L.kkt_bind(sk._h, dummy, 16, 1, None) == K.ERR_NOMEM
     assert sk.workspace_bytes(1) > 8 * (sk.nnz_lu * 2)
+
+
+def test_scratch_bind_host_checks():
+    """kkt_bind_scratch rejects bad arguments and systems whose workspace exceeds the static
+    array before it touches a device; the binding's size constant matches the header's."""
+    hdr = open(os.path.join(ROOT, "include", "kkt.h")).read()
+    m = re.search(r"#define KKT_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == K.SCRATCH_BYTES
+    L = K._lib()
+    q = kktgen.make_sequence(kktgen.small(20, config_id=134))
+    sk = K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0))
+    assert L.kkt_bind_scratch(sk._h, 0, None) == K.ERR_ARG
+    assert L.kkt_bind_scratch(None, 1, None) == K.ERR_ARG
+    big = kktgen.make_sequence(kktgen.small(6000, config_id=134, steps=1))
+    sb = K.KKTSolver(big.n, big.rowptr, big.colind, big.values(0))
+    assert sb.workspace_bytes(1) > K.SCRATCH_BYTES
+    assert L.kkt_bind_scratch(sb._h, 1, None) == K.ERR_NOMEM
+    # still unbound: no state changed
+    assert L.kkt_refactor(sb._h, ctypes.c_void_p(256), None) == K.ERR_STATE
