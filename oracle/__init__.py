@@ -61,6 +61,7 @@ def lib():
         L.orc_residual.restype = C.c_double
         L.orc_fgmres.argtypes = [p, p, p, p, p, p, p, C.c_int32, C.c_int32, C.c_double,
                                  C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        L.orc_approx_solve.argtypes = [p, p, p, p, p, C.c_int32, C.c_int32, C.c_int32, p, p]
         _lib = L
     return _lib
 
@@ -171,6 +172,18 @@ class Symbolic:
         x = np.empty(self.n)
         w = np.empty(self.n)
         lib().orc_solve(self._h, _p(lu), _p(r), _p(c), _p(b), _p(x), _p(w))
+        return x
+
+    def approx_solve(self, lu, r, c, b, sweeps, kind=0, chunk=32):
+        """O9: x from `sweeps` Jacobi (kind 0) or block Gauss-Seidel (kind 1, chunks of
+        `chunk` permuted rows) sweeps per triangle, each triangle from the zero vector."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.empty(self.n)
+        w = np.empty(3 * self.n)
+        rc = lib().orc_approx_solve(self._h, _p(np.ascontiguousarray(lu, dtype=np.float64)), _p(r), _p(c), _p(b),
+                                    int(sweeps), int(kind), int(chunk), _p(x), _p(w))
+        if rc:
+            raise OracleError(rc, "approx_solve")
         return x
 
     def fgmres(self, values, lu, r, c, b, *, restart=30, max_it=100, tol=1e-10):

@@ -30,7 +30,8 @@
  *      ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf);
  *   O8 right-preconditioned flexible GMRES(m) with classical Gram-Schmidt applied twice,
  *      preconditioned by O6, stopped on the true backward error (Algorithm 1: the solve
- *      is always followed by iterative refinement; Section V asks for a configurable one).
+ *      is always followed by iterative refinement; Section V asks for a configurable one);
+ *   O9 approximate triangular solves by Jacobi or block Gauss-Seidel sweeps (Section V).
  *
  * Arithmetic rules: every update of a factor entry is t = l*x (rounded), x = x - t
  * (rounded), applied in ascending pivot step; division is a true division; build with
@@ -697,6 +698,87 @@ void orc_solve(const orc_sym *s, const double *lu, const double *r, const double
         }
     }
     for (int32_t k = 0; k < n; k++) x[s->Q[k]] = c[s->Q[k]] * y[k];
+}
+
+/* ------------------------------------------------------------------ O9 approximate solves */
+
+/*
+ * One approximate application of the preconditioner (Section V: the triangular solves may
+ * be approximated by Jacobi or Gauss-Seidel iterations).  With y~ = P R b (permuted,
+ * scaled right-hand side), `sweeps` sweeps on L y = y~ from y = 0, then `sweeps` sweeps on
+ * U x~ = y from x~ = 0, and x = Q C x~.
+ *   kind 0, Jacobi: every row of a sweep reads the previous iterate only,
+ *       y'_i = y~_i - sum_{j<i} L_ij y_j,     x'_i = (y_i - sum_{j>i} U_ij x_j) / U_ii;
+ *   kind 1, block Gauss-Seidel: the rows are cut into consecutive chunks of `chunk` rows of
+ *       the permuted order; inside its chunk a row is taken after the rows before it
+ *       (ascending for L, descending for U) and reads the values of its own chunk from the
+ *       current sweep, every other value from the previous iterate (Jacobi between chunks).
+ * Each sum runs over the row's entries in ascending column order, one rounded product and
+ * one rounded addition at a time.  work: 3n doubles.
+ */
+int orc_approx_solve(const orc_sym *s, const double *lu, const double *r, const double *c,
+                     const double *b, int32_t sweeps, int32_t kind, int32_t chunk, double *x,
+                     double *work) {
+    int32_t n = s->n;
+    if (sweeps < 1 || (kind != 0 && kind != 1) || chunk < 1) return ORC_ERR_ARG;
+    /* row-wise view of L+U: entries of row i with their columns, ascending columns */
+    int64_t *rp = xcalloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *rc = malloc((size_t)(s->nnz_lu ? s->nnz_lu : 1) * sizeof(int32_t));
+    double *rv = malloc((size_t)(s->nnz_lu ? s->nnz_lu : 1) * sizeof(double));
+    int64_t *nx = malloc((size_t)(n ? n : 1) * sizeof(int64_t));
+    if (!rp || !rc || !rv || !nx) { free(rp); free(rc); free(rv); free(nx); return ORC_ERR_NOMEM; }
+    for (int64_t p = 0; p < s->nnz_lu; p++) rp[s->lu_rowidx[p] + 1]++;
+    for (int32_t i = 0; i < n; i++) rp[i + 1] += rp[i];
+    for (int32_t i = 0; i < n; i++) nx[i] = rp[i];
+    for (int32_t j = 0; j < n; j++)          /* columns ascending: rows list columns ascending */
+        for (int64_t p = s->lu_colptr[j]; p < s->lu_colptr[j + 1]; p++) {
+            int32_t i = s->lu_rowidx[p];
+            rc[nx[i]] = j;
+            rv[nx[i]] = lu[p];
+            nx[i]++;
+        }
+    double *bt = work, *cur = work + n, *nxt = work + 2 * (size_t)n;
+    for (int32_t k = 0; k < n; k++) bt[k] = r[s->P[k]] * b[s->P[k]];
+    /* forward: L y = bt */
+    for (int32_t i = 0; i < n; i++) cur[i] = 0.0;
+    for (int32_t t = 0; t < sweeps; t++) {
+        for (int32_t c0 = 0; c0 < n; c0 += chunk) {
+            int32_t c1 = c0 + chunk < n ? c0 + chunk : n;
+            for (int32_t i = c0; i < c1; i++) {
+                double sum = 0.0;
+                for (int64_t p = rp[i]; p < rp[i + 1] && rc[p] < i; p++) {
+                    int32_t j = rc[p];
+                    double v = (kind == 1 && j >= c0) ? nxt[j] : cur[j];
+                    sum = sum + rv[p] * v;
+                }
+                nxt[i] = bt[i] - sum;
+            }
+        }
+        double *tmp = cur; cur = nxt; nxt = tmp;
+    }
+    /* cur holds y; backward: U x~ = y, into bt (no longer needed) from zero */
+    double *y = cur, *xo = bt, *xn = nxt;
+    for (int32_t i = 0; i < n; i++) xo[i] = 0.0;
+    for (int32_t t = 0; t < sweeps; t++) {
+        for (int32_t c0 = 0; c0 < n; c0 += chunk) {
+            int32_t c1 = c0 + chunk < n ? c0 + chunk : n;
+            for (int32_t i = c1 - 1; i >= c0; i--) {
+                double sum = 0.0, d = 0.0;
+                for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+                    int32_t j = rc[p];
+                    if (j < i) continue;
+                    if (j == i) { d = rv[p]; continue; }
+                    double v = (kind == 1 && j < c1) ? xn[j] : xo[j];
+                    sum = sum + rv[p] * v;
+                }
+                xn[i] = (y[i] - sum) / d;
+            }
+        }
+        double *tmp = xo; xo = xn; xn = tmp;
+    }
+    for (int32_t k = 0; k < n; k++) x[s->Q[k]] = c[s->Q[k]] * xo[k];
+    free(rp); free(rc); free(rv); free(nx);
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------ O7 residual */

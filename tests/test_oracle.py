@@ -629,3 +629,76 @@ def test_sequence_reaches_target_backward_error_2000bus():
         lu, r, c, _, _ = s.refactor(v)
         x, it, be, rc = s.fgmres(v, lu, r, c, q.rhs(t))
         assert rc == oracle.OK and be <= 1e-10
+
+
+# ------------------------------------------------------------------ O9 approximate solves
+
+def _sym3_identity():
+    """3x3 full pattern with P = Q = I and no scaling; returns (Symbolic, canonical lu) for
+    the hand-worked factors of tests/golden/approx_sweeps_3x3.txt."""
+    L = np.array([[1.0, 0, 0], [2, 1, 0], [-1, 3, 1]])
+    U = np.array([[2.0, 1, -1], [0, 4, 2], [0, 0, 0.5]])
+    A = L @ U
+    rowptr = np.array([0, 3, 6, 9])
+    colind = np.tile(np.arange(3, dtype=np.int32), 3)
+    ident = np.arange(3, dtype=np.int32)
+    so = oracle.Symbolic(3, rowptr, colind, A.ravel(), scale=False, fixed_p=ident, fixed_q=ident)
+    lu = np.empty(so.nnz_lu)
+    for k in range(3):
+        for p in range(so.colptr[k], so.colptr[k + 1]):
+            i = so.rowidx[p]
+            lu[p] = L[i, k] if i > k else U[i, k]
+    return so, lu
+
+
+def test_approx_sweeps_hand_example():
+    so, lu = _sym3_identity()
+    one = np.ones(3)
+    b = np.array([1.0, 2.0, 3.0])
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "approx_sweeps_3x3.txt")) if l.strip() and l[0] != "#"]
+    assert len(rows) == 5
+    for kind, chunk, sweeps, *xs in rows:
+        x = so.approx_solve(lu, one, one, b, int(sweeps), int(kind), int(chunk))
+        assert np.array_equal(x, np.array([float(v) for v in xs])), (kind, chunk, sweeps, x)
+
+
+def _well_conditioned_factors(so, seed):
+    """Random factor values on the analysed pattern with a dominant U diagonal, so that the
+    triangular systems are well conditioned."""
+    rng = np.random.default_rng(seed)
+    cols = np.repeat(np.arange(so.n), np.diff(so.colptr))
+    lu = rng.uniform(-0.3, 0.3, so.nnz_lu)
+    diag = so.rowidx == cols
+    lu[diag] = rng.uniform(2.0, 3.0, int(diag.sum())) * rng.choice([-1.0, 1.0], int(diag.sum()))
+    return lu
+
+
+def test_approx_sweeps_closed_forms():
+    """One Jacobi sweep is x = Q C D^-1 P R b; enough Jacobi sweeps (more than the level
+    depth: the strictly triangular parts are nilpotent) and one block Gauss-Seidel sweep
+    with a single chunk are the exact triangular solves; block Gauss-Seidel with chunks of
+    one row is Jacobi, bit for bit."""
+    q = kktgen.make_sequence(kktgen.config(0))
+    so = oracle.Symbolic(q.n, q.rowptr, q.colind, q.values(0))
+    lu = _well_conditioned_factors(so, 5)
+    _, r, c, _, _ = so.refactor(q.values(1))
+    b = q.rhs(1)
+    Lm, Um = so.dense_factors(lu)
+    bt = r[so.P] * b[so.P]
+    exact_t = scipy.linalg.solve_triangular(Um, scipy.linalg.solve_triangular(Lm, bt, lower=True, unit_diagonal=True))
+    exact = np.empty(so.n)
+    exact[so.Q] = c[so.Q] * exact_t
+    one = np.empty(so.n)
+    one[so.Q] = c[so.Q] * (bt / np.diag(Um))
+    assert np.allclose(so.approx_solve(lu, r, c, b, 1, 0), one, rtol=4e-16, atol=0)
+    depth = max(so.lev_l.max(), so.lev_u.max()) + 1
+    xj = so.approx_solve(lu, r, c, b, depth, 0)
+    assert np.allclose(xj, exact, rtol=1e-11, atol=1e-11 * abs(exact).max())
+    xg = so.approx_solve(lu, r, c, b, 1, 1, chunk=so.n)
+    assert np.allclose(xg, exact, rtol=1e-11, atol=1e-11 * abs(exact).max())
+    for sweeps in (1, 3):
+        assert np.array_equal(so.approx_solve(lu, r, c, b, sweeps, 1, chunk=1), so.approx_solve(lu, r, c, b, sweeps, 0))
+    # three Jacobi sweeps, fewer than the depth, are not exact
+    assert depth > 3 and abs(so.approx_solve(lu, r, c, b, 3, 0) - exact).max() > 1e-6
+    with pytest.raises(oracle.OracleError):
+        so.approx_solve(lu, r, c, b, 0, 0)
