@@ -79,7 +79,12 @@ typedef struct {
     /* 1 = hybrid triangular solves (default): one launch per dependency level while levels
      * are wide, and one persistent launch for the narrow levels at the top of the tree, in
      * which blocks take work items in dependency order and wait, bounded, for the unknowns
-     * they read; 0 = one launch per dependency level throughout. */
+     * they read; items are assigned to blocks in a fixed order, which needs every block of
+     * the launch resident (a cooperative launch on a device the solve has to itself).
+     * 2 = the same with items taken from a ticket counter by the running blocks: slightly
+     * slower, but safe when other streams' work shares the device (the serving engine
+     * uses it).  0 = one launch per dependency level throughout.  All three give bitwise
+     * identical results. */
     int32_t persistent_solve;
     /* 1 = the refactorization's per-level launches (everything after the value update) are
      * recorded into a HIP graph at the first kkt_refactor after kkt_bind and replayed by
@@ -88,12 +93,33 @@ typedef struct {
      * recording fails.  0 = always one by one.  Results are bitwise identical either way. */
     int32_t graph_refactor;
     /* 0 = every preconditioner application inside kkt_refine is an exact triangular solve
-     * (default).  k in 1..1024 = the applications inside the FGMRES iterations use k Jacobi
-     * sweeps per triangle instead (L from y = the permuted scaled right-hand side, U from
-     * D^-1 y), fully parallel but approximate; the first solve of kkt_refine and kkt_solve
-     * stay exact, and FGMRES, being flexible, accepts the varying preconditioner. */
+     * (default).  k in 1..1024 = the applications inside the FGMRES iterations are
+     * approximate instead (Section V: the triangular solves approximated by Jacobi or
+     * Gauss-Seidel iterations): k sweeps per triangle of the kind approx_kind, each triangle
+     * from the zero vector; the first solve of kkt_refine and kkt_solve stay exact, and
+     * FGMRES, being flexible, accepts the varying preconditioner.  kkt_solve_approx applies
+     * the approximation alone. */
     int32_t approx_sweeps;
+    /* Storage and arithmetic of the factors (the mixed-precision pattern of the refactor
+     * path): KKT_FP64 (default) or KKT_FP32 = the value update rounds the scaled values to
+     * FP32 once, the refactorization computes in FP32 (dense update blocks on the FP32 matrix
+     * cores, FP32 accumulation) and stores FP32 factors; the triangular solves read the FP32
+     * factors into FP64 sums; residuals, orthogonalisation and the solution update of the
+     * refinement stay FP64, so kkt_refine still reaches berr_tol on the original A. */
+    int32_t factor_precision;
+    /* Tiny-pivot factor of the FP32 factors (in place of tiny_pivot): default 2^-26, the
+     * FP64 value (measured on the grid workloads, larger factors such as 2^-12 replace so
+     * many pivots that refinement needs tens to hundreds of FGMRES steps). */
+    double tiny_pivot_fp32;
+    /* Kind of the approximate sweeps: 0 = Jacobi (every row reads the previous iterate;
+     * default), 1 = block Gauss-Seidel (rows cut into chunks of 32 consecutive rows of the
+     * permuted order; inside its chunk a row uses the values already updated in the sweep,
+     * ascending for L and descending for U, and the previous iterate elsewhere). */
+    int32_t approx_kind;
 } kkt_opts;
+
+#define KKT_FP64 0
+#define KKT_FP32 1
 
 typedef struct {
     int32_t iters;              /* FGMRES (Arnoldi) steps after the first solve */
@@ -118,9 +144,12 @@ typedef struct {
     double flops_refactor;      /* sum_k 2 |L(:,k)| |U(k,:)| + |L(:,k)| */
     int64_t nnz_lu_wide;        /* L+U entries of the columns factored by the 512-thread launches
                                  * (their wide items and the narrow items that ride with them) */
-    int64_t nnz_lu_medium;      /* L+U entries of the columns factored by the 256-thread launches */
+    int64_t nnz_lu_medium;      /* L+U entries of the columns factored by the 256-thread launches
+                                 * of panels up to 16 columns */
     int64_t copy_in_levels;     /* entries of the row-ordered factor copy done by the level
                                  * launches (the rest by a copy after the last level) */
+    int64_t nnz_lu_w256;        /* L+U entries of the columns factored by the 256-thread launches
+                                 * of panels up to 32 columns (kkt_tuning.wide256) */
 } kkt_stats;
 
 /* Fills *o with the defaults listed in kkt_opts. */
@@ -133,6 +162,11 @@ void kkt_default_opts(kkt_opts *o);
  * Errors: ARG, PATTERN, SINGULAR, NONFINITE, NOMEM. */
 int kkt_analyze(int32_t n, const int64_t *rowptr, const int32_t *colind,
                 const double *values_k1, const kkt_opts *opts, kkt_handle **out);
+
+/* A new, unbound handle with src's analysis, options and schedule (host copies; no
+ * analysis is repeated): several resident replicas of one pattern, each with its own
+ * workspace, can then serve requests at the same time.  Errors: ARG, NOMEM. */
+int kkt_clone(const kkt_handle *src, kkt_handle **out);
 
 /* Sizes and schedule statistics of an analysed handle. */
 int kkt_get_stats(const kkt_handle *h, kkt_stats *out);
@@ -199,6 +233,13 @@ int kkt_refactor_status(kkt_handle *h, int64_t *perturbed, hipStream_t stream);
 int kkt_solve(kkt_handle *h, const double *d_b, double *d_x, int32_t nrhs, int64_t ld,
               hipStream_t stream);
 
+/* One approximate preconditioner application (Section V): x = Q C x~ with x~ from
+ * opts.approx_sweeps sweeps of kind opts.approx_kind on U x~ = y after as many on
+ * L y = P R b, each from the zero vector.  Same buffers and ld rules as kkt_solve.
+ * Asynchronous.  Errors: ARG (also when approx_sweeps is 0), STATE, DEVICE. */
+int kkt_solve_approx(kkt_handle *h, const double *d_b, double *d_x, int32_t nrhs, int64_t ld,
+                     hipStream_t stream);
+
 /* Solve followed by FGMRES(m) iterative refinement with FP64 residuals on the original A
  * (Algorithm 1: the solve is always followed by iterative refinement; Section V: a
  * configurable refinement).  Stops when berr <= berr_tol or after max_iters Arnoldi steps.
@@ -213,6 +254,126 @@ int kkt_refine(kkt_handle *h, const double *d_b, double *d_x, int32_t nrhs, int6
 int kkt_export_factors(kkt_handle *h, double *h_lu, double *h_r, double *h_c,
                        hipStream_t stream);
 
+/* Schedule choices of the GPU refactorization (they change launch shapes and rounding
+ * order, never the symbolic factorization):
+ *   panel_max  widest panel cut from a supernode (1..32; default 32);
+ *   small_rows narrow 16-lane path for panels of <= 4 columns and <= small_rows rows below
+ *              (0..64; default 64);
+ *   group      targets of one source panel grouped into one pull item (1..32; default 32);
+ *   wide256    1 = a level whose wide items all factor panels of at most 256 rows runs them
+ *              in 256-thread blocks (two per compute unit) instead of 512-thread blocks
+ *              (default 1), 0 = always 512. */
+typedef struct {
+    int32_t panel_max;
+    int32_t small_rows;
+    int32_t group;
+    int32_t wide256;
+} kkt_tuning;
+
+/* The handle's current schedule choices. */
+int kkt_get_tuning(const kkt_handle *h, kkt_tuning *t);
+
+/* Rebuilds the schedule with the given choices (host).  A bound handle is unbound first
+ * (after its last refactorization finished): bind again, since the workspace size may
+ * change.  Errors: ARG (values out of range), SCHEDULE, NOMEM, DEVICE. */
+int kkt_set_tuning(kkt_handle *h, const kkt_tuning *t);
+
+/* Autotuner of the schedule: for each candidate (panel_max 32/16/8, small_rows 64/32,
+ * group 32/16, wide256 1/0) builds the schedule, binds a temporary workspace (allocated and freed
+ * here), refactors d_values (device FP64[nnz_a]) once and then reps times under HIP
+ * events on stream, and keeps the fastest; returns with that schedule set and the handle
+ * unbound (bind again).  best / best_ms (host, may be NULL) receive the choice and its
+ * mean refactorization time in ms.  Errors: ARG, NOMEM, DEVICE, or a refactorization
+ * error (NONFINITE). */
+int kkt_autotune(kkt_handle *h, const double *d_values, int32_t reps, kkt_tuning *best, double *best_ms,
+                 hipStream_t stream);
+
+/* Batched refactorization (many same- or different-pattern systems per call): a batch
+ * groups bound handles of one device and one factor precision; kkt_batch_refactor then
+ * does for all of them what kkt_refactor does for one, with one launch per dependency
+ * level across the batch (each handle's share of a launch runs exactly the blocks of its
+ * own launch, so every result is bitwise the one of kkt_refactor alone), the value update
+ * merged likewise, and all launches of a step recorded at the first call into one HIP
+ * graph that later calls replay. */
+typedef struct kkt_batch kkt_batch;
+
+/* handles: host array of count distinct bound handles.  The batch keeps pointers to them
+ * and to their workspaces: a handle must stay alive and bound to the same workspace while
+ * the batch is used (calls return STATE otherwise).  Allocates a small device table.
+ * Errors: ARG (null, duplicate, mixed device or precision), STATE (unbound), NOMEM, DEVICE. */
+int kkt_batch_create(kkt_handle *const *handles, int32_t count, kkt_batch **out);
+
+/* d_values: host array of count device pointers, the values of each handle's system in
+ * its analysed CSR order (borrowed as by kkt_refactor).  Asynchronous on stream; each
+ * handle is then refactored as if kkt_refactor had been called on it (kkt_refactor_status,
+ * kkt_solve and kkt_refine work per handle).  Errors: ARG, STATE, DEVICE. */
+int kkt_batch_refactor(kkt_batch *b, const double *const *d_values, hipStream_t stream);
+
+/* kkt_refine of every handle of the batch with one right-hand side each: d_b, d_x host
+ * arrays of count device pointers (FP64[n] of that handle), info host kkt_info[count] (may
+ * be NULL).  Up to 8 handles are refined at once, each by a host thread on a stream of the
+ * batch ordered after the caller's stream (which is why a batch's handles take their
+ * persistent solve items by ticket, see persistent_solve = 2).  Waits.  Returns the first
+ * error, else the worst warning. */
+int kkt_batch_refine(kkt_batch *b, const double *const *d_b, double *const *d_x, kkt_info *info,
+                     hipStream_t stream);
+
+/* Frees the batch (not the handles).  NULL is ignored. */
+void kkt_batch_destroy(kkt_batch *b);
+
+/* Serving (a request loop with continuous admission; kkt_server.cpp).  Each pattern is
+ * analysed once when registered; its resident replicas (kkt_clone of the analysed handle,
+ * each bound to a workspace the server allocates) keep the symbolic structure and the
+ * factors on the device between requests.  A request is one system of a registered
+ * pattern: refactor (Algorithm 1) + solve + FGMRES refinement for 1..max_nrhs right-hand
+ * sides.  Requests wait in arrival order; max_inflight worker threads, one HIP stream each,
+ * take the first request that can run now (a free replica of its pattern, or a new replica
+ * while all workspaces stay within hbm_budget bytes, evicting idle replicas of other
+ * patterns, least recently used first, when that makes room), so requests that arrive
+ * while others run are admitted as slots and memory free up and their work overlaps on the
+ * device.  Every replica of a pattern runs the same kernels, so a result does not depend
+ * on what else runs. */
+typedef struct kkt_server kkt_server;
+typedef struct {
+    size_t hbm_budget;     /* device bytes of all replica workspaces together (default 16 GiB) */
+    int32_t max_inflight;  /* requests running at once, 1..64 (default 4) */
+    int32_t max_nrhs;      /* right-hand sides per request, >= 1 (default 4) */
+} kkt_server_opts;
+typedef struct {
+    int32_t replicas, patterns;
+    size_t bytes_in_use, peak_bytes;
+    int64_t replicas_created, evictions, completed, queued;
+} kkt_server_stats;
+
+void kkt_server_default_opts(kkt_server_opts *o);
+
+/* Starts the worker threads on the current device.  Errors: ARG, NOMEM, DEVICE. */
+int kkt_server_create(const kkt_server_opts *opts, kkt_server **out);
+
+/* Analyses a pattern (as kkt_analyze; host arrays borrowed for the call) and registers it;
+ * *pattern receives its index.  NOMEM when one replica's workspace exceeds the budget. */
+int kkt_server_add_pattern(kkt_server *s, int32_t n, const int64_t *rowptr, const int32_t *colind,
+                           const double *values_k1, const kkt_opts *opts, int32_t *pattern);
+
+/* Queues a request; returns at once with *ticket.  d_values (FP64[nnz], CSR order of the
+ * pattern), d_b and d_x (nrhs columns at stride ld >= n; d_x may equal d_b) are device
+ * memory of the server's device, borrowed until kkt_server_wait returns for the ticket.
+ * Errors: ARG, NOMEM. */
+int kkt_server_submit(kkt_server *s, int32_t pattern, const double *d_values, const double *d_b, double *d_x,
+                      int32_t nrhs, int64_t ld, int64_t *ticket);
+
+/* Waits for a ticket and forgets it.  info: host kkt_info[nrhs] (may be NULL); times_ms:
+ * host double[4] (may be NULL) = admission wait, time on the device, latency (submit to
+ * completion), 1 if a new replica was made for it.  Returns the request's status (as
+ * kkt_refine).  ARG for an unknown ticket.  Not concurrently with kkt_server_destroy. */
+int kkt_server_wait(kkt_server *s, int64_t ticket, kkt_info *info, double *times_ms);
+
+int kkt_server_get_stats(kkt_server *s, kkt_server_stats *out);
+
+/* Stops the workers after their running requests, drops queued ones, frees every replica
+ * and pattern.  NULL is ignored. */
+void kkt_server_destroy(kkt_server *s);
+
 /* Kernel classes timed by the optional launch profiler. */
 #define KKT_PROF_UPDATE 0          /* equilibration, norms, value gather, counters */
 #define KKT_PROF_REFACTOR_LARGE 1  /* 512-thread level launches: wide panel items up to 32 columns
@@ -225,7 +386,10 @@ int kkt_export_factors(kkt_handle *h, double *h_lu, double *h_r, double *h_c,
 #define KKT_PROF_KRYLOV 7          /* FGMRES vector kernels */
 #define KKT_PROF_REFACTOR_MEDIUM 8 /* 256-thread level launches: wide items of panels up to 16
                                     * columns and the level's narrow items */
-#define KKT_PROF_NCLASS 9
+#define KKT_PROF_REFACTOR_W256 9   /* 256-thread level launches: wide items of panels up to 32
+                                    * columns with factored panels of at most 256 rows, and the
+                                    * level's narrow items */
+#define KKT_PROF_NCLASS 10
 
 typedef struct {
     int64_t launches[KKT_PROF_NCLASS];

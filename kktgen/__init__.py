@@ -43,7 +43,8 @@ import scipy.sparse as sp
 from scipy.sparse import csgraph
 from scipy.spatial import cKDTree
 
-__all__ = ["GridSpec", "KKTSequence", "CONFIGS", "config", "make_sequence", "closed_form_sizes"]
+__all__ = ["GridSpec", "KKTSequence", "CONFIGS", "config", "make_sequence", "closed_form_sizes", "batch_specs",
+           "serve_specs", "serve_trace", "SERVE_SIZES", "SERVE_PROBS"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -79,6 +80,40 @@ def small(buses: int, *, config_id: int = 100, steps: int = 4, schedule: str = "
     """A reduced grid with the same generator rules (for tests)."""
     return GridSpec(f"grid{buses}_s{config_id}", config_id, buses, avg_degree, gen_frac,
                     steps, schedule, flows)
+
+
+def batch_specs(patterns: int = 8, steps: int = 8, lo: int = 1_000, hi: int = 10_000,
+                config_id: int = 3) -> list[GridSpec]:
+    """The batched workload: `patterns` grids whose bus counts are drawn log-uniform in
+    [lo, hi] (SeedSequence([0, config_id, 6, 0])), same generator rules, `steps` value sets
+    each on the widening schedule.  Pattern k uses config id 100 * config_id + k."""
+    rng = np.random.default_rng(np.random.SeedSequence([0, config_id, 6, 0]))
+    buses = np.round(np.exp(rng.uniform(np.log(lo), np.log(hi), patterns))).astype(int)
+    return [GridSpec(f"batch{k}_{int(b)}", 100 * config_id + k, int(b), 2.5, 0.25, steps, "widening")
+            for k, b in enumerate(buses)]
+
+
+SERVE_SIZES = (500, 2_000, 10_000, 25_000)
+SERVE_PROBS = (0.4, 0.3, 0.2, 0.1)
+
+
+def serve_specs(steps: int = 16, config_id: int = 4) -> list[GridSpec]:
+    """One pattern per serving grid size, `steps` value sets each (widening schedule);
+    pattern k uses config id 100 * config_id + k."""
+    return [GridSpec(f"serve{k}_{b}", 100 * config_id + k, b, 2.5, 0.25, steps, "widening")
+            for k, b in enumerate(SERVE_SIZES)]
+
+
+def serve_trace(rate: float, count: int, steps: int = 16, config_id: int = 4, seed_k: int = 0):
+    """Poisson arrivals of `count` requests at mean `rate` per second: (arrival time s,
+    pattern index drawn with SERVE_PROBS, value-set index, right-hand sides 1..4), from
+    SeedSequence([0, config_id, 7, seed_k])."""
+    rng = np.random.default_rng(np.random.SeedSequence([0, config_id, 7, seed_k]))
+    t = np.cumsum(rng.exponential(1.0 / rate, count))
+    pat = rng.choice(len(SERVE_SIZES), size=count, p=SERVE_PROBS)
+    val = rng.integers(0, steps, count)
+    nrhs = rng.integers(1, 5, count)
+    return [(float(a), int(p), int(v), int(r)) for a, p, v, r in zip(t, pat, val, nrhs)]
 
 
 def closed_form_sizes(buses: int, gens: int, branches: int, flows: int) -> tuple[int, int]:

@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkkt.so")
-SOURCES = ["kkt_runtime.hip", "kkt_symbolic.cpp", "kkt_schedule.cpp"]
-HEADERS = ["kkt_internal.h", "kkt_kernels.h", "kkt_kernels.hip"]
+SOURCES = ["kkt_runtime.hip", "kkt_symbolic.cpp", "kkt_schedule.cpp", "kkt_server.cpp"]
+HEADERS = ["kkt_internal.h", "kkt_kernels.h", "kkt_kernels.hip", "kkt_batch.hip"]
 # host-only sources (plain C++17, no HIP), also built alone by the sanitizer test
 HOST_SOURCES = ["kkt_symbolic.cpp", "kkt_schedule.cpp"]
 

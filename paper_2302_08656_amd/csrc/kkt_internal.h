@@ -50,6 +50,8 @@ constexpr int kSmallR = 64;
 constexpr int kGroup = 32;
 constexpr int kMedW = 16;
 constexpr int kMedRows = 256;
+// rows of a factored panel up to which a 32-column wide item runs in a 256-thread block
+constexpr int kW256Rows = 256;
 // Solve helpers: a wide panel gets helper items kHelpAhead levels before it when one of
 // its rows has at least kHelpMin early entries (columns of panels more than kHelpAhead
 // levels below); each helper item sums the early entries of kHelpRows rows.
@@ -63,8 +65,17 @@ constexpr int kPackW = 4;
 constexpr int kCopyItems = 16;
 constexpr int kCopyLaunches = 4;
 
+// Tunable choices of the schedule builder (kkt_tuning); every value keeps the kernels' limits.
+struct SchedParams {
+    int32_t panel_max = kPanelMax;   // widest panel cut from a supernode (1..kPanelMax)
+    int32_t small_rows = kSmallR;    // narrow path: panels of <= kSmallW columns and <= this many rows below
+    int32_t group = kGroup;          // targets of one source grouped into one pull item (1..kGroup)
+    int32_t wide256 = 1;             // levels whose wide items all fit 256 rows use 256-thread blocks
+};
+
 // Device schedule, built on the host once per pattern and uploaded by kkt_bind.
 struct Schedule {
+    SchedParams params;
     int32_t npan = 0;
     std::vector<int32_t> pan_start;     // [npan+1] first column of each panel
     std::vector<int32_t> pan_r;         // [npan] L rows below the panel (= U columns right)
@@ -76,6 +87,9 @@ struct Schedule {
     // columns of its (source panel, target column) pairs, listed source-major, and then
     // factors its panel (f_item_panel >= 0).
     std::vector<int32_t> f_lvl, f_nlarge, f_nmed;
+    // levels whose 32-column wide items run in 256-thread blocks (every factored panel of the
+    // level has at most 256 rows): 1, else 0
+    std::vector<int32_t> f_w256;
     // row-ordered copy: copy_k lists CSR positions; launch copy_lvl + c (c < copy_ptr.size()
     // - 1) copies copy_k[copy_ptr[c] .. copy_ptr[c+1]), the copy after the last level the rest
     int32_t copy_lvl = 0;
@@ -124,9 +138,10 @@ struct Schedule {
     std::vector<int32_t> a_cptr, a_cpos, a_crow;
     double flops = 0.0;
     int64_t nnz_lu_wide = 0;            // L+U entries of columns factored by 512-thread launches
-    int64_t nnz_lu_med = 0;             // ... by 256-thread launches
+    int64_t nnz_lu_med = 0;             // ... by 256-thread launches of panels up to 16 columns
+    int64_t nnz_lu_w256 = 0;            // ... by 256-thread launches of panels up to 32 columns
 };
 
-int build_schedule(const Symbolic &s, Schedule &g);
+int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g);
 
 }  // namespace kkt

@@ -43,7 +43,7 @@ __device__ __forceinline__ double group_sum(double v, int width) {
 
 // Clears the status words and the replaced-pivot counter slots of a refactorization (one
 // block, launched before k_row_scale, whose blocks may raise the non-finite flag).
-__global__ __launch_bounds__(256) void k_clear_status(DevStatus *st, unsigned long long *pcount) {
+__device__ __forceinline__ void clear_status_body(DevStatus *st, unsigned long long *pcount) {
     if (threadIdx.x == 0) {
         st->anorm_scaled = 0.0;
         st->anorm = 0.0;
@@ -54,11 +54,15 @@ __global__ __launch_bounds__(256) void k_clear_status(DevStatus *st, unsigned lo
     for (int t = threadIdx.x; t < kCountSlots; t += blockDim.x) pcount[t] = 0;
 }
 
+__global__ __launch_bounds__(256) void k_clear_status(DevStatus *st, unsigned long long *pcount) {
+    clear_status_body(st, pcount);
+}
+
 // r_i = 2^-floor(log2 max_j |a_ij|), 8 lanes per row; a non-finite value raises the flag
-__global__ __launch_bounds__(256) void k_row_scale(int n, const int32_t *__restrict__ rowptr,
-                                                   const double *__restrict__ v, int scale,
-                                                   double *__restrict__ r, DevStatus *st) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void row_scale_body(int blk, int n, const int32_t *__restrict__ rowptr,
+                                               const double *__restrict__ v, int scale, double *__restrict__ r,
+                                               DevStatus *st) {
+    const int gid = blk * blockDim.x + threadIdx.x;
     const int i = gid >> 3, gl = gid & 7;
     double m = 0.0;
     int bad = 0;
@@ -78,14 +82,19 @@ __global__ __launch_bounds__(256) void k_row_scale(int n, const int32_t *__restr
     }
 }
 
+__global__ __launch_bounds__(256) void k_row_scale(int n, const int32_t *__restrict__ rowptr,
+                                                   const double *__restrict__ v, int scale,
+                                                   double *__restrict__ r, DevStatus *st) {
+    row_scale_body(blockIdx.x, n, rowptr, v, scale, r, st);
+}
+
 // c_j from the row-scaled matrix, 8 lanes per column of the CSC view (crow: row of each
 // CSC entry, cpos: its position in the CSR value array)
-__global__ __launch_bounds__(256) void k_col_scale(int n, const int32_t *__restrict__ cptr,
-                                                   const int32_t *__restrict__ cpos,
-                                                   const int32_t *__restrict__ crow,
-                                                   const double *__restrict__ v, const double *__restrict__ r,
-                                                   int scale, double *__restrict__ c) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void col_scale_body(int blk, int n, const int32_t *__restrict__ cptr,
+                                               const int32_t *__restrict__ cpos, const int32_t *__restrict__ crow,
+                                               const double *__restrict__ v, const double *__restrict__ r,
+                                               int scale, double *__restrict__ c) {
+    const int gid = blk * blockDim.x + threadIdx.x;
     const int j = gid >> 3, gl = gid & 7;
     double m = 0.0;
     if (j < n)
@@ -94,18 +103,27 @@ __global__ __launch_bounds__(256) void k_col_scale(int n, const int32_t *__restr
     if (j < n && gl == 0) c[j] = scale ? inv_pow2_floor_log2(m) : 1.0;
 }
 
-// Scaled values into the factor, lu[map[p]] = (r_i a_ip) c_j, and the row sums of |A| and
-// |R A C| in CSR order (one thread per row, entries loaded eight at a time), block maxima
-// into part[2 * block]; then the fill-in slots of the factor are set to zero.
-__global__ __launch_bounds__(256) void k_scatter_norms(int n, const int32_t *__restrict__ rowptr,
-                                                       const int32_t *__restrict__ col,
-                                                       const double *__restrict__ v, const double *__restrict__ r,
-                                                       const double *__restrict__ c,
-                                                       const int32_t *__restrict__ map, int64_t nfill,
-                                                       const int32_t *__restrict__ fill, double *__restrict__ lu,
-                                                       double *__restrict__ part) {
+__global__ __launch_bounds__(256) void k_col_scale(int n, const int32_t *__restrict__ cptr,
+                                                   const int32_t *__restrict__ cpos,
+                                                   const int32_t *__restrict__ crow,
+                                                   const double *__restrict__ v, const double *__restrict__ r,
+                                                   int scale, double *__restrict__ c) {
+    col_scale_body(blockIdx.x, n, cptr, cpos, crow, v, r, scale, c);
+}
+
+// Scaled values into the factor, lu[map[p]] = (r_i a_ip) c_j (exact in FP64; rounded once
+// when the factor is FP32), and the row sums of |A| and |R A C| in CSR order (one thread
+// per row, entries loaded eight at a time), block maxima into part[2 * block]; then the
+// fill-in slots of the factor are set to zero.
+template <class T>
+__device__ __forceinline__ void scatter_norms_body(int blk, int nblk, int n, const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ col, const double *__restrict__ v,
+                                                   const double *__restrict__ r, const double *__restrict__ c,
+                                                   const int32_t *__restrict__ map, int64_t nfill,
+                                                   const int32_t *__restrict__ fill, T *__restrict__ lu,
+                                                   double *__restrict__ part) {
     __shared__ double red[2][4];
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    const int gid = blk * blockDim.x + threadIdx.x, stride = nblk * blockDim.x;
     double s = 0.0, a = 0.0;
     for (int i = gid; i < n; i += stride) {
         const int p0 = rowptr[i], p1 = rowptr[i + 1];
@@ -127,7 +145,7 @@ __global__ __launch_bounds__(256) void k_scatter_norms(int n, const int32_t *__r
             for (int k = 0; k < 8; ++k) {
                 if (p + k < p1) {
                     const double t = (ri * vv[k]) * cj[k];
-                    lu[mm[k]] = t;
+                    lu[mm[k]] = (T)t;
                     ai = ai + fabs(vv[k]);
                     si = si + fabs(t);
                 }
@@ -146,15 +164,26 @@ __global__ __launch_bounds__(256) void k_scatter_norms(int n, const int32_t *__r
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
-        part[2 * blockIdx.x + 1] = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+        part[2 * blk] = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+        part[2 * blk + 1] = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
     }
-    for (int64_t k = gid; k < nfill; k += stride) lu[fill[k]] = 0.0;
+    for (int64_t k = gid; k < nfill; k += stride) lu[fill[k]] = T(0);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_scatter_norms(int n, const int32_t *__restrict__ rowptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const double *__restrict__ v, const double *__restrict__ r,
+                                                       const double *__restrict__ c,
+                                                       const int32_t *__restrict__ map, int64_t nfill,
+                                                       const int32_t *__restrict__ fill, T *__restrict__ lu,
+                                                       double *__restrict__ part) {
+    scatter_norms_body<T>(blockIdx.x, gridDim.x, n, rowptr, col, v, r, c, map, nfill, fill, lu, part);
 }
 
 // dst[j] = max over blocks b of part[nfield * b + j] (NaN propagates), j < nfield
-__global__ __launch_bounds__(256) void k_max_parts(int nblk, int nfield, const double *__restrict__ part,
-                                                   double *__restrict__ dst) {
+__device__ __forceinline__ void max_parts_body(int nblk, int nfield, const double *__restrict__ part,
+                                               double *__restrict__ dst) {
     __shared__ double red[4];
     for (int j = 0; j < nfield; ++j) {
         double m = 0.0;
@@ -177,9 +206,14 @@ __global__ __launch_bounds__(256) void k_max_parts(int nblk, int nfield, const d
     }
 }
 
+__global__ __launch_bounds__(256) void k_max_parts(int nblk, int nfield, const double *__restrict__ part,
+                                                   double *__restrict__ dst) {
+    max_parts_body(nblk, nfield, part, dst);
+}
+
 // st->perturbed = sum of the spread counter slots
-__global__ __launch_bounds__(256) void k_sum_counts(const unsigned long long *__restrict__ pcount,
-                                                    unsigned long long *out) {
+__device__ __forceinline__ void sum_counts_body(const unsigned long long *__restrict__ pcount,
+                                                unsigned long long *out) {
     __shared__ unsigned long long red[4];
     unsigned long long c = 0;
     for (int i = threadIdx.x; i < kCountSlots; i += blockDim.x) c += pcount[i];
@@ -189,10 +223,16 @@ __global__ __launch_bounds__(256) void k_sum_counts(const unsigned long long *__
     if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
 }
 
+__global__ __launch_bounds__(256) void k_sum_counts(const unsigned long long *__restrict__ pcount,
+                                                    unsigned long long *out) {
+    sum_counts_body(pcount, out);
+}
+
 // lucsr[k] = lu[csr_src[k]] for k = copy_k[q], q in [q0, q1)
+template <class T>
 __global__ void k_to_csr(int q0, int q1, const int32_t *__restrict__ copy_k, const int32_t *__restrict__ csr_src,
-                         const double *__restrict__ lu, double *__restrict__ lucsr) {
-    const int q = q0 + blockIdx.x * blockDim.x + threadIdx.x;
+                         const T *__restrict__ lu, T *__restrict__ lucsr) {
+    const int q = q0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (q < q1) {
         const int k = copy_k[q];
         lucsr[k] = lu[csr_src[k]];
@@ -215,6 +255,12 @@ __device__ __forceinline__ int lower_bound_row(const int32_t *__restrict__ rowid
 constexpr int kBlock = 256;   // threads of the elementwise, small-item and solve blocks
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// Two consecutive values of the factor type, for paired LDS reads and writes.
+template <class T> struct Pair;
+template <> struct Pair<double> { using type = double2; };
+template <> struct Pair<float> { using type = float2; };
 
 // Packed 32-byte records (two int4 each):
 //   item[2i]   = {panel to factor or -1, first pair, end of pairs, 0}
@@ -222,12 +268,15 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 //   pair[2q]   = {source panel, slot of the source's first row in the target column,
 //                 first index into rel, target column}
 //   pair[2q+1] = {source's first column, width, rows below, slot of its first diagonal}
+// T: the type in which the factor is stored and refactored (double, or float for the
+// mixed-precision path).
+template <class T>
 struct RefArgs {
     const int32_t *ldiag;      // slot of the diagonal of each column
     const int4 *item;
     const int4 *pair;
     const int32_t *rel;
-    double *lu;
+    T *lu;
     DevStatus *st;
     unsigned long long *pcount;   // replaced-pivot counter, spread over kCountSlots slots
     double tiny;
@@ -236,18 +285,20 @@ struct RefArgs {
     // in copy_k
     const int32_t *copy_k;
     const int32_t *csr_src;
-    double *lucsr;
+    T *lucsr;
 };
 
-// slot of the first L entry (row j+1 or below) of column j
-__device__ __forceinline__ int lbeg(const RefArgs &a, int j) { return a.ldiag[j] + 1; }
-// slot of row s (the panel's first row) in column j = s + jj of a panel starting at s
-__device__ __forceinline__ int seg(const RefArgs &a, int j, int jj) { return a.ldiag[j] - jj; }
+// the tiny-pivot threshold tiny * ||A~||_inf of the current refactorization, in T
+template <class T>
+__device__ __forceinline__ T pivot_threshold(const RefArgs<T> &a) {
+    return (T)(a.tiny * a.st->anorm_scaled);
+}
 
-__device__ __forceinline__ double perturb(double p, double thresh, int &npert) {
+template <class T>
+__device__ __forceinline__ T perturb(T p, T thresh, int &npert) {
     if (fabs(p) < thresh) {
         ++npert;
-        return p < 0.0 ? -thresh : thresh;
+        return p < T(0) ? -thresh : thresh;
     }
     return p;
 }
@@ -259,15 +310,17 @@ __device__ __forceinline__ double perturb(double p, double thresh, int &npert) {
 // slots of those rows in the target.  Independent of the target's values, so the next
 // pair's source side is loaded while the current pair is applied.
 constexpr int kSmallRows = kSmallR / 16;
+template <class T>
 struct SmallSrc {
     int ps, w, r;
     int pos[kSmallRows];
-    double l_row[kSmallW - 1];          // L(s + gl, s + j) for j < gl
-    double lr[kSmallRows][kSmallW];     // L(R_i, s + j) for this lane's rows i
+    T l_row[kSmallW - 1];          // L(s + gl, s + j) for j < gl
+    T lr[kSmallRows][kSmallW];     // L(R_i, s + j) for this lane's rows i
 };
 
 // pa, pb: the pair's record {ldiag[s+1], pos, rel, ldiag[s+2]}, {ldiag[s+3], w, r, ldiag[s]}
-__device__ __forceinline__ void small_load_src(const RefArgs &a, int4 pa, int4 pb, int gl, SmallSrc &x) {
+template <class T>
+__device__ __forceinline__ void small_load_src(const RefArgs<T> &a, int4 pa, int4 pb, int gl, SmallSrc<T> &x) {
     const int ld[kSmallW] = {pb.w, pa.x, pa.w, pb.x};
     x.ps = pa.y;
     x.w = pb.y;
@@ -275,38 +328,39 @@ __device__ __forceinline__ void small_load_src(const RefArgs &a, int4 pa, int4 p
     const int w = x.w, r = x.r;
     const int32_t *rel = a.rel + pa.z;
 #pragma unroll
-    for (int j = 0; j < kSmallW - 1; ++j) x.l_row[j] = (j + 1 < w && gl > j && gl < w) ? a.lu[ld[j] + (gl - j)] : 0.0;
+    for (int j = 0; j < kSmallW - 1; ++j) x.l_row[j] = (j + 1 < w && gl > j && gl < w) ? a.lu[ld[j] + (gl - j)] : T(0);
 #pragma unroll
     for (int k = 0; k < kSmallRows; ++k) {
         const int i = gl + 16 * k;
         x.pos[k] = i < r ? rel[i] : 0;
 #pragma unroll
-        for (int j = 0; j < kSmallW; ++j) x.lr[k][j] = (i < r && j < w) ? a.lu[ld[j] + 1 + (w - 1 - j) + i] : 0.0;
+        for (int j = 0; j < kSmallW; ++j) x.lr[k][j] = (i < r && j < w) ? a.lu[ld[j] + 1 + (w - 1 - j) + i] : T(0);
     }
 }
 
 // Target side: rows s..s+w-1 of column k (from slot ps on) become final U entries (unit
 // lower solve with S's diagonal block) and the rows R of S lose L(R, S) times them.
-__device__ __forceinline__ void small_apply(const RefArgs &a, const SmallSrc &x, int gl) {
+template <class T>
+__device__ __forceinline__ void small_apply(const RefArgs<T> &a, const SmallSrc<T> &x, int gl) {
     const int w = x.w, r = x.r;
     // one round: the target's rows of S and of R
-    double u = gl < w ? a.lu[x.ps + gl] : 0.0;
-    double tv[kSmallRows];
+    T u = gl < w ? a.lu[x.ps + gl] : T(0);
+    T tv[kSmallRows];
 #pragma unroll
-    for (int k = 0; k < kSmallRows; ++k) tv[k] = gl + 16 * k < r ? a.lu[x.pos[k]] : 0.0;
+    for (int k = 0; k < kSmallRows; ++k) tv[k] = gl + 16 * k < r ? a.lu[x.pos[k]] : T(0);
 #pragma unroll
     for (int j = 0; j < kSmallW - 1; ++j) {
-        const double uj = __shfl(u, j, 16);
+        const T uj = __shfl(u, j, 16);
         if (j + 1 < w && gl > j && gl < w) u = fma(-x.l_row[j], uj, u);
     }
     if (gl < w) a.lu[x.ps + gl] = u;
-    double uu[kSmallW];
+    T uu[kSmallW];
 #pragma unroll
     for (int j = 0; j < kSmallW; ++j) uu[j] = __shfl(u, j, 16);
 #pragma unroll
     for (int k = 0; k < kSmallRows; ++k) {
         if (gl + 16 * k < r) {
-            double acc = 0.0;
+            T acc = T(0);
 #pragma unroll
             for (int j = 0; j < kSmallW; ++j)
                 if (j < w) acc = fma(x.lr[k][j], uu[j], acc);
@@ -319,37 +373,38 @@ __device__ __forceinline__ void small_apply(const RefArgs &a, const SmallSrc &x,
 // Dense LU without pivoting of a narrow panel's block column (w <= kSmallW, r <= kSmallR).
 // pn = {s, w, r, slot of the first diagonal}.  Returns the number of replaced pivots (the
 // same value on every lane of the group).
-__device__ __forceinline__ int small_factor(const RefArgs &a, int4 pn, int ldg, int gl, double thresh) {
+template <class T>
+__device__ __forceinline__ int small_factor(const RefArgs<T> &a, int4 pn, int ldg, int gl, T thresh) {
     const int w = pn.y, r = pn.z;
     int sg[kSmallW];
 #pragma unroll
     for (int c = 0; c < kSmallW; ++c) sg[c] = __shfl(ldg, c, 16) - c;
     // one round: the diagonal block (lane gl < w holds row gl) and this lane's rows below
-    double d[kSmallW];
+    T d[kSmallW];
 #pragma unroll
-    for (int c = 0; c < kSmallW; ++c) d[c] = (c < w && gl < w) ? a.lu[sg[c] + gl] : 0.0;
+    for (int c = 0; c < kSmallW; ++c) d[c] = (c < w && gl < w) ? a.lu[sg[c] + gl] : T(0);
     constexpr int kRows = kSmallR / 16;
-    double x[kRows][kSmallW];
+    T x[kRows][kSmallW];
 #pragma unroll
     for (int k = 0; k < kRows; ++k)
 #pragma unroll
-        for (int c = 0; c < kSmallW; ++c) x[k][c] = (c < w && gl + 16 * k < r) ? a.lu[sg[c] + w + gl + 16 * k] : 0.0;
+        for (int c = 0; c < kSmallW; ++c) x[k][c] = (c < w && gl + 16 * k < r) ? a.lu[sg[c] + w + gl + 16 * k] : T(0);
     int npert = 0, bad = 0;
-    double U[kSmallW][kSmallW];   // final U of the diagonal block, known to every lane
+    T U[kSmallW][kSmallW];   // final U of the diagonal block, known to every lane
 #pragma unroll
     for (int jj = 0; jj < kSmallW; ++jj) {
         if (jj < w) {
-            double ur[kSmallW];
+            T ur[kSmallW];
 #pragma unroll
             for (int c = 0; c < kSmallW; ++c) ur[c] = __shfl(d[c], jj, 16);
-            const double p = perturb(ur[jj], thresh, npert);
+            const T p = perturb(ur[jj], thresh, npert);
             bad |= !isfinite(p);
             if (gl == jj) d[jj] = p;
             ur[jj] = p;
 #pragma unroll
             for (int c = 0; c < kSmallW; ++c) U[jj][c] = ur[c];
             if (gl > jj && gl < w) {
-                const double l = d[jj] / p;
+                const T l = d[jj] / p;
                 d[jj] = l;
 #pragma unroll
                 for (int c = jj + 1; c < kSmallW; ++c)
@@ -368,7 +423,7 @@ __device__ __forceinline__ int small_factor(const RefArgs &a, int4 pn, int ldg, 
 #pragma unroll
             for (int jj = 0; jj < kSmallW; ++jj) {
                 if (jj < w) {
-                    const double l = x[k][jj] / U[jj][jj];
+                    const T l = x[k][jj] / U[jj][jj];
                     bad |= !isfinite(l);
                     x[k][jj] = l;
 #pragma unroll
@@ -391,9 +446,9 @@ __device__ __forceinline__ int small_factor(const RefArgs &a, int4 pn, int ldg, 
 // Group g (16 lanes) runs narrow item item0 + g when g < nsmall; the wavefront's perturbed
 // pivots go to counter slot `slot`.  No block-wide synchronisation: the groups of a block
 // are independent.
-template <bool kPipe>
-__device__ __forceinline__ void small_group(int item0, int nsmall, const RefArgs &a, int g, int slot) {
-    const double thresh = a.tiny * a.st->anorm_scaled;
+template <class T, bool kPipe>
+__device__ __forceinline__ void small_group(int item0, int nsmall, const RefArgs<T> &a, int g, int slot) {
+    const T thresh = pivot_threshold(a);
     const int gl = threadIdx.x & 15;
     int npert = 0;
     if (g < nsmall) {
@@ -419,7 +474,7 @@ __device__ __forceinline__ void small_group(int item0, int nsmall, const RefArgs
         };
         if constexpr (kPipe) {
             if (np > 0) {
-                SmallSrc cur, nxt;
+                SmallSrc<T> cur, nxt;
                 int4 pa, pb;
                 rec(0, pa, pb);
                 small_load_src(a, pa, pb, gl, cur);
@@ -434,7 +489,7 @@ __device__ __forceinline__ void small_group(int item0, int nsmall, const RefArgs
             }
         } else {
             for (int q = 0; q < np; ++q) {
-                SmallSrc cur;
+                SmallSrc<T> cur;
                 int4 pa, pb;
                 rec(q, pa, pb);
                 small_load_src(a, pa, pb, gl, cur);
@@ -449,20 +504,40 @@ __device__ __forceinline__ void small_group(int item0, int nsmall, const RefArgs
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(&a.pcount[slot % kCountSlots], (unsigned long long)c);
 }
 
-template <bool kPipe>
-__global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, RefArgs a) {
-    small_group<kPipe>(item0, nsmall, a, blockIdx.x * (kBlock / 16) + (threadIdx.x >> 4),
-                       blockIdx.x * 4 + (threadIdx.x >> 6));
+template <class T, bool kPipe>
+__global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, RefArgs<T> a) {
+    small_group<T, kPipe>(item0, nsmall, a, blockIdx.x * (kBlock / 16) + (threadIdx.x >> 4),
+                          blockIdx.x * 4 + (threadIdx.x >> 6));
 }
 
 // ----------------------------------------------------------------- 512-thread path
 
 constexpr int kStagePairs = 256;
 
-// LDS row stride (doubles) of per-lane rows that the lanes of a wavefront read or write at
-// the same column at once: rows start four banks apart, so 16 consecutive lanes touch
-// distinct banks, and 16-byte alignment is kept for paired reads
+// LDS row stride (values) of per-lane rows that the lanes of a wavefront read or write at
+// the same column at once: FP64 rows start four banks apart, so 16 consecutive lanes touch
+// distinct banks, and the alignment of paired reads is kept
 constexpr int kRowLd = kPanelMax + 2;
+
+// Update tiles on the matrix cores, 16x16 outputs with k in steps of 4: lane holds
+// A[lane % 16][lane / 16] and B[lane / 16][lane % 16]; its four outputs are rows row(lk, v)
+// (lk = lane / 16, v = 0..3) of column lane % 16 (the FP64 and FP32 instructions place them
+// differently).
+template <class T> struct Mfma;
+template <> struct Mfma<double> {
+    using acc_t = double4_t;
+    static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+template <> struct Mfma<float> {
+    using acc_t = float4_t;
+    static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
 
 // Configurations of the wide path: threads per block, minimum waves per SIMD, source L rows
 // staged per chunk, widest panel (target and sources) and update tiles per wavefront and
@@ -470,26 +545,30 @@ constexpr int kRowLd = kPanelMax + 2;
 // | Ub (solved rows per target) | Lr (a chunk of the source's L rows) | lds (the source's
 // diagonal slots) | sgs (slot of row s in each column of the panel to factor) | flg (pivot
 // rows published by the panel sweep) | staged pair records.
-template <int T, int WV, int CH, int MW, int TI>
+template <class TV, int NT, int WV, int CH, int MW, int TI>
 struct WideCfg {
-    static constexpr int kThreads = T;
+    using T = TV;   // factor type
+    static constexpr int kThreads = NT;
     static constexpr int kWaves = WV;
     static constexpr int kChunk = CH;
     static constexpr int kMaxW = MW;
     static constexpr int kTiles = TI;
     static constexpr int kOffLd = 0;
-    static constexpr int kOffUb = kOffLd + kMaxW * kPanelMax * 8;
-    static constexpr int kOffLr = kOffUb + kRowLd * kGroup * 8;
-    static constexpr int kOffLds = kOffLr + kChunk * kMaxW * 8;
+    static constexpr int kOffUb = kOffLd + kMaxW * kPanelMax * (int)sizeof(T);
+    static constexpr int kOffLr = kOffUb + kRowLd * kGroup * (int)sizeof(T);
+    static constexpr int kOffLds = kOffLr + kChunk * kMaxW * (int)sizeof(T);
     static constexpr int kOffSgs = kOffLds + kPanelMax * 4;
     static constexpr int kOffFlg = kOffSgs + kPanelMax * 4;
     static constexpr int kOffPairs = kOffFlg + kPanelMax * 4;
     static constexpr int kLds = kOffPairs + kStagePairs * 32;
+    static_assert(kOffPairs % 16 == 0, "staged pair records are read as int4");
 };
 // panels up to 32 columns: one block per CU
-using BigCfg = WideCfg<512, 2, 256, 32, 4>;
+template <class T> using BigCfg = WideCfg<T, 512, 2, 256, 32, 4>;
 // panels up to 16 columns: four blocks per CU
-using MedCfg = WideCfg<256, 4, 128, 16, 2>;
+template <class T> using MedCfg = WideCfg<T, 256, 4, 128, 16, 2>;
+// panels up to 32 columns whose factored panels have at most 256 rows: two blocks per CU
+template <class T> using W256Cfg = WideCfg<T, 256, 2, 128, 32, 4>;
 
 // Shifted sweeps.  A row of a panel of width w <= KW lives in registers x[0..KW-1] with
 // zeros past column w.  Step j of a triangular sweep consumes x[0] (column j) and moves
@@ -498,43 +577,43 @@ using MedCfg = WideCfg<256, 4, 128, 16, 2>;
 // the same FMA, in the same order, as in the unshifted form.
 // The row of multipliers (LDS, 16-byte aligned) is read into registers in one round before
 // the FMAs; otherwise the compiler interleaves one LDS round trip per pair of columns.
-template <int KW>
-__device__ __forceinline__ void load_lds_row(double (&rw)[kPanelMax], const double *row) {
-    const double2 *r2 = reinterpret_cast<const double2 *>(row);
+template <int KW, class T>
+__device__ __forceinline__ void load_lds_row(T (&rw)[kPanelMax], const T *row) {
+    using P2 = typename Pair<T>::type;
+    const P2 *r2 = reinterpret_cast<const P2 *>(row);
 #pragma unroll
     for (int c = 0; c < KW / 2; ++c) {
-        const double2 v = r2[c];
+        const P2 v = r2[c];
         rw[2 * c] = v.x;
         rw[2 * c + 1] = v.y;
     }
 }
 
-template <int KW>
-__device__ __forceinline__ void shift_fma(double (&x)[kPanelMax], double l, const double (&rw)[kPanelMax]) {
+template <int KW, class T>
+__device__ __forceinline__ void shift_fma(T (&x)[kPanelMax], T l, const T (&rw)[kPanelMax]) {
 #pragma unroll
     for (int c = 1; c < KW; ++c) x[c - 1] = fma(-l, rw[c], x[c]);
-    x[KW - 1] = 0.0;
+    x[KW - 1] = T(0);
 }
 
 // x[c] = lu[base[c] + off] for c < w, 0 beyond (every address in bounds)
-template <int KW>
-__device__ __forceinline__ void load_row(double (&x)[kPanelMax], const double *lu, const int *base,
-                                         int w, int off) {
+template <int KW, class T>
+__device__ __forceinline__ void load_row(T (&x)[kPanelMax], const T *lu, const int *base, int w, int off) {
 #pragma unroll
     for (int c = 0; c < KW; ++c) {
-        const double v = lu[base[c < w ? c : 0] + off];
-        x[c] = c < w ? v : 0.0;
+        const T v = lu[base[c < w ? c : 0] + off];
+        x[c] = c < w ? v : T(0);
     }
 }
 
 // One step j of the panel sweep on a row (shifted, KW columns): the pivot row's entries
 // U(j, j + c) are read from LDS in one round; the row's multiplier is stored.
-template <int KW>
-__device__ __forceinline__ void sweep_step(double (&x)[kPanelMax], const double *urow, double *dst, int &bad) {
-    double rw[kPanelMax];
+template <int KW, class T>
+__device__ __forceinline__ void sweep_step(T (&x)[kPanelMax], const T *urow, T *dst, int &bad) {
+    T rw[kPanelMax];
     load_lds_row<KW>(rw, urow);
     __builtin_amdgcn_sched_barrier(0);
-    const double l = x[0] / rw[0];
+    const T l = x[0] / rw[0];
     bad |= !isfinite(l);
     *dst = l;
     shift_fma<KW>(x, l, rw);
@@ -553,16 +632,19 @@ __device__ __forceinline__ void sweep_step(double (&x)[kPanelMax], const double 
 constexpr int kSweepSpin = 1 << 22;
 
 template <class C, int KW>
-__device__ __forceinline__ void large_factor_w(const RefArgs &a, int w, int r, char *sm, double thresh) {
+__device__ __forceinline__ void large_factor_w(const RefArgs<typename C::T> &a, int w, int r, char *sm,
+                                               typename C::T thresh) {
+    using T = typename C::T;
+    using P2 = typename Pair<T>::type;
     const int tid = threadIdx.x, lane = tid & 63;
-    double *Us = reinterpret_cast<double *>(sm + C::kOffLd);
+    T *Us = reinterpret_cast<T *>(sm + C::kOffLd);
     const int *sgs = reinterpret_cast<const int *>(sm + C::kOffSgs);
     int *flg = reinterpret_cast<int *>(sm + C::kOffFlg);
     const int nrow = w + r;
     int npert = 0, bad = 0;
-    double x[kPanelMax];
+    T x[kPanelMax];
 #pragma unroll
-    for (int c = 0; c < kPanelMax; ++c) x[c] = 0.0;
+    for (int c = 0; c < kPanelMax; ++c) x[c] = T(0);
     if (tid < nrow) load_row<KW>(x, a.lu, sgs, w, tid);
     if (tid < kPanelMax) flg[tid] = 0;
     __syncthreads();
@@ -576,13 +658,13 @@ __device__ __forceinline__ void large_factor_w(const RefArgs &a, int w, int r, c
             if (tid == j) {
                 x[0] = perturb(x[0], thresh, npert);
                 bad |= !isfinite(x[0]);
-                double2 *o = reinterpret_cast<double2 *>(Us + j * kPanelMax);
+                P2 *o = reinterpret_cast<P2 *>(Us + j * kPanelMax);
 #pragma unroll
-                for (int c = 0; c < KW / 2; ++c) o[c] = double2{x[2 * c], x[2 * c + 1]};
+                for (int c = 0; c < KW / 2; ++c) o[c] = P2{x[2 * c], x[2 * c + 1]};
             }
             __builtin_amdgcn_wave_barrier();
             if (tid > j && tid < nrow) {
-                double *dst = a.lu + sgs[j] + tid;
+                T *dst = a.lu + sgs[j] + tid;
                 if (j < jsplit) sweep_step<KW>(x, Us + j * kPanelMax, dst, bad);
                 else sweep_step<KH>(x, Us + j * kPanelMax, dst, bad);
             }
@@ -602,7 +684,7 @@ __device__ __forceinline__ void large_factor_w(const RefArgs &a, int w, int r, c
                 break;
             }
             if (tid < nrow) {
-                double *dst = a.lu + sgs[j] + tid;
+                T *dst = a.lu + sgs[j] + tid;
                 if (j < jsplit) sweep_step<KW>(x, Us + j * kPanelMax, dst, bad);
                 else sweep_step<KH>(x, Us + j * kPanelMax, dst, bad);
             }
@@ -625,7 +707,8 @@ __device__ __forceinline__ void large_factor_w(const RefArgs &a, int w, int r, c
 }
 
 template <class C>
-__device__ __forceinline__ void large_factor(const RefArgs &a, int4 pn, char *sm, double thresh) {
+__device__ __forceinline__ void large_factor(const RefArgs<typename C::T> &a, int4 pn, char *sm,
+                                             typename C::T thresh) {
     if constexpr (C::kMaxW > 16) {
         if (pn.y > 16) {
             large_factor_w<C, 32>(a, pn.y, pn.z, sm, thresh);
@@ -639,33 +722,33 @@ __device__ __forceinline__ void large_factor(const RefArgs &a, int4 pn, char *sm
 // Rows of the source panel (width w) in one target: unit lower solve with the source's
 // diagonal block Ls[j * kPanelMax + c] = L(j + c, j) (zero past the panel), in registers,
 // shifted; writes the solved rows to the factor and to ub.
-template <int KW>
-__device__ __forceinline__ void unit_lower_w(double *lu, int ps, int w, const double *Ls, double *ub) {
-    double u[kPanelMax];
+template <int KW, class T>
+__device__ __forceinline__ void unit_lower_w(T *lu, int ps, int w, const T *Ls, T *ub) {
+    T u[kPanelMax];
 #pragma unroll
     for (int c = 0; c < KW; ++c) {
-        const double v = lu[ps + (c < w ? c : 0)];
-        u[c] = c < w ? v : 0.0;
+        const T v = lu[ps + (c < w ? c : 0)];
+        u[c] = c < w ? v : T(0);
     }
     // the window narrows to KW / 2 columns once no more remain (the rest are zeros)
     constexpr int KH = KW / 2;
     const int jsplit = max(0, w - KH);
 #pragma unroll 1
     for (int j = 0; j < jsplit; ++j) {
-        double rw[kPanelMax];
+        T rw[kPanelMax];
         load_lds_row<KW>(rw, Ls + j * kPanelMax);
         __builtin_amdgcn_sched_barrier(0);
-        const double uj = u[0];
+        const T uj = u[0];
         lu[ps + j] = uj;
         ub[j] = uj;
         shift_fma<KW>(u, uj, rw);
     }
 #pragma unroll 1
     for (int j = jsplit; j < w; ++j) {
-        double rw[kPanelMax];
+        T rw[kPanelMax];
         load_lds_row<KH>(rw, Ls + j * kPanelMax);
         __builtin_amdgcn_sched_barrier(0);
-        const double uj = u[0];
+        const T uj = u[0];
         lu[ps + j] = uj;
         ub[j] = uj;
         shift_fma<KH>(u, uj, rw);
@@ -674,13 +757,15 @@ __device__ __forceinline__ void unit_lower_w(double *lu, int ps, int w, const do
 
 // All pulls of one item with the source panel staged in LDS, then the panel factorization.
 template <class C>
-__device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char *sm) {
-    const double thresh = a.tiny * a.st->anorm_scaled;
+__device__ __forceinline__ void wide_item(const int item, const RefArgs<typename C::T> &a, char *sm) {
+    using T = typename C::T;
+    using MM = Mfma<T>;
+    const T thresh = pivot_threshold(a);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     constexpr int nw = C::kThreads / 64;
-    double *Ld = reinterpret_cast<double *>(sm + C::kOffLd);
-    double *Ub = reinterpret_cast<double *>(sm + C::kOffUb);
-    double *Lr = reinterpret_cast<double *>(sm + C::kOffLr);
+    T *Ld = reinterpret_cast<T *>(sm + C::kOffLd);
+    T *Ub = reinterpret_cast<T *>(sm + C::kOffUb);
+    T *Lr = reinterpret_cast<T *>(sm + C::kOffLr);
     int *lds = reinterpret_cast<int *>(sm + C::kOffLds);
     int *sgs = reinterpret_cast<int *>(sm + C::kOffSgs);
     int4 *prs = reinterpret_cast<int4 *>(sm + C::kOffPairs);
@@ -705,7 +790,7 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char
         // one round: S's diagonal block and the first chunk of its L rows
         for (int t = tid; t < w * kPanelMax; t += C::kThreads) {
             const int j = t / kPanelMax, c = t % kPanelMax;
-            Ld[t] = (c >= 1 && j + c < w) ? a.lu[lds[j] + c] : 0.0;
+            Ld[t] = (c >= 1 && j + c < w) ? a.lu[lds[j] + c] : T(0);
         }
         const int nr0 = min(C::kChunk, r);
         for (int t = tid; t < w * nr0; t += C::kThreads) {
@@ -714,9 +799,8 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char
         }
         __syncthreads();
         // Update of the rows R of each target by S on the matrix cores (more than one target):
-        // the block Lr (nr x w) times the solved rows (w x m) in 16x16 output tiles, k in steps
-        // of 4; lane holds A[lane % 16][lane / 16], B[lane / 16][lane % 16] and the four outputs
-        // D[lane / 16 + 4 v][lane % 16].  Wavefronts 1.. own the tiles, kTiles at a time; for
+        // the block Lr (nr x w) times the solved rows (w x m) in 16x16 output tiles (Mfma),
+        // accumulated in T.  Wavefronts 1.. own the tiles, kTiles at a time; for
         // the first pass of the first chunk they load the destination slots and current values
         // while wavefront 0 solves the targets' rows of S.
         constexpr int kTiles = C::kTiles;
@@ -730,12 +814,12 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char
             const int32_t *rel = ok ? a.rel + pra(g0 + tb).z + i0 : a.rel;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = ti * 16 + lk + 4 * v;
+                const int i = ti * 16 + MM::row(lk, v);
                 sl[v] = (ok && i < nr) ? rel[i] : -1;
             }
         };
         int pslot[kTiles][4];
-        double pcur[kTiles][4];
+        T pcur[kTiles][4];
         const int mt0 = (min(C::kChunk, r) + 15) >> 4;
         if (mf && wv > 0) {
 #pragma unroll
@@ -743,14 +827,14 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char
 #pragma unroll
             for (int k = 0; k < kTiles; ++k)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) pcur[k][v] = pslot[k][v] >= 0 ? a.lu[pslot[k][v]] : 0.0;
+                for (int v = 0; v < 4; ++v) pcur[k][v] = pslot[k][v] >= 0 ? a.lu[pslot[k][v]] : T(0);
         }
         // rows of S in each target: unit lower solve with S's diagonal block, one lane per
         // target (wavefront 0; a group holds at most kGroup targets); the lane keeps its
         // target's rows in registers
         if (wv == 0 && lane < m) {
             const int ps = pra(g0 + lane).y;
-            double *ub = Ub + lane * kRowLd;
+            T *ub = Ub + lane * kRowLd;
             if (C::kMaxW > 16 && w > 16) unit_lower_w<C::kMaxW>(a.lu, ps, w, Ld, ub);
             else if (w > 8) unit_lower_w<16>(a.lu, ps, w, Ld, ub);
             else unit_lower_w<8>(a.lu, ps, w, Ld, ub);
@@ -771,27 +855,26 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char
                 if (wv > 0) {
                     for (int tile0 = (wv - 1) * kTiles, pass = 0; tile0 < mt * nt;
                          tile0 += (nw - 1) * kTiles, ++pass) {
-                        double4_t acc[kTiles];
+                        typename MM::acc_t acc[kTiles];
 #pragma unroll
-                        for (int k = 0; k < kTiles; ++k) acc[k] = double4_t{0.0, 0.0, 0.0, 0.0};
+                        for (int k = 0; k < kTiles; ++k) acc[k] = typename MM::acc_t{T(0), T(0), T(0), T(0)};
                         for (int k0 = 0; k0 < w; k0 += 4) {
                             const int kk = k0 + lk;
-                            double av[kTiles], bv[kTiles];
+                            T av[kTiles], bv[kTiles];
 #pragma unroll
                             for (int k = 0; k < kTiles; ++k) {
                                 const int tile = tile0 + k;
                                 const int ti = tile % mt, tt = tile / mt;
                                 const int ia2 = ti * 16 + li, tb = tt * 16 + li;
                                 const bool ok = tile < mt * nt && kk < w;
-                                av[k] = (ok && ia2 < nr) ? Lr[kk * C::kChunk + ia2] : 0.0;
-                                bv[k] = (ok && tb < m) ? Ub[tb * kRowLd + kk] : 0.0;
+                                av[k] = (ok && ia2 < nr) ? Lr[kk * C::kChunk + ia2] : T(0);
+                                bv[k] = (ok && tb < m) ? Ub[tb * kRowLd + kk] : T(0);
                             }
 #pragma unroll
-                            for (int k = 0; k < kTiles; ++k)
-                                acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[k], bv[k], acc[k], 0, 0, 0);
+                            for (int k = 0; k < kTiles; ++k) acc[k] = MM::step(av[k], bv[k], acc[k]);
                         }
                         int slot[kTiles][4];
-                        double cur[kTiles][4];
+                        T cur[kTiles][4];
                         if (i0 == 0 && pass == 0) {
 #pragma unroll
                             for (int k = 0; k < kTiles; ++k)
@@ -806,7 +889,7 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char
 #pragma unroll
                             for (int k = 0; k < kTiles; ++k)
 #pragma unroll
-                                for (int v = 0; v < 4; ++v) cur[k][v] = slot[k][v] >= 0 ? a.lu[slot[k][v]] : 0.0;
+                                for (int v = 0; v < 4; ++v) cur[k][v] = slot[k][v] >= 0 ? a.lu[slot[k][v]] : T(0);
                         }
 #pragma unroll
                         for (int k = 0; k < kTiles; ++k)
@@ -818,9 +901,9 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char
             } else {
                 for (int q = g0 + wv; q < g1; q += nw) {
                     const int32_t *rel = a.rel + pra(q).z + i0;
-                    const double *ub = Ub + (q - g0) * kRowLd;
+                    const T *ub = Ub + (q - g0) * kRowLd;
                     for (int i = lane; i < nr; i += 64) {
-                        double acc = 0.0;
+                        T acc = T(0);
                         for (int j = 0; j < w; ++j) acc = fma(Lr[j * C::kChunk + i], ub[j], acc);
                         a.lu[rel[i]] -= acc;
                     }
@@ -839,26 +922,35 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs &a, char
 // touch other columns than the wide items, so one launch needs no ordering between them);
 // any blocks after those copy copy_k[c0 .. c1) of the row-ordered factor (columns that no
 // launch from this one on writes).
+// Block blk of nblk of one level launch (the work of one handle: its wide items, narrow
+// items and copy chunk).
 template <class C>
-__global__ __launch_bounds__(C::kThreads, C::kWaves) void k_refactor_wide(int item0, RefArgs a, int nwide, int small0,
-                                                                         int nsmall, int c0, int c1) {
-    extern __shared__ __align__(16) char sm[];
+__device__ __forceinline__ void refactor_block(int blk, int nblk, int item0, const RefArgs<typename C::T> &a,
+                                               int nwide, int small0, int nsmall, int c0, int c1, char *sm) {
     const int nsb = (nsmall + C::kThreads / 16 - 1) / (C::kThreads / 16);
-    if ((int)blockIdx.x >= nwide + nsb) {
-        const int b = blockIdx.x - nwide - nsb, nbc = gridDim.x - nwide - nsb;
+    if (blk >= nwide + nsb) {
+        const int b = blk - nwide - nsb, nbc = nblk - nwide - nsb;
         for (int q = c0 + b * C::kThreads + threadIdx.x; q < c1; q += nbc * C::kThreads) {
             const int k = a.copy_k[q];
             a.lucsr[k] = a.lu[a.csr_src[k]];
         }
         return;
     }
-    if ((int)blockIdx.x >= nwide) {
-        const int b = blockIdx.x - nwide;
-        small_group<(C::kMaxW > 16)>(small0, nsmall, a, b * (C::kThreads / 16) + (threadIdx.x >> 4),
-                                     b * (C::kThreads / 64) + (threadIdx.x >> 6));
+    if (blk >= nwide) {
+        const int b = blk - nwide;
+        small_group<typename C::T, (C::kMaxW > 16)>(small0, nsmall, a, b * (C::kThreads / 16) + (threadIdx.x >> 4),
+                                                    b * (C::kThreads / 64) + (threadIdx.x >> 6));
         return;
     }
-    wide_item<C>(item0 + blockIdx.x, a, sm);
+    wide_item<C>(item0 + blk, a, sm);
+}
+
+template <class C>
+__global__ __launch_bounds__(C::kThreads, C::kWaves) void k_refactor_wide(int item0, RefArgs<typename C::T> a,
+                                                                         int nwide, int small0, int nsmall, int c0,
+                                                                         int c1) {
+    extern __shared__ __align__(16) char sm[];
+    refactor_block<C>(blockIdx.x, gridDim.x, item0, a, nwide, small0, nsmall, c0, c1, sm);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -878,13 +970,16 @@ __global__ __launch_bounds__(C::kThreads, C::kWaves) void k_refactor_wide(int it
 // inputs were written by earlier launches) and one persistent launch per triangle (kWait =
 // true: an unknown is read with a device-coherent load and waited for while it still holds
 // the unset sentinel; results are published with device-coherent stores).  The arithmetic
-// is the same in both modes.
+// is the same in both modes.  TF is the type of the stored factor (FP64, or FP32 in the
+// mixed-precision path); each factor value is widened to FP64 as it is read, so the
+// right-hand sides, the unknowns and every sum stay FP64.
 
-
+template <class TF>
 struct SolveArgs {
     const int4 *item, *rows, *rinfo;
     const int32_t *col, *Q;
-    const double *lucsr, *c;
+    const TF *lucsr;
+    const double *c;
     const double *bp;     // forward right-hand side r[P[i]] * b[P[i]] (permuted order)
     double *y;            // forward output / backward input (permuted)
     double *xt;           // backward output (permuted)
@@ -892,6 +987,7 @@ struct SolveArgs {
     double *psum;         // forward: partial sums of the early L columns of helped rows
     double *usum;         // backward: partial sums of the early U columns of helped rows
     int *abort;           // persistent mode: raised by a wait that timed out
+    int *tick;            // persistent mode: next item to take (forward, backward)
 };
 
 constexpr unsigned long long kUnset = 0x7ff4dead0badf00dULL;   // signaling NaN
@@ -966,8 +1062,8 @@ __device__ __forceinline__ void put_value(double *p, double v) {
 // entries are taken four at a time into four accumulators, a remainder of fewer than four
 // into the first.  Loads go in batches of B entries per lane: the batch's indices and
 // factor values in one round, then its unknowns in one round.
-template <bool kWait, int B>
-__device__ __forceinline__ double sdot(const SolveArgs &a, const double *v, int q0, int q1, int gl, int width) {
+template <bool kWait, int B, class TF>
+__device__ __forceinline__ double sdot(const SolveArgs<TF> &a, const double *v, int q0, int q1, int gl, int width) {
     static_assert(B % 4 == 0, "batch of whole groups of four");
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     for (int q = q0 + gl; q < q1; q += B * width) {
@@ -978,7 +1074,7 @@ __device__ __forceinline__ double sdot(const SolveArgs &a, const double *v, int 
         for (int k = 0; k < B; ++k) {
             const bool h = k < rem;
             cc[k] = h ? a.col[q + k * width] : 0;
-            ll[k] = h ? a.lucsr[q + k * width] : 0.0;
+            ll[k] = h ? (double)a.lucsr[q + k * width] : 0.0;
         }
         if constexpr (kWait) {
             unsigned long long bb[B];
@@ -1043,8 +1139,8 @@ __device__ __forceinline__ double inpanel_backward(const double (&Urow)[kPanelMa
     return xv;
 }
 
-template <bool kWait>
-__device__ __forceinline__ void lsolve_item(const SolveArgs &a, int item, double *ext, double *blk) {
+template <bool kWait, class TF>
+__device__ __forceinline__ void lsolve_item(const SolveArgs<TF> &a, int item, double *ext, double *blk) {
     const int4 it = a.item[item];
     const int tid = threadIdx.x, lane = tid & 63;
     if (it.x < 0) {                                     // pack of whole small panels
@@ -1055,7 +1151,7 @@ __device__ __forceinline__ void lsolve_item(const SolveArgs &a, int item, double
         const bool lead = rr.x >= 0 && gl == 0;
         double bv = 0.0, Lp[kPackW - 1];
 #pragma unroll
-        for (int k = 0; k < kPackW - 1; ++k) Lp[k] = lead && k < t ? a.lucsr[rr.z + k] : 0.0;
+        for (int k = 0; k < kPackW - 1; ++k) Lp[k] = lead && k < t ? (double)a.lucsr[rr.z + k] : 0.0;
         if (lead) bv = a.bp[rr.x];
         const double acc = sdot<kWait, 4>(a, a.y, rr.y, rr.z, gl, lanes);
         double yv = bv - acc;
@@ -1090,7 +1186,7 @@ __device__ __forceinline__ void lsolve_item(const SolveArgs &a, int item, double
         for (int e = tid; e < w * kPanelMax; e += kBlock) {
             const int r = e / kPanelMax, c = e % kPanelMax;
             const int d = a.rinfo[s + r].z;
-            blk[r * kRowLd + c] = c < r ? a.lucsr[d - r + c] : 0.0;
+            blk[r * kRowLd + c] = c < r ? (double)a.lucsr[d - r + c] : 0.0;
         }
         if (t < w) {
             const double bv = gl == 0 ? a.bp[s + t] : 0.0;
@@ -1111,8 +1207,8 @@ __device__ __forceinline__ void lsolve_item(const SolveArgs &a, int item, double
     __syncthreads();
 }
 
-template <bool kWait>
-__device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double *ext, double *blk) {
+template <bool kWait, class TF>
+__device__ __forceinline__ void usolve_item(const SolveArgs<TF> &a, int item, double *ext, double *blk) {
     const int4 it = a.item[item];
     const int tid = threadIdx.x, lane = tid & 63;
     if (it.x < 0) {                                     // pack of whole small panels
@@ -1126,10 +1222,10 @@ __device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double
         int qi = 0;
         const int d = rr.y - (w - t);                   // diagonal slot
 #pragma unroll
-        for (int k = 0; k < kPackW - 1; ++k) Up[k] = lead && k < e ? a.lucsr[d + 1 + k] : 0.0;
+        for (int k = 0; k < kPackW - 1; ++k) Up[k] = lead && k < e ? (double)a.lucsr[d + 1 + k] : 0.0;
         if (lead) {
             yv = a.y[rr.x];
-            dd = a.lucsr[d];
+            dd = (double)a.lucsr[d];
             qi = a.Q[rr.x];
             ci = a.c[qi];
         }
@@ -1169,11 +1265,11 @@ __device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double
         for (int e = tid; e < w * kPanelMax; e += kBlock) {
             const int r = e / kPanelMax, c = e % kPanelMax;
             const int d = a.rinfo[s + r].x;
-            blk[r * kRowLd + c] = c > r && c < w ? a.lucsr[d + (c - r)] : 0.0;
+            blk[r * kRowLd + c] = c > r && c < w ? (double)a.lucsr[d + (c - r)] : 0.0;
         }
         if (tid < w) {
             const int i = s + tid;
-            dv = a.lucsr[a.rinfo[i].x];
+            dv = (double)a.lucsr[a.rinfo[i].x];
             yv = a.y[i];
             qi = a.Q[i];
             ci = a.c[qi];
@@ -1201,40 +1297,79 @@ __device__ __forceinline__ void usolve_item(const SolveArgs &a, int item, double
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_lsolve_level(int item0, SolveArgs a) {
+template <class TF>
+__global__ __launch_bounds__(256) void k_lsolve_level(int item0, SolveArgs<TF> a) {
     __shared__ double ext[kPanelMax];
     __shared__ __align__(16) double blk[kPanelMax * kRowLd];
     lsolve_item<false>(a, item0 + blockIdx.x, ext, blk);
 }
 
-__global__ __launch_bounds__(256) void k_usolve_level(int item0, SolveArgs a) {
+template <class TF>
+__global__ __launch_bounds__(256) void k_usolve_level(int item0, SolveArgs<TF> a) {
     __shared__ double ext[kPanelMax];
     __shared__ __align__(16) double blk[kPanelMax * kRowLd];
     usolve_item<false>(a, item0 + blockIdx.x, ext, blk);
 }
 
-// Persistent solves: the items of levels [i0, i1) in level order, item i0 + k on block
-// k % gridDim.x, each block in increasing order.  An item only reads unknowns of items of
-// lower levels, i.e. of smaller index, so the unfinished item of smallest index can always
-// proceed: with every block resident (cooperative launch) the launch always drains.
-__global__ __launch_bounds__(256) void k_lsolve_persistent(int i0, int i1, SolveArgs a) {
+// Persistent solves: the items of levels [i0, i1) in level order; an item only reads
+// unknowns of items of lower levels, i.e. of smaller index.  Two ways to hand out items:
+//  - fixed (kTicket = false): item i0 + k on block k % gridDim.x, each block in increasing
+//    order.  The unfinished item of smallest index can always proceed once its block runs,
+//    so the launch drains when every block is resident at once (a cooperative launch on a
+//    device the launch has to itself);
+//  - ticket (kTicket = true): running blocks take items from a counter (*tick, zeroed by
+//    k_solve_reset), each block in increasing order.  A block takes a ticket only while it
+//    runs and works through its tickets in order, so the unfinished item of smallest index
+//    is always held by a running block that is working on it: the launch drains on whatever
+//    share of the device it gets, with other streams' kernels beside it.  The next ticket
+//    is requested at the start of an item and read at its end, so the counter's round trip
+//    overlaps the item's loads; the counter still costs a round trip per item, which is why
+//    the fixed order is kept for a device that the solve has to itself.
+template <bool kFwd, bool kTicket, class TF>
+__device__ __forceinline__ void persistent_items(int i0, int i1, const SolveArgs<TF> &a, int *tick) {
     __shared__ double ext[kPanelMax];
     __shared__ __align__(16) double blk[kPanelMax * kRowLd];
-    for (int item = i0 + blockIdx.x; item < i1; item += gridDim.x) lsolve_item<true>(a, item, ext, blk);
+    if constexpr (!kTicket) {
+        for (int item = i0 + blockIdx.x; item < i1; item += gridDim.x) {
+            if constexpr (kFwd) lsolve_item<true>(a, item, ext, blk);
+            else usolve_item<true>(a, item, ext, blk);
+        }
+        return;
+    }
+    __shared__ int next;
+    if (threadIdx.x == 0) next = atomicAdd(tick, 1);
+    __syncthreads();
+    int cur = next;
+    while (i0 + cur < i1) {
+        int nt = 0;
+        if (threadIdx.x == 0) nt = atomicAdd(tick, 1);
+        if constexpr (kFwd) lsolve_item<true>(a, i0 + cur, ext, blk);
+        else usolve_item<true>(a, i0 + cur, ext, blk);
+        __syncthreads();                     // every thread is done with the item and `next`
+        if (threadIdx.x == 0) next = nt;
+        __syncthreads();
+        cur = next;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_usolve_persistent(int i0, int i1, SolveArgs a) {
-    __shared__ double ext[kPanelMax];
-    __shared__ __align__(16) double blk[kPanelMax * kRowLd];
-    for (int item = i0 + blockIdx.x; item < i1; item += gridDim.x) usolve_item<true>(a, item, ext, blk);
+template <class TF, bool kTicket>
+__global__ __launch_bounds__(256) void k_lsolve_persistent(int i0, int i1, SolveArgs<TF> a) {
+    persistent_items<true, kTicket>(i0, i1, a, a.tick);
 }
 
-// bp = r[P] .* b[P]; with mark, every unknown of the persistent mode starts unset
+template <class TF, bool kTicket>
+__global__ __launch_bounds__(256) void k_usolve_persistent(int i0, int i1, SolveArgs<TF> a) {
+    persistent_items<false, kTicket>(i0, i1, a, a.tick + 1);
+}
+
+// bp = r[P] .* b[P]; with mark, every unknown of the persistent mode starts unset and the
+// item tickets start at zero
 __global__ void k_solve_reset(int n, const double *__restrict__ b, const double *__restrict__ r,
                               const int32_t *__restrict__ P, double *__restrict__ bp, double *__restrict__ y,
                               double *__restrict__ xt, double *__restrict__ psum, double *__restrict__ usum,
-                              int mark) {
+                              int mark, int *__restrict__ tick) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (mark && i < 2) tick[i] = 0;
     if (i < n) {
         const int pi = P[i];
         bp[i] = r[pi] * b[pi];
@@ -1248,38 +1383,118 @@ __global__ void k_solve_reset(int n, const double *__restrict__ b, const double 
     }
 }
 
-// Approximate triangular solves for the preconditioner inside refinement: Jacobi sweeps over
-// the CSR copy of L+U in the permuted, scaled space, 8 lanes per row, with no dependency
-// between rows (every sweep reads the previous iterate only).
-// One sweep of the unit lower triangle: yout = bp - (L - I) yin.
+// Approximate triangular solves for the preconditioner inside refinement (the triangular
+// solves replaced by Jacobi or Gauss-Seidel iterations): sweeps over the CSR copy of L+U in
+// the permuted, scaled space.  Each triangle starts from the zero vector (yin / xin null).
+// Jacobi: 8 lanes per row, no dependency between rows (every sweep reads the previous
+// iterate only).  One sweep of the unit lower triangle: yout = bp - (L - I) yin.
+template <class TF>
 __global__ __launch_bounds__(256) void k_jacobi_l(int n, const int4 *__restrict__ rinfo, const int32_t *__restrict__ col,
-                                                  const double *__restrict__ lucsr, const double *__restrict__ bp,
+                                                  const TF *__restrict__ lucsr, const double *__restrict__ bp,
                                                   const double *__restrict__ yin, double *__restrict__ yout) {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = gid >> 3, gl = gid & 7;
     if (i >= n) return;                                 // whole 8-lane groups
     const int4 ri = rinfo[i];                           // L entries of row i: [x, z)
     double s = 0.0;
-    for (int q = ri.x + gl; q < ri.z; q += 8) s = fma(lucsr[q], yin[col[q]], s);
+    if (yin)
+        for (int q = ri.x + gl; q < ri.z; q += 8) s = fma((double)lucsr[q], yin[col[q]], s);
     s = group_sum(s, 8);
     if (gl == 0) yout[i] = bp[i] - s;
 }
 
-// One sweep of the upper triangle: xout = D^-1 (y - (U - D) xin); first = 1 starts from
-// xin = 0 (xout = D^-1 y) without reading xin.
+// One sweep of the upper triangle: xout = D^-1 (y - (U - D) xin).
+template <class TF>
 __global__ __launch_bounds__(256) void k_jacobi_u(int n, const int4 *__restrict__ urinfo,
-                                                  const int32_t *__restrict__ col, const double *__restrict__ lucsr,
+                                                  const int32_t *__restrict__ col, const TF *__restrict__ lucsr,
                                                   const double *__restrict__ y, const double *__restrict__ xin,
-                                                  double *__restrict__ xout, int first) {
+                                                  double *__restrict__ xout) {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = gid >> 3, gl = gid & 7;
     if (i >= n) return;
     const int4 ri = urinfo[i];                          // diagonal at x, U entries (x, z)
     double s = 0.0;
-    if (!first)
-        for (int q = ri.x + 1 + gl; q < ri.z; q += 8) s = fma(lucsr[q], xin[col[q]], s);
+    if (xin)
+        for (int q = ri.x + 1 + gl; q < ri.z; q += 8) s = fma((double)lucsr[q], xin[col[q]], s);
     s = group_sum(s, 8);
-    if (gl == 0) xout[i] = (y[i] - s) / lucsr[ri.x];
+    if (gl == 0) xout[i] = (y[i] - s) / (double)lucsr[ri.x];
+}
+
+// Block Gauss-Seidel sweeps: the rows are cut into chunks of kGsChunk consecutive permuted
+// rows, one 256-thread block per chunk.  A row reads the values of its own chunk from the
+// current sweep and every other value from the previous iterate (Jacobi between chunks):
+// 8 lanes per row sum the entries outside the chunk while the entries inside it are staged
+// as a dense triangle in LDS, then wavefront 0 substitutes inside the chunk in registers.
+constexpr int kGsChunk = kPanelMax;
+
+// yout = chunk-wise solve of L_cc yout_c = bp_c - L_c,out yin (unit L_cc)
+template <class TF>
+__global__ __launch_bounds__(256) void k_bgs_l(int n, const int4 *__restrict__ rinfo, const int32_t *__restrict__ col,
+                                               const TF *__restrict__ lucsr, const double *__restrict__ bp,
+                                               const double *__restrict__ yin, double *__restrict__ yout) {
+    __shared__ double ext[kGsChunk];
+    __shared__ __align__(16) double blk[kGsChunk * kRowLd];
+    const int c0 = blockIdx.x * kGsChunk, w = min(kGsChunk, n - c0);
+    const int tid = threadIdx.x, t = tid >> 3, gl = tid & 7;
+    for (int e = tid; e < kGsChunk * kRowLd; e += kBlock) blk[e] = 0.0;
+    __syncthreads();
+    double s = 0.0;
+    if (t < w) {
+        const int4 ri = rinfo[c0 + t];                  // L entries of the row: [x, z)
+        for (int q = ri.x + gl; q < ri.z; q += 8) {
+            const int j = col[q];
+            const double l = (double)lucsr[q];
+            if (j >= c0) blk[t * kRowLd + (j - c0)] = l;
+            else if (yin) s = fma(l, yin[j], s);
+        }
+    }
+    s = group_sum(s, 8);
+    if (t < w && gl == 0) ext[t] = bp[c0 + t] - s;
+    __syncthreads();
+    if (tid < 64) {
+        double Lrow[kPanelMax];
+        load_lds_row<kPanelMax>(Lrow, blk + min(tid, kGsChunk - 1) * kRowLd);
+        double yv = tid < w ? ext[tid] : 0.0;
+        yv = inpanel_forward(Lrow, w, tid, yv);
+        if (tid < w) yout[c0 + tid] = yv;
+    }
+}
+
+// xout = chunk-wise solve of U_cc xout_c = y_c - U_c,out xin
+template <class TF>
+__global__ __launch_bounds__(256) void k_bgs_u(int n, const int4 *__restrict__ urinfo, const int32_t *__restrict__ col,
+                                               const TF *__restrict__ lucsr, const double *__restrict__ y,
+                                               const double *__restrict__ xin, double *__restrict__ xout) {
+    __shared__ double ext[kGsChunk], dg[kGsChunk];
+    __shared__ __align__(16) double blk[kGsChunk * kRowLd];
+    const int c0 = blockIdx.x * kGsChunk, w = min(kGsChunk, n - c0), c1 = c0 + w;
+    const int tid = threadIdx.x, t = tid >> 3, gl = tid & 7;
+    for (int e = tid; e < kGsChunk * kRowLd; e += kBlock) blk[e] = 0.0;
+    __syncthreads();
+    double s = 0.0;
+    int4 ri = int4{0, 0, 0, 0};
+    if (t < w) {
+        ri = urinfo[c0 + t];                            // diagonal at x, U entries (x, z)
+        for (int q = ri.x + 1 + gl; q < ri.z; q += 8) {
+            const int j = col[q];
+            const double u = (double)lucsr[q];
+            if (j < c1) blk[t * kRowLd + (j - c0)] = u;
+            else if (xin) s = fma(u, xin[j], s);
+        }
+    }
+    s = group_sum(s, 8);
+    if (t < w && gl == 0) {
+        ext[t] = y[c0 + t] - s;
+        dg[t] = (double)lucsr[ri.x];
+    }
+    __syncthreads();
+    if (tid < 64) {
+        double Urow[kPanelMax];
+        load_lds_row<kPanelMax>(Urow, blk + min(tid, kGsChunk - 1) * kRowLd);
+        const double val = tid < w ? ext[tid] : 0.0;
+        const double xv = inpanel_backward(Urow, tid < w ? 1.0 / dg[tid] : 1.0, w, tid, val);
+        if (tid < w) xout[c0 + tid] = xv;
+    }
 }
 
 // x[Q[i]] = c[Q[i]] xt[i]: back to the original ordering and scaling

@@ -3,10 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "kkt_kernels.h"
@@ -25,10 +28,12 @@ struct Dev {
     unsigned long long *pcount;
     int4 *l_item4, *u_item4, *l_rows4, *u_rows4, *rinfo4, *urinfo4;
     int32_t *csr_col, *csr_src, *copy_k, *P, *Q;
-    double *r, *c, *lu, *lucsr, *y, *xt, *psum, *usum, *bp, *bsave;
+    void *lu, *lucsr;   // factor values (FP64, or FP32 with factor_precision = KKT_FP32)
+    double *r, *c, *y, *xt, *psum, *usum, *bp, *bsave;
     double *V, *Z, *w, *res, *part, *hbuf, *ybuf;
     DevStatus *st;
     ResNorms *rn;
+    int *tick;          // ticket counters of the persistent solves
 };
 
 constexpr int kDotBlocks = 512;
@@ -70,6 +75,9 @@ struct kkt_handle {
     // bound to the library's static scratch array: nothing is allocated after the bind (no
     // graph is recorded; the level launches go one by one)
     bool on_scratch = false;
+    // the persistent solves take items by ticket (persistent_solve = 2, or a device without
+    // cooperative launches): safe when other streams share the device
+    bool tickets = false;
     int grid_l = 1, grid_u = 1;  // co-resident blocks of the persistent solve kernels
     int ncu = 1;                 // compute units of the bound device
     // the refactorization's per-level launches, recorded once per bind on the capture stream
@@ -92,6 +100,7 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     const Schedule &g = h->sch;
     const size_t n = s.n, nlu = s.nnz_lu(), na = s.nnz_a;
     const int m = h->opts.gmres_restart;
+    const size_t fb = h->opts.factor_precision == KKT_FP32 ? sizeof(float) : sizeof(double);
     Carver c{base};
     d.a_rowptr = c.take<int32_t>(n + 1);
     d.a_colind = c.take<int32_t>(na);
@@ -123,8 +132,8 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.Q = c.take<int32_t>(n);
     d.r = c.take<double>(n);
     d.c = c.take<double>(n);
-    d.lu = c.take<double>(nlu);
-    d.lucsr = c.take<double>(nlu);
+    d.lu = c.take<char>(nlu * fb);
+    d.lucsr = c.take<char>(nlu * fb);
     d.y = c.take<double>(n);
     d.xt = c.take<double>(n);
     d.psum = c.take<double>(n);
@@ -140,6 +149,7 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.ybuf = c.take<double>((size_t)m + 2);
     d.st = c.take<DevStatus>(1);
     d.rn = c.take<ResNorms>(1);
+    d.tick = c.take<int>(2);
     *bytes = c.off + 256;
 }
 
@@ -155,6 +165,13 @@ struct DeviceGuard {
         if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
     }
 };
+
+// Runs f with a value of the handle's factor type (double, or float for KKT_FP32).
+template <class F>
+auto by_precision(const kkt_handle *h, F &&f) {
+    if (h->opts.factor_precision == KKT_FP32) return f(float{});
+    return f(double{});
+}
 
 #define HIPCHK(x)                                  \
     do {                                           \
@@ -215,35 +232,46 @@ int upload(T *dst, const std::vector<T> &src, hipStream_t s) {
 }
 
 // x = Q C (L U)^-1 P R b for one column (both in original order)
-// One cooperative launch of a persistent solve kernel over items [i0, i1).
-template <class K>
-hipError_t launch_persistent(K kernel, int grid, int i0, int i1, SolveArgs &a, hipStream_t s) {
+// One launch of a persistent solve kernel over items [i0, i1) with at most as many blocks
+// as the device holds at once: cooperative for the fixed item order (every block resident),
+// plain for the ticket order (progress does not need residency).
+template <class K, class A>
+hipError_t launch_persistent(K kernel, bool ticket, int grid, int i0, int i1, A &a, hipStream_t s) {
+    if (ticket) {
+        kernel<<<grid, kBlock, 0, s>>>(i0, i1, a);
+        return hipGetLastError();
+    }
     void *args[] = {&i0, &i1, &a};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kernel), dim3(grid), dim3(kBlock), args, 0, s);
 }
 
-int enqueue_solve(kkt_handle *h, const double *b, double *x, hipStream_t s) {
+template <class TF>
+int enqueue_solve_t(kkt_handle *h, const double *b, double *x, hipStream_t s) {
     const Schedule &g = h->sch;
     const Dev &d = h->d;
     const int n = h->sym.n;
     const bool pers = h->opts.persistent_solve != 0;
-    SolveArgs a{d.l_item4, d.l_rows4, d.rinfo4, d.csr_col, d.Q, d.lucsr, d.c, d.bp, d.y, d.xt, x, d.psum, d.usum,
-                &d.st->abort};
+    SolveArgs<TF> a{d.l_item4, d.l_rows4, d.rinfo4, d.csr_col, d.Q, static_cast<const TF *>(d.lucsr), d.c, d.bp, d.y,
+                    d.xt, x, d.psum, d.usum, &d.st->abort, d.tick};
     timed(h, KKT_PROF_LSOLVE, s, [&] {
         k_solve_reset<<<blocks_for(n, 256), 256, 0, s>>>(n, b, d.r, d.P, d.bp, d.y, d.xt, d.psum, d.usum,
-                                                         pers ? 1 : 0);
+                                                         pers ? 1 : 0, d.tick);
     });
     // forward: level launches below l_split, then the persistent launch
     const int lsplit = pers ? g.l_split : (int)g.l_lvl.size() - 1;
     for (int l = 0; l < lsplit; ++l) {
         const int cnt = g.l_lvl[l + 1] - g.l_lvl[l];
-        if (cnt) timed(h, KKT_PROF_LSOLVE, s, [&] { k_lsolve_level<<<cnt, kBlock, 0, s>>>(g.l_lvl[l], a); });
+        if (cnt) timed(h, KKT_PROF_LSOLVE, s, [&] { k_lsolve_level<TF><<<cnt, kBlock, 0, s>>>(g.l_lvl[l], a); });
     }
     const int li0 = g.l_lvl[lsplit], li1 = g.l_lvl.back();
     if (li1 > li0) {
         hipError_t e = hipSuccess;
         timed(h, KKT_PROF_LSOLVE, s,
-              [&] { e = launch_persistent(k_lsolve_persistent, std::min(li1 - li0, h->grid_l), li0, li1, a, s); });
+              [&] {
+                  const int gr = std::min(li1 - li0, h->grid_l);
+                  e = h->tickets ? launch_persistent(k_lsolve_persistent<TF, true>, true, gr, li0, li1, a, s)
+                                 : launch_persistent(k_lsolve_persistent<TF, false>, false, gr, li0, li1, a, s);
+              });
         HIPCHK(e);
     }
     // backward: the persistent launch for levels below u_split, then level launches
@@ -255,15 +283,23 @@ int enqueue_solve(kkt_handle *h, const double *b, double *x, hipStream_t s) {
     if (ui1 > 0) {
         hipError_t e = hipSuccess;
         timed(h, KKT_PROF_USOLVE, s,
-              [&] { e = launch_persistent(k_usolve_persistent, std::min(ui1, h->grid_u), 0, ui1, a, s); });
+              [&] {
+                  const int gr = std::min(ui1, h->grid_u);
+                  e = h->tickets ? launch_persistent(k_usolve_persistent<TF, true>, true, gr, 0, ui1, a, s)
+                                 : launch_persistent(k_usolve_persistent<TF, false>, false, gr, 0, ui1, a, s);
+              });
         HIPCHK(e);
     }
     for (size_t l = usplit; l + 1 < g.u_lvl.size(); ++l) {
         const int cnt = g.u_lvl[l + 1] - g.u_lvl[l];
-        if (cnt) timed(h, KKT_PROF_USOLVE, s, [&] { k_usolve_level<<<cnt, kBlock, 0, s>>>(g.u_lvl[l], a); });
+        if (cnt) timed(h, KKT_PROF_USOLVE, s, [&] { k_usolve_level<TF><<<cnt, kBlock, 0, s>>>(g.u_lvl[l], a); });
     }
     HIPCHK(hipGetLastError());
     return KKT_OK;
+}
+
+int enqueue_solve(kkt_handle *h, const double *b, double *x, hipStream_t s) {
+    return by_precision(h, [&](auto tag) { return enqueue_solve_t<decltype(tag)>(h, b, x, s); });
 }
 
 // value update: scale factors, scaled values scattered into the factor, norms
@@ -280,8 +316,13 @@ int enqueue_update(kkt_handle *h, const double *v, hipStream_t s) {
         k_col_scale<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_cptr, d.a_cpos, d.a_crow, v, d.r, eq, d.c);
     });
     timed(h, KKT_PROF_UPDATE, s, [&] {
-        k_scatter_norms<<<kNormBlocks, 256, 0, s>>>(n, d.a_rowptr, d.a_colind, v, d.r, d.c, d.a_map,
-                                                   (int64_t)g.lu_fill.size(), d.lu_fill, d.lu, d.part);
+        by_precision(h, [&](auto tag) {
+            using T = decltype(tag);
+            k_scatter_norms<T><<<kNormBlocks, 256, 0, s>>>(n, d.a_rowptr, d.a_colind, v, d.r, d.c, d.a_map,
+                                                          (int64_t)g.lu_fill.size(), d.lu_fill, static_cast<T *>(d.lu),
+                                                          d.part);
+            return 0;
+        });
     });
     timed(h, KKT_PROF_UPDATE, s, [&] { k_max_parts<<<1, 256, 0, s>>>(kNormBlocks, 2, d.part, &d.st->anorm_scaled); });
     HIPCHK(hipGetLastError());
@@ -290,11 +331,16 @@ int enqueue_update(kkt_handle *h, const double *v, hipStream_t s) {
 
 // the level launches of the refactorization, the row-ordered copy and the pivot count; they
 // read only workspace buffers, so one recording serves every later call
-int enqueue_levels(kkt_handle *h, hipStream_t s) {
+template <class T>
+int enqueue_levels_t(kkt_handle *h, hipStream_t s) {
+    using Big = BigCfg<T>;
+    using Med = MedCfg<T>;
+    using W256 = W256Cfg<T>;
     const Schedule &g = h->sch;
     const Dev &d = h->d;
-    RefArgs a{d.ldiag, d.item8, d.pair8, d.f_rel, d.lu, d.st, d.pcount,
-              h->opts.tiny_pivot, h->opts.dense_mfma != 0, d.copy_k, d.csr_src, d.lucsr};
+    const double tiny = std::is_same<T, float>::value ? h->opts.tiny_pivot_fp32 : h->opts.tiny_pivot;
+    RefArgs<T> a{d.ldiag, d.item8, d.pair8, d.f_rel, static_cast<T *>(d.lu), d.st, d.pcount,
+                 tiny, h->opts.dense_mfma != 0, d.copy_k, d.csr_src, static_cast<T *>(d.lucsr)};
     const int ncopy = (int)g.copy_ptr.size() - 1;   // launches that carry a chunk of the copy
     for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
         // the kinds of items of a level touch disjoint target columns, so one launch runs the
@@ -306,9 +352,9 @@ int enqueue_levels(kkt_handle *h, hipStream_t s) {
             timed(h, KKT_PROF_REFACTOR_SMALL, s, [&] {
                 // many items: keep more in flight; few: shorten each item's dependent chain
                 if (ns > kSmallPipeMax)
-                    k_refactor_small<false><<<blocks_for(ns, kBlock / 16), kBlock, 0, s>>>(i0, ns, a);
+                    k_refactor_small<T, false><<<blocks_for(ns, kBlock / 16), kBlock, 0, s>>>(i0, ns, a);
                 else
-                    k_refactor_small<true><<<blocks_for(ns, kBlock / 16), kBlock, 0, s>>>(i0, ns, a);
+                    k_refactor_small<T, true><<<blocks_for(ns, kBlock / 16), kBlock, 0, s>>>(i0, ns, a);
             });
         // otherwise the narrow items are extra blocks of the level's first wide launch, and so
         // is a chunk of the row-ordered copy on the top levels (columns already final)
@@ -317,16 +363,21 @@ int enqueue_levels(kkt_handle *h, hipStream_t s) {
         const bool copy = cc >= 0 && cc < ncopy && (nb || nm);
         const int c0 = copy ? g.copy_ptr[cc] : 0, c1 = copy ? g.copy_ptr[cc + 1] : 0;
         const int cb = c1 > c0 ? h->ncu : 0;
-        if (nb)
+        if (nb && g.f_w256[l])
+            timed(h, KKT_PROF_REFACTOR_W256, s, [&] {
+                const int grid = nb + (int)blocks_for(mb, W256::kThreads / 16) + cb;
+                k_refactor_wide<W256><<<grid, W256::kThreads, W256::kLds, s>>>(i0, a, nb, s0, mb, c0, c1);
+            });
+        else if (nb)
             timed(h, KKT_PROF_REFACTOR_LARGE, s, [&] {
-                const int grid = nb + (int)blocks_for(mb, BigCfg::kThreads / 16) + cb;
-                k_refactor_wide<BigCfg><<<grid, BigCfg::kThreads, BigCfg::kLds, s>>>(i0, a, nb, s0, mb, c0, c1);
+                const int grid = nb + (int)blocks_for(mb, Big::kThreads / 16) + cb;
+                k_refactor_wide<Big><<<grid, Big::kThreads, Big::kLds, s>>>(i0, a, nb, s0, mb, c0, c1);
             });
         if (nm)
             timed(h, KKT_PROF_REFACTOR_MEDIUM, s, [&] {
-                const int grid = nm + (int)blocks_for(mm, MedCfg::kThreads / 16) + (nb ? 0 : cb);
-                k_refactor_wide<MedCfg><<<grid, MedCfg::kThreads, MedCfg::kLds, s>>>(i0 + nb, a, nm, s0, mm,
-                                                                                    nb ? 0 : c0, nb ? 0 : c1);
+                const int grid = nm + (int)blocks_for(mm, Med::kThreads / 16) + (nb ? 0 : cb);
+                k_refactor_wide<Med><<<grid, Med::kThreads, Med::kLds, s>>>(i0 + nb, a, nm, s0, mm, nb ? 0 : c0,
+                                                                          nb ? 0 : c1);
             });
     }
     {
@@ -334,11 +385,15 @@ int enqueue_levels(kkt_handle *h, hipStream_t s) {
         const int q0 = ncopy > 0 ? g.copy_ptr.back() : 0, q1 = (int)g.copy_k.size();
         if (q1 > q0)
             timed(h, KKT_PROF_TO_CSR, s,
-                  [&] { k_to_csr<<<blocks_for(q1 - q0, 256), 256, 0, s>>>(q0, q1, d.copy_k, d.csr_src, d.lu, d.lucsr); });
+                  [&] { k_to_csr<T><<<blocks_for(q1 - q0, 256), 256, 0, s>>>(q0, q1, d.copy_k, d.csr_src, a.lu, a.lucsr); });
     }
     timed(h, KKT_PROF_UPDATE, s, [&] { k_sum_counts<<<1, 256, 0, s>>>(d.pcount, &d.st->perturbed); });
     HIPCHK(hipGetLastError());
     return KKT_OK;
+}
+
+int enqueue_levels(kkt_handle *h, hipStream_t s) {
+    return by_precision(h, [&](auto tag) { return enqueue_levels_t<decltype(tag)>(h, s); });
 }
 
 // dst[0..nv) = V[0..nv) . w  (deterministic two-pass reduction)
@@ -371,23 +426,27 @@ int residual_berr(kkt_handle *h, const double *x, const double *b, double *berr,
     return KKT_OK;
 }
 
-// Preconditioner application inside refinement with `sweeps` Jacobi sweeps per triangle
-// instead of the exact solves: L from y = bp, U from x = D^-1 y.  The exact solve's helper
-// sums (psum, usum) serve as the second iterate buffers.
-int enqueue_approx_solve(kkt_handle *h, const double *b, double *x, int sweeps, hipStream_t s) {
+// Approximate preconditioner application: `sweeps` sweeps per triangle, each triangle from
+// the zero vector, Jacobi (kind 0) or block Gauss-Seidel over chunks of kGsChunk rows
+// (kind 1).  The exact solve's helper sums (psum, usum) serve as second iterate buffers.
+template <class TF>
+int enqueue_approx_solve_t(kkt_handle *h, const double *b, double *x, int sweeps, hipStream_t s) {
     const Dev &d = h->d;
+    const TF *lucsr = static_cast<const TF *>(d.lucsr);
     const int n = h->sym.n;
+    const bool gs = h->opts.approx_kind == 1;
     const unsigned nb8 = blocks_for((int64_t)n * 8, 256), nb = blocks_for(n, 256);
+    const unsigned nch = blocks_for(n, kGsChunk);
     timed(h, KKT_PROF_LSOLVE, s, [&] {
-        k_solve_reset<<<nb, 256, 0, s>>>(n, b, d.r, d.P, d.bp, d.y, d.xt, d.psum, d.usum, 0);
+        k_solve_reset<<<nb, 256, 0, s>>>(n, b, d.r, d.P, d.bp, d.y, d.xt, d.psum, d.usum, 0, d.tick);
     });
-    const double *yin = d.bp;
+    const double *yin = nullptr;
     double *ybuf[2] = {d.psum, d.y};
     for (int k = 0; k < sweeps; ++k) {
         double *yout = ybuf[k & 1];
         timed(h, KKT_PROF_LSOLVE, s, [&] {
-            k_jacobi_l<<<nb8, 256, 0, s>>>(n, d.rinfo4, d.csr_col, d.lucsr, d.bp,
-                                           yin, yout);
+            if (gs) k_bgs_l<TF><<<nch, kBlock, 0, s>>>(n, d.rinfo4, d.csr_col, lucsr, d.bp, yin, yout);
+            else k_jacobi_l<TF><<<nb8, 256, 0, s>>>(n, d.rinfo4, d.csr_col, lucsr, d.bp, yin, yout);
         });
         yin = yout;
     }
@@ -396,14 +455,18 @@ int enqueue_approx_solve(kkt_handle *h, const double *b, double *x, int sweeps, 
     for (int k = 0; k < sweeps; ++k) {
         double *xout = xbuf[k & 1];
         timed(h, KKT_PROF_USOLVE, s, [&] {
-            k_jacobi_u<<<nb8, 256, 0, s>>>(n, d.urinfo4, d.csr_col, d.lucsr, yin,
-                                           xin, xout, k == 0 ? 1 : 0);
+            if (gs) k_bgs_u<TF><<<nch, kBlock, 0, s>>>(n, d.urinfo4, d.csr_col, lucsr, yin, xin, xout);
+            else k_jacobi_u<TF><<<nb8, 256, 0, s>>>(n, d.urinfo4, d.csr_col, lucsr, yin, xin, xout);
         });
         xin = xout;
     }
     timed(h, KKT_PROF_USOLVE, s, [&] { k_unpermute<<<nb, 256, 0, s>>>(n, d.Q, d.c, xin, x); });
     HIPCHK(hipGetLastError());
     return KKT_OK;
+}
+
+int enqueue_approx_solve(kkt_handle *h, const double *b, double *x, int sweeps, hipStream_t s) {
+    return by_precision(h, [&](auto tag) { return enqueue_approx_solve_t<decltype(tag)>(h, b, x, sweeps, s); });
 }
 
 int fgmres_column(kkt_handle *h, const double *b, double *x, kkt_info *info, hipStream_t s) {
@@ -509,6 +572,9 @@ void kkt_default_opts(kkt_opts *o) {
     o->persistent_solve = 1;
     o->graph_refactor = 1;
     o->approx_sweeps = 0;
+    o->factor_precision = KKT_FP64;
+    o->tiny_pivot_fp32 = std::ldexp(1.0, -26);
+    o->approx_kind = 0;
 }
 
 int kkt_analyze(int32_t n, const int64_t *rowptr, const int32_t *colind, const double *values_k1,
@@ -519,14 +585,16 @@ int kkt_analyze(int32_t n, const int64_t *rowptr, const int32_t *colind, const d
     kkt_default_opts(&o);
     if (opts) o = *opts;
     if (o.gmres_restart < 1 || o.gmres_restart > kMaxRestart || o.max_iters < 0 || !(o.berr_tol >= 0.0) ||
-        !(o.tiny_pivot >= 0.0) || o.approx_sweeps < 0 || o.approx_sweeps > kMaxSweeps)
+        !(o.tiny_pivot >= 0.0) || o.approx_sweeps < 0 || o.approx_sweeps > kMaxSweeps ||
+        (o.factor_precision != KKT_FP64 && o.factor_precision != KKT_FP32) || !(o.tiny_pivot_fp32 >= 0.0) ||
+        (o.approx_kind != 0 && o.approx_kind != 1) || o.persistent_solve < 0 || o.persistent_solve > 2)
         return KKT_ERR_ARG;
     kkt_handle *h = new (std::nothrow) kkt_handle;
     if (!h) return KKT_ERR_NOMEM;
     int rc;
     try {
         rc = analyze_symbolic(n, rowptr, colind, values_k1, o, h->sym);
-        if (rc == KKT_OK) rc = build_schedule(h->sym, h->sch);
+        if (rc == KKT_OK) rc = build_schedule(h->sym, SchedParams{}, h->sch);
     } catch (const std::bad_alloc &) {
         rc = KKT_ERR_NOMEM;
     }
@@ -537,6 +605,25 @@ int kkt_analyze(int32_t n, const int64_t *rowptr, const int32_t *colind, const d
     o.fixed_p = nullptr;   // borrowed for the call only
     o.fixed_q = nullptr;
     h->opts = o;
+    h->tickets = o.persistent_solve == 2;
+    *out = h;
+    return KKT_OK;
+}
+
+int kkt_clone(const kkt_handle *src, kkt_handle **out) {
+    if (!src || !out) return KKT_ERR_ARG;
+    *out = nullptr;
+    kkt_handle *h = new (std::nothrow) kkt_handle;
+    if (!h) return KKT_ERR_NOMEM;
+    try {
+        h->opts = src->opts;
+        h->sym = src->sym;
+        h->sch = src->sch;
+        h->tickets = src->opts.persistent_solve == 2;
+    } catch (const std::bad_alloc &) {
+        delete h;
+        return KKT_ERR_NOMEM;
+    }
     *out = h;
     return KKT_OK;
 }
@@ -562,6 +649,7 @@ int kkt_get_stats(const kkt_handle *h, kkt_stats *out) {
     out->nnz_lu_wide = h->sch.nnz_lu_wide;
     out->nnz_lu_medium = h->sch.nnz_lu_med;
     out->copy_in_levels = h->sch.copy_ptr.empty() ? 0 : h->sch.copy_ptr.back();
+    out->nnz_lu_w256 = h->sch.nnz_lu_w256;
     return KKT_OK;
 }
 
@@ -626,21 +714,30 @@ int bind_common(kkt_handle *h, char *ws, size_t bytes, int32_t max_nrhs, hipStre
     HIPCHK(hipGetDevice(&dev));
     int ncu = 0;
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_refactor_wide<BigCfg>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, BigCfg::kLds));
-    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_refactor_wide<MedCfg>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, MedCfg::kLds));
-    {
-        int coop = 0, bl = 0, bu = 0;
-        HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
-        if (!coop && h->opts.persistent_solve) return KKT_ERR_DEVICE;
-        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bl, reinterpret_cast<const void *>(&k_lsolve_persistent),
-                                                            kBlock, 0));
-        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bu, reinterpret_cast<const void *>(&k_usolve_persistent),
-                                                            kBlock, 0));
+    const int ok = by_precision(h, [&](auto tag) {
+        using T = decltype(tag);
+        int bl = 0, bu = 0;
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_refactor_wide<BigCfg<T>>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, BigCfg<T>::kLds) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_refactor_wide<W256Cfg<T>>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, W256Cfg<T>::kLds) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_refactor_wide<MedCfg<T>>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, MedCfg<T>::kLds) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &bl, reinterpret_cast<const void *>(&k_lsolve_persistent<T, false>), kBlock, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &bu, reinterpret_cast<const void *>(&k_usolve_persistent<T, false>), kBlock, 0) != hipSuccess)
+            return -1;
         h->grid_l = std::max(1, bl) * std::max(1, ncu);
         h->grid_u = std::max(1, bu) * std::max(1, ncu);
-        h->ncu = std::max(1, ncu);
+        return 0;
+    });
+    if (ok != 0) return KKT_ERR_DEVICE;
+    h->ncu = std::max(1, ncu);
+    {
+        int coop = 0;
+        HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        if (!coop) h->tickets = true;   // the fixed item order needs a cooperative launch
     }
     if (h->device >= 0 && h->device != dev) return KKT_ERR_STATE;   // rebinding keeps the device
     h->device = dev;
@@ -827,6 +924,24 @@ int kkt_solve(kkt_handle *h, const double *d_b, double *d_x, int32_t nrhs, int64
     return KKT_OK;
 }
 
+int kkt_solve_approx(kkt_handle *h, const double *d_b, double *d_x, int32_t nrhs, int64_t ld, hipStream_t stream) {
+    if (!h || !d_b || !d_x || nrhs < 1 || ld < h->sym.n || h->opts.approx_sweeps < 1) return KKT_ERR_ARG;
+    if (!h->factored) return KKT_ERR_STATE;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return KKT_ERR_DEVICE;
+    for (int32_t j = 0; j < nrhs; ++j) {
+        const double *b = d_b + (size_t)j * ld;
+        double *x = d_x + (size_t)j * ld;
+        if (b == x) {   // the sweeps read b after x is written
+            HIPCHK(hipMemcpyAsync(h->d.bsave, b, sizeof(double) * h->sym.n, hipMemcpyDeviceToDevice, stream));
+            b = h->d.bsave;
+        }
+        const int rc = enqueue_approx_solve(h, b, x, h->opts.approx_sweeps, stream);
+        if (rc) return rc;
+    }
+    return KKT_OK;
+}
+
 int kkt_refine(kkt_handle *h, const double *d_b, double *d_x, int32_t nrhs, int64_t ld, kkt_info *info,
                hipStream_t stream) {
     if (!h || !d_b || !d_x || nrhs < 1 || ld < h->sym.n) return KKT_ERR_ARG;
@@ -858,12 +973,151 @@ int kkt_refine(kkt_handle *h, const double *d_b, double *d_x, int32_t nrhs, int6
     return worst;
 }
 
+int kkt_get_tuning(const kkt_handle *h, kkt_tuning *t) {
+    if (!h || !t) return KKT_ERR_ARG;
+    t->panel_max = h->sch.params.panel_max;
+    t->small_rows = h->sch.params.small_rows;
+    t->group = h->sch.params.group;
+    t->wide256 = h->sch.params.wide256;
+    return KKT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// drops the device binding of h (after its last work finished): the recorded graph goes,
+// the workspace is no longer used
+int unbind(kkt_handle *h) {
+    if (h->levels) {
+        HIPCHK(hipEventSynchronize(h->levels_done));
+        HIPCHK(hipGraphExecDestroy(h->levels));
+        h->levels = nullptr;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        release_scratch_locked(h);
+    }
+    h->bound = false;
+    h->factored = false;
+    h->ws = nullptr;
+    return KKT_OK;
+}
+
+int set_schedule(kkt_handle *h, const SchedParams &p) {
+    Schedule g;
+    int rc;
+    try {
+        rc = build_schedule(h->sym, p, g);
+    } catch (const std::bad_alloc &) {
+        rc = KKT_ERR_NOMEM;
+    }
+    if (rc != KKT_OK) return rc;
+    h->sch = std::move(g);
+    return KKT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kkt_set_tuning(kkt_handle *h, const kkt_tuning *t) {
+    if (!h || !t) return KKT_ERR_ARG;
+    if (h->device >= 0) {
+        DeviceGuard dg(h->device);
+        if (!dg.ok) return KKT_ERR_DEVICE;
+        const int rc = unbind(h);
+        if (rc) return rc;
+    }
+    return set_schedule(h, SchedParams{t->panel_max, t->small_rows, t->group, t->wide256});
+}
+
+int kkt_autotune(kkt_handle *h, const double *d_values, int32_t reps, kkt_tuning *best, double *best_ms,
+                 hipStream_t stream) {
+    if (!h || !d_values || reps < 1) return KKT_ERR_ARG;
+    if (h->device >= 0) {
+        DeviceGuard dg(h->device);
+        if (!dg.ok) return KKT_ERR_DEVICE;
+        const int rc = unbind(h);
+        if (rc) return rc;
+    }
+    const SchedParams start = h->sch.params;
+    SchedParams win = start;
+    double win_ms = INFINITY;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int rc = KKT_OK;
+    for (int32_t pm : {32, 16, 8})
+        for (int32_t sr : {64, 32})
+            for (int32_t gr : {32, 16})
+            for (int32_t w2 : {1, 0}) {
+                rc = set_schedule(h, SchedParams{pm, sr, gr, w2});
+                if (rc == KKT_ERR_SCHEDULE) { rc = KKT_OK; continue; }   // not a valid cut for this pattern
+                if (rc) break;
+                size_t bytes = 0;
+                Dev probe{};
+                carve(h, nullptr, probe, &bytes);
+                void *ws = nullptr;
+                if (hipMalloc(&ws, bytes) != hipSuccess) { rc = KKT_ERR_NOMEM; break; }
+                float ms = 0.0f;
+                rc = bind_common(h, static_cast<char *>(ws), bytes, 1, stream, false);
+                if (!rc) rc = kkt_refactor(h, d_values, stream);   // records the graph
+                if (!rc && hipEventRecord(e0, stream) != hipSuccess) rc = KKT_ERR_DEVICE;
+                for (int32_t k = 0; k < reps && !rc; ++k) rc = kkt_refactor(h, d_values, stream);
+                if (!rc && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    rc = KKT_ERR_DEVICE;
+                if (!rc) {
+                    int64_t pert = 0;
+                    const int st = kkt_refactor_status(h, &pert, stream);
+                    if (st < 0) rc = st;
+                }
+                (void)hipStreamSynchronize(stream);
+                const int urc = unbind(h);
+                (void)hipFree(ws);
+                if (rc) break;
+                if (urc) { rc = urc; break; }
+                if (ms / reps < win_ms) {
+                    win_ms = ms / reps;
+                    win = SchedParams{pm, sr, gr, w2};
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const int rc2 = set_schedule(h, rc ? start : win);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    if (best) {
+        best->panel_max = win.panel_max;
+        best->small_rows = win.small_rows;
+        best->group = win.group;
+        best->wide256 = win.wide256;
+    }
+    if (best_ms) *best_ms = win_ms;
+    return KKT_OK;
+}
+
 int kkt_export_factors(kkt_handle *h, double *h_lu, double *h_r, double *h_c, hipStream_t stream) {
     if (!h || !h_lu) return KKT_ERR_ARG;
     if (!h->factored) return KKT_ERR_STATE;
     DeviceGuard dg(h->device);
     if (!dg.ok) return KKT_ERR_DEVICE;
-    HIPCHK(hipMemcpyAsync(h_lu, h->d.lu, sizeof(double) * h->sym.nnz_lu(), hipMemcpyDeviceToHost, stream));
+    const size_t nlu = (size_t)h->sym.nnz_lu();
+    if (h->opts.factor_precision == KKT_FP32) {
+        // FP32 factors are widened (exactly) into the caller's FP64 array
+        std::vector<float> tmp;
+        try {
+            tmp.resize(nlu);
+        } catch (const std::bad_alloc &) {
+            return KKT_ERR_NOMEM;
+        }
+        HIPCHK(hipMemcpyAsync(tmp.data(), h->d.lu, sizeof(float) * nlu, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        for (size_t k = 0; k < nlu; ++k) h_lu[k] = (double)tmp[k];
+    } else {
+        HIPCHK(hipMemcpyAsync(h_lu, h->d.lu, sizeof(double) * nlu, hipMemcpyDeviceToHost, stream));
+    }
     if (h_r) HIPCHK(hipMemcpyAsync(h_r, h->d.r, sizeof(double) * h->sym.n, hipMemcpyDeviceToHost, stream));
     if (h_c) HIPCHK(hipMemcpyAsync(h_c, h->d.c, sizeof(double) * h->sym.n, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
@@ -928,3 +1182,4 @@ const char *kkt_strerror(int status) {
 }
 
 }  // extern "C"
+#include "kkt_batch.hip"

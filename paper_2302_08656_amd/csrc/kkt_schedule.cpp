@@ -1,7 +1,7 @@
 // Device schedule of the refactorization and of the triangular solves, built once per
 // pattern on the host (the one-time data movement and mapping of Section III).
 //
-// Panels.  Each structural supernode is cut into panels of at most kPanelMax consecutive
+// Panels.  Each structural supernode is cut into panels of at most panel_max consecutive
 // columns.  Every column j of a panel [s, e) has the L rows {j+1..e-1} followed by the
 // panel's common rows R below e-1, and every row of the panel has the same U columns C to
 // the right of e-1; consequently each column k in C holds the rows s..e-1 consecutively.
@@ -27,15 +27,20 @@
 
 namespace kkt {
 
-int build_schedule(const Symbolic &s, Schedule &g) {
+int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
     const int32_t n = s.n;
+    if (prm.panel_max < 1 || prm.panel_max > kPanelMax || prm.small_rows < 0 || prm.small_rows > kSmallR ||
+        prm.group < 1 || prm.group > kGroup || (prm.wide256 != 0 && prm.wide256 != 1))
+        return KKT_ERR_ARG;
+    g = Schedule{};
+    g.params = prm;
     const int64_t nlu = s.nnz_lu();
     if (nlu >= INT32_MAX || s.nnz_a >= INT32_MAX) return KKT_ERR_ARG;   // int32 slots on the device
     // panels
     g.pan_start.clear();
     for (int32_t t = 0; t + 1 < (int32_t)s.sn_start.size(); ++t) {
         const int32_t a = s.sn_start[t], b = s.sn_start[t + 1], w = b - a;
-        const int32_t m = (w + kPanelMax - 1) / kPanelMax;
+        const int32_t m = (w + prm.panel_max - 1) / prm.panel_max;
         for (int32_t q = 0; q < m; ++q) g.pan_start.push_back(a + (int32_t)((int64_t)w * q / m));
     }
     g.pan_start.push_back(n);
@@ -110,10 +115,11 @@ int build_schedule(const Symbolic &s, Schedule &g) {
     std::vector<std::vector<int32_t>> panels_at(nlev);
     for (int32_t p = 0; p < np; ++p) panels_at[plev[p]].push_back(p);
     auto pw = [&](int32_t p) { return g.pan_start[p + 1] - g.pan_start[p]; };
-    auto is_small = [&](int32_t p) { return pw(p) <= kSmallW && g.pan_r[p] <= kSmallR; };
+    auto is_small = [&](int32_t p) { return pw(p) <= kSmallW && g.pan_r[p] <= prm.small_rows; };
     g.f_lvl.assign(1, 0);
     g.f_nlarge.clear();
     g.f_nmed.clear();
+    g.f_w256.clear();
     g.f_item_panel.clear();
     g.f_item_pair.assign(1, 0);
     g.f_pair_src.clear();
@@ -127,7 +133,7 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         std::vector<std::pair<int32_t, int32_t>> pairs;   // (source, target)
         bool small;
         double cost;
-        int kind = 0;   // 0 wide (up to kPanelMax columns), 1 medium, 2 narrow
+        int kind = 0;   // 0 wide (up to panel_max columns), 1 medium, 2 narrow
     };
     for (int32_t l = 0; l < nlev; ++l) {
         auto &pl = by_launch[l];                  // (target, source)
@@ -159,7 +165,7 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         std::sort(single.begin(), single.end());
         for (size_t q = 0; q < single.size();) {
             const int32_t S = single[q].first;
-            const size_t cap = is_small(S) ? 1 : kGroup;
+            const size_t cap = is_small(S) ? 1 : (size_t)prm.group;
             Item it{-1, {}, true, 0.0};
             size_t q1 = q;
             while (q1 < single.size() && single[q1].first == S && q1 - q < cap) it.pairs.push_back(single[q1++]);
@@ -181,11 +187,15 @@ int build_schedule(const Symbolic &s, Schedule &g) {
         }
         // the medium configuration only where a level has no item that needs the big one
         // (one launch per level for the wide items)
-        bool any_big = false;
-        for (const auto &it : items) any_big |= it.kind == 0;
+        bool any_big = false, fit256 = true;
+        for (const auto &it : items) {
+            any_big |= it.kind == 0;
+            if (it.kind == 0 && it.panel >= 0 && pw(it.panel) + g.pan_r[it.panel] > kW256Rows) fit256 = false;
+        }
         if (any_big)
             for (auto &it : items)
                 if (it.kind == 1) it.kind = 0;
+        g.f_w256.push_back(any_big && fit256 && prm.wide256 ? 1 : 0);
         for (int32_t T : panels_at[l]) fac_index[T] = -1;
         std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
             if (a.kind != b.kind) return a.kind < b.kind;
@@ -504,7 +514,7 @@ int build_schedule(const Symbolic &s, Schedule &g) {
     // per launch kind: the 512-thread launch of a level factors its wide items and its narrow
     // ones, the 256-thread launch its medium items and (with no 512-thread launch) the narrow
     // ones; levels without wide items have a narrow launch
-    g.nnz_lu_wide = g.nnz_lu_med = 0;
+    g.nnz_lu_wide = g.nnz_lu_med = g.nnz_lu_w256 = 0;
     for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
         const int32_t nm = g.f_nmed[l], nb = g.f_nlarge[l] - nm;
         for (int32_t it = g.f_lvl[l]; it < g.f_lvl[l + 1]; ++it) {
@@ -512,7 +522,7 @@ int build_schedule(const Symbolic &s, Schedule &g) {
             if (P < 0) continue;
             const int64_t e = s.colptr[g.pan_start[P + 1]] - s.colptr[g.pan_start[P]];
             const bool med = (it >= g.f_lvl[l] + nb && it < g.f_lvl[l] + nb + nm) || (nb == 0 && nm > 0);
-            if (nb > 0 && !med) g.nnz_lu_wide += e;
+            if (nb > 0 && !med) (g.f_w256[l] ? g.nnz_lu_w256 : g.nnz_lu_wide) += e;
             else if (med) g.nnz_lu_med += e;
         }
     }

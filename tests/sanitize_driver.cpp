@@ -36,7 +36,13 @@ int main(int argc, char **argv) {
     kkt::Symbolic s;
     kkt::Schedule g;
     int rc = kkt::analyze_symbolic(n, rowptr.data(), colind.data(), vals.data(), o, s);
-    if (rc == KKT_OK) rc = kkt::build_schedule(s, g);
+    if (rc == KKT_OK) rc = kkt::build_schedule(s, kkt::SchedParams{}, g);
+    // the other tunable schedules too (narrow panels, fewer narrow rows, small groups)
+    for (int32_t pm : {8, 16})
+        if (rc == KKT_OK) {
+            kkt::Schedule g2;
+            rc = kkt::build_schedule(s, kkt::SchedParams{pm, 32, 8}, g2);
+        }
     std::printf("%d %d %lld %d %zu %zu %zu\n", rc, n, (long long)s.nnz_lu(), g.npan, g.f_item_panel.size(),
                 g.l_item4.size() / 4, g.u_item4.size() / 4);
     return 0;

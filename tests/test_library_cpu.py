@@ -172,3 +172,26 @@ def test_scratch_bind_host_checks():
     assert L.kkt_bind_scratch(sb._h, 1, None) == K.ERR_NOMEM
     # still unbound: no state changed
     assert L.kkt_refactor(sb._h, ctypes.c_void_p(256), None) == K.ERR_STATE
+
+
+def test_precision_and_sweep_options():
+    """The FP32 factor option and the sweep kind: defaults, rejected values, the smaller
+    workspace of FP32 factors, and the call-order errors of kkt_solve_approx."""
+    o = K.default_opts()
+    assert o["factor_precision"] == K.FP64 and o["tiny_pivot_fp32"] == 2.0 ** -26 and o["approx_kind"] == 0
+    q = kktgen.make_sequence(kktgen.small(30, config_id=134))
+    for kw in ({"factor_precision": 2}, {"factor_precision": -1}, {"approx_kind": 2}, {"tiny_pivot_fp32": -1.0}):
+        with pytest.raises(K.KKTError) as e:
+            K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0), **kw)
+        assert e.value.code == K.ERR_ARG, kw
+    s64 = K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0))
+    s32 = K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0), factor_precision=K.FP32)
+    assert s32.opts["factor_precision"] == K.FP32
+    # the factor and its row-ordered copy shrink from 8 to 4 bytes per entry
+    assert s64.workspace_bytes(1) - s32.workspace_bytes(1) >= 8 * s64.nnz_lu - 2 * 256
+    L = K._lib()
+    dummy = ctypes.c_void_p(256)
+    sa = K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0), approx_sweeps=2, approx_kind=1)
+    assert L.kkt_solve_approx(sa._h, dummy, dummy, 1, q.n, None) == K.ERR_STATE
+    assert L.kkt_solve_approx(s64._h, dummy, dummy, 1, q.n, None) == K.ERR_ARG   # no sweeps configured
+    assert L.kkt_solve_approx(sa._h, dummy, dummy, 0, q.n, None) == K.ERR_ARG
