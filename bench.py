@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--precision", choices=("fp64", "fp32"), default=None,
                     help="factor storage and refactorization precision (refinement stays FP64); default "
                          "fp64 for the grid workloads, fp32 for the batched one")
+    ap.add_argument("--solve-mode", choices=("fixed", "ticket", "levels"), default="fixed",
+                    help="triangular solves: persistent launch with fixed item order (default), with "
+                         "ticket order, or one launch per level")
     ap.add_argument("--workload", choices=("grid", "batch", "serve"), default="grid",
                     help="grid: one grid's refactor+solve sequence (--config); batch: 64 systems of 8 "
                          "patterns (1k-10k buses) refactored together; serve: Poisson request streams "
@@ -376,7 +379,8 @@ def main():
     t0 = time.perf_counter()
     fp32 = args.precision == "fp32"
     sk = K.KKTSolver(q.n, q.rowptr, q.colind, vals[0], approx_sweeps=args.approx_sweeps,
-                     factor_precision=K.FP32 if fp32 else K.FP64)
+                     factor_precision=K.FP32 if fp32 else K.FP64,
+                     persistent_solve={"fixed": 1, "ticket": 2, "levels": 0}[args.solve_mode])
     t_analyze = time.perf_counter() - t0
     st = sk.stats
     print(f"[bench] analyze {t_analyze:.2f}s nnz_lu={st['nnz_lu']} levels={st['levels_f']} "
@@ -491,7 +495,8 @@ def main():
                    "timed_order": f"system (i * {stride}) mod {T} for unit i = 0..{args.steps - 1}",
                    "timed_systems": (f"all {T}" if len(timed) == T else timed),
                    "refinement_preconditioner": (f"{args.approx_sweeps} Jacobi sweeps per triangle"
-                                                 if args.approx_sweeps else "exact triangular solves")},
+                                                 if args.approx_sweeps else "exact triangular solves"),
+                   "solve_mode": args.solve_mode},
         "p50_ms": round(nearest_rank(lat, 50), 4), "p99_ms": round(nearest_rank(lat, 99), 4),
         "failures": fails, "fgmres_iters_mean": round(float(np.mean(iters)), 3),
         "berr_max": float(np.max(berrs)),

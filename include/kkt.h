@@ -260,14 +260,20 @@ int kkt_export_factors(kkt_handle *h, double *h_lu, double *h_r, double *h_c,
  *   small_rows narrow 16-lane path for panels of <= 4 columns and <= small_rows rows below
  *              (0..64; default 64);
  *   group      targets of one source panel grouped into one pull item (1..32; default 32);
- *   wide256    1 = a level whose wide items all factor panels of at most 256 rows runs them
- *              in 256-thread blocks (two per compute unit) instead of 512-thread blocks
- *              (default 1), 0 = always 512. */
+ *   wide256    1 = a level with at least 256 wide items, all factoring panels of at most 256
+ *              rows, runs them in 256-thread blocks (two per compute unit) instead of
+ *              512-thread blocks (default), 0 = always 512;
+ *   fuse_chains 1 = consecutive panels of one supernode are factored by one item (with the
+ *              pulls between them) whenever no outside dependency would wait for it, so a
+ *              wide supernode costs one launch instead of one per panel; 0 = one panel per
+ *              item (default: on the grid workloads the fused items serialise trailing
+ *              updates that separate items run in parallel). */
 typedef struct {
     int32_t panel_max;
     int32_t small_rows;
     int32_t group;
     int32_t wide256;
+    int32_t fuse_chains;
 } kkt_tuning;
 
 /* The handle's current schedule choices. */
@@ -279,7 +285,7 @@ int kkt_get_tuning(const kkt_handle *h, kkt_tuning *t);
 int kkt_set_tuning(kkt_handle *h, const kkt_tuning *t);
 
 /* Autotuner of the schedule: for each candidate (panel_max 32/16/8, small_rows 64/32,
- * group 32/16, wide256 1/0) builds the schedule, binds a temporary workspace (allocated and freed
+ * group 32/16, wide256 1/0, fuse_chains 0/1) builds the schedule, binds a temporary workspace (allocated and freed
  * here), refactors d_values (device FP64[nnz_a]) once and then reps times under HIP
  * events on stream, and keeps the fastest; returns with that schedule set and the handle
  * unbound (bind again).  best / best_ms (host, may be NULL) receive the choice and its

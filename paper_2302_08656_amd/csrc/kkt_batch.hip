@@ -143,7 +143,8 @@ BatchSys<T> batch_sys(const kkt_handle *h) {
     BatchSys<T> b{};
     b.ref = RefArgs<T>{d.ldiag, d.item8, d.pair8, d.f_rel, static_cast<T *>(d.lu), d.st, d.pcount,
                        std::is_same<T, float>::value ? h->opts.tiny_pivot_fp32 : h->opts.tiny_pivot,
-                       h->opts.dense_mfma != 0, d.copy_k, d.csr_src, static_cast<T *>(d.lucsr)};
+                       h->opts.dense_mfma != 0, d.copy_k, d.csr_src, static_cast<T *>(d.lucsr),
+                       d.pan_start, d.pan_r};
     b.a_rowptr = d.a_rowptr;
     b.a_colind = d.a_colind;
     b.a_cptr = d.a_cptr;

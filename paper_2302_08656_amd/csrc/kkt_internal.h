@@ -50,8 +50,11 @@ constexpr int kSmallR = 64;
 constexpr int kGroup = 32;
 constexpr int kMedW = 16;
 constexpr int kMedRows = 256;
-// rows of a factored panel up to which a 32-column wide item runs in a 256-thread block
+// rows of a factored panel up to which a 32-column wide item runs in a 256-thread block, and
+// the wide items a level needs for its launch to use 256-thread blocks (two per compute
+// unit): levels with fewer are bound by one item's latency, which 512 threads shorten
 constexpr int kW256Rows = 256;
+constexpr int kW256MinItems = 256;
 // Solve helpers: a wide panel gets helper items kHelpAhead levels before it when one of
 // its rows has at least kHelpMin early entries (columns of panels more than kHelpAhead
 // levels below); each helper item sums the early entries of kHelpRows rows.
@@ -70,7 +73,8 @@ struct SchedParams {
     int32_t panel_max = kPanelMax;   // widest panel cut from a supernode (1..kPanelMax)
     int32_t small_rows = kSmallR;    // narrow path: panels of <= kSmallW columns and <= this many rows below
     int32_t group = kGroup;          // targets of one source grouped into one pull item (1..kGroup)
-    int32_t wide256 = 1;             // levels whose wide items all fit 256 rows use 256-thread blocks
+    int32_t wide256 = 1;             // levels with many wide items, all fitting 256 rows, use 256-thread blocks
+    int32_t fuse_chains = 0;         // consecutive panels of a supernode factored by one item when possible
 };
 
 // Device schedule, built on the host once per pattern and uploaded by kkt_bind.
@@ -94,14 +98,16 @@ struct Schedule {
     // - 1) copies copy_k[copy_ptr[c] .. copy_ptr[c+1]), the copy after the last level the rest
     int32_t copy_lvl = 0;
     std::vector<int32_t> copy_k, copy_ptr;
-    std::vector<int32_t> f_item_panel;  // panel to factor after the pulls, or -1
+    std::vector<int32_t> f_item_panel;  // (first) panel to factor after the pulls, or -1
+    std::vector<int32_t> f_item_npan;   // panels factored by the item (consecutive, one supernode)
     std::vector<int32_t> f_item_pair;   // [nitems+1] range into f_pair_src / f_pair_tgt
     std::vector<int32_t> f_pair_src, f_pair_tgt;
     std::vector<int32_t> f_pair_pos;    // slot of the source's first row in the target column
     std::vector<int64_t> f_pair_rel;    // [npairs+1] range into f_rel
     std::vector<int32_t> f_rel;         // slot of each row R of the source in the target column
     // packed records read by the refactorization kernels (8 x int32 each):
-    // item8[i] = {panel to factor or -1, first pair, end pair, 0, s, w, r, ldiag[s]};
+    // item8[i] = {panel to factor or -1, first pair, end pair, panels factored, s, w, r,
+    //             ldiag[s]} (s, w, r of the first panel);
     // pair8[q] = {source panel, f_pair_pos, f_pair_rel (first index), target column,
     //             s, w, r, ldiag[s]}, with s, w, r the panel's first column, width, rows below;
     // for pairs of narrow items {ldiag[s+1], f_pair_pos, f_pair_rel, ldiag[s+2], ldiag[s+3],

@@ -263,8 +263,12 @@ template <> struct Pair<double> { using type = double2; };
 template <> struct Pair<float> { using type = float2; };
 
 // Packed 32-byte records (two int4 each):
-//   item[2i]   = {panel to factor or -1, first pair, end of pairs, 0}
+//   item[2i]   = {panel to factor or -1, first pair, end of pairs, panels factored}
 //   item[2i+1] = {its first column s, width w, rows below r, slot of the diagonal of column s}
+// An item that factors several panels (consecutive panels of one supernode) factors them in
+// order; its pairs list the pulls from outside first, then the pulls of each of its panels
+// into the later ones, by source: a panel is factored before the first pull whose source
+// it is, and after the pulls into it.
 //   pair[2q]   = {source panel, slot of the source's first row in the target column,
 //                 first index into rel, target column}
 //   pair[2q+1] = {source's first column, width, rows below, slot of its first diagonal}
@@ -286,6 +290,9 @@ struct RefArgs {
     const int32_t *copy_k;
     const int32_t *csr_src;
     T *lucsr;
+    // panel geometry (first column, rows below) for items that factor several panels
+    const int32_t *pan_start;
+    const int32_t *pan_r;
 };
 
 // the tiny-pivot threshold tiny * ||A~||_inf of the current refactorization, in T
@@ -771,18 +778,38 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs<typename
     int4 *prs = reinterpret_cast<int4 *>(sm + C::kOffPairs);
     const int4 ia = a.item[2 * item], ib = a.item[2 * item + 1];
     const int pbeg = ia.y, p1 = ia.z, npr = p1 - pbeg;
+    const int npan = ia.x >= 0 ? max(1, ia.w) : 0;
+    int done = 0;   // panels of the item factored so far
     const bool staged = npr <= kStagePairs;
-    // one round: the pair records and the slots of the panel to factor
+    // one round: the pair records and the slots of the (first) panel to factor
     if (staged)
         for (int t = tid; t < 2 * npr; t += C::kThreads) prs[t] = a.pair[2 * pbeg + t];
     if (ia.x >= 0 && tid < ib.y) sgs[tid] = a.ldiag[ib.x + tid] - tid;
     __syncthreads();
     auto pra = [&](int q) { return staged ? prs[2 * (q - pbeg)] : a.pair[2 * q]; };
     auto prb = [&](int q) { return staged ? prs[2 * (q - pbeg) + 1] : a.pair[2 * q + 1]; };
+    // factors the item's next panel (the first one's geometry is ib, the others' is read)
+    auto factor_next = [&]() {
+        int4 pn = ib;
+        if (done > 0) {
+            const int P = ia.x + done;
+            const int s0 = a.pan_start[P];
+            pn = int4{s0, a.pan_start[P + 1] - s0, a.pan_r[P], a.ldiag[s0]};
+            if (tid < pn.y) sgs[tid] = a.ldiag[s0 + tid] - tid;
+            __syncthreads();
+        }
+        large_factor<C>(a, pn, sm, thresh);
+        // the factored panel is read by the item's later pulls
+        __threadfence_block();
+        __syncthreads();
+        ++done;
+    };
     for (int g0 = pbeg, g1; g0 < p1; g0 = g1) {
         const int S = pra(g0).x;
+        // a pull from one of the item's own panels: factor the panels up to it first
+        while (done < npan && S >= ia.x + done && S < ia.x + npan) factor_next();
         g1 = g0 + 1;
-        while (g1 < p1 && pra(g1).x == S) ++g1;
+        while (g1 < p1 && pra(g1).x == S && g1 - g0 < kGroup) ++g1;
         const int4 pn = prb(g0);
         const int s = pn.x, w = pn.y, r = pn.z;
         if (tid < w) lds[tid] = tid == 0 ? pn.w : a.ldiag[s + tid];
@@ -914,7 +941,7 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs<typename
         __threadfence_block();
         __syncthreads();
     }
-    if (ia.x >= 0) large_factor<C>(a, ib, sm, thresh);
+    while (done < npan) factor_next();
 }
 
 // One launch per level: block b < nwide runs wide item item0 + b; the blocks after it run

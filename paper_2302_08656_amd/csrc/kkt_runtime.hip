@@ -340,7 +340,8 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s) {
     const Dev &d = h->d;
     const double tiny = std::is_same<T, float>::value ? h->opts.tiny_pivot_fp32 : h->opts.tiny_pivot;
     RefArgs<T> a{d.ldiag, d.item8, d.pair8, d.f_rel, static_cast<T *>(d.lu), d.st, d.pcount,
-                 tiny, h->opts.dense_mfma != 0, d.copy_k, d.csr_src, static_cast<T *>(d.lucsr)};
+                 tiny, h->opts.dense_mfma != 0, d.copy_k, d.csr_src, static_cast<T *>(d.lucsr),
+                 d.pan_start, d.pan_r};
     const int ncopy = (int)g.copy_ptr.size() - 1;   // launches that carry a chunk of the copy
     for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
         // the kinds of items of a level touch disjoint target columns, so one launch runs the
@@ -979,6 +980,7 @@ int kkt_get_tuning(const kkt_handle *h, kkt_tuning *t) {
     t->small_rows = h->sch.params.small_rows;
     t->group = h->sch.params.group;
     t->wide256 = h->sch.params.wide256;
+    t->fuse_chains = h->sch.params.fuse_chains;
     return KKT_OK;
 }
 
@@ -1029,7 +1031,7 @@ int kkt_set_tuning(kkt_handle *h, const kkt_tuning *t) {
         const int rc = unbind(h);
         if (rc) return rc;
     }
-    return set_schedule(h, SchedParams{t->panel_max, t->small_rows, t->group, t->wide256});
+    return set_schedule(h, SchedParams{t->panel_max, t->small_rows, t->group, t->wide256, t->fuse_chains});
 }
 
 int kkt_autotune(kkt_handle *h, const double *d_values, int32_t reps, kkt_tuning *best, double *best_ms,
@@ -1051,8 +1053,9 @@ int kkt_autotune(kkt_handle *h, const double *d_values, int32_t reps, kkt_tuning
     for (int32_t pm : {32, 16, 8})
         for (int32_t sr : {64, 32})
             for (int32_t gr : {32, 16})
-            for (int32_t w2 : {1, 0}) {
-                rc = set_schedule(h, SchedParams{pm, sr, gr, w2});
+            for (int32_t w2 : {1, 0})
+            for (int32_t fc : {0, 1}) {
+                rc = set_schedule(h, SchedParams{pm, sr, gr, w2, fc});
                 if (rc == KKT_ERR_SCHEDULE) { rc = KKT_OK; continue; }   // not a valid cut for this pattern
                 if (rc) break;
                 size_t bytes = 0;
@@ -1080,7 +1083,7 @@ int kkt_autotune(kkt_handle *h, const double *d_values, int32_t reps, kkt_tuning
                 if (urc) { rc = urc; break; }
                 if (ms / reps < win_ms) {
                     win_ms = ms / reps;
-                    win = SchedParams{pm, sr, gr, w2};
+                    win = SchedParams{pm, sr, gr, w2, fc};
                 }
             }
     (void)hipEventDestroy(e0);
@@ -1093,6 +1096,7 @@ int kkt_autotune(kkt_handle *h, const double *d_values, int32_t reps, kkt_tuning
         best->small_rows = win.small_rows;
         best->group = win.group;
         best->wide256 = win.wide256;
+        best->fuse_chains = win.fuse_chains;
     }
     if (best_ms) *best_ms = win_ms;
     return KKT_OK;

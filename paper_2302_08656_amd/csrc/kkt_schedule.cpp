@@ -30,7 +30,8 @@ namespace kkt {
 int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
     const int32_t n = s.n;
     if (prm.panel_max < 1 || prm.panel_max > kPanelMax || prm.small_rows < 0 || prm.small_rows > kSmallR ||
-        prm.group < 1 || prm.group > kGroup || (prm.wide256 != 0 && prm.wide256 != 1))
+        prm.group < 1 || prm.group > kGroup || (prm.wide256 != 0 && prm.wide256 != 1) ||
+        (prm.fuse_chains != 0 && prm.fuse_chains != 1))
         return KKT_ERR_ARG;
     g = Schedule{};
     g.params = prm;
@@ -80,18 +81,68 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
     // panel S with U(S, T) != 0 (its columns need S's update) and for every panel S with
     // L(T, S) != 0 (its rows of a later column must be updated by S before T's own update
     // of that column solves them); for symmetric patterns the two sets coincide.
-    std::vector<int32_t> plev(np, 0);
+    //
+    // Chains (fuse_chains): consecutive panels of one supernode form a chain of levels, one
+    // launch per panel.  A panel joins the group of the panel before it when every panel it
+    // waits for outside the group is at a level below the group's: the group's item then
+    // factors its panels in order and pulls each finished panel's update into the later
+    // panels itself (internal pairs, in the group's launch), so the chain costs one launch.
+    // Each group is at the level of its first panel; its panels share that level.
+    std::vector<int32_t> plev(np, 0), grp(np);
+    std::vector<int32_t> sn_of(n);
+    for (int32_t t = 0; t + 1 < (int32_t)s.sn_start.size(); ++t)
+        for (int32_t j = s.sn_start[t]; j < s.sn_start[t + 1]; ++j) sn_of[j] = t;
+    // columns of the L entries of each row (row-wise view of L)
+    std::vector<int64_t> lrp(n + 1, 0);
+    std::vector<int32_t> lcol;
+    if (prm.fuse_chains) {
+        for (int32_t j = 0; j < n; ++j)
+            for (int64_t p = lbeg(j); p < s.colptr[j + 1]; ++p) lrp[s.rowidx[p] + 1]++;
+        for (int32_t i = 0; i < n; ++i) lrp[i + 1] += lrp[i];
+        lcol.resize(lrp[n]);
+        std::vector<int64_t> nx(lrp.begin(), lrp.end() - 1);
+        for (int32_t j = 0; j < n; ++j)
+            for (int64_t p = lbeg(j); p < s.colptr[j + 1]; ++p) lcol[nx[s.rowidx[p]]++] = j;
+    }
     std::vector<std::pair<int32_t, int32_t>> pairs;   // (source panel, target column)
     for (int32_t T = 0; T < np; ++T) {
-        for (int32_t k = g.pan_start[T]; k < g.pan_start[T + 1]; ++k)
-            for (int64_t p = s.colptr[k]; p < s.colptr[k] + s.ulen[k]; ++p) {
-                const int32_t j = s.rowidx[p];
-                const int32_t S = pan_of[j];
-                if (S == T) continue;
-                plev[T] = std::max(plev[T], plev[S] + 1);
-                if (j == g.pan_start[S + 1] - 1) pairs.emplace_back(S, k);
-            }
-        // plev[T] is final: push it along the L entries of T's columns
+        grp[T] = T;
+        if (prm.fuse_chains && T > 0 && grp[T - 1] >= 0 && sn_of[g.pan_start[T]] == sn_of[g.pan_start[T - 1]]) {
+            // the levels of T's dependencies outside the group of T - 1
+            const int32_t G = grp[T - 1];
+            int32_t ext = -1;
+            for (int32_t k = g.pan_start[T]; k < g.pan_start[T + 1]; ++k)
+                for (int64_t p = s.colptr[k]; p < s.colptr[k] + s.ulen[k]; ++p) {
+                    const int32_t S = pan_of[s.rowidx[p]];
+                    if (S != T && (S < G || S > T)) ext = std::max(ext, plev[S]);
+                }
+            for (int32_t i = g.pan_start[T]; i < g.pan_start[T + 1]; ++i)
+                for (int64_t p = lrp[i]; p < lrp[i + 1]; ++p) {
+                    const int32_t S = pan_of[lcol[p]];
+                    if (S != T && (S < G || S > T)) ext = std::max(ext, plev[S]);
+                }
+            if (ext < plev[G]) grp[T] = G;
+        }
+        const int32_t G = grp[T];
+        if (G != T) {
+            plev[T] = plev[G];
+            for (int32_t k = g.pan_start[T]; k < g.pan_start[T + 1]; ++k)
+                for (int64_t p = s.colptr[k]; p < s.colptr[k] + s.ulen[k]; ++p) {
+                    const int32_t j = s.rowidx[p];
+                    const int32_t S = pan_of[j];
+                    if (S != T && j == g.pan_start[S + 1] - 1) pairs.emplace_back(S, k);
+                }
+        } else {
+            for (int32_t k = g.pan_start[T]; k < g.pan_start[T + 1]; ++k)
+                for (int64_t p = s.colptr[k]; p < s.colptr[k] + s.ulen[k]; ++p) {
+                    const int32_t j = s.rowidx[p];
+                    const int32_t S = pan_of[j];
+                    if (S == T) continue;
+                    plev[T] = std::max(plev[T], plev[S] + 1);
+                    if (j == g.pan_start[S + 1] - 1) pairs.emplace_back(S, k);
+                }
+        }
+        // plev[T] is final: push it along the L entries of T's columns (not into its group)
         for (int32_t j = g.pan_start[T]; j < g.pan_start[T + 1]; ++j)
             for (int64_t p = lbeg(j); p < s.colptr[j + 1]; ++p) {
                 const int32_t R = pan_of[s.rowidx[p]];
@@ -109,11 +160,18 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
             if (it[t] != sp + t) return KKT_ERR_SCHEDULE;
     }
     const int32_t nlev = np ? 1 + *std::max_element(plev.begin(), plev.end()) : 0;
-    // group pairs by launch (= source level + 1), then target column, then source
+    // group pairs by launch (= source level + 1, or the group's own launch for a pair inside
+    // a group), then target column, then source
     std::vector<std::vector<std::pair<int32_t, int32_t>>> by_launch(nlev + 1);
-    for (const auto &pr : pairs) by_launch[plev[pr.first] + 1].emplace_back(pr.second, pr.first);
+    for (const auto &pr : pairs) {
+        const bool inside = grp[pr.first] == grp[pan_of[pr.second]];
+        by_launch[plev[pr.first] + (inside ? 0 : 1)].emplace_back(pr.second, pr.first);
+    }
     std::vector<std::vector<int32_t>> panels_at(nlev);
-    for (int32_t p = 0; p < np; ++p) panels_at[plev[p]].push_back(p);
+    for (int32_t p = 0; p < np; ++p)
+        if (grp[p] == p) panels_at[plev[p]].push_back(p);   // group leaders
+    std::vector<int32_t> gsize(np, 0);
+    for (int32_t p = 0; p < np; ++p) gsize[grp[p]]++;
     auto pw = [&](int32_t p) { return g.pan_start[p + 1] - g.pan_start[p]; };
     auto is_small = [&](int32_t p) { return pw(p) <= kSmallW && g.pan_r[p] <= prm.small_rows; };
     g.f_lvl.assign(1, 0);
@@ -121,6 +179,7 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
     g.f_nmed.clear();
     g.f_w256.clear();
     g.f_item_panel.clear();
+    g.f_item_npan.clear();
     g.f_item_pair.assign(1, 0);
     g.f_pair_src.clear();
     g.f_pair_tgt.clear();
@@ -134,17 +193,21 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
         bool small;
         double cost;
         int kind = 0;   // 0 wide (up to panel_max columns), 1 medium, 2 narrow
+        int32_t npan = 1;   // panels factored (a group's leader and the panels after it)
     };
     for (int32_t l = 0; l < nlev; ++l) {
         auto &pl = by_launch[l];                  // (target, source)
         std::sort(pl.begin(), pl.end());
         std::vector<Item> items;
-        // factor items: the panel and every pair that targets one of its columns
+        // factor items: the panel (or group of panels) and every pair that targets one of
+        // its columns
         for (int32_t T : panels_at[l]) {
-            Item it{T, {}, is_small(T), 0.0};
+            Item it{T, {}, gsize[T] == 1 && is_small(T), 0.0};
+            it.npan = gsize[T];
             items.push_back(it);
         }
-        for (size_t i = 0; i < items.size(); ++i) fac_index[items[i].panel] = (int32_t)i;
+        for (size_t i = 0; i < items.size(); ++i)
+            for (int32_t t = 0; t < items[i].npan; ++t) fac_index[items[i].panel + t] = (int32_t)i;
         // pull-only targets: single-source targets are grouped by source
         std::vector<std::pair<int32_t, int32_t>> single;   // (source, target)
         for (size_t q = 0; q < pl.size();) {
@@ -180,38 +243,42 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
                 it.cost += (double)pw(pr.first) * (pw(pr.first) + g.pan_r[pr.first]);
                 mw = std::max(mw, pw(pr.first));
             }
-            if (it.panel >= 0) it.cost += (double)pw(it.panel) * pw(it.panel) * (pw(it.panel) + g.pan_r[it.panel]);
+            for (int32_t t = 0; t < (it.panel >= 0 ? it.npan : 0); ++t) {
+                const int32_t P = it.panel + t;
+                it.cost += (double)pw(P) * pw(P) * (pw(P) + g.pan_r[P]);
+            }
             const bool fits_med =
-                mw <= kMedW && (it.panel < 0 || pw(it.panel) + g.pan_r[it.panel] <= kMedRows);
+                mw <= kMedW && (it.panel < 0 || pw(it.panel) + g.pan_r[it.panel] <= kMedRows) && it.npan == 1;
             it.kind = it.small ? 2 : fits_med ? 1 : 0;
         }
         // the medium configuration only where a level has no item that needs the big one
         // (one launch per level for the wide items)
         bool any_big = false, fit256 = true;
+        int32_t nbig = 0;
         for (const auto &it : items) {
             any_big |= it.kind == 0;
-            if (it.kind == 0 && it.panel >= 0 && pw(it.panel) + g.pan_r[it.panel] > kW256Rows) fit256 = false;
+            nbig += it.kind == 0 || it.kind == 1;
+            if (it.kind == 0 && it.panel >= 0 && (pw(it.panel) + g.pan_r[it.panel] > kW256Rows || it.npan > 1))
+                fit256 = false;
         }
         if (any_big)
             for (auto &it : items)
                 if (it.kind == 1) it.kind = 0;
-        g.f_w256.push_back(any_big && fit256 && prm.wide256 ? 1 : 0);
-        for (int32_t T : panels_at[l]) fac_index[T] = -1;
+        g.f_w256.push_back(any_big && fit256 && nbig >= kW256MinItems && prm.wide256 ? 1 : 0);
+        for (int32_t T : panels_at[l])
+            for (int32_t t = 0; t < gsize[T]; ++t) fac_index[T + t] = -1;
         std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
             if (a.kind != b.kind) return a.kind < b.kind;
             return a.cost > b.cost;
         });
         int32_t nlarge = 0, nmed = 0;
         for (const auto &it : items) {
-            // the wide path solves one source's targets on the lanes of one wavefront
-            for (size_t q = 0, q1; q < it.pairs.size(); q = q1) {
-                q1 = q;
-                while (q1 < it.pairs.size() && it.pairs[q1].first == it.pairs[q].first) ++q1;
-                if (q1 - q > (size_t)kGroup) return KKT_ERR_SCHEDULE;
-            }
+            // the wide path solves a source's targets kGroup at a time on the lanes of one
+            // wavefront; narrow items take their pairs one at a time
             nlarge += !it.small;
             nmed += it.kind == 1;
             g.f_item_panel.push_back(it.panel);
+            g.f_item_npan.push_back(it.npan);
             for (const auto &pr : it.pairs) {
                 g.f_pair_src.push_back(pr.first);
                 g.f_pair_tgt.push_back(pr.second);
@@ -257,7 +324,7 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
         o[0] = g.f_item_panel[i];
         o[1] = g.f_item_pair[i];
         o[2] = g.f_item_pair[i + 1];
-        o[3] = 0;
+        o[3] = g.f_item_npan[i];
         geom(o + 4, g.f_item_panel[i]);
     }
     // pairs of narrow items (16-lane path) carry the diagonal slots of all source columns
@@ -520,7 +587,7 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
         for (int32_t it = g.f_lvl[l]; it < g.f_lvl[l + 1]; ++it) {
             const int32_t P = g.f_item_panel[it];
             if (P < 0) continue;
-            const int64_t e = s.colptr[g.pan_start[P + 1]] - s.colptr[g.pan_start[P]];
+            const int64_t e = s.colptr[g.pan_start[P + g.f_item_npan[it]]] - s.colptr[g.pan_start[P]];
             const bool med = (it >= g.f_lvl[l] + nb && it < g.f_lvl[l] + nb + nm) || (nb == 0 && nm > 0);
             if (nb > 0 && !med) (g.f_w256[l] ? g.nnz_lu_w256 : g.nnz_lu_wide) += e;
             else if (med) g.nnz_lu_med += e;

@@ -74,7 +74,8 @@ def test_batch_rejects_bad_input():
     b.close()
 
 
-@pytest.mark.parametrize("tuning", [(16, 32, 16, 1), (8, 64, 32, 0), (32, 0, 8, 1), (32, 64, 32, 0)])
+@pytest.mark.parametrize("tuning", [(16, 32, 16, 1, 1), (8, 64, 32, 0, 1), (32, 0, 8, 1, 0), (32, 64, 32, 0, 0),
+                                    (32, 64, 32, 1, 1)])
 def test_set_tuning_parity(tuning):
     print(f"[gpu] tuned schedule {tuning}", flush=True)
     q = kktgen.make_sequence(kktgen.small(2000, config_id=147, steps=2))
@@ -82,7 +83,7 @@ def test_set_tuning_parity(tuning):
     so = oracle.Symbolic(q.n, q.rowptr, q.colind, v0)
     sk = K.KKTSolver(q.n, q.rowptr, q.colind, v0)
     sk.set_tuning(*tuning)
-    assert sk.tuning() == dict(zip(("panel_max", "small_rows", "group", "wide256"), tuning))
+    assert sk.tuning() == dict(zip(("panel_max", "small_rows", "group", "wide256", "fuse_chains"), tuning))
     sk.bind()
     for t in range(q.steps):
         v, b = q.values(t), q.rhs(t)
