@@ -59,7 +59,10 @@ typedef struct {
      * candidate (lowest row index on ties).  0 = static diagonal pivoting (default). */
     double pivot_tau;
     /* Refactor: |u_kk| < tiny_pivot * ||A~||_inf is replaced by +-tiny_pivot*||A~||_inf
-     * (sign kept, zero counts as +) and counted.  Default 2^-26. */
+     * (sign kept, zero counts as +) and counted.  Default 2^-40: on the grid KKT systems the
+     * small pivots are genuine (the Schur complements of the -delta_c I block), and
+     * replacing them at 2^-26 (the square root of the unit roundoff) cost refinement steps
+     * that 2^-34 and below never needed. */
     double tiny_pivot;
     /* 1 = power-of-two row-then-column max equilibration, recomputed per refactor. */
     int32_t equilibrate;
@@ -107,9 +110,10 @@ typedef struct {
      * factors into FP64 sums; residuals, orthogonalisation and the solution update of the
      * refinement stay FP64, so kkt_refine still reaches berr_tol on the original A. */
     int32_t factor_precision;
-    /* Tiny-pivot factor of the FP32 factors (in place of tiny_pivot): default 2^-26, the
-     * FP64 value (measured on the grid workloads, larger factors such as 2^-12 replace so
-     * many pivots that refinement needs tens to hundreds of FGMRES steps). */
+    /* Tiny-pivot factor of the FP32 factors (in place of tiny_pivot): default 2^-26
+     * (measured on the grid workloads: larger factors such as 2^-12 replace so many pivots
+     * that refinement needs tens to hundreds of FGMRES steps, and smaller ones leave FP32
+     * pivots so small that refinement stalls). */
     double tiny_pivot_fp32;
     /* Kind of the approximate sweeps: 0 = Jacobi (every row reads the previous iterate;
      * default), 1 = block Gauss-Seidel (rows cut into chunks of 32 consecutive rows of the

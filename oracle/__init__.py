@@ -19,7 +19,7 @@ OK, WARN_PERTURBED, WARN_NOT_CONVERGED = 0, 1, 2
 ERR_ARG, ERR_PATTERN, ERR_SINGULAR, ERR_NONFINITE, ERR_NOMEM = -1, -2, -3, -4, -6
 
 TAU = 0.0             # threshold-pivoting tolerance (0: keep every nonzero diagonal)
-EPS = 2.0 ** -26      # tiny-pivot replacement factor
+EPS = 2.0 ** -40      # tiny-pivot replacement factor (reading C4)
 SN_MAX = 256          # supernode width cap
 
 

@@ -561,7 +561,7 @@ extern "C" {
 void kkt_default_opts(kkt_opts *o) {
     if (!o) return;
     o->pivot_tau = 0.0;
-    o->tiny_pivot = std::ldexp(1.0, -26);
+    o->tiny_pivot = std::ldexp(1.0, -40);
     o->equilibrate = 1;
     o->gmres_restart = 30;
     o->max_iters = 100;

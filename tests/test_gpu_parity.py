@@ -57,6 +57,17 @@ def check_factor_parity(so, lu_g, lu_o, npert, thresh):
     assert np.all(excess <= (2 * thresh if npert else 0.0)), f"diagonal excess {excess.max():.3e}"
 
 
+def berr_close(q, berr_gpu, berr_host):
+    """The backward error that refinement reports against the host's recomputation.  Each
+    side forms r_i = b_i - sum_j a_ij x_j with an error of at most g |b_i| + g (|A||x|)_i,
+    g = gamma of the longest row plus one, and both terms are at most the denominator
+    ||A|| ||x|| + ||b|| (up to its own relative rounding), so the two values differ by at most
+    2 g plus a relative 1e-12 of berr."""
+    m = int(np.diff(q.rowptr).max()) + 1
+    g = m * U_RND / (1 - m * U_RND)
+    return abs(berr_gpu - berr_host) <= 2 * g * (1 + 1e-9) + 1e-12 * berr_host
+
+
 def check_solve_componentwise(so, lu_g, r, c, b, x):
     """One triangular-solve application x = Q C (L^U^)^-1 P R b with the GPU's own factors:
     with x~ = C^-1 Q^T x and b~ = P R b (both exact, power-of-two scaling), the forward and
@@ -142,7 +153,7 @@ def test_refine_reaches_target(name, spec, kw):
         xh = x.cpu().numpy()
         _, berr = oracle.residual(q.n, q.rowptr, q.colind, v, xh, b)
         assert info[0].status == K.OK and berr <= 1e-10, (t, berr, info)
-        assert abs(info[0].berr - berr) <= 1e-6 * berr + 1e-20
+        assert berr_close(q, info[0].berr, berr), (t, berr, info)
 
 
 def test_solve_matches_oracle_on_well_conditioned():
@@ -226,7 +237,7 @@ def test_refine_with_jacobi_sweeps(spec, sweeps, converges):
         xh = x.cpu().numpy()
         _, berr = oracle.residual(q.n, q.rowptr, q.colind, v, xh, b)
         assert np.isfinite(xh).all() and info[0].status in (K.OK, K.WARN_NOT_CONVERGED), (t, info)
-        assert abs(info[0].berr - berr) <= 1e-6 * berr + 1e-20, (t, berr, info)
+        assert berr_close(q, info[0].berr, berr), (t, berr, info)
         if converges:
             assert info[0].status == K.OK and berr <= 1e-10, (t, berr, info)
 
