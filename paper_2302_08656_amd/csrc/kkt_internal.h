@@ -108,8 +108,9 @@ struct Schedule {
     // packed records read by the refactorization kernels (8 x int32 each):
     // item8[i] = {panel to factor or -1, first pair, end pair, panels factored, s, w, r,
     //             ldiag[s]} (s, w, r of the first panel);
-    // pair8[q] = {source panel, f_pair_pos, f_pair_rel (first index), target column,
-    //             s, w, r, ldiag[s]}, with s, w, r the panel's first column, width, rows below;
+    // pair8[q] = {source panel, f_pair_pos, f_pair_rel (first index), end of q's group,
+    //             s, w, r, ldiag[s]}, with s, w, r the panel's first column, width, rows below
+    //             (a group: consecutive pairs of one source, at most kGroup);
     // for pairs of narrow items {ldiag[s+1], f_pair_pos, f_pair_rel, ldiag[s+2], ldiag[s+3],
     //             w, r, ldiag[s]} (slots past the width are 0)
     std::vector<int32_t> item8, pair8;

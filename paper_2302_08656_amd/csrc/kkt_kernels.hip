@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "kkt_kernels.h"
 
@@ -19,6 +20,14 @@ __device__ __forceinline__ double bcast(double v, int lane) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
     return __hiloint2double(hi, lo);
+}
+
+// Barrier over the block for data exchanged through LDS only: global memory operations of
+// the waves may stay in flight across it (a plain __syncthreads waits for them).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 __device__ __forceinline__ double inv_pow2_floor_log2(double m) {
@@ -270,7 +279,8 @@ template <> struct Pair<float> { using type = float2; };
 // into the later ones, by source: a panel is factored before the first pull whose source
 // it is, and after the pulls into it.
 //   pair[2q]   = {source panel, slot of the source's first row in the target column,
-//                 first index into rel, target column}
+//                 first index into rel, end of the group of q: the consecutive pairs of one
+//                 source, at most kGroup, pulled together}
 //   pair[2q+1] = {source's first column, width, rows below, slot of its first diagonal}
 // T: the type in which the factor is stored and refactored (double, or float for the
 // mixed-precision path).
@@ -548,10 +558,11 @@ template <> struct Mfma<float> {
 
 // Configurations of the wide path: threads per block, minimum waves per SIMD, source L rows
 // staged per chunk, widest panel (target and sources) and update tiles per wavefront and
-// pass.  LDS layout (bytes): Ld (the source's diagonal block, later the factored panel's U)
-// | Ub (solved rows per target) | Lr (a chunk of the source's L rows) | lds (the source's
-// diagonal slots) | sgs (slot of row s in each column of the panel to factor) | flg (pivot
-// rows published by the panel sweep) | staged pair records.
+// pass.  LDS layout (bytes): Ld (the pivot rows of the panel being factored) | Ub (solved
+// rows per target) | Lr (a chunk of the source's L rows) | lds (the diagonal slots of the
+// current and the next group's source, two buffers) | sgs (slot of row s in each column of
+// the panel to factor) | flg (pivot rows published by the panel sweep) | staged pair
+// records.
 template <class TV, int NT, int WV, int CH, int MW, int TI>
 struct WideCfg {
     using T = TV;   // factor type
@@ -564,7 +575,7 @@ struct WideCfg {
     static constexpr int kOffUb = kOffLd + kMaxW * kPanelMax * (int)sizeof(T);
     static constexpr int kOffLr = kOffUb + kRowLd * kGroup * (int)sizeof(T);
     static constexpr int kOffLds = kOffLr + kChunk * kMaxW * (int)sizeof(T);
-    static constexpr int kOffSgs = kOffLds + kPanelMax * 4;
+    static constexpr int kOffSgs = kOffLds + 2 * kPanelMax * 4;
     static constexpr int kOffFlg = kOffSgs + kPanelMax * 4;
     static constexpr int kOffPairs = kOffFlg + kPanelMax * 4;
     static constexpr int kLds = kOffPairs + kStagePairs * 32;
@@ -577,13 +588,22 @@ template <class T> using MedCfg = WideCfg<T, 256, 4, 128, 16, 2>;
 // panels up to 32 columns whose factored panels have at most 256 rows: two blocks per CU
 template <class T> using W256Cfg = WideCfg<T, 256, 2, 128, 32, 4>;
 
-// Shifted sweeps.  A row of a panel of width w <= KW lives in registers x[0..KW-1] with
-// zeros past column w.  Step j of a triangular sweep consumes x[0] (column j) and moves
-// the remaining columns down by one while it applies the step's update, so each register
-// index is static while the loop over j stays rolled; the update of column c at step j is
-// the same FMA, in the same order, as in the unshifted form.
-// The row of multipliers (LDS, 16-byte aligned) is read into registers in one round before
-// the FMAs; otherwise the compiler interleaves one LDS round trip per pair of columns.
+// Panel sweeps in registers.  A row of a panel of width w <= KW lives in registers
+// x[0..KW-1] with zeros past column w.  Step j of the elimination consumes x[0] (column j)
+// and moves the remaining columns down by one while it applies the step's update, so every
+// register index is static while the loop over j stays rolled; the update of column c at
+// step j is the same FMA, in the same order, as in the unshifted form.
+// The window narrows in four phases of K_p = KW, 3KW/4, KW/2, KW/4 registers: phase p runs
+// steps [b_p, b_{p+1}), b_0 = 0, b_{p+1} = max(b_p, w - K_{p+1}), b_4 = w, so that no step
+// carries more than KW/4 columns past the panel's remaining ones.
+// The register freed at the top of the window takes, for a row of the diagonal block (a
+// future pivot row), a zero, so that its window holds zeros past its remaining columns when
+// it is published; such a row keeps its multipliers in LDS.  A row below the block takes its
+// multiplier L(row, j) there instead: phase p's n_p = b_{p+1} - b_p multipliers then sit, in
+// order, in registers [K_p - n_p, K_p) when the sweep ends (K_p - n_p >= K_{p+1}, so later
+// phases leave them alone), and stay in registers until the panel is stored.
+// The pivot row (LDS, 16-byte aligned) is read into registers in one round before the FMAs;
+// otherwise the compiler interleaves one LDS round trip per pair of columns.
 template <int KW, class T>
 __device__ __forceinline__ void load_lds_row(T (&rw)[kPanelMax], const T *row) {
     using P2 = typename Pair<T>::type;
@@ -596,13 +616,6 @@ __device__ __forceinline__ void load_lds_row(T (&rw)[kPanelMax], const T *row) {
     }
 }
 
-template <int KW, class T>
-__device__ __forceinline__ void shift_fma(T (&x)[kPanelMax], T l, const T (&rw)[kPanelMax]) {
-#pragma unroll
-    for (int c = 1; c < KW; ++c) x[c - 1] = fma(-l, rw[c], x[c]);
-    x[KW - 1] = T(0);
-}
-
 // x[c] = lu[base[c] + off] for c < w, 0 beyond (every address in bounds)
 template <int KW, class T>
 __device__ __forceinline__ void load_row(T (&x)[kPanelMax], const T *lu, const int *base, int w, int off) {
@@ -613,29 +626,67 @@ __device__ __forceinline__ void load_row(T (&x)[kPanelMax], const T *lu, const i
     }
 }
 
-// One step j of the panel sweep on a row (shifted, KW columns): the pivot row's entries
-// U(j, j + c) are read from LDS in one round; the row's multiplier is stored.
-template <int KW, class T>
-__device__ __forceinline__ void sweep_step(T (&x)[kPanelMax], const T *urow, T *dst, int &bad) {
+// window sizes of the four phases of a sweep of width class KW
+template <int KW> struct Phases {
+    static constexpr int K0 = KW, K1 = 3 * KW / 4, K2 = KW / 2, K3 = KW / 4;
+    static_assert(K3 >= 2 && K3 % 2 == 0, "even windows of at least two columns");
+};
+
+// first steps b[0..4] of the four phases of a sweep of w columns
+template <int KW>
+__device__ __forceinline__ void phase_bounds(int w, int (&b)[5]) {
+    using P = Phases<KW>;
+    b[0] = 0;
+    b[1] = max(b[0], w - P::K1);
+    b[2] = max(b[1], w - P::K2);
+    b[3] = max(b[2], w - P::K3);
+    b[4] = w;
+}
+
+// One step of the panel sweep on a row (window K) with pivot row urow; a row of the diagonal
+// block (diag) stores its multiplier to *lslot.
+template <int K, class T>
+__device__ __forceinline__ void sweep_step(T (&x)[kPanelMax], const T *urow, bool diag, T *lslot, int &bad) {
     T rw[kPanelMax];
-    load_lds_row<KW>(rw, urow);
+    load_lds_row<K>(rw, urow);
     __builtin_amdgcn_sched_barrier(0);
     const T l = x[0] / rw[0];
     bad |= !isfinite(l);
-    *dst = l;
-    shift_fma<KW>(x, l, rw);
+#pragma unroll
+    for (int c = 1; c < K; ++c) x[c - 1] = fma(-l, rw[c], x[c]);
+    x[K - 1] = diag ? T(0) : l;
+    if (diag) *lslot = l;
 }
 
-// Dense LU without pivoting of a wide panel's block column (w + r rows, w columns).  Thread
-// t owns panel row t (t < w: the diagonal block; below: the L rows) for t < C::kThreads.
-// All pivot rows are in wavefront 0, which runs the whole sweep without waiting: at step j
-// lane j perturbs its pivot if tiny, publishes U(j, j..) in LDS (Us[j * kPanelMax + c] =
-// U(j, j + c), zero past the panel) and raises flg[j]; every later row of the wavefront
-// takes its multiplier and update from it.  The other wavefronts follow, waiting (bounded)
-// on flg[j] before step j.  The sweep narrows from KW to KW / 2 register columns once no
-// more than KW / 2 columns remain.  Rows beyond the first C::kThreads are eliminated
-// afterwards from the finished Us.  sgs[c] = slot of row s in column s + c (staged by the
-// caller); row t of the panel is at slot sgs[c] + t.
+// Stores the multipliers L(row, i), i < w, of a row below the diagonal block after the whole
+// sweep to lu[sgs[i] + row]: register c belongs to the phase p with K_{p+1} <= c < K_p.
+template <int KW, class T>
+__device__ __forceinline__ void store_multipliers(const T (&x)[kPanelMax], T *lu, const int *sgs, int row,
+                                                  const int (&b)[5]) {
+    using P = Phases<KW>;
+#pragma unroll
+    for (int c = 0; c < KW; ++c) {
+        const int p = c >= P::K1 ? 0 : c >= P::K2 ? 1 : c >= P::K3 ? 2 : 3;
+        const int kp = p == 0 ? P::K0 : p == 1 ? P::K1 : p == 2 ? P::K2 : P::K3;
+        const int first = kp - (b[p + 1] - b[p]);
+        if (c >= first) lu[sgs[b[p] + c - first] + row] = x[c];
+    }
+}
+
+// Dense LU without pivoting of a wide panel's block column (w + r rows, w columns).  The
+// block's threads own one panel row each: wavefront 0 rows 0..63 (the diagonal block and the
+// first L rows), the others 64 rows each, the wavefront that shares wavefront 0's SIMD last
+// (for 512 threads), so that wavefront 0 runs alone on its SIMD for panels of up to 448
+// rows.  Wavefront 0 runs the whole sweep without waiting: at step j lane j perturbs its
+// pivot if tiny, publishes its window U(j, j..) in LDS (Us[j * kPanelMax + c] = U(j, j + c),
+// zero past the panel) and raises flg[j] (ordered after the row by an LDS-only release), and
+// every later row of the wavefront takes its multiplier and update from it.  The other
+// wavefronts follow, waiting (bounded) on flg[j] before step j.  No global memory operation
+// is outstanding inside the sweep: the multipliers stay in registers or LDS and are stored
+// when it ends.  Rows beyond the threads of the block are eliminated afterwards from the
+// finished Us.  sgs[c] = slot of row s in column s + c (staged by the caller); row t of the
+// panel is at slot sgs[c] + t.  The diagonal block's multipliers go to Ltri (the chunk area
+// of the pulls, free here): Ltri[t * kPanelMax + j] = L(t, j).
 constexpr int kSweepSpin = 1 << 22;
 
 template <class C, int KW>
@@ -643,71 +694,97 @@ __device__ __forceinline__ void large_factor_w(const RefArgs<typename C::T> &a, 
                                                typename C::T thresh) {
     using T = typename C::T;
     using P2 = typename Pair<T>::type;
-    const int tid = threadIdx.x, lane = tid & 63;
+    using P = Phases<KW>;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     T *Us = reinterpret_cast<T *>(sm + C::kOffLd);
+    T *Ltri = reinterpret_cast<T *>(sm + C::kOffLr);
     const int *sgs = reinterpret_cast<const int *>(sm + C::kOffSgs);
     int *flg = reinterpret_cast<int *>(sm + C::kOffFlg);
     const int nrow = w + r;
+    const int row = (C::kThreads == 512 ? (wv < 4 ? wv : wv == 4 ? 7 : wv - 1) : wv) * 64 + lane;
+    const bool diag = row < w;
+    int b[5];
+    phase_bounds<KW>(w, b);
     int npert = 0, bad = 0;
     T x[kPanelMax];
 #pragma unroll
     for (int c = 0; c < kPanelMax; ++c) x[c] = T(0);
-    if (tid < nrow) load_row<KW>(x, a.lu, sgs, w, tid);
+    if (row < nrow) load_row<KW>(x, a.lu, sgs, w, row);
     if (tid < kPanelMax) flg[tid] = 0;
-    __syncthreads();
-    constexpr int KH = KW / 2;
-    const int jsplit = max(0, w - KH);          // steps with more than KH columns left
-    if (tid < 64) {
+    lds_barrier();
+    if (wv == 0) {
+        auto run = [&](auto kc, int j0, int j1) {
+            constexpr int K = decltype(kc)::value;
 #pragma unroll 1
-        for (int j = 0; j < w; ++j) {
-            // the window past the panel's remaining columns holds zeros (shifted in, and
-            // untouched by the narrowed sweep), so the whole window is published as it is
-            if (tid == j) {
-                x[0] = perturb(x[0], thresh, npert);
-                bad |= !isfinite(x[0]);
-                P2 *o = reinterpret_cast<P2 *>(Us + j * kPanelMax);
+            for (int j = j0; j < j1; ++j) {
+                if (lane == j) {
+                    x[0] = perturb(x[0], thresh, npert);
+                    bad |= !isfinite(x[0]);
+                    P2 *o = reinterpret_cast<P2 *>(Us + j * kPanelMax);
 #pragma unroll
-                for (int c = 0; c < KW / 2; ++c) o[c] = P2{x[2 * c], x[2 * c + 1]};
+                    for (int c = 0; c < K / 2; ++c) o[c] = P2{x[2 * c], x[2 * c + 1]};
+                    // the other wavefronts may read row j once it is complete in LDS
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                    __hip_atomic_store(flg + j, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (lane > j && row < nrow)
+                    sweep_step<K>(x, Us + j * kPanelMax, diag, Ltri + lane * kPanelMax + j, bad);
             }
-            __builtin_amdgcn_wave_barrier();
-            if (tid > j && tid < nrow) {
-                T *dst = a.lu + sgs[j] + tid;
-                if (j < jsplit) sweep_step<KW>(x, Us + j * kPanelMax, dst, bad);
-                else sweep_step<KH>(x, Us + j * kPanelMax, dst, bad);
-            }
-            // the other wavefronts may read row j once it is complete in LDS
-            if (tid == j) __hip_atomic_store(flg + j, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-    } else if (tid - lane < nrow) {             // a wavefront with rows to eliminate
+        };
+        run(std::integral_constant<int, P::K0>{}, b[0], b[1]);
+        run(std::integral_constant<int, P::K1>{}, b[1], b[2]);
+        run(std::integral_constant<int, P::K2>{}, b[2], b[3]);
+        run(std::integral_constant<int, P::K3>{}, b[3], b[4]);
+    } else if (row - lane < nrow) {             // a wavefront with rows to eliminate
+        bool ok = true;
+        auto run = [&](auto kc, int j0, int j1) {
+            constexpr int K = decltype(kc)::value;
 #pragma unroll 1
-        for (int j = 0; j < w; ++j) {
-            int spin = 0;
-            while (__hip_atomic_load(flg + j, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
-                if (++spin > kSweepSpin) break;
-                __builtin_amdgcn_s_sleep(1);
+            for (int j = j0; j < j1 && ok; ++j) {
+                int spin = 0;
+                while (__hip_atomic_load(flg + j, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
+                    if (++spin > kSweepSpin) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                if (spin > kSweepSpin) {
+                    if (lane == 0) atomicOr(&a.st->flags, kFlagInternal);
+                    ok = false;
+                } else if (row < nrow) {
+                    sweep_step<K>(x, Us + j * kPanelMax, false, Ltri, bad);
+                }
             }
-            if (spin > kSweepSpin) {
-                if (lane == 0) atomicOr(&a.st->flags, kFlagInternal);
-                break;
-            }
-            if (tid < nrow) {
-                T *dst = a.lu + sgs[j] + tid;
-                if (j < jsplit) sweep_step<KW>(x, Us + j * kPanelMax, dst, bad);
-                else sweep_step<KH>(x, Us + j * kPanelMax, dst, bad);
-            }
-        }
+        };
+        run(std::integral_constant<int, P::K0>{}, b[0], b[1]);
+        run(std::integral_constant<int, P::K1>{}, b[1], b[2]);
+        run(std::integral_constant<int, P::K2>{}, b[2], b[3]);
+        run(std::integral_constant<int, P::K3>{}, b[3], b[4]);
     }
-    __syncthreads();
-    // U rows of the diagonal block (diagonal included) from LDS
+    lds_barrier();
+    // U rows of the diagonal block (diagonal included) from LDS: row j's window covers its
+    // w - j remaining columns
     for (int t = tid; t < w * KW; t += C::kThreads) {
         const int j = t / KW, c = t % KW;
         if (j + c < w) a.lu[sgs[j + c] + j] = Us[j * kPanelMax + c];
     }
+    // multipliers of the diagonal block from LDS, of the rows below it from registers
+    for (int t = tid; t < w * kPanelMax; t += C::kThreads) {
+        const int i = t / kPanelMax, j = t % kPanelMax;
+        if (j < i) a.lu[sgs[j] + i] = Ltri[t];
+    }
+    if (!diag && row < nrow) store_multipliers<KW>(x, a.lu, sgs, row, b);
     // rows beyond the threads of the block
     for (int i = tid + C::kThreads; i < nrow; i += C::kThreads) {
         load_row<KW>(x, a.lu, sgs, w, i);
 #pragma unroll 1
-        for (int j = 0; j < w; ++j) sweep_step<KW>(x, Us + j * kPanelMax, a.lu + sgs[j] + i, bad);
+        for (int j = b[0]; j < b[1]; ++j) sweep_step<P::K0>(x, Us + j * kPanelMax, false, Ltri, bad);
+#pragma unroll 1
+        for (int j = b[1]; j < b[2]; ++j) sweep_step<P::K1>(x, Us + j * kPanelMax, false, Ltri, bad);
+#pragma unroll 1
+        for (int j = b[2]; j < b[3]; ++j) sweep_step<P::K2>(x, Us + j * kPanelMax, false, Ltri, bad);
+#pragma unroll 1
+        for (int j = b[3]; j < b[4]; ++j) sweep_step<P::K3>(x, Us + j * kPanelMax, false, Ltri, bad);
+        store_multipliers<KW>(x, a.lu, sgs, i, b);
     }
     if (npert) atomicAdd(&a.pcount[blockIdx.x % kCountSlots], (unsigned long long)npert);   // row j counts pivot j
     if (__any(bad) && lane == 0) atomicOr(&a.st->flags, kFlagNonfinite);
@@ -716,6 +793,9 @@ __device__ __forceinline__ void large_factor_w(const RefArgs<typename C::T> &a, 
 template <class C>
 __device__ __forceinline__ void large_factor(const RefArgs<typename C::T> &a, int4 pn, char *sm,
                                              typename C::T thresh) {
+    // the panel's geometry is the same for the whole block: scalar from here on
+    pn.y = __builtin_amdgcn_readfirstlane(pn.y);
+    pn.z = __builtin_amdgcn_readfirstlane(pn.z);
     if constexpr (C::kMaxW > 16) {
         if (pn.y > 16) {
             large_factor_w<C, 32>(a, pn.y, pn.z, sm, thresh);
@@ -726,43 +806,36 @@ __device__ __forceinline__ void large_factor(const RefArgs<typename C::T> &a, in
     else large_factor_w<C, 8>(a, pn.y, pn.z, sm, thresh);
 }
 
-// Rows of the source panel (width w) in one target: unit lower solve with the source's
-// diagonal block Ls[j * kPanelMax + c] = L(j + c, j) (zero past the panel), in registers,
-// shifted; writes the solved rows to the factor and to ub.
-template <int KW, class T>
-__device__ __forceinline__ void unit_lower_w(T *lu, int ps, int w, const T *Ls, T *ub) {
-    T u[kPanelMax];
+__device__ __forceinline__ float bcast(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Rows of the source panel S (width w) in the targets of a group: the unit lower solve
+// U(S, t) = L_SS^-1 A(S, t) for each target column t.  Wavefront v takes targets v, v + nw,
+// ... (NT of them); lane c < w holds row c of S in each (u[k]).  Lcol holds the columns of
+// L_SS in LDS, unshifted: Lcol[j * kPanelMax + c] = L(c, j) for j < c < w, zero for c <= j.
+// Step j broadcasts the finished entry of row j of each target (readlane) and applies it to
+// the rows below it (lanes c <= j add zero products), so every entry receives the same FMAs
+// in the same order as a row-by-row forward substitution.  The next step's column is read
+// while the current one is applied.
+template <int NT, class T>
+__device__ __forceinline__ void lower_run(const T *Lcol, T (&u)[NT], int w, int lane) {
+    T l = Lcol[lane];
+#pragma unroll 1
+    for (int j = 0; j + 1 < w; ++j) {
+        const T ln = Lcol[(j + 1) * kPanelMax + lane];
 #pragma unroll
-    for (int c = 0; c < KW; ++c) {
-        const T v = lu[ps + (c < w ? c : 0)];
-        u[c] = c < w ? v : T(0);
-    }
-    // the window narrows to KW / 2 columns once no more remain (the rest are zeros)
-    constexpr int KH = KW / 2;
-    const int jsplit = max(0, w - KH);
-#pragma unroll 1
-    for (int j = 0; j < jsplit; ++j) {
-        T rw[kPanelMax];
-        load_lds_row<KW>(rw, Ls + j * kPanelMax);
-        __builtin_amdgcn_sched_barrier(0);
-        const T uj = u[0];
-        lu[ps + j] = uj;
-        ub[j] = uj;
-        shift_fma<KW>(u, uj, rw);
-    }
-#pragma unroll 1
-    for (int j = jsplit; j < w; ++j) {
-        T rw[kPanelMax];
-        load_lds_row<KH>(rw, Ls + j * kPanelMax);
-        __builtin_amdgcn_sched_barrier(0);
-        const T uj = u[0];
-        lu[ps + j] = uj;
-        ub[j] = uj;
-        shift_fma<KH>(u, uj, rw);
+        for (int k = 0; k < NT; ++k) u[k] = fma(-l, bcast(u[k], j), u[k]);
+        l = ln;
     }
 }
 
-// All pulls of one item with the source panel staged in LDS, then the panel factorization.
+// All pulls of one item, one group (one source S, up to kGroup target columns) at a time,
+// then the panel factorization.  Per group: the loads of the update's destination slots and
+// current values, of S's first chunk of L rows and of the lower solve's operands are issued
+// together; the lower solve runs on all wavefronts; the update of the rows R of the targets
+// runs on the matrix cores (16x16 tiles of Lr (nr x w) times the solved rows (w x m)).  The
+// diagonal slots of the next group's source are loaded during the current group.
 template <class C>
 __device__ __forceinline__ void wide_item(const int item, const RefArgs<typename C::T> &a, char *sm) {
     using T = typename C::T;
@@ -770,24 +843,34 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs<typename
     const T thresh = pivot_threshold(a);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     constexpr int nw = C::kThreads / 64;
-    T *Ld = reinterpret_cast<T *>(sm + C::kOffLd);
+    constexpr int NT = (kGroup + nw - 1) / nw;       // targets per wavefront in the lower solve
+    constexpr int kJ = C::kThreads / C::kChunk;      // source columns staged per round
+    constexpr int kLr = C::kMaxW / kJ;               // rounds
+    constexpr int kTiles = C::kTiles;
+    static_assert(C::kThreads % C::kChunk == 0 && C::kMaxW % kJ == 0, "staging rounds");
     T *Ub = reinterpret_cast<T *>(sm + C::kOffUb);
     T *Lr = reinterpret_cast<T *>(sm + C::kOffLr);
-    int *lds = reinterpret_cast<int *>(sm + C::kOffLds);
+    int *ldsb = reinterpret_cast<int *>(sm + C::kOffLds);
     int *sgs = reinterpret_cast<int *>(sm + C::kOffSgs);
     int4 *prs = reinterpret_cast<int4 *>(sm + C::kOffPairs);
     const int4 ia = a.item[2 * item], ib = a.item[2 * item + 1];
-    const int pbeg = ia.y, p1 = ia.z, npr = p1 - pbeg;
+    const int pbeg = ia.y, p1 = ia.z;
     const int npan = ia.x >= 0 ? max(1, ia.w) : 0;
     int done = 0;   // panels of the item factored so far
-    const bool staged = npr <= kStagePairs;
-    // one round: the pair records and the slots of the (first) panel to factor
-    if (staged)
-        for (int t = tid; t < 2 * npr; t += C::kThreads) prs[t] = a.pair[2 * pbeg + t];
+    // pair records pbeg .. are staged in LDS, kStagePairs at a time: a window [wbeg, wend)
+    // holds the current group and the first pair of the next one
+    int wbeg = pbeg, wend = min(p1, pbeg + kStagePairs);
+    // one round: the pair records, the slots of the (first) panel to factor and the
+    // diagonal slots of the first group's source
+    for (int t = tid; t < 2 * (wend - wbeg); t += C::kThreads) prs[t] = a.pair[2 * wbeg + t];
     if (ia.x >= 0 && tid < ib.y) sgs[tid] = a.ldiag[ib.x + tid] - tid;
-    __syncthreads();
-    auto pra = [&](int q) { return staged ? prs[2 * (q - pbeg)] : a.pair[2 * q]; };
-    auto prb = [&](int q) { return staged ? prs[2 * (q - pbeg) + 1] : a.pair[2 * q + 1]; };
+    if (p1 > pbeg) {
+        const int4 pn = a.pair[2 * pbeg + 1];
+        if (tid < pn.y) ldsb[tid] = tid == 0 ? pn.w : a.ldiag[pn.x + tid];
+    }
+    lds_barrier();
+    auto pra = [&](int q) { return prs[2 * (q - wbeg)]; };
+    auto prb = [&](int q) { return prs[2 * (q - wbeg) + 1]; };
     // factors the item's next panel (the first one's geometry is ib, the others' is read)
     auto factor_next = [&]() {
         int4 pn = ib;
@@ -804,126 +887,197 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs<typename
         __syncthreads();
         ++done;
     };
-    for (int g0 = pbeg, g1; g0 < p1; g0 = g1) {
-        const int S = pra(g0).x;
+    const int li = lane & 15, lk = lane >> 4;
+    // destination slots of the four outputs of this lane in update tile `tile` of a group
+    // (g0, m targets; mt row tiles of a chunk of nr rows from i0): q[v], valid where ok[v].
+    // A group has at most kGroup = 32 targets, so tile / mt is 0 or 1.  The loads are only
+    // issued here; their values are consumed later.
+    auto tile_slots = [&](int g0, int m, int tile, int mt, int nr, int i0, int (&q)[4], bool (&ok)[4]) {
+        const int tt = tile >= mt ? 1 : 0, ti = tile - tt * mt, tb = tt * 16 + li;
+        const bool okt = tile < 2 * mt && tb < m;
+        const int rb = pra(g0 + (okt ? tb : 0)).z + i0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = ti * 16 + MM::row(lk, v);
+            ok[v] = okt && i < nr;
+            q[v] = a.rel[rb + (ok[v] ? i : 0)];
+        }
+    };
+    int buf = 0;
+    for (int g0 = pbeg, g1; g0 < p1; g0 = g1, buf ^= 1) {
+        if (wend < p1 && g0 + kGroup >= wend) {
+            // the group or the next one's first pair is past the staged window: restage
+            // from g0 (every wavefront is done with the records of the previous groups)
+            wbeg = g0;
+            wend = min(p1, g0 + kStagePairs);
+            for (int t = tid; t < 2 * (wend - wbeg); t += C::kThreads) prs[t] = a.pair[2 * wbeg + t];
+            __syncthreads();
+        }
+        const int4 pa0 = pra(g0);
+        const int S = pa0.x;
+        g1 = __builtin_amdgcn_readfirstlane(pa0.w);
         // a pull from one of the item's own panels: factor the panels up to it first
         while (done < npan && S >= ia.x + done && S < ia.x + npan) factor_next();
-        g1 = g0 + 1;
-        while (g1 < p1 && pra(g1).x == S && g1 - g0 < kGroup) ++g1;
         const int4 pn = prb(g0);
-        const int s = pn.x, w = pn.y, r = pn.z;
-        if (tid < w) lds[tid] = tid == 0 ? pn.w : a.ldiag[s + tid];
-        __syncthreads();
-        // one round: S's diagonal block and the first chunk of its L rows
-        for (int t = tid; t < w * kPanelMax; t += C::kThreads) {
-            const int j = t / kPanelMax, c = t % kPanelMax;
-            Ld[t] = (c >= 1 && j + c < w) ? a.lu[lds[j] + c] : T(0);
-        }
-        const int nr0 = min(C::kChunk, r);
-        for (int t = tid; t < w * nr0; t += C::kThreads) {
-            const int j = t / nr0, i = t % nr0;
-            Lr[j * C::kChunk + i] = a.lu[lds[j] + 1 + (w - 1 - j) + i];
-        }
-        __syncthreads();
-        // Update of the rows R of each target by S on the matrix cores (more than one target):
-        // the block Lr (nr x w) times the solved rows (w x m) in 16x16 output tiles (Mfma),
-        // accumulated in T.  Wavefronts 1.. own the tiles, kTiles at a time; for
-        // the first pass of the first chunk they load the destination slots and current values
-        // while wavefront 0 solves the targets' rows of S.
-        constexpr int kTiles = C::kTiles;
+        const int w = __builtin_amdgcn_readfirstlane(pn.y), r = __builtin_amdgcn_readfirstlane(pn.z);
         const int m = g1 - g0;
+        const int *lds = ldsb + buf * kPanelMax;
+        // the next group's diagonal slots, stored to the other buffer when this group ends
+        int ndiag = 0, ndiag0 = 0;
+        bool nstore = false;
+        if (g1 < p1) {
+            const int4 pq = prb(g1);
+            nstore = tid < pq.y;
+            ndiag = a.ldiag[nstore ? pq.x + tid : 0];
+            ndiag0 = pq.w;
+        }
         const bool mf = a.use_mfma && m > 1;
         const int nt = (m + 15) >> 4;
-        const int li = lane & 15, lk = lane >> 4;
-        auto tile_slots = [&](int tile, int mt, int nr, int i0, int (&sl)[4]) {
-            const int ti = tile % mt, tt = tile / mt, tb = tt * 16 + li;
-            const bool ok = tile < mt * nt && tb < m;
-            const int32_t *rel = ok ? a.rel + pra(g0 + tb).z + i0 : a.rel;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = ti * 16 + MM::row(lk, v);
-                sl[v] = (ok && i < nr) ? rel[i] : -1;
-            }
-        };
+        const int nr0 = min(C::kChunk, r), mt0 = (nr0 + 15) >> 4;
+        // (1) destination slots of this wavefront's first update tiles
         int pslot[kTiles][4];
+        bool pok[kTiles][4];
         T pcur[kTiles][4];
-        const int mt0 = (min(C::kChunk, r) + 15) >> 4;
-        if (mf && wv > 0) {
+        if (mf) {
 #pragma unroll
-            for (int k = 0; k < kTiles; ++k) tile_slots((wv - 1) * kTiles + k, mt0, min(C::kChunk, r), 0, pslot[k]);
+            for (int k = 0; k < kTiles; ++k) tile_slots(g0, m, wv * kTiles + k, mt0, nr0, 0, pslot[k], pok[k]);
+        }
+        // (2) the first chunk of S's L rows: column j = lj + k kJ, row lrow of the chunk
+        const int lrow = tid % C::kChunk, lj = tid / C::kChunk;
+        T lv[kLr];
+#pragma unroll
+        for (int k = 0; k < kLr; ++k) {
+            const int j = lj + k * kJ, dj = lds[j];
+            const bool ok = lrow < nr0 && j < w;
+            lv[k] = a.lu[ok ? dj + 1 + (w - 1 - j) + lrow : 0];
+        }
+        // (3) the columns of L_SS (entry e = j kPanelMax + c of Lcol: L(c, j), zero unless
+        // j < c < w) and the rows of S in this wavefront's targets
+        constexpr int kLc = C::kMaxW * kPanelMax / C::kThreads;
+        static_assert(C::kMaxW * kPanelMax % C::kThreads == 0, "Lcol rounds");
+        T lc[kLc];
+#pragma unroll
+        for (int k = 0; k < kLc; ++k) {
+            const int e = tid + k * C::kThreads, j = e / kPanelMax, c = e % kPanelMax, dj = lds[j];
+            lc[k] = a.lu[j < c && c < w ? dj + (c - j) : 0];
+        }
+        int ps[NT], tg[NT];
+        bool own[NT];
+        T u[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            tg[k] = wv + k * nw;
+            own[k] = tg[k] < m && lane < w;
+            ps[k] = pra(g0 + (tg[k] < m ? tg[k] : 0)).y;
+            u[k] = a.lu[own[k] ? ps[k] + lane : 0];
+        }
+        // (4) the chunk and the columns to LDS
+#pragma unroll
+        for (int k = 0; k < kLr; ++k) {
+            const int j = lj + k * kJ;
+            if (lrow < nr0 && j < w) Lr[j * C::kChunk + lrow] = lv[k];
+        }
+        T *Lcol = reinterpret_cast<T *>(sm + C::kOffLd);
+#pragma unroll
+        for (int k = 0; k < kLc; ++k) {
+            const int e = tid + k * C::kThreads, j = e / kPanelMax, c = e % kPanelMax;
+            Lcol[e] = j < c && c < w ? lc[k] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NT; ++k) u[k] = own[k] ? u[k] : T(0);
+        lds_barrier();
+        // (5) the lower solve on every wavefront; the solved rows to the factor and to Ub;
+        // then the current values at the slots (in flight during the barrier and the products)
+        lower_run<NT>(Lcol, u, w, lane);
+#pragma unroll
+        for (int k = 0; k < NT; ++k)
+            if (own[k]) {
+                a.lu[ps[k] + lane] = u[k];
+                Ub[tg[k] * kRowLd + lane] = u[k];
+            }
+        if (mf) {
 #pragma unroll
             for (int k = 0; k < kTiles; ++k)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) pcur[k][v] = pslot[k][v] >= 0 ? a.lu[pslot[k][v]] : T(0);
+                for (int v = 0; v < 4; ++v) {
+                    pslot[k][v] = pok[k][v] ? pslot[k][v] : -1;
+                    pcur[k][v] = a.lu[pok[k][v] ? pslot[k][v] : 0];
+                }
         }
-        // rows of S in each target: unit lower solve with S's diagonal block, one lane per
-        // target (wavefront 0; a group holds at most kGroup targets); the lane keeps its
-        // target's rows in registers
-        if (wv == 0 && lane < m) {
-            const int ps = pra(g0 + lane).y;
-            T *ub = Ub + lane * kRowLd;
-            if (C::kMaxW > 16 && w > 16) unit_lower_w<C::kMaxW>(a.lu, ps, w, Ld, ub);
-            else if (w > 8) unit_lower_w<16>(a.lu, ps, w, Ld, ub);
-            else unit_lower_w<8>(a.lu, ps, w, Ld, ub);
-        }
-        __syncthreads();
+        lds_barrier();   // Ub is complete; the loads and stores above stay in flight
         // rows R of each target: chunks of S's L rows in LDS, precomputed slots
         for (int i0 = 0; i0 < r; i0 += C::kChunk) {
             const int nr = min(C::kChunk, r - i0);
             if (i0 > 0) {
-                for (int t = tid; t < w * nr; t += C::kThreads) {
-                    const int j = t / nr, i = t % nr;
-                    Lr[j * C::kChunk + i] = a.lu[lds[j] + 1 + (w - 1 - j) + i0 + i];
+                lds_barrier();   // every wavefront is done with the previous chunk
+#pragma unroll
+                for (int k = 0; k < kLr; ++k) {
+                    const int j = lj + k * kJ, dj = lds[j];
+                    const bool ok = lrow < nr && j < w;
+                    lv[k] = a.lu[ok ? dj + 1 + (w - 1 - j) + i0 + lrow : 0];
                 }
-                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < kLr; ++k) {
+                    const int j = lj + k * kJ;
+                    if (lrow < nr && j < w) Lr[j * C::kChunk + lrow] = lv[k];
+                }
+                lds_barrier();
             }
             if (mf) {
                 const int mt = (nr + 15) >> 4;
-                if (wv > 0) {
-                    for (int tile0 = (wv - 1) * kTiles, pass = 0; tile0 < mt * nt;
-                         tile0 += (nw - 1) * kTiles, ++pass) {
-                        typename MM::acc_t acc[kTiles];
+                for (int tile0 = wv * kTiles, pass = 0; tile0 < mt * nt; tile0 += nw * kTiles, ++pass) {
+                    typename MM::acc_t acc[kTiles];
 #pragma unroll
-                        for (int k = 0; k < kTiles; ++k) acc[k] = typename MM::acc_t{T(0), T(0), T(0), T(0)};
-                        for (int k0 = 0; k0 < w; k0 += 4) {
-                            const int kk = k0 + lk;
-                            T av[kTiles], bv[kTiles];
+                    for (int k = 0; k < kTiles; ++k) acc[k] = typename MM::acc_t{T(0), T(0), T(0), T(0)};
+                    int ia2[kTiles], tb[kTiles];
+                    bool okt[kTiles];
 #pragma unroll
-                            for (int k = 0; k < kTiles; ++k) {
-                                const int tile = tile0 + k;
-                                const int ti = tile % mt, tt = tile / mt;
-                                const int ia2 = ti * 16 + li, tb = tt * 16 + li;
-                                const bool ok = tile < mt * nt && kk < w;
-                                av[k] = (ok && ia2 < nr) ? Lr[kk * C::kChunk + ia2] : T(0);
-                                bv[k] = (ok && tb < m) ? Ub[tb * kRowLd + kk] : T(0);
-                            }
+                    for (int k = 0; k < kTiles; ++k) {
+                        const int tile = tile0 + k, tt = tile >= mt ? 1 : 0;
+                        okt[k] = tile < mt * nt;
+                        ia2[k] = (tile - tt * mt) * 16 + li;
+                        tb[k] = tt * 16 + li;
+                    }
+                    for (int k0 = 0; k0 < w; k0 += 4) {
+                        const int kk = k0 + lk;
+                        T av[kTiles], bv[kTiles];
 #pragma unroll
-                            for (int k = 0; k < kTiles; ++k) acc[k] = MM::step(av[k], bv[k], acc[k]);
+                        for (int k = 0; k < kTiles; ++k) {
+                            const bool ok = okt[k] && kk < w;
+                            av[k] = (ok && ia2[k] < nr) ? Lr[kk * C::kChunk + ia2[k]] : T(0);
+                            bv[k] = (ok && tb[k] < m) ? Ub[tb[k] * kRowLd + kk] : T(0);
                         }
-                        int slot[kTiles][4];
-                        T cur[kTiles][4];
-                        if (i0 == 0 && pass == 0) {
 #pragma unroll
-                            for (int k = 0; k < kTiles; ++k)
+                        for (int k = 0; k < kTiles; ++k) acc[k] = MM::step(av[k], bv[k], acc[k]);
+                    }
+                    int slot[kTiles][4];
+                    T cur[kTiles][4];
+                    if (i0 == 0 && pass == 0) {
 #pragma unroll
-                                for (int v = 0; v < 4; ++v) {
-                                    slot[k][v] = pslot[k][v];
-                                    cur[k][v] = pcur[k][v];
-                                }
-                        } else {
+                        for (int k = 0; k < kTiles; ++k)
 #pragma unroll
-                            for (int k = 0; k < kTiles; ++k) tile_slots(tile0 + k, mt, nr, i0, slot[k]);
+                            for (int v = 0; v < 4; ++v) {
+                                slot[k][v] = pslot[k][v];
+                                cur[k][v] = pcur[k][v];
+                            }
+                    } else {
 #pragma unroll
-                            for (int k = 0; k < kTiles; ++k)
+                        for (int k = 0; k < kTiles; ++k) {
+                            bool ok[4];
+                            tile_slots(g0, m, tile0 + k, mt, nr, i0, slot[k], ok);
 #pragma unroll
-                                for (int v = 0; v < 4; ++v) cur[k][v] = slot[k][v] >= 0 ? a.lu[slot[k][v]] : T(0);
+                            for (int v = 0; v < 4; ++v) slot[k][v] = ok[v] ? slot[k][v] : -1;
                         }
 #pragma unroll
                         for (int k = 0; k < kTiles; ++k)
 #pragma unroll
-                            for (int v = 0; v < 4; ++v)
-                                if (slot[k][v] >= 0) a.lu[slot[k][v]] = cur[k][v] - acc[k][v];
+                            for (int v = 0; v < 4; ++v) cur[k][v] = a.lu[slot[k][v] >= 0 ? slot[k][v] : 0];
                     }
+#pragma unroll
+                    for (int k = 0; k < kTiles; ++k)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (slot[k][v] >= 0) a.lu[slot[k][v]] = cur[k][v] - acc[k][v];
                 }
             } else {
                 for (int q = g0 + wv; q < g1; q += nw) {
@@ -936,8 +1090,9 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs<typename
                     }
                 }
             }
-            __syncthreads();
         }
+        if (nstore) ldsb[(buf ^ 1) * kPanelMax + tid] = tid == 0 ? ndiag0 : ndiag;
+        // the updated targets are read by the item's factorization
         __threadfence_block();
         __syncthreads();
     }

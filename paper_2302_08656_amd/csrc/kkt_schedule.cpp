@@ -309,7 +309,7 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
     for (int32_t j = 0; j < n; ++j) g.ldiag[j] = (int32_t)(s.colptr[j] + s.ulen[j]);
     // packed records (8 x int32 each): item i = {T, first pair, end pair, 0, s, w, r,
     // ldiag[s]} with T the panel it factors (or -1) and s, w, r that panel's first column,
-    // width and rows below; pair q = {S, pos, rel, target column, s, w, r, ldiag[s]} with
+    // width and rows below; pair q = {S, pos, rel, end of its group, s, w, r, ldiag[s]} with
     // the source panel's geometry
     auto geom = [&](int32_t *o, int32_t P) {
         o[0] = P >= 0 ? g.pan_start[P] : 0;
@@ -328,13 +328,26 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
         geom(o + 4, g.f_item_panel[i]);
     }
     // pairs of narrow items (16-lane path) carry the diagonal slots of all source columns
-    // instead: {ldiag[s+1], pos, rel, ldiag[s+2], ldiag[s+3], w, r, ldiag[s]} (0 past w)
+    // instead: {ldiag[s+1], pos, rel, ldiag[s+2], ldiag[s+3], w, r, ldiag[s]} (0 past w).
+    // Pairs of wide items carry, in place of the target column, the end of their group: the
+    // run of consecutive pairs of one source, at most kGroup long, that the wide path pulls
+    // together.
     const size_t npairs = g.f_pair_src.size();
     g.pair8.resize(8 * npairs);
     std::vector<char> narrow_pair(npairs, 0);
-    for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l)
+    std::vector<int32_t> group_end(npairs, 0);
+    for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
         for (int32_t it = g.f_lvl[l] + g.f_nlarge[l]; it < g.f_lvl[l + 1]; ++it)
             for (int32_t q = g.f_item_pair[it]; q < g.f_item_pair[it + 1]; ++q) narrow_pair[q] = 1;
+        for (int32_t it = g.f_lvl[l]; it < g.f_lvl[l] + g.f_nlarge[l]; ++it) {
+            const int32_t q1 = g.f_item_pair[it + 1];
+            for (int32_t g0 = g.f_item_pair[it], g1; g0 < q1; g0 = g1) {
+                g1 = g0 + 1;
+                while (g1 < q1 && g.f_pair_src[g1] == g.f_pair_src[g0] && g1 - g0 < kGroup) ++g1;
+                for (int32_t q = g0; q < g1; ++q) group_end[q] = g1;
+            }
+        }
+    }
     for (size_t q = 0; q < npairs; ++q) {
         int32_t *o = &g.pair8[8 * q];
         const int32_t S = g.f_pair_src[q];
@@ -349,7 +362,7 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
             o[4] = dslot(3);
         } else {
             o[0] = S;
-            o[3] = g.f_pair_tgt[q];
+            o[3] = group_end[q];
         }
     }
     // solve levels
