@@ -22,6 +22,10 @@ __device__ __forceinline__ double bcast(double v, int lane) {
     return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ float bcast(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
 // Barrier over the block for data exchanged through LDS only: global memory operations of
 // the waves may stay in flight across it (a plain __syncthreads waits for them).
 __device__ __forceinline__ void lds_barrier() {
@@ -723,13 +727,19 @@ __device__ __forceinline__ void large_factor_w(const RefArgs<typename C::T> &a, 
                     P2 *o = reinterpret_cast<P2 *>(Us + j * kPanelMax);
 #pragma unroll
                     for (int c = 0; c < K / 2; ++c) o[c] = P2{x[2 * c], x[2 * c + 1]};
-                    // the other wavefronts may read row j once it is complete in LDS
+                }
+                // this wavefront's own reads of row j follow its writes in LDS order; the
+                // compiler is kept from moving them ahead (no instruction is emitted)
+                __builtin_amdgcn_wave_barrier();
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                if (lane > j && row < nrow)
+                    sweep_step<K>(x, Us + j * kPanelMax, diag, Ltri + lane * kPanelMax + j, bad);
+                if (lane == j) {
+                    // the other wavefronts may read row j once it is complete in LDS (long
+                    // since, by now: the wait is off the sweep's chain)
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
                     __hip_atomic_store(flg + j, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
-                __builtin_amdgcn_wave_barrier();
-                if (lane > j && row < nrow)
-                    sweep_step<K>(x, Us + j * kPanelMax, diag, Ltri + lane * kPanelMax + j, bad);
             }
         };
         run(std::integral_constant<int, P::K0>{}, b[0], b[1]);
@@ -804,10 +814,6 @@ __device__ __forceinline__ void large_factor(const RefArgs<typename C::T> &a, in
     }
     if (pn.y > 8) large_factor_w<C, 16>(a, pn.y, pn.z, sm, thresh);
     else large_factor_w<C, 8>(a, pn.y, pn.z, sm, thresh);
-}
-
-__device__ __forceinline__ float bcast(float v, int lane) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
 // Rows of the source panel S (width w) in the targets of a group: the unit lower solve
