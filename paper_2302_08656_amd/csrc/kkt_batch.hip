@@ -141,7 +141,7 @@ BatchSys<T> batch_sys(const kkt_handle *h) {
     const Dev &d = h->d;
     const Schedule &g = h->sch;
     BatchSys<T> b{};
-    b.ref = RefArgs<T>{d.ldiag, d.item8, d.pair8, d.f_rel, static_cast<T *>(d.lu), d.st, d.pcount,
+    b.ref = RefArgs<T>{d.ldiag, d.itemrec, d.pair8, d.f_rel, static_cast<T *>(d.lu), d.st, d.pcount,
                        std::is_same<T, float>::value ? h->opts.tiny_pivot_fp32 : h->opts.tiny_pivot,
                        h->opts.dense_mfma != 0, d.copy_k, d.csr_src, static_cast<T *>(d.lucsr),
                        d.pan_start, d.pan_r};

@@ -106,14 +106,15 @@ struct Schedule {
     std::vector<int64_t> f_pair_rel;    // [npairs+1] range into f_rel
     std::vector<int32_t> f_rel;         // slot of each row R of the source in the target column
     // packed records read by the refactorization kernels (8 x int32 each):
-    // item8[i] = {panel to factor or -1, first pair, end pair, panels factored, s, w, r,
-    //             ldiag[s]} (s, w, r of the first panel);
+    // itemrec[i] = {panel to factor or -1, first pair, end pair, panels factored, s, w, r,
+    //               ldiag[s], s', w', r', ldiag[s']} (s, w, r of the first panel; s', w', r' of
+    //               the first pair's source, zero for an item without pairs);
     // pair8[q] = {source panel, f_pair_pos, f_pair_rel (first index), end of q's group,
     //             s, w, r, ldiag[s]}, with s, w, r the panel's first column, width, rows below
     //             (a group: consecutive pairs of one source, at most kGroup);
     // for pairs of narrow items {ldiag[s+1], f_pair_pos, f_pair_rel, ldiag[s+2], ldiag[s+3],
     //             w, r, ldiag[s]} (slots past the width are 0)
-    std::vector<int32_t> item8, pair8;
+    std::vector<int32_t> itemrec, pair8;
     std::vector<int32_t> ldiag;         // slot of the diagonal of each column
     // triangular solves: level l has items [x_lvl[l], x_lvl[l+1]), 4 x int32 each:
     // {1, lanes, s, w}: wide panel of rows s..s+w-1; {0, t0, s, w}: helper summing the

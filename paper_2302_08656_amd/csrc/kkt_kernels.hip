@@ -275,9 +275,10 @@ template <class T> struct Pair;
 template <> struct Pair<double> { using type = double2; };
 template <> struct Pair<float> { using type = float2; };
 
-// Packed 32-byte records (two int4 each):
-//   item[2i]   = {panel to factor or -1, first pair, end of pairs, panels factored}
-//   item[2i+1] = {its first column s, width w, rows below r, slot of the diagonal of column s}
+// Packed records, an item three int4, a pair two:
+//   item[3i]   = {panel to factor or -1, first pair, end of pairs, panels factored}
+//   item[3i+1] = {its first column s, width w, rows below r, slot of the diagonal of column s}
+//   item[3i+2] = the same for the source of its first pair (zero without pairs)
 // An item that factors several panels (consecutive panels of one supernode) factors them in
 // order; its pairs list the pulls from outside first, then the pulls of each of its panels
 // into the later ones, by source: a panel is factored before the first pull whose source
@@ -474,7 +475,7 @@ __device__ __forceinline__ void small_group(int item0, int nsmall, const RefArgs
     int npert = 0;
     if (g < nsmall) {
         const int item = item0 + g;
-        const int4 ia = a.item[2 * item], ib = a.item[2 * item + 1];
+        const int4 ia = a.item[3 * item], ib = a.item[3 * item + 1];
         // one round: the records of up to 16 pairs (lane t holds pair p0 + t) and the
         // diagonal slots of the panel to factor
         const int p0 = ia.y, np = ia.z - ia.y;
@@ -859,7 +860,7 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs<typename
     int *ldsb = reinterpret_cast<int *>(sm + C::kOffLds);
     int *sgs = reinterpret_cast<int *>(sm + C::kOffSgs);
     int4 *prs = reinterpret_cast<int4 *>(sm + C::kOffPairs);
-    const int4 ia = a.item[2 * item], ib = a.item[2 * item + 1];
+    const int4 ia = a.item[3 * item], ib = a.item[3 * item + 1], ic = a.item[3 * item + 2];
     const int pbeg = ia.y, p1 = ia.z;
     const int npan = ia.x >= 0 ? max(1, ia.w) : 0;
     int done = 0;   // panels of the item factored so far
@@ -870,10 +871,7 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs<typename
     // diagonal slots of the first group's source
     for (int t = tid; t < 2 * (wend - wbeg); t += C::kThreads) prs[t] = a.pair[2 * wbeg + t];
     if (ia.x >= 0 && tid < ib.y) sgs[tid] = a.ldiag[ib.x + tid] - tid;
-    if (p1 > pbeg) {
-        const int4 pn = a.pair[2 * pbeg + 1];
-        if (tid < pn.y) ldsb[tid] = tid == 0 ? pn.w : a.ldiag[pn.x + tid];
-    }
+    if (p1 > pbeg && tid < ic.y) ldsb[tid] = tid == 0 ? ic.w : a.ldiag[ic.x + tid];
     lds_barrier();
     auto pra = [&](int q) { return prs[2 * (q - wbeg)]; };
     auto prb = [&](int q) { return prs[2 * (q - wbeg) + 1]; };

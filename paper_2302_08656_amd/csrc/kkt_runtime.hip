@@ -24,7 +24,7 @@ struct Dev {
     int32_t *a_rowptr, *a_colind, *a_crow, *a_cptr, *a_cpos, *a_map, *lu_fill;
     int32_t *colptr, *rowidx, *ulen, *pan_start, *pan_r;
     int32_t *f_rel, *ldiag;
-    int4 *item8, *pair8;
+    int4 *itemrec, *pair8;
     unsigned long long *pcount;
     int4 *l_item4, *u_item4, *l_rows4, *u_rows4, *rinfo4, *urinfo4;
     int32_t *csr_col, *csr_src, *copy_k, *P, *Q;
@@ -114,7 +114,7 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.ulen = c.take<int32_t>(n);
     d.pan_start = c.take<int32_t>(g.pan_start.size());
     d.pan_r = c.take<int32_t>(g.pan_r.size());
-    d.item8 = c.take<int4>(std::max<size_t>(2, g.item8.size() / 4));
+    d.itemrec = c.take<int4>(std::max<size_t>(3, g.itemrec.size() / 4));
     d.pair8 = c.take<int4>(std::max<size_t>(2, g.pair8.size() / 4));
     d.ldiag = c.take<int32_t>(n);
     d.f_rel = c.take<int32_t>(std::max<size_t>(1, g.f_rel.size()));
@@ -339,7 +339,7 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s) {
     const Schedule &g = h->sch;
     const Dev &d = h->d;
     const double tiny = std::is_same<T, float>::value ? h->opts.tiny_pivot_fp32 : h->opts.tiny_pivot;
-    RefArgs<T> a{d.ldiag, d.item8, d.pair8, d.f_rel, static_cast<T *>(d.lu), d.st, d.pcount,
+    RefArgs<T> a{d.ldiag, d.itemrec, d.pair8, d.f_rel, static_cast<T *>(d.lu), d.st, d.pcount,
                  tiny, h->opts.dense_mfma != 0, d.copy_k, d.csr_src, static_cast<T *>(d.lucsr),
                  d.pan_start, d.pan_r};
     const int ncopy = (int)g.copy_ptr.size() - 1;   // launches that carry a chunk of the copy
@@ -774,7 +774,7 @@ int bind_common(kkt_handle *h, char *ws, size_t bytes, int32_t max_nrhs, hipStre
     rc |= upload(d.ulen, s.ulen, stream);
     rc |= upload(d.pan_start, g.pan_start, stream);
     rc |= upload(d.pan_r, g.pan_r, stream);
-    rc |= upload(reinterpret_cast<int32_t *>(d.item8), g.item8, stream);
+    rc |= upload(reinterpret_cast<int32_t *>(d.itemrec), g.itemrec, stream);
     rc |= upload(reinterpret_cast<int32_t *>(d.pair8), g.pair8, stream);
     rc |= upload(d.ldiag, g.ldiag, stream);
     rc |= upload(d.f_rel, g.f_rel, stream);

@@ -307,9 +307,9 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
     if (g.f_rel.size() >= (size_t)INT32_MAX) return KKT_ERR_ARG;
     g.ldiag.resize(n);
     for (int32_t j = 0; j < n; ++j) g.ldiag[j] = (int32_t)(s.colptr[j] + s.ulen[j]);
-    // packed records (8 x int32 each): item i = {T, first pair, end pair, 0, s, w, r,
-    // ldiag[s]} with T the panel it factors (or -1) and s, w, r that panel's first column,
-    // width and rows below; pair q = {S, pos, rel, end of its group, s, w, r, ldiag[s]} with
+    // packed records: item i = {T, first pair, end pair, panels factored, s, w, r, ldiag[s],
+    // s', w', r', ldiag[s']} with T the panel it factors (or -1), s, w, r that panel's first
+    // column, width and rows below, and s', w', r' those of its first pair's source; pair q = {S, pos, rel, end of its group, s, w, r, ldiag[s]} with
     // the source panel's geometry
     auto geom = [&](int32_t *o, int32_t P) {
         o[0] = P >= 0 ? g.pan_start[P] : 0;
@@ -318,14 +318,15 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
         o[3] = P >= 0 ? g.ldiag[g.pan_start[P]] : 0;
     };
     const size_t nitems = g.f_item_panel.size();
-    g.item8.resize(8 * nitems);
+    g.itemrec.resize(12 * nitems);
     for (size_t i = 0; i < nitems; ++i) {
-        int32_t *o = &g.item8[8 * i];
+        int32_t *o = &g.itemrec[12 * i];
         o[0] = g.f_item_panel[i];
         o[1] = g.f_item_pair[i];
         o[2] = g.f_item_pair[i + 1];
         o[3] = g.f_item_npan[i];
         geom(o + 4, g.f_item_panel[i]);
+        geom(o + 8, g.f_item_pair[i] < g.f_item_pair[i + 1] ? g.f_pair_src[g.f_item_pair[i]] : -1);
     }
     // pairs of narrow items (16-lane path) carry the diagonal slots of all source columns
     // instead: {ldiag[s+1], pos, rel, ldiag[s+2], ldiag[s+3], w, r, ldiag[s]} (0 past w).
