@@ -5,7 +5,7 @@ the roofline position of the dominant kernel and the CPU-oracle baseline.
 
 One step (unit) = kkt_refactor(K_t) followed by kkt_refine(b_t) (triangular solve plus FGMRES
 refinement, as Algorithm 1 pairs every solve with refinement) that ends with a backward error
-<= 1e-10, for t cycling through the 50-system sequence.  All values and
+<= 1e-10, by default as one kkt_refactor_refine call (same results bit for bit), for t cycling through the 50-system sequence.  All values and
 right-hand sides are resident in HBM before the timed region starts; analysis (host, once
 per pattern) is timed separately.  One GPU only.
 """
@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--solve-mode", choices=("fixed", "ticket", "levels"), default="fixed",
                     help="triangular solves: persistent launch with fixed item order (default), with "
                          "ticket order, or one launch per level")
+    ap.add_argument("--path", choices=("fused", "separate"), default="fused",
+                    help="grid: kkt_refactor_refine (forward substitution beside the refactorization, "
+                         "default) or kkt_refactor followed by kkt_refine; the results are the same bit for bit")
     ap.add_argument("--workload", choices=("grid", "batch", "serve"), default="grid",
                     help="grid: one grid's refactor+solve sequence (--config); batch: 64 systems of 8 "
                          "patterns (1k-10k buses) refactored together; serve: Poisson request streams "
@@ -394,6 +397,8 @@ def main():
     torch.cuda.synchronize()
 
     def unit(t):
+        if args.path == "fused":
+            return sk.refactor_refine(dvals[t], drhs[t], x)[1]
         sk.refactor(dvals[t])
         _, info = sk.refine(drhs[t], x)
         return info[0]
@@ -496,7 +501,7 @@ def main():
                    "timed_systems": (f"all {T}" if len(timed) == T else timed),
                    "refinement_preconditioner": (f"{args.approx_sweeps} Jacobi sweeps per triangle"
                                                  if args.approx_sweeps else "exact triangular solves"),
-                   "solve_mode": args.solve_mode},
+                   "solve_mode": args.solve_mode, "path": args.path},
         "p50_ms": round(nearest_rank(lat, 50), 4), "p99_ms": round(nearest_rank(lat, 99), 4),
         "failures": fails, "fgmres_iters_mean": round(float(np.mean(iters)), 3),
         "berr_max": float(np.max(berrs)),

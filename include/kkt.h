@@ -252,6 +252,19 @@ int kkt_solve_approx(kkt_handle *h, const double *d_b, double *d_x, int32_t nrhs
 int kkt_refine(kkt_handle *h, const double *d_b, double *d_x, int32_t nrhs, int64_t ld,
                kkt_info *info, hipStream_t stream);
 
+/* One step of Algorithm 1 for one right-hand side: kkt_refactor(h, d_values) followed by
+ * kkt_refine(h, d_b, d_x, 1, n, info), with the same results bit for bit (factors, x and
+ * info).  The forward substitution of the first solve runs beside the refactorization: each
+ * part of L y = P R b starts once the columns it reads are factored (replayed from a second
+ * graph, recorded at the first call after kkt_bind; without graphs, with the profiler on or
+ * on a capturing stream the two calls run one after the other).  d_values as for
+ * kkt_refactor (BORROWED); d_b, d_x: device FP64[n], d_x may equal d_b; info: host
+ * kkt_info[1] (may be NULL).  Waits for completion.  Returns what kkt_refine returns; a
+ * failed factorization (ERR_NONFINITE, ERR_DEVICE) is reported with info = {0, error, inf,
+ * perturbed pivots}, d_x then holds no solution.  Errors also: ARG, STATE (not bound). */
+int kkt_refactor_refine(kkt_handle *h, const double *d_values, const double *d_b, double *d_x,
+                        kkt_info *info, hipStream_t stream);
+
 /* Test hook: copies the factors of the last refactorization to host memory in the
  * canonical L+U CSC order (FP64[nnz_lu]) and the scale factors (FP64[n] each, may be
  * NULL).  Waits. */

@@ -81,7 +81,7 @@ class _Stats(C.Structure):
 
 EXPORTS = ["kkt_default_opts", "kkt_analyze", "kkt_get_stats", "kkt_export_symbolic",
            "kkt_workspace_bytes", "kkt_bind", "kkt_bind_scratch", "kkt_refactor", "kkt_refactor_status", "kkt_solve", "kkt_solve_approx",
-           "kkt_refine", "kkt_get_tuning", "kkt_set_tuning", "kkt_autotune", "kkt_export_factors", "kkt_profile_enable", "kkt_profile_read",
+           "kkt_refine", "kkt_refactor_refine", "kkt_get_tuning", "kkt_set_tuning", "kkt_autotune", "kkt_export_factors", "kkt_profile_enable", "kkt_profile_read",
            "kkt_batch_create", "kkt_batch_refactor", "kkt_batch_refine", "kkt_batch_destroy", "kkt_clone",
            "kkt_server_default_opts", "kkt_server_create", "kkt_server_add_pattern", "kkt_server_submit",
            "kkt_server_wait", "kkt_server_get_stats", "kkt_server_destroy",
@@ -126,6 +126,7 @@ def _lib():
         L.kkt_solve.argtypes = [p, p, p, C.c_int32, C.c_int64, p]
         L.kkt_solve_approx.argtypes = [p, p, p, C.c_int32, C.c_int64, p]
         L.kkt_refine.argtypes = [p, p, p, C.c_int32, C.c_int64, C.POINTER(_Info), p]
+        L.kkt_refactor_refine.argtypes = [p, p, p, p, C.POINTER(_Info), p]
         L.kkt_export_factors.argtypes = [p, p, p, p, p]
         L.kkt_get_tuning.argtypes = [p, C.POINTER(_Tuning)]
         L.kkt_set_tuning.argtypes = [p, C.POINTER(_Tuning)]
@@ -326,6 +327,25 @@ class KKTSolver:
         if rc < 0:
             raise KKTError(rc, "kkt_refine")
         return x, [Info(i.iters, i.status, i.berr, i.perturbed_pivots) for i in info]
+
+    def refactor_refine(self, values, b, x=None, stream=None):
+        """kkt_refactor(values) then kkt_refine(b) for one right-hand side, with the forward
+        substitution running beside the refactorization (kkt_refactor_refine).  b: cuda
+        float64 [n]; returns (x, Info)."""
+        import torch
+        self._check_vec(values, self.nnz_a)
+        self._check_vec(b, self.n)
+        if x is None:
+            x = torch.empty_like(b)
+        else:
+            self._check_vec(x, self.n)
+        info = _Info()
+        rc = _lib().kkt_refactor_refine(self._h, _dev_ptr(values), _dev_ptr(b), _dev_ptr(x), C.byref(info),
+                                        _stream_ptr(stream))
+        self._values = values
+        if rc < 0:
+            raise KKTError(rc, "kkt_refactor_refine")
+        return x, Info(info.iters, info.status, info.berr, info.perturbed_pivots)
 
     def tuning(self) -> dict:
         t = _Tuning()

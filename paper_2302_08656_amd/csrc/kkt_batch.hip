@@ -82,7 +82,8 @@ __global__ __launch_bounds__(C::kThreads, C::kWaves) void k_batch_level(const Ba
     extern __shared__ __align__(16) char sm[];
     const BatchPart P = parts[find_part(parts, nparts, blockIdx.x)];
     const RefArgs<typename C::T> a = sys[P.sys].ref;
-    refactor_block<C>(blockIdx.x - P.blk0, P.nblk, P.item0, a, P.nwide, P.small0, P.nsmall, P.c0, P.c1, sm);
+    refactor_block<C>(blockIdx.x - P.blk0, P.nblk, P.item0, a, P.nwide, P.small0, P.nsmall, P.c0, P.c1,
+                      FuseArgs<typename C::T>{}, sm);
 }
 
 // the copy after the last level and the replaced-pivot sums

@@ -94,10 +94,15 @@ struct Schedule {
     // levels whose 32-column wide items run in 256-thread blocks (every factored panel of the
     // level has at most 256 rows): 1, else 0
     std::vector<int32_t> f_w256;
-    // row-ordered copy: copy_k lists CSR positions; launch copy_lvl + c (c < copy_ptr.size()
-    // - 1) copies copy_k[copy_ptr[c] .. copy_ptr[c+1]), the copy after the last level the rest
+    // row-ordered copy: copy_k lists CSR positions grouped by the launch that finishes their
+    // column (launch l: copy_k[copy_at[l] .. copy_at[l+1])); launch copy_lvl + c (c <
+    // copy_ptr.size() - 1) copies copy_k[copy_ptr[c] .. copy_ptr[c+1]), the copy after the
+    // last level the rest
     int32_t copy_lvl = 0;
-    std::vector<int32_t> copy_k, copy_ptr;
+    std::vector<int32_t> copy_k, copy_ptr, copy_at;
+    // forward solve fused with the refactorization: the items of forward level k read only
+    // columns final after refactor launch l_ready[k] (and unknowns of lower forward levels)
+    std::vector<int32_t> l_ready;
     std::vector<int32_t> f_item_panel;  // (first) panel to factor after the pulls, or -1
     std::vector<int32_t> f_item_npan;   // panels factored by the item (consecutive, one supernode)
     std::vector<int32_t> f_item_pair;   // [nitems+1] range into f_pair_src / f_pair_tgt

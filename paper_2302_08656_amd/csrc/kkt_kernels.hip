@@ -9,6 +9,7 @@
 // launch per panel level; residuals and Krylov vector work for the refinement.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 #include <type_traits>
 
@@ -245,8 +246,7 @@ __global__ __launch_bounds__(256) void k_sum_counts(const unsigned long long *__
 template <class T>
 __global__ void k_to_csr(int q0, int q1, const int32_t *__restrict__ copy_k, const int32_t *__restrict__ csr_src,
                          const T *__restrict__ lu, T *__restrict__ lucsr) {
-    const int q = q0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (q < q1) {
+    for (int q = q0 + (int)(blockIdx.x * blockDim.x + threadIdx.x); q < q1; q += gridDim.x * blockDim.x) {
         const int k = copy_k[q];
         lucsr[k] = lu[csr_src[k]];
     }
@@ -526,8 +526,25 @@ __device__ __forceinline__ void small_group(int item0, int nsmall, const RefArgs
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(&a.pcount[slot % kCountSlots], (unsigned long long)c);
 }
 
+// lucsr[k] = lu[csr_src[k]] for k = copy_k[q], q in [c0, c1), by block b of nb blocks of
+// nthreads threads
+template <class T>
+__device__ __forceinline__ void copy_block(const RefArgs<T> &a, int c0, int c1, int b, int nb, int nthreads) {
+    for (int q = c0 + b * nthreads + (int)threadIdx.x; q < c1; q += nb * nthreads) {
+        const int k = a.copy_k[q];
+        a.lucsr[k] = a.lu[a.csr_src[k]];
+    }
+}
+
+// A level without wide items: its narrow items, kBlock / 16 to a block; the blocks after
+// them copy copy_k[c0 .. c1) of the row-ordered factor (columns final before the launch)
 template <class T, bool kPipe>
-__global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, RefArgs<T> a) {
+__global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, RefArgs<T> a, int c0, int c1) {
+    const int nsb = (nsmall + kBlock / 16 - 1) / (kBlock / 16);
+    if ((int)blockIdx.x >= nsb) {
+        copy_block(a, c0, c1, blockIdx.x - nsb, gridDim.x - nsb, kBlock);
+        return;
+    }
     small_group<T, kPipe>(item0, nsmall, a, blockIdx.x * (kBlock / 16) + (threadIdx.x >> 4),
                           blockIdx.x * 4 + (threadIdx.x >> 6));
 }
@@ -1103,27 +1120,40 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs<typename
     while (done < npan) factor_next();
 }
 
-// One launch per level: block b < nwide runs wide item item0 + b; the blocks after it run
-// the level's narrow items small0 .. small0 + nsmall - 1, C::kThreads / 16 to a block (they
-// touch other columns than the wide items, so one launch needs no ordering between them);
-// any blocks after those copy copy_k[c0 .. c1) of the row-ordered factor (columns that no
-// launch from this one on writes).
+// One launch per level: block b < nwide runs wide item item0 + b; the next f.nsolve blocks
+// run the forward-solve items f.j0 .. f.j1 - 1 (one forward level; they read only columns and
+// unknowns final before the launch), ahead of the narrow items so that they start beside the
+// factor work; the next ones run the level's narrow items small0 .. small0 + nsmall - 1,
+// C::kThreads / 16 to a block (they touch other columns than the wide items, so one launch
+// needs no ordering between them); any blocks after those copy copy_k[c0 .. c1) of the
+// row-ordered factor (columns that no launch from this one on writes).
 // Block blk of nblk of one level launch (the work of one handle: its wide items, narrow
 // items and copy chunk).
+template <class TF> struct SolveArgs;
+// the forward items [j0, j1) of the solve s (one forward level: independent items) run by
+// nsolve extra blocks of a refactor launch
+template <class T> struct FuseArgs {
+    SolveArgs<T> s;
+    int j0, j1, nsolve;
+};
+template <class T> __device__ void fused_forward_block(const FuseArgs<T> &f, int blk, char *sm);
+
 template <class C>
 __device__ __forceinline__ void refactor_block(int blk, int nblk, int item0, const RefArgs<typename C::T> &a,
-                                               int nwide, int small0, int nsmall, int c0, int c1, char *sm) {
+                                               int nwide, int small0, int nsmall, int c0, int c1,
+                                               const FuseArgs<typename C::T> &f, char *sm) {
     const int nsb = (nsmall + C::kThreads / 16 - 1) / (C::kThreads / 16);
-    if (blk >= nwide + nsb) {
-        const int b = blk - nwide - nsb, nbc = nblk - nwide - nsb;
-        for (int q = c0 + b * C::kThreads + threadIdx.x; q < c1; q += nbc * C::kThreads) {
-            const int k = a.copy_k[q];
-            a.lucsr[k] = a.lu[a.csr_src[k]];
-        }
+    if (blk >= nwide && blk < nwide + f.nsolve) {
+        fused_forward_block(f, blk - nwide, sm);
+        return;
+    }
+    if (blk >= nwide + f.nsolve + nsb) {
+        const int b = blk - nwide - f.nsolve - nsb, nbc = nblk - nwide - f.nsolve - nsb;
+        copy_block(a, c0, c1, b, nbc, C::kThreads);
         return;
     }
     if (blk >= nwide) {
-        const int b = blk - nwide;
+        const int b = blk - nwide - f.nsolve;
         small_group<typename C::T, (C::kMaxW > 16)>(small0, nsmall, a, b * (C::kThreads / 16) + (threadIdx.x >> 4),
                                                     b * (C::kThreads / 64) + (threadIdx.x >> 6));
         return;
@@ -1134,9 +1164,9 @@ __device__ __forceinline__ void refactor_block(int blk, int nblk, int item0, con
 template <class C>
 __global__ __launch_bounds__(C::kThreads, C::kWaves) void k_refactor_wide(int item0, RefArgs<typename C::T> a,
                                                                          int nwide, int small0, int nsmall, int c0,
-                                                                         int c1) {
+                                                                         int c1, FuseArgs<typename C::T> f) {
     extern __shared__ __align__(16) char sm[];
-    refactor_block<C>(blockIdx.x, gridDim.x, item0, a, nwide, small0, nsmall, c0, c1, sm);
+    refactor_block<C>(blockIdx.x, gridDim.x, item0, a, nwide, small0, nsmall, c0, c1, f, sm);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1325,12 +1355,14 @@ __device__ __forceinline__ double inpanel_backward(const double (&Urow)[kPanelMa
     return xv;
 }
 
+// ext[kPanelMax], blk[kPanelMax * kRowLd] (16-byte aligned) and ys[kSolvePack] are LDS of
+// the caller.  The block has 256 threads or more; threads past 256 take no row and only
+// join the barriers.
 template <bool kWait, class TF>
-__device__ __forceinline__ void lsolve_item(const SolveArgs<TF> &a, int item, double *ext, double *blk) {
+__device__ __forceinline__ void lsolve_item(const SolveArgs<TF> &a, int item, double *ext, double *blk, double *ys) {
     const int4 it = a.item[item];
     const int tid = threadIdx.x, lane = tid & 63;
     if (it.x < 0) {                                     // pack of whole small panels
-        __shared__ double ys[kSolvePack];
         const int lanes = it.z, g = tid / lanes, gl = tid % lanes;
         const int4 rr = g < -it.x ? a.rows[it.y + g] : int4{-1, 0, 0, 0};
         const int t = rr.w & 255;
@@ -1369,7 +1401,7 @@ __device__ __forceinline__ void lsolve_item(const SolveArgs<TF> &a, int item, do
     {
         const int lanes = it.y, t = tid / lanes, gl = tid % lanes;
         const int4 ri = a.rinfo[s + min(t, w - 1)];
-        for (int e = tid; e < w * kPanelMax; e += kBlock) {
+        for (int e = tid; e < w * kPanelMax; e += blockDim.x) {
             const int r = e / kPanelMax, c = e % kPanelMax;
             const int d = a.rinfo[s + r].z;
             blk[r * kRowLd + c] = c < r ? (double)a.lucsr[d - r + c] : 0.0;
@@ -1485,9 +1517,9 @@ __device__ __forceinline__ void usolve_item(const SolveArgs<TF> &a, int item, do
 
 template <class TF>
 __global__ __launch_bounds__(256) void k_lsolve_level(int item0, SolveArgs<TF> a) {
-    __shared__ double ext[kPanelMax];
+    __shared__ double ext[kPanelMax], ys[kSolvePack];
     __shared__ __align__(16) double blk[kPanelMax * kRowLd];
-    lsolve_item<false>(a, item0 + blockIdx.x, ext, blk);
+    lsolve_item<false>(a, item0 + blockIdx.x, ext, blk, ys);
 }
 
 template <class TF>
@@ -1511,31 +1543,46 @@ __global__ __launch_bounds__(256) void k_usolve_level(int item0, SolveArgs<TF> a
 //    is requested at the start of an item and read at its end, so the counter's round trip
 //    overlaps the item's loads; the counter still costs a round trip per item, which is why
 //    the fixed order is kept for a device that the solve has to itself.
-template <bool kFwd, bool kTicket, class TF>
-__device__ __forceinline__ void persistent_items(int i0, int i1, const SolveArgs<TF> &a, int *tick) {
-    __shared__ double ext[kPanelMax];
-    __shared__ __align__(16) double blk[kPanelMax * kRowLd];
-    if constexpr (!kTicket) {
-        for (int item = i0 + blockIdx.x; item < i1; item += gridDim.x) {
-            if constexpr (kFwd) lsolve_item<true>(a, item, ext, blk);
-            else usolve_item<true>(a, item, ext, blk);
-        }
-        return;
-    }
-    __shared__ int next;
-    if (threadIdx.x == 0) next = atomicAdd(tick, 1);
+// LDS of the persistent and fused forward loops: ext, ys, the ticket and the staged panel
+struct SolveLds {
+    double ext[kPanelMax];
+    double ys[kSolvePack];
+    int next;
+    int pad[3];
+    double blk[kPanelMax * kRowLd];
+};
+static_assert(offsetof(SolveLds, blk) % 16 == 0, "the staged panel is read in 16-byte pairs");
+
+// The ticket loop (blocks take items i0 + *tick++ in increasing order, see above) over the
+// forward (kFwd) or backward items [i0, i1).
+template <bool kFwd, class TF>
+__device__ __forceinline__ void ticket_items(int i0, int i1, const SolveArgs<TF> &a, int *tick, SolveLds &L) {
+    if (threadIdx.x == 0) L.next = atomicAdd(tick, 1);
     __syncthreads();
-    int cur = next;
+    int cur = L.next;
     while (i0 + cur < i1) {
         int nt = 0;
         if (threadIdx.x == 0) nt = atomicAdd(tick, 1);
-        if constexpr (kFwd) lsolve_item<true>(a, i0 + cur, ext, blk);
-        else usolve_item<true>(a, i0 + cur, ext, blk);
+        if constexpr (kFwd) lsolve_item<true>(a, i0 + cur, L.ext, L.blk, L.ys);
+        else usolve_item<true>(a, i0 + cur, L.ext, L.blk);
         __syncthreads();                     // every thread is done with the item and `next`
-        if (threadIdx.x == 0) next = nt;
+        if (threadIdx.x == 0) L.next = nt;
         __syncthreads();
-        cur = next;
+        cur = L.next;
     }
+}
+
+template <bool kFwd, bool kTicket, class TF>
+__device__ __forceinline__ void persistent_items(int i0, int i1, const SolveArgs<TF> &a, int *tick) {
+    __shared__ SolveLds L;
+    if constexpr (!kTicket) {
+        for (int item = i0 + blockIdx.x; item < i1; item += gridDim.x) {
+            if constexpr (kFwd) lsolve_item<true>(a, item, L.ext, L.blk, L.ys);
+            else usolve_item<true>(a, item, L.ext, L.blk);
+        }
+        return;
+    }
+    ticket_items<kFwd>(i0, i1, a, tick, L);
 }
 
 template <class TF, bool kTicket>
@@ -1548,14 +1595,24 @@ __global__ __launch_bounds__(256) void k_usolve_persistent(int i0, int i1, Solve
     persistent_items<false, kTicket>(i0, i1, a, a.tick + 1);
 }
 
-// bp = r[P] .* b[P]; with mark, every unknown of the persistent mode starts unset and the
-// item tickets start at zero
+// Block blk of the f.nsolve extra blocks of a refactorization launch that run the items of
+// one forward level (every input final before the launch, as in a level launch), with the
+// launch's dynamic LDS
+template <class T>
+__device__ __forceinline__ void fused_forward_block(const FuseArgs<T> &f, int blk, char *sm) {
+    SolveLds &L = *reinterpret_cast<SolveLds *>(sm);
+    // an item that uses LDS ends with a barrier, so the next one may overwrite it
+    for (int item = f.j0 + blk; item < f.j1; item += f.nsolve) lsolve_item<false>(f.s, item, L.ext, L.blk, L.ys);
+}
+
+// bp = r[P] .* b[P]; with mark, every unknown of the persistent mode starts unset; the
+// first ntick item tickets start at zero (ntick <= n, or the grid covers ntick threads)
 __global__ void k_solve_reset(int n, const double *__restrict__ b, const double *__restrict__ r,
                               const int32_t *__restrict__ P, double *__restrict__ bp, double *__restrict__ y,
                               double *__restrict__ xt, double *__restrict__ psum, double *__restrict__ usum,
-                              int mark, int *__restrict__ tick) {
+                              int mark, int ntick, int *__restrict__ tick) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (mark && i < 2) tick[i] = 0;
+    if (i < ntick) tick[i] = 0;
     if (i < n) {
         const int pi = P[i];
         bp[i] = r[pi] * b[pi];

@@ -33,9 +33,14 @@ struct Dev {
     double *V, *Z, *w, *res, *part, *hbuf, *ybuf;
     DevStatus *st;
     ResNorms *rn;
-    int *tick;          // ticket counters of the persistent solves
+    int *tick;          // ticket counters of the persistent solves (forward, backward, fused tail)
 };
 
+#ifndef KKT_FZ_SOLVE_BLOCKS
+#define KKT_FZ_SOLVE_BLOCKS 256
+#endif
+// most blocks of a refactor launch that run forward-solve items (kkt_refactor_refine)
+constexpr int kFuseSolveBlocks = KKT_FZ_SOLVE_BLOCKS;
 constexpr int kDotBlocks = 512;
 constexpr int kSmallPipeMax = 100000;  // narrow items per level up to which the pipelined variant runs
 constexpr int kNormBlocks = 4096;
@@ -86,6 +91,10 @@ struct kkt_handle {
     hipGraphExec_t levels = nullptr;
     hipEvent_t levels_done = nullptr;   // recorded after every replay, on the caller's stream
     bool levels_failed = false;
+    // kkt_refactor_refine: the level launches with the forward solve riding in them,
+    // recorded at its first call
+    hipGraphExec_t fused = nullptr;
+    bool fused_failed = false;
     // launch profiler
     bool prof = false;
     kkt_profile acc{};
@@ -149,7 +158,7 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.ybuf = c.take<double>((size_t)m + 2);
     d.st = c.take<DevStatus>(1);
     d.rn = c.take<ResNorms>(1);
-    d.tick = c.take<int>(2);
+    d.tick = c.take<int>(3);
     *bytes = c.off + 256;
 }
 
@@ -245,25 +254,28 @@ hipError_t launch_persistent(K kernel, bool ticket, int grid, int i0, int i1, A 
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kernel), dim3(grid), dim3(kBlock), args, 0, s);
 }
 
+// forward = false: the forward part already ran (the fused refactorization), only the
+// backward part is enqueued
 template <class TF>
-int enqueue_solve_t(kkt_handle *h, const double *b, double *x, hipStream_t s) {
+int enqueue_solve_t(kkt_handle *h, const double *b, double *x, hipStream_t s, bool forward) {
     const Schedule &g = h->sch;
     const Dev &d = h->d;
     const int n = h->sym.n;
     const bool pers = h->opts.persistent_solve != 0;
     SolveArgs<TF> a{d.l_item4, d.l_rows4, d.rinfo4, d.csr_col, d.Q, static_cast<const TF *>(d.lucsr), d.c, d.bp, d.y,
                     d.xt, x, d.psum, d.usum, &d.st->abort, d.tick};
-    timed(h, KKT_PROF_LSOLVE, s, [&] {
-        k_solve_reset<<<blocks_for(n, 256), 256, 0, s>>>(n, b, d.r, d.P, d.bp, d.y, d.xt, d.psum, d.usum,
-                                                         pers ? 1 : 0, d.tick);
-    });
+    if (forward)
+        timed(h, KKT_PROF_LSOLVE, s, [&] {
+            k_solve_reset<<<blocks_for(n, 256), 256, 0, s>>>(n, b, d.r, d.P, d.bp, d.y, d.xt, d.psum, d.usum,
+                                                             pers ? 1 : 0, pers ? 2 : 0, d.tick);
+        });
     // forward: level launches below l_split, then the persistent launch
-    const int lsplit = pers ? g.l_split : (int)g.l_lvl.size() - 1;
+    const int lsplit = !forward ? 0 : pers ? g.l_split : (int)g.l_lvl.size() - 1;
     for (int l = 0; l < lsplit; ++l) {
         const int cnt = g.l_lvl[l + 1] - g.l_lvl[l];
         if (cnt) timed(h, KKT_PROF_LSOLVE, s, [&] { k_lsolve_level<TF><<<cnt, kBlock, 0, s>>>(g.l_lvl[l], a); });
     }
-    const int li0 = g.l_lvl[lsplit], li1 = g.l_lvl.back();
+    const int li0 = g.l_lvl[lsplit], li1 = forward ? g.l_lvl.back() : li0;
     if (li1 > li0) {
         hipError_t e = hipSuccess;
         timed(h, KKT_PROF_LSOLVE, s,
@@ -298,8 +310,8 @@ int enqueue_solve_t(kkt_handle *h, const double *b, double *x, hipStream_t s) {
     return KKT_OK;
 }
 
-int enqueue_solve(kkt_handle *h, const double *b, double *x, hipStream_t s) {
-    return by_precision(h, [&](auto tag) { return enqueue_solve_t<decltype(tag)>(h, b, x, s); });
+int enqueue_solve(kkt_handle *h, const double *b, double *x, hipStream_t s, bool forward = true) {
+    return by_precision(h, [&](auto tag) { return enqueue_solve_t<decltype(tag)>(h, b, x, s, forward); });
 }
 
 // value update: scale factors, scaled values scattered into the factor, norms
@@ -329,10 +341,23 @@ int enqueue_update(kkt_handle *h, const double *v, hipStream_t s) {
     return KKT_OK;
 }
 
+// extra blocks of `threads` threads of a refactor launch that copy `entries` entries of the
+// row-ordered factor (they run after the factor work of the launch, in its tail)
+int copy_blocks(const kkt_handle *h, int entries, int threads) {
+    return entries > 0 ? std::min(4 * h->ncu, (int)blocks_for(entries, threads)) : 0;
+}
+
 // the level launches of the refactorization, the row-ordered copy and the pivot count; they
-// read only workspace buffers, so one recording serves every later call
+// read only workspace buffers, so one recording serves every later call.
+// fused: the forward solve of the right-hand side set up by k_solve_reset rides in the same
+// launches, so no launch waits on another queue.  Each launch has extra blocks that copy the
+// entries of the columns finished by the launches before it into the row-ordered copy; each
+// wide launch also has extra blocks that run the next forward level once every column its
+// items read was copied by an earlier launch (its lower levels ran in earlier launches; its
+// items are independent, as in a level launch).  What is left after the last level runs in
+// a copy launch and a ticket-ordered forward launch of its own.
 template <class T>
-int enqueue_levels_t(kkt_handle *h, hipStream_t s) {
+int enqueue_levels_t(kkt_handle *h, hipStream_t s, bool fused) {
     using Big = BigCfg<T>;
     using Med = MedCfg<T>;
     using W256 = W256Cfg<T>;
@@ -342,59 +367,89 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s) {
     RefArgs<T> a{d.ldiag, d.itemrec, d.pair8, d.f_rel, static_cast<T *>(d.lu), d.st, d.pcount,
                  tiny, h->opts.dense_mfma != 0, d.copy_k, d.csr_src, static_cast<T *>(d.lucsr),
                  d.pan_start, d.pan_r};
-    const int ncopy = (int)g.copy_ptr.size() - 1;   // launches that carry a chunk of the copy
-    for (size_t l = 0; l + 1 < g.f_lvl.size(); ++l) {
+    const int nlev = (int)g.f_lvl.size() - 1;
+    const int ncopy = fused ? 0 : (int)g.copy_ptr.size() - 1;   // launches that carry a chunk of the copy
+    const SolveArgs<T> fs{d.l_item4, d.l_rows4, d.rinfo4, d.csr_col, d.Q, static_cast<const T *>(d.lucsr), d.c,
+                          d.bp, d.y, d.xt, nullptr, d.psum, d.usum, &d.st->abort, d.tick + 2};
+    const int nfl = (int)g.l_lvl.size() - 1;
+    int copied = 0, solved = 0;   // fused: levels whose columns a launch copies, forward levels launched
+    for (int l = 0; l < nlev; ++l) {
         // the kinds of items of a level touch disjoint target columns, so one launch runs the
         // wide items (32- or 16-column configuration) and the narrow ones together; a level
         // without wide items has a launch of the narrow kernel
         const int nm = g.f_nmed[l], nb = g.f_nlarge[l] - nm, ns = g.f_lvl[l + 1] - g.f_lvl[l] - nb - nm;
         const int i0 = g.f_lvl[l];
-        if (ns && !nb && !nm)
+        if (ns && !nb && !nm) {
+            // with fused, extra blocks copy the columns of the levels since the last launch
+            const int c0 = fused ? g.copy_at[copied] : 0, c1 = fused ? g.copy_at[l] : 0;
+            if (fused) copied = l;
+            const int grid = (int)blocks_for(ns, kBlock / 16) + copy_blocks(h, c1 - c0, kBlock);
             timed(h, KKT_PROF_REFACTOR_SMALL, s, [&] {
                 // many items: keep more in flight; few: shorten each item's dependent chain
                 if (ns > kSmallPipeMax)
-                    k_refactor_small<T, false><<<blocks_for(ns, kBlock / 16), kBlock, 0, s>>>(i0, ns, a);
+                    k_refactor_small<T, false><<<grid, kBlock, 0, s>>>(i0, ns, a, c0, c1);
                 else
-                    k_refactor_small<T, true><<<blocks_for(ns, kBlock / 16), kBlock, 0, s>>>(i0, ns, a);
+                    k_refactor_small<T, true><<<grid, kBlock, 0, s>>>(i0, ns, a, c0, c1);
             });
-        // otherwise the narrow items are extra blocks of the level's first wide launch, and so
-        // is a chunk of the row-ordered copy on the top levels (columns already final)
+        }
+        if (!nb && !nm) continue;
+        // otherwise the narrow items are extra blocks of the level's wide launch, and so is a
+        // chunk of the row-ordered copy (columns already final): on the top levels, or with
+        // fused the columns of the levels since the last wide launch
         const int s0 = i0 + nb + nm, mb = nb ? ns : 0, mm = nb ? 0 : ns;
-        const int cc = (int)l - g.copy_lvl;
-        const bool copy = cc >= 0 && cc < ncopy && (nb || nm);
-        const int c0 = copy ? g.copy_ptr[cc] : 0, c1 = copy ? g.copy_ptr[cc + 1] : 0;
-        const int cb = c1 > c0 ? h->ncu : 0;
+        const int cc = l - g.copy_lvl;
+        const bool copy = cc >= 0 && cc < ncopy;
+        int c0 = copy ? g.copy_ptr[cc] : 0, c1 = copy ? g.copy_ptr[cc + 1] : 0;
+        FuseArgs<T> f{fs, 0, 0, 0};
+        if (fused) {
+            if (kFuseSolveBlocks > 0 && solved < nfl && g.l_ready[solved] < copied) {
+                f.j0 = g.l_lvl[solved];
+                f.j1 = g.l_lvl[solved + 1];
+                f.nsolve = std::min(f.j1 - f.j0, kFuseSolveBlocks);
+                ++solved;
+            }
+            c0 = g.copy_at[copied];
+            c1 = g.copy_at[l];
+            copied = l;
+        }
+        const int threads = nb ? (g.f_w256[l] ? W256::kThreads : Big::kThreads) : Med::kThreads;
+        const int cb = copy_blocks(h, c1 - c0, threads);
         if (nb && g.f_w256[l])
             timed(h, KKT_PROF_REFACTOR_W256, s, [&] {
-                const int grid = nb + (int)blocks_for(mb, W256::kThreads / 16) + cb;
-                k_refactor_wide<W256><<<grid, W256::kThreads, W256::kLds, s>>>(i0, a, nb, s0, mb, c0, c1);
+                const int grid = nb + (int)blocks_for(mb, W256::kThreads / 16) + f.nsolve + cb;
+                k_refactor_wide<W256><<<grid, W256::kThreads, W256::kLds, s>>>(i0, a, nb, s0, mb, c0, c1, f);
             });
         else if (nb)
             timed(h, KKT_PROF_REFACTOR_LARGE, s, [&] {
-                const int grid = nb + (int)blocks_for(mb, Big::kThreads / 16) + cb;
-                k_refactor_wide<Big><<<grid, Big::kThreads, Big::kLds, s>>>(i0, a, nb, s0, mb, c0, c1);
+                const int grid = nb + (int)blocks_for(mb, Big::kThreads / 16) + f.nsolve + cb;
+                k_refactor_wide<Big><<<grid, Big::kThreads, Big::kLds, s>>>(i0, a, nb, s0, mb, c0, c1, f);
             });
-        if (nm)
+        else
             timed(h, KKT_PROF_REFACTOR_MEDIUM, s, [&] {
-                const int grid = nm + (int)blocks_for(mm, Med::kThreads / 16) + (nb ? 0 : cb);
-                k_refactor_wide<Med><<<grid, Med::kThreads, Med::kLds, s>>>(i0 + nb, a, nm, s0, mm, nb ? 0 : c0,
-                                                                          nb ? 0 : c1);
+                const int grid = nm + (int)blocks_for(mm, Med::kThreads / 16) + f.nsolve + cb;
+                k_refactor_wide<Med><<<grid, Med::kThreads, Med::kLds, s>>>(i0, a, nm, s0, mm, c0, c1, f);
             });
     }
-    {
-        // the rest of the copy: the columns of the top levels (all of it without such levels)
-        const int q0 = ncopy > 0 ? g.copy_ptr.back() : 0, q1 = (int)g.copy_k.size();
-        if (q1 > q0)
-            timed(h, KKT_PROF_TO_CSR, s,
-                  [&] { k_to_csr<T><<<blocks_for(q1 - q0, 256), 256, 0, s>>>(q0, q1, d.copy_k, d.csr_src, a.lu, a.lucsr); });
+    // the rest of the copy: the columns of the top levels (all of it without such levels), or
+    // with fused the columns of the levels since the last wide launch; then the remaining
+    // forward levels
+    const int q0 = fused ? g.copy_at[copied] : ncopy > 0 ? g.copy_ptr.back() : 0, q1 = (int)g.copy_k.size();
+    if (q1 > q0)
+        timed(h, KKT_PROF_TO_CSR, s,
+              [&] { k_to_csr<T><<<blocks_for(q1 - q0, 256), 256, 0, s>>>(q0, q1, d.copy_k, d.csr_src, a.lu, a.lucsr); });
+    if (fused && solved < nfl) {
+        const int j0 = g.l_lvl[solved], j1 = g.l_lvl[nfl];
+        timed(h, KKT_PROF_LSOLVE, s, [&] {
+            k_lsolve_persistent<T, true><<<std::min(j1 - j0, h->grid_l), kBlock, 0, s>>>(j0, j1, fs);
+        });
     }
     timed(h, KKT_PROF_UPDATE, s, [&] { k_sum_counts<<<1, 256, 0, s>>>(d.pcount, &d.st->perturbed); });
     HIPCHK(hipGetLastError());
     return KKT_OK;
 }
 
-int enqueue_levels(kkt_handle *h, hipStream_t s) {
-    return by_precision(h, [&](auto tag) { return enqueue_levels_t<decltype(tag)>(h, s); });
+int enqueue_levels(kkt_handle *h, hipStream_t s, bool fused = false) {
+    return by_precision(h, [&](auto tag) { return enqueue_levels_t<decltype(tag)>(h, s, fused); });
 }
 
 // dst[0..nv) = V[0..nv) . w  (deterministic two-pass reduction)
@@ -405,8 +460,10 @@ void enqueue_dots(kkt_handle *h, int nv, const double *V, const double *w, doubl
     timed(h, KKT_PROF_KRYLOV, s, [&] { k_reduce_parts<<<nv, 256, 0, s>>>(nv, kDotBlocks, h->d.part, dst, accumulate); });
 }
 
-// infinity norms of b - A x into the status block; returns berr on the host
-int residual_berr(kkt_handle *h, const double *x, const double *b, double *berr, double *den, hipStream_t s) {
+// infinity norms of b - A x into the status block; returns berr on the host (and the
+// status block read with it in *sto)
+int residual_berr(kkt_handle *h, const double *x, const double *b, double *berr, double *den, hipStream_t s,
+                  DevStatus *sto = nullptr) {
     const Dev &d = h->d;
     const int n = h->sym.n;
     timed(h, KKT_PROF_RESIDUAL, s, [&] {
@@ -420,6 +477,7 @@ int residual_berr(kkt_handle *h, const double *x, const double *b, double *berr,
     ResNorms rn;
     std::memcpy(&st, h->h_small, sizeof(st));
     std::memcpy(&rn, h->h_small + 8, sizeof(rn));
+    if (sto) *sto = st;
     if (st.abort) return KKT_ERR_DEVICE;
     *den = st.anorm * rn.xnorm + rn.bnorm;
     if (*den == 0.0) *berr = rn.rnorm == 0.0 ? 0.0 : INFINITY;
@@ -439,7 +497,7 @@ int enqueue_approx_solve_t(kkt_handle *h, const double *b, double *x, int sweeps
     const unsigned nb8 = blocks_for((int64_t)n * 8, 256), nb = blocks_for(n, 256);
     const unsigned nch = blocks_for(n, kGsChunk);
     timed(h, KKT_PROF_LSOLVE, s, [&] {
-        k_solve_reset<<<nb, 256, 0, s>>>(n, b, d.r, d.P, d.bp, d.y, d.xt, d.psum, d.usum, 0, d.tick);
+        k_solve_reset<<<nb, 256, 0, s>>>(n, b, d.r, d.P, d.bp, d.y, d.xt, d.psum, d.usum, 0, 0, d.tick);
     });
     const double *yin = nullptr;
     double *ybuf[2] = {d.psum, d.y};
@@ -470,20 +528,36 @@ int enqueue_approx_solve(kkt_handle *h, const double *b, double *x, int sweeps, 
     return by_precision(h, [&](auto tag) { return enqueue_approx_solve_t<decltype(tag)>(h, b, x, sweeps, s); });
 }
 
-int fgmres_column(kkt_handle *h, const double *b, double *x, kkt_info *info, hipStream_t s) {
+// FGMRES on one column from the first solve x = M^-1 b.  fused: the refactorization and the
+// forward part of that solve were enqueued together; the backward part is enqueued here and
+// the factorization's status is checked with the first residual (a failed factorization
+// returns its error with info = {0, error, inf, perturbed pivots}, as kkt_refine does).
+int fgmres_column(kkt_handle *h, const double *b, double *x, kkt_info *info, hipStream_t s, bool fused = false) {
     const Dev &d = h->d;
     const int n = h->sym.n;
     const int m = h->opts.gmres_restart;
     const double tol = h->opts.berr_tol;
-    int rc = enqueue_solve(h, b, x, s);
+    int rc = enqueue_solve(h, b, x, s, !fused);
     if (rc) return rc;
+    int64_t pert = 0;
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1), yv(m);
     int it = 0;
     double berr = 0.0, den = 0.0;
     int status = KKT_OK;
     const unsigned nb = blocks_for(n, 256);
-    for (;;) {
-        rc = residual_berr(h, x, b, &berr, &den, s);
+    for (bool first = true;; first = false) {
+        DevStatus st{};
+        rc = residual_berr(h, x, b, &berr, &den, s, &st);
+        if (fused && first) {
+            pert = (int64_t)st.perturbed;
+            const int fst = ((st.flags & kFlagInternal) || st.abort) ? KKT_ERR_DEVICE
+                            : (st.flags & kFlagNonfinite)            ? KKT_ERR_NONFINITE
+                                                                     : KKT_OK;
+            if (fst < 0) {
+                if (info) *info = kkt_info{0, fst, INFINITY, pert};
+                return fst;
+            }
+        }
         if (rc) return rc;
         if (berr <= tol) { status = KKT_OK; break; }
         if (it >= h->opts.max_iters || !std::isfinite(berr)) { status = KKT_WARN_NOT_CONVERGED; break; }
@@ -550,6 +624,7 @@ int fgmres_column(kkt_handle *h, const double *b, double *x, kkt_info *info, hip
         info->iters = it;
         info->berr = berr;
         info->status = status;
+        if (fused) info->perturbed_pivots = pert;
     }
     return status;
 }
@@ -703,6 +778,17 @@ void release_scratch_locked(kkt_handle *h) {
     h->on_scratch = false;
 }
 
+// drops the recorded graphs (their addresses belong to the current workspace); the last
+// replay may still run on a caller's stream
+int drop_graphs(kkt_handle *h) {
+    if (h->levels || h->fused) HIPCHK(hipEventSynchronize(h->levels_done));
+    if (h->levels) HIPCHK(hipGraphExecDestroy(h->levels));
+    if (h->fused) HIPCHK(hipGraphExecDestroy(h->fused));
+    h->levels = nullptr;
+    h->fused = nullptr;
+    return KKT_OK;
+}
+
 // Common part of kkt_bind and kkt_bind_scratch: checks the size, records the device,
 // uploads the structure into ws and waits.  no_alloc: take no pinned buffer, create no
 // stream, event or graph (the level launches then go one by one).
@@ -747,12 +833,12 @@ int bind_common(kkt_handle *h, char *ws, size_t bytes, int32_t max_nrhs, hipStre
     if (!h->h_pinned && !no_alloc)
         HIPCHK(hipHostMalloc(&h->h_pinned, sizeof(double) * 4 * (kMaxRestart + 2) + 256));
     h->h_small = h->h_pinned ? h->h_pinned : h->h_stage;
-    if (h->levels) {   // recorded with the previous workspace's addresses; the last replay
-        HIPCHK(hipEventSynchronize(h->levels_done));   // may still run on a caller's stream
-        HIPCHK(hipGraphExecDestroy(h->levels));
-        h->levels = nullptr;
+    {
+        const int rc = drop_graphs(h);   // recorded with the previous workspace's addresses
+        if (rc) return rc;
     }
     h->levels_failed = false;
+    h->fused_failed = false;
     if (!no_alloc) {
         if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
         if (!h->levels_done) HIPCHK(hipEventCreateWithFlags(&h->levels_done, hipEventDisableTiming));
@@ -867,6 +953,34 @@ void record_levels(kkt_handle *h) {
     if (graph) (void)hipGraphDestroy(graph);
 }
 
+// records the level launches with the forward solve riding in them into h->fused; on any
+// failure kkt_refactor_refine runs the two calls
+void record_fused(kkt_handle *h) {
+    hipGraph_t graph = nullptr;
+    bool ok = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        const int rc = enqueue_levels(h, h->cap, true);
+        const hipError_t e = hipStreamEndCapture(h->cap, &graph);
+        ok = rc == KKT_OK && e == hipSuccess && graph &&
+             hipGraphInstantiate(&h->fused, graph, nullptr, nullptr, 0) == hipSuccess;
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        h->fused = nullptr;
+        h->fused_failed = true;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+}
+
+// whether kkt_refactor_refine can replay the fused graph on s (recording it if needed)
+bool fused_ready(kkt_handle *h, hipStream_t s) {
+    if (!h->opts.graph_refactor || h->prof || h->fused_failed || h->on_scratch) return false;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+    if (!h->fused) record_fused(h);
+    return h->fused != nullptr;
+}
+
 int run_levels(kkt_handle *h, hipStream_t s) {
     if (h->opts.graph_refactor && !h->prof && !h->levels_failed && !h->on_scratch) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -896,6 +1010,40 @@ int kkt_refactor(kkt_handle *h, const double *d_values, hipStream_t stream) {
     h->d_values = d_values;
     h->factored = true;
     return KKT_OK;
+}
+
+int kkt_refactor_refine(kkt_handle *h, const double *d_values, const double *d_b, double *d_x, kkt_info *info,
+                        hipStream_t stream) {
+    if (!h || !d_values || !d_b || !d_x) return KKT_ERR_ARG;
+    if (!h->bound) return KKT_ERR_STATE;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return KKT_ERR_DEVICE;
+    if (!fused_ready(h, stream)) {
+        const int rc = kkt_refactor(h, d_values, stream);
+        return rc ? rc : kkt_refine(h, d_b, d_x, 1, h->sym.n, info, stream);
+    }
+    const Dev &d = h->d;
+    const int n = h->sym.n;
+    const double *b = d_b;
+    if (b == d_x) {   // the residuals read b after x is written
+        HIPCHK(hipMemcpyAsync(d.bsave, b, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
+        b = d.bsave;
+    }
+    int rc = enqueue_update(h, d_values, stream);
+    if (rc) return rc;
+    // bp, the unset unknowns and the tickets (the forward tail's included), then the graph
+    const int ntick = 3;
+    k_solve_reset<<<blocks_for(std::max(n, ntick), 256), 256, 0, stream>>>(n, b, d.r, d.P, d.bp, d.y, d.xt, d.psum,
+                                                                          d.usum, 1, ntick, d.tick);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipGraphLaunch(h->fused, stream));
+    HIPCHK(hipEventRecord(h->levels_done, stream));
+    h->d_values = d_values;
+    h->factored = true;
+    kkt_info inf{};
+    rc = fgmres_column(h, b, d_x, &inf, stream, true);
+    if (info && (rc >= 0 || inf.status < 0)) *info = inf;   // a failed factorization fills inf
+    return rc;
 }
 
 int kkt_refactor_status(kkt_handle *h, int64_t *perturbed, hipStream_t stream) {
@@ -991,10 +1139,9 @@ namespace {
 // drops the device binding of h (after its last work finished): the recorded graph goes,
 // the workspace is no longer used
 int unbind(kkt_handle *h) {
-    if (h->levels) {
-        HIPCHK(hipEventSynchronize(h->levels_done));
-        HIPCHK(hipGraphExecDestroy(h->levels));
-        h->levels = nullptr;
+    {
+        const int rc = drop_graphs(h);
+        if (rc) return rc;
     }
     {
         std::lock_guard<std::mutex> lk(g_scratch_mu);
@@ -1156,6 +1303,7 @@ void kkt_destroy(kkt_handle *h) {
         for (auto &pe : h->ev_pending) (void)hipEventSynchronize(pe.second.second);
         if (h->cap) (void)hipStreamSynchronize(h->cap);
         if (h->levels) (void)hipGraphExecDestroy(h->levels);
+        if (h->fused) (void)hipGraphExecDestroy(h->fused);
         if (h->cap) (void)hipStreamDestroy(h->cap);
         if (h->levels_done) (void)hipEventDestroy(h->levels_done);
         for (auto &pe : h->ev_pending) h->ev_free.push_back(pe.second);

@@ -573,24 +573,76 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
     }
     g.flops = fl;
     // the row-ordered copy of the factor: an entry can be copied once its column is final,
-    // i.e. after the launch that factors the column's panel.  The top levels have few items
-    // and leave most of the GPU idle, so the entries of every column final before the first
-    // of them are copied by extra blocks of up to kCopyLaunches of those launches (in
-    // consecutive chunks); the rest after the last level
+    // i.e. after the launch that factors the column's panel.  copy_k lists the entries by the
+    // launch that finishes their column (copy_at[l] = first entry of launch l), in CSR
+    // order within a launch.  The top levels have few items and leave most of the GPU idle, so the
+    // entries of every column final before the first of them are copied by extra blocks of up
+    // to kCopyLaunches of those launches (in consecutive chunks); the rest after the last level
+    const int32_t nlev_f = (int32_t)g.f_lvl.size() - 1;
     {
-        const int32_t nlev = (int32_t)g.f_lvl.size() - 1;
-        int32_t win = nlev;
+        int32_t win = nlev_f;
         while (win > 0 && g.f_lvl[win] - g.f_lvl[win - 1] <= kCopyItems && g.f_nlarge[win - 1] > 0) --win;
-        const int32_t nwin = std::min<int32_t>(kCopyLaunches, nlev - win);
+        const int32_t nwin = std::min<int32_t>(kCopyLaunches, nlev_f - win);
         g.copy_lvl = win;
-        g.copy_k.clear();
+        g.copy_at.assign(nlev_f + 1, 0);
+        for (int64_t q = 0; q < nlu; ++q) g.copy_at[plev[pan_of[g.csr_col[q]]] + 1]++;
+        for (int32_t l = 0; l < nlev_f; ++l) g.copy_at[l + 1] += g.copy_at[l];
+        g.copy_k.resize(nlu);
+        {
+            std::vector<int32_t> nxt(g.copy_at.begin(), g.copy_at.end() - 1);
+            for (int64_t q = 0; q < nlu; ++q) g.copy_k[nxt[plev[pan_of[g.csr_col[q]]]]++] = (int32_t)q;
+        }
         g.copy_ptr.assign(1, 0);
-        std::vector<int32_t> late;
-        for (int64_t q = 0; q < nlu; ++q)
-            (nwin > 0 && plev[pan_of[g.csr_col[q]]] < win ? g.copy_k : late).push_back((int32_t)q);
-        const int64_t ne = (int64_t)g.copy_k.size();
+        const int64_t ne = nwin > 0 ? g.copy_at[win] : 0;
         for (int32_t c = 1; c <= nwin; ++c) g.copy_ptr.push_back((int32_t)(ne * c / nwin));
-        g.copy_k.insert(g.copy_k.end(), late.begin(), late.end());
+    }
+    // forward solve fused with the refactorization: the ready launch of a forward item is the
+    // latest launch that finishes a column whose entries it reads (its own panel's included)
+    // or that is the ready launch of an item whose unknowns or partial sums it reads;
+    // l_ready[k] = the latest ready launch of the items of forward level k
+    {
+        const int32_t nit = (int32_t)(g.l_item4.size() / 4);
+        std::vector<int32_t> yprod(n, -1), hprod(n, -1), rl(nit, 0);
+        bool okp = true;
+        auto ready = [&](int32_t q0, int32_t q1, int32_t r) {
+            for (int32_t q = q0; q < q1; ++q) {
+                const int32_t j = g.csr_col[q];
+                r = std::max(r, plev[pan_of[j]]);
+                if (yprod[j] < 0) okp = false;
+                else r = std::max(r, rl[yprod[j]]);
+            }
+            return r;
+        };
+        for (int32_t it = 0; it < nit; ++it) {
+            const int32_t *c = &g.l_item4[4 * (size_t)it];
+            int32_t r = 0;
+            if (c[0] < 0) {                      // pack: rows {row, first external, end external, t|w<<8}
+                for (int32_t k = 0; k < -c[0]; ++k) {
+                    const int32_t *rr = &g.l_rows4[4 * (size_t)(c[1] + k)];
+                    r = ready(rr[1], rr[2], std::max(r, plev[pan_of[rr[0]]]));
+                }
+                for (int32_t k = 0; k < -c[0]; ++k) yprod[g.l_rows4[4 * (size_t)(c[1] + k)]] = it;
+            } else if (c[0] == 0) {              // helper: early entries of kHelpRows rows
+                for (int32_t t = c[1]; t < std::min(c[3], c[1] + kHelpRows); ++t) {
+                    const int32_t i = c[2] + t;
+                    r = ready(g.rinfo4[4 * (size_t)i], g.rinfo4[4 * (size_t)i + 1], r);
+                }
+                for (int32_t t = c[1]; t < std::min(c[3], c[1] + kHelpRows); ++t) hprod[c[2] + t] = it;
+            } else {                             // wide panel: late external entries, partial sums
+                r = plev[pan_of[c[2]]];
+                for (int32_t t = 0; t < c[3]; ++t) {
+                    const int32_t i = c[2] + t;
+                    r = ready(g.rinfo4[4 * (size_t)i + 1], g.rinfo4[4 * (size_t)i + 2] - t, r);
+                    if (hprod[i] >= 0) r = std::max(r, rl[hprod[i]]);
+                }
+                for (int32_t t = 0; t < c[3]; ++t) yprod[c[2] + t] = it;
+            }
+            rl[it] = r;
+        }
+        if (!okp) return KKT_ERR_SCHEDULE;
+        g.l_ready.assign(g.l_lvl.size() - 1, 0);
+        for (size_t k = 0; k + 1 < g.l_lvl.size(); ++k)
+            for (int32_t it = g.l_lvl[k]; it < g.l_lvl[k + 1]; ++it) g.l_ready[k] = std::max(g.l_ready[k], rl[it]);
     }
     // per launch kind: the 512-thread launch of a level factors its wide items and its narrow
     // ones, the 256-thread launch its medium items and (with no 512-thread launch) the narrow
