@@ -14,9 +14,10 @@ namespace kkt {
 template <class T>
 struct BatchSys {
     RefArgs<T> ref;
-    const int32_t *a_rowptr, *a_colind, *a_cptr, *a_cpos, *a_crow, *a_map, *lu_fill;
+    const int32_t *a_rowptr, *a_colind, *colptr, *Q;
+    const int2 *lu_src;
     double *r, *c, *part;
-    int64_t nfill;
+    int16_t *er, *ec;
     int n, eq, nb_norm, q0, q1;
 };
 
@@ -47,7 +48,7 @@ __global__ __launch_bounds__(256) void k_batch_rows(const BatchSys<T> *__restric
                                                     const double *const *__restrict__ vals) {
     const BatchPart P = parts[find_part(parts, nparts, blockIdx.x)];
     const BatchSys<T> &S = sys[P.sys];
-    row_scale_body(blockIdx.x - P.blk0, S.n, S.a_rowptr, vals[P.sys], S.eq, S.r, S.ref.st);
+    row_scale_body(blockIdx.x - P.blk0, S.n, S.a_rowptr, vals[P.sys], S.eq, S.r, S.er, S.ref.st);
 }
 
 template <class T>
@@ -56,17 +57,17 @@ __global__ __launch_bounds__(256) void k_batch_cols(const BatchSys<T> *__restric
                                                     const double *const *__restrict__ vals) {
     const BatchPart P = parts[find_part(parts, nparts, blockIdx.x)];
     const BatchSys<T> &S = sys[P.sys];
-    col_scale_body(blockIdx.x - P.blk0, S.n, S.a_cptr, S.a_cpos, S.a_crow, vals[P.sys], S.r, S.eq, S.c);
+    col_store_body<T>(blockIdx.x - P.blk0, S.n, S.colptr, S.lu_src, S.Q, vals[P.sys], S.er, S.eq, S.c, S.ec,
+                      S.ref.lu);
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_batch_scatter(const BatchSys<T> *__restrict__ sys,
+__global__ __launch_bounds__(256) void k_batch_rowsums(const BatchSys<T> *__restrict__ sys,
                                                        const BatchPart *__restrict__ parts, int nparts,
                                                        const double *const *__restrict__ vals) {
     const BatchPart P = parts[find_part(parts, nparts, blockIdx.x)];
     const BatchSys<T> &S = sys[P.sys];
-    scatter_norms_body<T>(blockIdx.x - P.blk0, P.nblk, S.n, S.a_rowptr, S.a_colind, vals[P.sys], S.r, S.c, S.a_map,
-                          S.nfill, S.lu_fill, S.ref.lu, S.part);
+    norms_body(blockIdx.x - P.blk0, P.nblk, S.n, S.a_rowptr, S.a_colind, vals[P.sys], S.r, S.ec, S.part);
 }
 
 template <class T>
@@ -148,18 +149,17 @@ BatchSys<T> batch_sys(const kkt_handle *h) {
                        d.pan_start, d.pan_r};
     b.a_rowptr = d.a_rowptr;
     b.a_colind = d.a_colind;
-    b.a_cptr = d.a_cptr;
-    b.a_cpos = d.a_cpos;
-    b.a_crow = d.a_crow;
-    b.a_map = d.a_map;
-    b.lu_fill = d.lu_fill;
+    b.colptr = d.colptr;
+    b.Q = d.Q;
+    b.lu_src = d.lu_src;
     b.r = d.r;
     b.c = d.c;
+    b.er = d.er;
+    b.ec = d.ec;
     b.part = d.part;
-    b.nfill = (int64_t)g.lu_fill.size();
     b.n = h->sym.n;
     b.eq = h->opts.equilibrate != 0;
-    b.nb_norm = (int)std::min<int64_t>(kNormBlocks, std::max<int64_t>(1, (h->sym.n + 255) / 256));
+    b.nb_norm = norm_blocks(h->sym.n);
     const int ncopy = (int)g.copy_ptr.size() - 1;
     b.q0 = ncopy > 0 ? g.copy_ptr.back() : 0;
     b.q1 = (int)g.copy_k.size();
@@ -198,9 +198,8 @@ int batch_build(kkt_batch *b, std::vector<BatchPart> &parts, std::vector<char> &
         return ps;
     };
     add(0, {});
-    const auto rows = shares([&](int i, BatchPart &) { return (int)blocks_for((int64_t)sys[i].n * 8, 256); });
-    add(1, rows);
-    add(2, rows);
+    add(1, shares([&](int i, BatchPart &) { return row_blocks(sys[i].n); }));
+    add(2, shares([&](int i, BatchPart &) { return col_blocks(sys[i].n); }));
     add(3, shares([&](int i, BatchPart &) { return sys[i].nb_norm; }));
     add(4, {});
     int nlev = 0;
@@ -238,7 +237,7 @@ int batch_enqueue(kkt_batch *b, hipStream_t s) {
             case 0: k_batch_clear<T><<<L.grid, 256, 0, s>>>(sys); break;
             case 1: k_batch_rows<T><<<L.grid, 256, 0, s>>>(sys, p, L.np, b->d_vals); break;
             case 2: k_batch_cols<T><<<L.grid, 256, 0, s>>>(sys, p, L.np, b->d_vals); break;
-            case 3: k_batch_scatter<T><<<L.grid, 256, 0, s>>>(sys, p, L.np, b->d_vals); break;
+            case 3: k_batch_rowsums<T><<<L.grid, 256, 0, s>>>(sys, p, L.np, b->d_vals); break;
             case 4: k_batch_norms<T><<<L.grid, 256, 0, s>>>(sys); break;
             case 5: k_batch_level<Big><<<L.grid, Big::kThreads, Big::kLds, s>>>(sys, p, L.np); break;
             case 6: k_batch_copy<T><<<L.grid, 256, 0, s>>>(sys, p, L.np); break;

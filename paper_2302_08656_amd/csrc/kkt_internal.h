@@ -145,10 +145,9 @@ struct Schedule {
     std::vector<int32_t> csr_rowptr, csr_col, csr_src, csr_diag, csr_early, csr_uearly;
     // int32 row pointers of A and column pointers of L+U, as uploaded
     std::vector<int32_t> a_rowptr32, colptr32;
-    // value update: the L+U slot of each entry of A (CSR order) and the fill-in slots
-    std::vector<int32_t> a_map, lu_fill;
-    // CSC view of A's pattern (positions into the CSR value array, rows)
-    std::vector<int32_t> a_cptr, a_cpos, a_crow;
+    // value update: per L+U slot {position of its entry in A's CSR value array or -1 for
+    // fill-in, that entry's row of A}
+    std::vector<int32_t> lu_src;
     double flops = 0.0;
     int64_t nnz_lu_wide = 0;            // L+U entries of columns factored by 512-thread launches
     int64_t nnz_lu_med = 0;             // ... by 256-thread launches of panels up to 16 columns

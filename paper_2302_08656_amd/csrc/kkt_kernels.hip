@@ -35,12 +35,16 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-__device__ __forceinline__ double inv_pow2_floor_log2(double m) {
-    if (!(m > 0.0)) return 1.0;
-    int e = ilogb(m);
-    e = e > 1020 ? 1020 : (e < -1020 ? -1020 : e);
-    return ldexp(1.0, -e);
+// the equilibration scale 2^-floor(log2 m) (1 for m <= 0 or NaN) is kept as its exponent e,
+// clamped to +-1020 so that 2^-e is a normal number; scale_of(e) rebuilds the scale exactly
+__device__ __forceinline__ int pow2_floor_log2(double m) {
+    if (!(m > 0.0)) return 0;
+    const int e = ilogb(m);
+    return e > 1020 ? 1020 : (e < -1020 ? -1020 : e);
 }
+__device__ __forceinline__ double scale_of(int e) { return ldexp(1.0, -e); }
+__device__ __forceinline__ double inv_pow2_floor_log2(double m) { return scale_of(pow2_floor_log2(m)); }
+
 
 // max of non-negative doubles through their ordered bit patterns
 __device__ __forceinline__ void atomic_max_pos(double *addr, double v) {
@@ -72,101 +76,178 @@ __global__ __launch_bounds__(256) void k_clear_status(DevStatus *st, unsigned lo
     clear_status_body(st, pcount);
 }
 
-// r_i = 2^-floor(log2 max_j |a_ij|), 8 lanes per row; a non-finite value raises the flag
+// Rows of the update passes taken by one group of 8 lanes: the group issues the loads of
+// all its rows together, so a wavefront has that many times more loads in flight (the passes
+// are bound by the latency of their dependent loads, not by bandwidth).
+constexpr int kRowsPerGroup = 4;
+
+// the row pointers of rows i0 .. i0 + kRowsPerGroup (0 past n)
+__device__ __forceinline__ void group_rows(const int32_t *__restrict__ rowptr, int n, int i0,
+                                           int (&rp)[kRowsPerGroup + 1]) {
+#pragma unroll
+    for (int k = 0; k <= kRowsPerGroup; ++k) rp[k] = i0 + k <= n ? rowptr[i0 + k] : 0;
+}
+
+// r_i = 2^-floor(log2 max_j |a_ij|), 8 lanes per row, kRowsPerGroup rows per group; a
+// non-finite value raises the flag
 __device__ __forceinline__ void row_scale_body(int blk, int n, const int32_t *__restrict__ rowptr,
                                                const double *__restrict__ v, int scale, double *__restrict__ r,
-                                               DevStatus *st) {
+                                               int16_t *__restrict__ er, DevStatus *st) {
     const int gid = blk * blockDim.x + threadIdx.x;
-    const int i = gid >> 3, gl = gid & 7;
-    double m = 0.0;
+    const int i0 = (gid >> 3) * kRowsPerGroup, gl = gid & 7;
+    int rp[kRowsPerGroup + 1];
+    group_rows(rowptr, n, i0, rp);
+    double m[kRowsPerGroup];
     int bad = 0;
-    if (i < n)
-        for (int p = rowptr[i] + gl; p < rowptr[i + 1]; p += 8) {
+#pragma unroll
+    for (int k = 0; k < kRowsPerGroup; ++k) {
+        const int p = rp[k] + gl;
+        m[k] = p < rp[k + 1] ? fabs(v[p]) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kRowsPerGroup; ++k) {
+        bad |= !isfinite(m[k]);
+        for (int p = rp[k] + gl + 8; p < rp[k + 1]; p += 8) {
             const double x = fabs(v[p]);
             bad |= !isfinite(x);
-            m = fmax(m, x);
+            m[k] = fmax(m[k], x);
         }
+    }
     for (int o = 4; o > 0; o >>= 1) {
-        m = fmax(m, __shfl_xor(m, o, 8));
+#pragma unroll
+        for (int k = 0; k < kRowsPerGroup; ++k) m[k] = fmax(m[k], __shfl_xor(m[k], o, 8));
         bad |= __shfl_xor(bad, o, 8);
     }
-    if (i < n && gl == 0) {
+    if (gl == 0 && i0 < n) {
         if (bad) atomicOr(&st->flags, kFlagNonfinite);
-        r[i] = scale ? inv_pow2_floor_log2(m) : 1.0;
+#pragma unroll
+        for (int k = 0; k < kRowsPerGroup; ++k)
+            if (i0 + k < n) {
+                const int e = scale ? pow2_floor_log2(m[k]) : 0;
+                r[i0 + k] = scale_of(e);
+                er[i0 + k] = (int16_t)e;
+            }
     }
 }
 
 __global__ __launch_bounds__(256) void k_row_scale(int n, const int32_t *__restrict__ rowptr,
                                                    const double *__restrict__ v, int scale,
-                                                   double *__restrict__ r, DevStatus *st) {
-    row_scale_body(blockIdx.x, n, rowptr, v, scale, r, st);
+                                                   double *__restrict__ r, int16_t *__restrict__ er,
+                                                   DevStatus *st) {
+    row_scale_body(blockIdx.x, n, rowptr, v, scale, r, er, st);
 }
 
-// c_j from the row-scaled matrix, 8 lanes per column of the CSC view (crow: row of each
-// CSC entry, cpos: its position in the CSR value array)
-__device__ __forceinline__ void col_scale_body(int blk, int n, const int32_t *__restrict__ cptr,
-                                               const int32_t *__restrict__ cpos, const int32_t *__restrict__ crow,
-                                               const double *__restrict__ v, const double *__restrict__ r,
-                                               int scale, double *__restrict__ c) {
-    const int gid = blk * blockDim.x + threadIdx.x;
-    const int j = gid >> 3, gl = gid & 7;
-    double m = 0.0;
-    if (j < n)
-        for (int t = cptr[j] + gl; t < cptr[j + 1]; t += 8) m = fmax(m, fabs(r[crow[t]] * v[cpos[t]]));
-    for (int o = 4; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 8));
-    if (j < n && gl == 0) c[j] = scale ? inv_pow2_floor_log2(m) : 1.0;
-}
+// c from the row-scaled matrix and the scaled values into the factor, per column j
+// of the factor (column Q[j] of A), its slots in storage order: src[p] = {position of slot
+// p's entry of A in the CSR value array, or -1 for a fill-in slot; that entry's row i of A}.
+// c[Q[j]] = 2^-floor(log2 max_i |r_i a_i,Q[j]|); then lu[p] = (r_i a) c (exact in FP64;
+// rounded once when the factor is FP32), 0 for fill-in.  The factor is written in its own
+// order (no scattered stores); the first kColRegs slots of each lane keep r_i a in registers
+// between the two sweeps, later slots of a long column are gathered again.  kColLanes lanes
+// per column, so that each lane has several gathers in flight.
+constexpr int kColLanes = 8;
+constexpr int kColRegs = 4;
 
-__global__ __launch_bounds__(256) void k_col_scale(int n, const int32_t *__restrict__ cptr,
-                                                   const int32_t *__restrict__ cpos,
-                                                   const int32_t *__restrict__ crow,
-                                                   const double *__restrict__ v, const double *__restrict__ r,
-                                                   int scale, double *__restrict__ c) {
-    col_scale_body(blockIdx.x, n, cptr, cpos, crow, v, r, scale, c);
-}
-
-// Scaled values into the factor, lu[map[p]] = (r_i a_ip) c_j (exact in FP64; rounded once
-// when the factor is FP32), and the row sums of |A| and |R A C| in CSR order (one thread
-// per row, entries loaded eight at a time), block maxima into part[2 * block]; then the
-// fill-in slots of the factor are set to zero.
 template <class T>
-__device__ __forceinline__ void scatter_norms_body(int blk, int nblk, int n, const int32_t *__restrict__ rowptr,
-                                                   const int32_t *__restrict__ col, const double *__restrict__ v,
-                                                   const double *__restrict__ r, const double *__restrict__ c,
-                                                   const int32_t *__restrict__ map, int64_t nfill,
-                                                   const int32_t *__restrict__ fill, T *__restrict__ lu,
-                                                   double *__restrict__ part) {
+__device__ __forceinline__ void col_store_body(int blk, int n, const int32_t *__restrict__ colptr,
+                                               const int2 *__restrict__ src, const int32_t *__restrict__ Q,
+                                               const double *__restrict__ v, const int16_t *__restrict__ er,
+                                               int scale, double *__restrict__ c, int16_t *__restrict__ ec,
+                                               T *__restrict__ lu) {
+    const int gid = blk * blockDim.x + threadIdx.x;
+    const int j = gid / kColLanes, gl = gid % kColLanes;
+    const int p0 = j < n ? colptr[j] : 0, p1 = j < n ? colptr[j + 1] : 0;
+    int2 e[kColRegs];
+#pragma unroll
+    for (int k = 0; k < kColRegs; ++k) {
+        const int p = p0 + gl + kColLanes * k;
+        e[k] = p < p1 ? src[p] : int2{-1, 0};
+    }
+    double ra[kColRegs];
+#pragma unroll
+    for (int k = 0; k < kColRegs; ++k) ra[k] = e[k].x >= 0 ? scale_of(er[e[k].y]) * v[e[k].x] : 0.0;
+    double m = 0.0;
+#pragma unroll
+    for (int k = 0; k < kColRegs; ++k) m = fmax(m, fabs(ra[k]));
+    for (int p = p0 + gl + kColLanes * kColRegs; p < p1; p += kColLanes) {
+        const int2 f = src[p];
+        if (f.x >= 0) m = fmax(m, fabs(scale_of(er[f.y]) * v[f.x]));
+    }
+    for (int o = kColLanes / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, kColLanes));
+    const int ej = scale ? pow2_floor_log2(m) : 0;
+    const double cj = scale_of(ej);
+    if (j < n && gl == 0) {
+        c[Q[j]] = cj;
+        ec[Q[j]] = (int16_t)ej;
+    }
+#pragma unroll
+    for (int k = 0; k < kColRegs; ++k) {
+        const int p = p0 + gl + kColLanes * k;
+        if (p < p1) lu[p] = e[k].x >= 0 ? (T)(ra[k] * cj) : T(0);
+    }
+    for (int p = p0 + gl + kColLanes * kColRegs; p < p1; p += kColLanes) {
+        const int2 f = src[p];
+        lu[p] = f.x >= 0 ? (T)((scale_of(er[f.y]) * v[f.x]) * cj) : T(0);
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_col_store(int n, const int32_t *__restrict__ colptr,
+                                                   const int2 *__restrict__ src, const int32_t *__restrict__ Q,
+                                                   const double *__restrict__ v, const int16_t *__restrict__ er,
+                                                   int scale, double *__restrict__ c, int16_t *__restrict__ ec,
+                                                   T *__restrict__ lu) {
+    col_store_body<T>(blockIdx.x, n, colptr, src, Q, v, er, scale, c, ec, lu);
+}
+
+// The row sums of |A| and |R A C| in CSR order, 8 lanes per row and kRowsPerGroup rows per
+// group (grid-stride): the lanes load 8 consecutive entries of a row at once and the sums
+// add them in CSR order (left to right across the lanes); block maxima into part[2 * block].
+__device__ __forceinline__ void norms_body(int blk, int nblk, int n, const int32_t *__restrict__ rowptr,
+                                           const int32_t *__restrict__ col, const double *__restrict__ v,
+                                           const double *__restrict__ r, const int16_t *__restrict__ ec,
+                                           double *__restrict__ part) {
     __shared__ double red[2][4];
-    const int gid = blk * blockDim.x + threadIdx.x, stride = nblk * blockDim.x;
+    const int gl = threadIdx.x & 7;
     double s = 0.0, a = 0.0;
-    for (int i = gid; i < n; i += stride) {
-        const int p0 = rowptr[i], p1 = rowptr[i + 1];
-        const double ri = r[i];
-        double si = 0.0, ai = 0.0;
-        for (int p = p0; p < p1; p += 8) {
-            int cc[8], mm[8];
-            double vv[8], cj[8];
+    for (int i0 = ((blk * blockDim.x + threadIdx.x) >> 3) * kRowsPerGroup; i0 < n;
+         i0 += ((nblk * blockDim.x) >> 3) * kRowsPerGroup) {
+        int rp[kRowsPerGroup + 1];
+        group_rows(rowptr, n, i0, rp);
+        double ri[kRowsPerGroup], vv[kRowsPerGroup], cj[kRowsPerGroup];
+        int cc[kRowsPerGroup];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const bool h = p + k < p1;
-                cc[k] = h ? col[p + k] : 0;
-                mm[k] = h ? map[p + k] : 0;
-                vv[k] = h ? v[p + k] : 0.0;
-            }
+        for (int k = 0; k < kRowsPerGroup; ++k) {
+            const int p = rp[k] + gl;
+            const bool h = p < rp[k + 1];
+            ri[k] = i0 + k < n ? r[i0 + k] : 0.0;
+            vv[k] = h ? v[p] : 0.0;
+            cc[k] = h ? col[p] : 0;
+        }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) cj[k] = p + k < p1 ? c[cc[k]] : 0.0;
+        for (int k = 0; k < kRowsPerGroup; ++k) cj[k] = rp[k] + gl < rp[k + 1] ? scale_of(ec[cc[k]]) : 0.0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (p + k < p1) {
-                    const double t = (ri * vv[k]) * cj[k];
-                    lu[mm[k]] = (T)t;
-                    ai = ai + fabs(vv[k]);
-                    si = si + fabs(t);
+        for (int k = 0; k < kRowsPerGroup; ++k) {
+            double si = 0.0, ai = 0.0;
+            for (int q = rp[k]; q < rp[k + 1]; q += 8) {
+                double tv = 0.0, av = 0.0;
+                if (q == rp[k]) {
+                    tv = fabs((ri[k] * vv[k]) * cj[k]);
+                    av = fabs(vv[k]);
+                } else if (q + gl < rp[k + 1]) {
+                    const double x = v[q + gl];
+                    tv = fabs((ri[k] * x) * scale_of(ec[col[q + gl]]));
+                    av = fabs(x);
+                }
+                const int cnt = min(8, rp[k + 1] - q);
+                for (int t = 0; t < cnt; ++t) {
+                    ai = ai + __shfl(av, t, 8);
+                    si = si + __shfl(tv, t, 8);
                 }
             }
+            s = fmax(s, si);
+            a = fmax(a, ai);
         }
-        s = fmax(s, si);
-        a = fmax(a, ai);
     }
     for (int o = 32; o > 0; o >>= 1) {
         s = fmax(s, __shfl_xor(s, o));
@@ -181,18 +262,13 @@ __device__ __forceinline__ void scatter_norms_body(int blk, int nblk, int n, con
         part[2 * blk] = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
         part[2 * blk + 1] = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
     }
-    for (int64_t k = gid; k < nfill; k += stride) lu[fill[k]] = T(0);
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_scatter_norms(int n, const int32_t *__restrict__ rowptr,
-                                                       const int32_t *__restrict__ col,
-                                                       const double *__restrict__ v, const double *__restrict__ r,
-                                                       const double *__restrict__ c,
-                                                       const int32_t *__restrict__ map, int64_t nfill,
-                                                       const int32_t *__restrict__ fill, T *__restrict__ lu,
-                                                       double *__restrict__ part) {
-    scatter_norms_body<T>(blockIdx.x, gridDim.x, n, rowptr, col, v, r, c, map, nfill, fill, lu, part);
+__global__ __launch_bounds__(256) void k_norms(int n, const int32_t *__restrict__ rowptr,
+                                               const int32_t *__restrict__ col, const double *__restrict__ v,
+                                               const double *__restrict__ r, const int16_t *__restrict__ ec,
+                                               double *__restrict__ part) {
+    norms_body(blockIdx.x, gridDim.x, n, rowptr, col, v, r, ec, part);
 }
 
 // dst[j] = max over blocks b of part[nfield * b + j] (NaN propagates), j < nfield
@@ -1753,8 +1829,8 @@ __global__ __launch_bounds__(256) void k_unpermute(int n, const int32_t *__restr
 // ---------------------------------------------------------------------------------------
 // residual, sparse products and Krylov vector kernels (FP64)
 
-// res = b - A x (8 lanes per row, grid-stride) and block maxima of |res|, |x|, |b| into
-// part[3 * block + {0, 1, 2}]
+// res = b - A x (8 lanes per row, kRowsPerGroup rows per group, grid-stride) and block
+// maxima of |res|, |x|, |b| into part[3 * block + {0, 1, 2}]
 __global__ __launch_bounds__(256) void k_residual(int n, const int32_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ col, const double *__restrict__ v,
                                                   const double *__restrict__ x, const double *__restrict__ b,
@@ -1763,16 +1839,34 @@ __global__ __launch_bounds__(256) void k_residual(int n, const int32_t *__restri
     const double qnan = __longlong_as_double(0x7ff8000000000000LL);
     double rn = 0.0, xn = 0.0, bn = 0.0;
     const int gl = threadIdx.x & 7;
-    for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; i < n; i += (gridDim.x * blockDim.x) >> 3) {
-        double s = 0.0;
-        for (int p = rowptr[i] + gl; p < rowptr[i + 1]; p += 8) s = fma(v[p], x[col[p]], s);
-        s = group_sum(s, 8);
-        if (gl == 0) {
-            const double ri = b[i] - s;
-            res[i] = ri;
-            rn = isnan(ri) ? qnan : fmax(rn, fabs(ri));
-            xn = isnan(x[i]) ? qnan : fmax(xn, fabs(x[i]));
-            bn = fmax(bn, fabs(b[i]));
+    for (int i0 = ((blockIdx.x * blockDim.x + threadIdx.x) >> 3) * kRowsPerGroup; i0 < n;
+         i0 += ((gridDim.x * blockDim.x) >> 3) * kRowsPerGroup) {
+        int rp[kRowsPerGroup + 1];
+        group_rows(rowptr, n, i0, rp);
+        double vv[kRowsPerGroup], xv[kRowsPerGroup];
+        int cc[kRowsPerGroup];
+#pragma unroll
+        for (int k = 0; k < kRowsPerGroup; ++k) {
+            const int p = rp[k] + gl;
+            const bool h = p < rp[k + 1];
+            vv[k] = h ? v[p] : 0.0;
+            cc[k] = h ? col[p] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kRowsPerGroup; ++k) xv[k] = rp[k] + gl < rp[k + 1] ? x[cc[k]] : 0.0;
+#pragma unroll
+        for (int k = 0; k < kRowsPerGroup; ++k) {
+            double sk = vv[k] * xv[k];
+            for (int p = rp[k] + gl + 8; p < rp[k + 1]; p += 8) sk = fma(v[p], x[col[p]], sk);
+            sk = group_sum(sk, 8);
+            const int i = i0 + k;
+            if (gl == 0 && i < n) {
+                const double ri = b[i] - sk;
+                res[i] = ri;
+                rn = isnan(ri) ? qnan : fmax(rn, fabs(ri));
+                xn = isnan(x[i]) ? qnan : fmax(xn, fabs(x[i]));
+                bn = fmax(bn, fabs(b[i]));
+            }
         }
     }
     for (int o = 32; o > 0; o >>= 1) {

@@ -21,7 +21,8 @@ namespace {
 
 // device pointers carved out of the caller's workspace
 struct Dev {
-    int32_t *a_rowptr, *a_colind, *a_crow, *a_cptr, *a_cpos, *a_map, *lu_fill;
+    int32_t *a_rowptr, *a_colind;
+    int2 *lu_src;       // per factor slot: {CSR position of its entry of A or -1, that entry's row}
     int32_t *colptr, *rowidx, *ulen, *pan_start, *pan_r;
     int32_t *f_rel, *ldiag;
     int4 *itemrec, *pair8;
@@ -30,6 +31,7 @@ struct Dev {
     int32_t *csr_col, *csr_src, *copy_k, *P, *Q;
     void *lu, *lucsr;   // factor values (FP64, or FP32 with factor_precision = KKT_FP32)
     double *r, *c, *y, *xt, *psum, *usum, *bp, *bsave;
+    int16_t *er, *ec;   // exponents of the scale factors: r_i = 2^-er[i], c_j = 2^-ec[j]
     double *V, *Z, *w, *res, *part, *hbuf, *ybuf;
     DevStatus *st;
     ResNorms *rn;
@@ -42,6 +44,7 @@ struct Dev {
 // most blocks of a refactor launch that run forward-solve items (kkt_refactor_refine)
 constexpr int kFuseSolveBlocks = KKT_FZ_SOLVE_BLOCKS;
 constexpr int kDotBlocks = 512;
+constexpr int kNormRowBlocks = 4096;   // most blocks of the row-norm pass (8 lanes per row)
 constexpr int kSmallPipeMax = 100000;  // narrow items per level up to which the pipelined variant runs
 constexpr int kNormBlocks = 4096;
 constexpr int kMaxSweeps = 1024;       // largest approx_sweeps accepted
@@ -113,11 +116,7 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     Carver c{base};
     d.a_rowptr = c.take<int32_t>(n + 1);
     d.a_colind = c.take<int32_t>(na);
-    d.a_crow = c.take<int32_t>(na);
-    d.a_cptr = c.take<int32_t>(n + 1);
-    d.a_cpos = c.take<int32_t>(na);
-    d.a_map = c.take<int32_t>(na);
-    d.lu_fill = c.take<int32_t>(std::max<size_t>(1, g.lu_fill.size()));
+    d.lu_src = c.take<int2>(std::max<size_t>(1, nlu));
     d.colptr = c.take<int32_t>(n + 1);
     d.rowidx = c.take<int32_t>(nlu);
     d.ulen = c.take<int32_t>(n);
@@ -141,6 +140,8 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.Q = c.take<int32_t>(n);
     d.r = c.take<double>(n);
     d.c = c.take<double>(n);
+    d.er = c.take<int16_t>(n);
+    d.ec = c.take<int16_t>(n);
     d.lu = c.take<char>(nlu * fb);
     d.lucsr = c.take<char>(nlu * fb);
     d.y = c.take<double>(n);
@@ -188,6 +189,12 @@ auto by_precision(const kkt_handle *h, F &&f) {
     } while (0)
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+// blocks of the update passes: 8 lanes per kRowsPerGroup rows, kColLanes lanes per column
+inline int row_blocks(int n) {
+    return (int)std::max<unsigned>(1, blocks_for((int64_t)(n + kRowsPerGroup - 1) / kRowsPerGroup * 8, 256));
+}
+inline int col_blocks(int n) { return (int)std::max<unsigned>(1, blocks_for((int64_t)n * kColLanes, 256)); }
+inline int norm_blocks(int n) { return std::min(kNormRowBlocks, row_blocks(n)); }
 
 // Runs `launch` (which enqueues one kernel on s); with the profiler on, brackets it with a
 // pair of events attributed to kernel class cls.
@@ -316,27 +323,24 @@ int enqueue_solve(kkt_handle *h, const double *b, double *x, hipStream_t s, bool
 
 // value update: scale factors, scaled values scattered into the factor, norms
 int enqueue_update(kkt_handle *h, const double *v, hipStream_t s) {
-    const Schedule &g = h->sch;
     const Dev &d = h->d;
     const int n = h->sym.n;
     const int eq = h->opts.equilibrate != 0;
     timed(h, KKT_PROF_UPDATE, s, [&] { k_clear_status<<<1, 256, 0, s>>>(d.st, d.pcount); });
     timed(h, KKT_PROF_UPDATE, s, [&] {
-        k_row_scale<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_rowptr, v, eq, d.r, d.st);
-    });
-    timed(h, KKT_PROF_UPDATE, s, [&] {
-        k_col_scale<<<blocks_for((int64_t)n * 8, 256), 256, 0, s>>>(n, d.a_cptr, d.a_cpos, d.a_crow, v, d.r, eq, d.c);
+        k_row_scale<<<row_blocks(n), 256, 0, s>>>(n, d.a_rowptr, v, eq, d.r, d.er, d.st);
     });
     timed(h, KKT_PROF_UPDATE, s, [&] {
         by_precision(h, [&](auto tag) {
             using T = decltype(tag);
-            k_scatter_norms<T><<<kNormBlocks, 256, 0, s>>>(n, d.a_rowptr, d.a_colind, v, d.r, d.c, d.a_map,
-                                                          (int64_t)g.lu_fill.size(), d.lu_fill, static_cast<T *>(d.lu),
-                                                          d.part);
+            k_col_store<T><<<col_blocks(n), 256, 0, s>>>(n, d.colptr, d.lu_src, d.Q, v, d.er, eq, d.c, d.ec,
+                                                      static_cast<T *>(d.lu));
             return 0;
         });
     });
-    timed(h, KKT_PROF_UPDATE, s, [&] { k_max_parts<<<1, 256, 0, s>>>(kNormBlocks, 2, d.part, &d.st->anorm_scaled); });
+    const int nbn = norm_blocks(n);
+    timed(h, KKT_PROF_UPDATE, s, [&] { k_norms<<<nbn, 256, 0, s>>>(n, d.a_rowptr, d.a_colind, v, d.r, d.ec, d.part); });
+    timed(h, KKT_PROF_UPDATE, s, [&] { k_max_parts<<<1, 256, 0, s>>>(nbn, 2, d.part, &d.st->anorm_scaled); });
     HIPCHK(hipGetLastError());
     return KKT_OK;
 }
@@ -850,11 +854,7 @@ int bind_common(kkt_handle *h, char *ws, size_t bytes, int32_t max_nrhs, hipStre
     int rc = KKT_OK;
     rc |= upload(d.a_rowptr, g.a_rowptr32, stream);
     rc |= upload(d.a_colind, s.a_colind, stream);
-    rc |= upload(d.a_crow, g.a_crow, stream);
-    rc |= upload(d.a_cptr, g.a_cptr, stream);
-    rc |= upload(d.a_cpos, g.a_cpos, stream);
-    rc |= upload(d.a_map, g.a_map, stream);
-    rc |= upload(d.lu_fill, g.lu_fill, stream);
+    rc |= upload(reinterpret_cast<int32_t *>(d.lu_src), g.lu_src, stream);
     rc |= upload(d.colptr, g.colptr32, stream);
     rc |= upload(d.rowidx, s.rowidx, stream);
     rc |= upload(d.ulen, s.ulen, stream);

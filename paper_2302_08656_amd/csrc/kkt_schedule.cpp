@@ -534,34 +534,16 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
         g.u_rows4[k + 1] = g.csr_diag[i] + (w - t);
         g.u_rows4[k + 2] = g.csr_rowptr[i + 1];
     }
-    // value update: the factor slot of each entry of A (CSR order), the fill-in slots, and
-    // the CSC view of A (position in the CSR value array and row of each entry)
-    g.a_map.resize(s.nnz_a);
-    {
-        std::vector<char> hit(nlu, 0);
-        for (int64_t e = 0; e < s.nnz_a; ++e) {
-            g.a_map[e] = (int32_t)s.map[e];
-            hit[s.map[e]] = 1;
-        }
-        g.lu_fill.clear();
-        for (int64_t p = 0; p < nlu; ++p)
-            if (!hit[p]) g.lu_fill.push_back((int32_t)p);
-    }
-    g.a_cptr.assign(n + 1, 0);
+    // value update: for each factor slot, the position of its entry of A in the CSR value
+    // array (-1 for a fill-in slot) and that entry's row of A
+    g.lu_src.assign(2 * (size_t)nlu, -1);
     for (int32_t i = 0; i < n; ++i)
-        for (int64_t p = s.a_rowptr[i]; p < s.a_rowptr[i + 1]; ++p) g.a_cptr[s.a_colind[p] + 1]++;
-    for (int32_t j = 0; j < n; ++j) g.a_cptr[j + 1] += g.a_cptr[j];
-    g.a_cpos.resize(s.nnz_a);
-    g.a_crow.resize(s.nnz_a);
-    {
-        std::vector<int32_t> nxt(g.a_cptr.begin(), g.a_cptr.end() - 1);
-        for (int32_t i = 0; i < n; ++i)
-            for (int64_t p = s.a_rowptr[i]; p < s.a_rowptr[i + 1]; ++p) {
-                const int32_t t = nxt[s.a_colind[p]]++;
-                g.a_cpos[t] = (int32_t)p;
-                g.a_crow[t] = i;
-            }
-    }
+        for (int64_t e = s.a_rowptr[i]; e < s.a_rowptr[i + 1]; ++e) {
+            const int64_t p = s.map[e];
+            if (g.lu_src[2 * p] >= 0) return KKT_ERR_SCHEDULE;   // two entries of A in one slot
+            g.lu_src[2 * p] = (int32_t)e;
+            g.lu_src[2 * p + 1] = i;
+        }
     // refactor flops: sum_k 2 |L(:,k)| |U(k,:)| + |L(:,k)|
     std::vector<int64_t> urow(n, 0);
     for (int32_t k = 0; k < n; ++k)
