@@ -94,8 +94,7 @@ __global__ void k_batch_copy(const BatchSys<T> *__restrict__ sys, const BatchPar
     const BatchSys<T> &S = sys[P.sys];
     const int q = S.q0 + (int)((blockIdx.x - P.blk0) * blockDim.x + threadIdx.x);
     if (q < S.q1) {
-        const int k = S.ref.copy_k[q];
-        S.ref.lucsr[k] = S.ref.lu[S.ref.csr_src[k]];
+        S.ref.lucsr[S.ref.copy_k[q]] = S.ref.lu[S.ref.copy_src[q]];
     }
 }
 
@@ -145,7 +144,7 @@ BatchSys<T> batch_sys(const kkt_handle *h) {
     BatchSys<T> b{};
     b.ref = RefArgs<T>{d.ldiag, d.itemrec, d.pair8, d.f_rel, static_cast<T *>(d.lu), d.st, d.pcount,
                        std::is_same<T, float>::value ? h->opts.tiny_pivot_fp32 : h->opts.tiny_pivot,
-                       h->opts.dense_mfma != 0, d.copy_k, d.csr_src, static_cast<T *>(d.lucsr),
+                       h->opts.dense_mfma != 0, d.copy_k, d.copy_src, static_cast<T *>(d.lucsr),
                        d.pan_start, d.pan_r};
     b.a_rowptr = d.a_rowptr;
     b.a_colind = d.a_colind;

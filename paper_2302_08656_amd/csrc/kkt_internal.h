@@ -99,7 +99,7 @@ struct Schedule {
     // copy_ptr.size() - 1) copies copy_k[copy_ptr[c] .. copy_ptr[c+1]), the copy after the
     // last level the rest
     int32_t copy_lvl = 0;
-    std::vector<int32_t> copy_k, copy_ptr, copy_at;
+    std::vector<int32_t> copy_k, copy_src, copy_ptr, copy_at;   // copy_src[q] = csr_src[copy_k[q]]
     // forward solve fused with the refactorization: the items of forward level k read only
     // columns final after refactor launch l_ready[k] (and unknowns of lower forward levels)
     std::vector<int32_t> l_ready;

@@ -318,13 +318,12 @@ __global__ __launch_bounds__(256) void k_sum_counts(const unsigned long long *__
     sum_counts_body(pcount, out);
 }
 
-// lucsr[k] = lu[csr_src[k]] for k = copy_k[q], q in [q0, q1)
+// lucsr[copy_k[q]] = lu[copy_src[q]], q in [q0, q1) (copy_src[q]: factor slot of CSR position copy_k[q])
 template <class T>
-__global__ void k_to_csr(int q0, int q1, const int32_t *__restrict__ copy_k, const int32_t *__restrict__ csr_src,
+__global__ void k_to_csr(int q0, int q1, const int32_t *__restrict__ copy_k, const int32_t *__restrict__ copy_src,
                          const T *__restrict__ lu, T *__restrict__ lucsr) {
     for (int q = q0 + (int)(blockIdx.x * blockDim.x + threadIdx.x); q < q1; q += gridDim.x * blockDim.x) {
-        const int k = copy_k[q];
-        lucsr[k] = lu[csr_src[k]];
+        lucsr[copy_k[q]] = lu[copy_src[q]];
     }
 }
 
@@ -376,10 +375,10 @@ struct RefArgs {
     unsigned long long *pcount;   // replaced-pivot counter, spread over kCountSlots slots
     double tiny;
     int use_mfma;                 // dense update blocks on the matrix cores
-    // row-ordered copy of the factor: lucsr[k] = lu[csr_src[k]] for the CSR positions k listed
-    // in copy_k
+    // row-ordered copy of the factor: lucsr[copy_k[q]] = lu[copy_src[q]] (copy_k: CSR
+    // positions, copy_src: their factor slots)
     const int32_t *copy_k;
-    const int32_t *csr_src;
+    const int32_t *copy_src;
     T *lucsr;
     // panel geometry (first column, rows below) for items that factor several panels
     const int32_t *pan_start;
@@ -602,13 +601,12 @@ __device__ __forceinline__ void small_group(int item0, int nsmall, const RefArgs
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(&a.pcount[slot % kCountSlots], (unsigned long long)c);
 }
 
-// lucsr[k] = lu[csr_src[k]] for k = copy_k[q], q in [c0, c1), by block b of nb blocks of
+// lucsr[copy_k[q]] = lu[copy_src[q]] for q in [c0, c1), by block b of nb blocks of
 // nthreads threads
 template <class T>
 __device__ __forceinline__ void copy_block(const RefArgs<T> &a, int c0, int c1, int b, int nb, int nthreads) {
     for (int q = c0 + b * nthreads + (int)threadIdx.x; q < c1; q += nb * nthreads) {
-        const int k = a.copy_k[q];
-        a.lucsr[k] = a.lu[a.csr_src[k]];
+        a.lucsr[a.copy_k[q]] = a.lu[a.copy_src[q]];
     }
 }
 

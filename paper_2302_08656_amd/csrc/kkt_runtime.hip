@@ -28,7 +28,7 @@ struct Dev {
     int4 *itemrec, *pair8;
     unsigned long long *pcount;
     int4 *l_item4, *u_item4, *l_rows4, *u_rows4, *rinfo4, *urinfo4;
-    int32_t *csr_col, *csr_src, *copy_k, *P, *Q;
+    int32_t *csr_col, *copy_k, *copy_src, *P, *Q;
     void *lu, *lucsr;   // factor values (FP64, or FP32 with factor_precision = KKT_FP32)
     double *r, *c, *y, *xt, *psum, *usum, *bp, *bsave;
     int16_t *er, *ec;   // exponents of the scale factors: r_i = 2^-er[i], c_j = 2^-ec[j]
@@ -38,11 +38,11 @@ struct Dev {
     int *tick;          // ticket counters of the persistent solves (forward, backward, fused tail)
 };
 
-#ifndef KKT_FZ_SOLVE_BLOCKS
-#define KKT_FZ_SOLVE_BLOCKS 256
-#endif
-// most blocks of a refactor launch that run forward-solve items (kkt_refactor_refine)
-constexpr int kFuseSolveBlocks = KKT_FZ_SOLVE_BLOCKS;
+// most blocks of a refactor launch that run forward-solve items (kkt_refactor_refine; at 70k
+// 128 and 512 measured 1% and 0.4% slower)
+constexpr int kFuseSolveBlocks = 256;
+// most copy blocks of a refactor launch per compute unit (1: 1.3% slower at 70k, 16: same)
+constexpr int kCopyBlocksPerCu = 4;
 constexpr int kDotBlocks = 512;
 constexpr int kNormRowBlocks = 4096;   // most blocks of the row-norm pass (8 lanes per row)
 constexpr int kSmallPipeMax = 100000;  // narrow items per level up to which the pipelined variant runs
@@ -134,8 +134,8 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.rinfo4 = c.take<int4>(n);
     d.urinfo4 = c.take<int4>(n);
     d.csr_col = c.take<int32_t>(nlu);
-    d.csr_src = c.take<int32_t>(nlu);
     d.copy_k = c.take<int32_t>(std::max<size_t>(1, g.copy_k.size()));
+    d.copy_src = c.take<int32_t>(std::max<size_t>(1, g.copy_src.size()));
     d.P = c.take<int32_t>(n);
     d.Q = c.take<int32_t>(n);
     d.r = c.take<double>(n);
@@ -348,7 +348,7 @@ int enqueue_update(kkt_handle *h, const double *v, hipStream_t s) {
 // extra blocks of `threads` threads of a refactor launch that copy `entries` entries of the
 // row-ordered factor (they run after the factor work of the launch, in its tail)
 int copy_blocks(const kkt_handle *h, int entries, int threads) {
-    return entries > 0 ? std::min(4 * h->ncu, (int)blocks_for(entries, threads)) : 0;
+    return entries > 0 ? std::min(kCopyBlocksPerCu * h->ncu, (int)blocks_for(entries, threads)) : 0;
 }
 
 // the level launches of the refactorization, the row-ordered copy and the pivot count; they
@@ -369,7 +369,7 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s, bool fused) {
     const Dev &d = h->d;
     const double tiny = std::is_same<T, float>::value ? h->opts.tiny_pivot_fp32 : h->opts.tiny_pivot;
     RefArgs<T> a{d.ldiag, d.itemrec, d.pair8, d.f_rel, static_cast<T *>(d.lu), d.st, d.pcount,
-                 tiny, h->opts.dense_mfma != 0, d.copy_k, d.csr_src, static_cast<T *>(d.lucsr),
+                 tiny, h->opts.dense_mfma != 0, d.copy_k, d.copy_src, static_cast<T *>(d.lucsr),
                  d.pan_start, d.pan_r};
     const int nlev = (int)g.f_lvl.size() - 1;
     const int ncopy = fused ? 0 : (int)g.copy_ptr.size() - 1;   // launches that carry a chunk of the copy
@@ -406,7 +406,7 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s, bool fused) {
         int c0 = copy ? g.copy_ptr[cc] : 0, c1 = copy ? g.copy_ptr[cc + 1] : 0;
         FuseArgs<T> f{fs, 0, 0, 0};
         if (fused) {
-            if (kFuseSolveBlocks > 0 && solved < nfl && g.l_ready[solved] < copied) {
+            if (solved < nfl && g.l_ready[solved] < copied) {
                 f.j0 = g.l_lvl[solved];
                 f.j1 = g.l_lvl[solved + 1];
                 f.nsolve = std::min(f.j1 - f.j0, kFuseSolveBlocks);
@@ -440,7 +440,7 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s, bool fused) {
     const int q0 = fused ? g.copy_at[copied] : ncopy > 0 ? g.copy_ptr.back() : 0, q1 = (int)g.copy_k.size();
     if (q1 > q0)
         timed(h, KKT_PROF_TO_CSR, s,
-              [&] { k_to_csr<T><<<blocks_for(q1 - q0, 256), 256, 0, s>>>(q0, q1, d.copy_k, d.csr_src, a.lu, a.lucsr); });
+              [&] { k_to_csr<T><<<blocks_for(q1 - q0, 256), 256, 0, s>>>(q0, q1, d.copy_k, d.copy_src, a.lu, a.lucsr); });
     if (fused && solved < nfl) {
         const int j0 = g.l_lvl[solved], j1 = g.l_lvl[nfl];
         timed(h, KKT_PROF_LSOLVE, s, [&] {
@@ -871,8 +871,8 @@ int bind_common(kkt_handle *h, char *ws, size_t bytes, int32_t max_nrhs, hipStre
     rc |= upload(reinterpret_cast<int32_t *>(d.rinfo4), g.rinfo4, stream);
     rc |= upload(reinterpret_cast<int32_t *>(d.urinfo4), g.urinfo4, stream);
     rc |= upload(d.csr_col, g.csr_col, stream);
-    rc |= upload(d.csr_src, g.csr_src, stream);
     rc |= upload(d.copy_k, g.copy_k, stream);
+    rc |= upload(d.copy_src, g.copy_src, stream);
     rc |= upload(d.P, s.P, stream);
     rc |= upload(d.Q, s.Q, stream);
     if (rc) return KKT_ERR_DEVICE;

@@ -556,8 +556,9 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
     g.flops = fl;
     // the row-ordered copy of the factor: an entry can be copied once its column is final,
     // i.e. after the launch that factors the column's panel.  copy_k lists the entries by the
-    // launch that finishes their column (copy_at[l] = first entry of launch l), in CSR
-    // order within a launch.  The top levels have few items and leave most of the GPU idle, so the
+    // launch that finishes their column (copy_at[l] = first entry of launch l), in factor
+    // storage order within a launch, and copy_src[q] = csr_src[copy_k[q]]: a copy reads the
+    // factor nearly in order and scatters only its stores.  The top levels have few items and leave most of the GPU idle, so the
     // entries of every column final before the first of them are copied by extra blocks of up
     // to kCopyLaunches of those launches (in consecutive chunks); the rest after the last level
     const int32_t nlev_f = (int32_t)g.f_lvl.size() - 1;
@@ -573,6 +574,11 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
         {
             std::vector<int32_t> nxt(g.copy_at.begin(), g.copy_at.end() - 1);
             for (int64_t q = 0; q < nlu; ++q) g.copy_k[nxt[plev[pan_of[g.csr_col[q]]]]++] = (int32_t)q;
+            for (int32_t l = 0; l < nlev_f; ++l)
+                std::sort(g.copy_k.begin() + g.copy_at[l], g.copy_k.begin() + g.copy_at[l + 1],
+                          [&](int32_t a, int32_t b) { return g.csr_src[a] < g.csr_src[b]; });
+            g.copy_src.resize(nlu);
+            for (int64_t q = 0; q < nlu; ++q) g.copy_src[q] = g.csr_src[g.copy_k[q]];
         }
         g.copy_ptr.assign(1, 0);
         const int64_t ne = nwin > 0 ? g.copy_at[win] : 0;
