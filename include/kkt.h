@@ -254,10 +254,11 @@ int kkt_refine(kkt_handle *h, const double *d_b, double *d_x, int32_t nrhs, int6
 
 /* One step of Algorithm 1 for one right-hand side: kkt_refactor(h, d_values) followed by
  * kkt_refine(h, d_b, d_x, 1, n, info), with the same results bit for bit (factors, x and
- * info).  The forward substitution of the first solve runs beside the refactorization: each
- * part of L y = P R b starts once the columns it reads are factored (replayed from a second
- * graph, recorded at the first call after kkt_bind; without graphs, with the profiler on or
- * on a capturing stream the two calls run one after the other).  d_values as for
+ * info).  The forward substitution of the first solve rides in the refactorization's level
+ * launches: each forward level runs in the first launch after the columns its rows read are
+ * factored and copied, the last levels after the last launch (replayed from a second graph
+ * recorded at the first call after kkt_bind when opts.graph_refactor is set; launched one by
+ * one without graphs, with the profiler on or on a capturing stream).  d_values as for
  * kkt_refactor (BORROWED); d_b, d_x: device FP64[n], d_x may equal d_b; info: host
  * kkt_info[1] (may be NULL).  Waits for completion.  Returns what kkt_refine returns; a
  * failed factorization (ERR_NONFINITE, ERR_DEVICE) is reported with info = {0, error, inf,
@@ -403,7 +404,9 @@ void kkt_server_destroy(kkt_server *s);
                                     * (LDS-staged, matrix cores) and the level's narrow items */
 #define KKT_PROF_REFACTOR_SMALL 2  /* narrow-only level launches (16 lanes per item) */
 #define KKT_PROF_TO_CSR 3          /* row-ordered copy of the factors */
-#define KKT_PROF_LSOLVE 4          /* forward substitution (and its Jacobi sweeps) */
+#define KKT_PROF_LSOLVE 4          /* forward substitution (and its Jacobi sweeps; with
+                                    * kkt_refactor_refine only its last levels and the set-up,
+                                    * the others ride in the refactorization's launches) */
 #define KKT_PROF_USOLVE 5          /* backward substitution (and its Jacobi sweeps) */
 #define KKT_PROF_RESIDUAL 6        /* residual, products with A */
 #define KKT_PROF_KRYLOV 7          /* FGMRES vector kernels */
@@ -416,13 +419,15 @@ void kkt_server_destroy(kkt_server *s);
 
 typedef struct {
     int64_t launches[KKT_PROF_NCLASS];
-    double ms[KKT_PROF_NCLASS];      /* summed GPU time between events around each launch */
+    double ms[KKT_PROF_NCLASS];      /* summed GPU time between the events around the launches */
 } kkt_profile;
 
 /* Test and benchmark hook: on = 1 resets the counters and records a pair of HIP events
- * around every later kernel launch of the handle (on the caller's stream); the
- * refactorization's levels are then launched one by one instead of from the recorded graph.
- * on = 0 stops.  Adds a few microseconds per launch while on. */
+ * around every later kernel launch of the handle (on the caller's stream), one pair around
+ * each run of consecutive refactorization level launches of one class (so a class's time per
+ * launch carries the events' cost once per run); the levels are then launched one by one
+ * instead of from the recorded graph.  on = 0 stops.  Adds a few microseconds per pair while
+ * on. */
 int kkt_profile_enable(kkt_handle *h, int32_t on);
 
 /* Waits for the stream and returns the accumulated launch counts and times. */

@@ -103,6 +103,9 @@ struct kkt_handle {
     kkt_profile acc{};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    std::vector<int> ev_count;     // launches bracketed by each pending pair
+    int ev_open = -1;              // pending pair whose end is not recorded yet (a run of launches)
+    hipStream_t ev_open_s = nullptr;
 };
 
 namespace {
@@ -196,13 +199,30 @@ inline int row_blocks(int n) {
 inline int col_blocks(int n) { return (int)std::max<unsigned>(1, blocks_for((int64_t)n * kColLanes, 256)); }
 inline int norm_blocks(int n) { return std::min(kNormRowBlocks, row_blocks(n)); }
 
+// ends the open run of launches of the profiler (records its end event)
+void close_run(kkt_handle *h) {
+    if (h->ev_open < 0) return;
+    (void)hipEventRecord(h->ev_pending[h->ev_open].second.second, h->ev_open_s);
+    h->ev_open = -1;
+}
+
 // Runs `launch` (which enqueues one kernel on s); with the profiler on, brackets it with a
-// pair of events attributed to kernel class cls.
+// pair of events attributed to kernel class cls.  run: consecutive launches of one class on
+// one stream (the refactorization's levels) share one pair, so the events' own cost (a few
+// microseconds a pair) is not counted once per launch.
 template <class F>
-void timed(kkt_handle *h, int cls, hipStream_t s, F &&launch) {
+void timed(kkt_handle *h, int cls, hipStream_t s, F &&launch, bool run = false) {
     if (!h->prof) {
         launch();
         return;
+    }
+    if (h->ev_open >= 0) {
+        if (run && h->ev_pending[h->ev_open].first == cls && h->ev_open_s == s) {
+            launch();
+            h->ev_count[h->ev_open] += 1;
+            return;
+        }
+        close_run(h);
     }
     std::pair<hipEvent_t, hipEvent_t> ev;
     if (!h->ev_free.empty()) {
@@ -214,14 +234,21 @@ void timed(kkt_handle *h, int cls, hipStream_t s, F &&launch) {
     }
     (void)hipEventRecord(ev.first, s);
     launch();
-    (void)hipEventRecord(ev.second, s);
     h->ev_pending.emplace_back(cls, ev);
+    h->ev_count.push_back(1);
+    if (run) {
+        h->ev_open = (int)h->ev_pending.size() - 1;
+        h->ev_open_s = s;
+    } else {
+        (void)hipEventRecord(ev.second, s);
+    }
 }
 
 void fold_events(kkt_handle *h);
 
 // waits for the stream, then folds the profiler's completed events
 hipError_t sync_fold(kkt_handle *h, hipStream_t s) {
+    close_run(h);
     const hipError_t e = hipStreamSynchronize(s);
     if (e == hipSuccess && !h->ev_pending.empty()) fold_events(h);
     return e;
@@ -229,15 +256,17 @@ hipError_t sync_fold(kkt_handle *h, hipStream_t s) {
 
 // folds completed event pairs into the profile (call after the stream was synchronized)
 void fold_events(kkt_handle *h) {
-    for (auto &pe : h->ev_pending) {
+    for (size_t i = 0; i < h->ev_pending.size(); ++i) {
+        const auto &pe = h->ev_pending[i];
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
             h->acc.ms[pe.first] += ms;
-            h->acc.launches[pe.first] += 1;
+            h->acc.launches[pe.first] += h->ev_count[i];
         }
         h->ev_free.push_back(pe.second);
     }
     h->ev_pending.clear();
+    h->ev_count.clear();
 }
 
 template <class T>
@@ -394,7 +423,7 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s, bool fused) {
                     k_refactor_small<T, false><<<grid, kBlock, 0, s>>>(i0, ns, a, c0, c1);
                 else
                     k_refactor_small<T, true><<<grid, kBlock, 0, s>>>(i0, ns, a, c0, c1);
-            });
+            }, true);
         }
         if (!nb && !nm) continue;
         // otherwise the narrow items are extra blocks of the level's wide launch, and so is a
@@ -422,17 +451,17 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s, bool fused) {
             timed(h, KKT_PROF_REFACTOR_W256, s, [&] {
                 const int grid = nb + (int)blocks_for(mb, W256::kThreads / 16) + f.nsolve + cb;
                 k_refactor_wide<W256><<<grid, W256::kThreads, W256::kLds, s>>>(i0, a, nb, s0, mb, c0, c1, f);
-            });
+            }, true);
         else if (nb)
             timed(h, KKT_PROF_REFACTOR_LARGE, s, [&] {
                 const int grid = nb + (int)blocks_for(mb, Big::kThreads / 16) + f.nsolve + cb;
                 k_refactor_wide<Big><<<grid, Big::kThreads, Big::kLds, s>>>(i0, a, nb, s0, mb, c0, c1, f);
-            });
+            }, true);
         else
             timed(h, KKT_PROF_REFACTOR_MEDIUM, s, [&] {
                 const int grid = nm + (int)blocks_for(mm, Med::kThreads / 16) + f.nsolve + cb;
                 k_refactor_wide<Med><<<grid, Med::kThreads, Med::kLds, s>>>(i0, a, nm, s0, mm, c0, c1, f);
-            });
+            }, true);
     }
     // the rest of the copy: the columns of the top levels (all of it without such levels), or
     // with fused the columns of the levels since the last wide launch; then the remaining
@@ -972,13 +1001,23 @@ void record_fused(kkt_handle *h) {
     if (graph) (void)hipGraphDestroy(graph);
 }
 
-// whether kkt_refactor_refine can replay the fused graph on s (recording it if needed)
-bool fused_ready(kkt_handle *h, hipStream_t s) {
-    if (!h->opts.graph_refactor || h->prof || h->fused_failed || h->on_scratch) return false;
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
-    if (!h->fused) record_fused(h);
-    return h->fused != nullptr;
+// the level launches with the forward solve riding in them, replayed from h->fused (recorded
+// at the first call) or, without graphs, with the profiler on or on a capturing stream,
+// launched one by one
+int run_fused_levels(kkt_handle *h, hipStream_t s) {
+    if (h->opts.graph_refactor && !h->prof && !h->fused_failed && !h->on_scratch) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIPCHK(hipStreamIsCapturing(s, &cs));
+        if (cs == hipStreamCaptureStatusNone) {
+            if (!h->fused) record_fused(h);
+            if (h->fused) {
+                HIPCHK(hipGraphLaunch(h->fused, s));
+                HIPCHK(hipEventRecord(h->levels_done, s));
+                return KKT_OK;
+            }
+        }
+    }
+    return enqueue_levels(h, s, true);
 }
 
 int run_levels(kkt_handle *h, hipStream_t s) {
@@ -1018,10 +1057,6 @@ int kkt_refactor_refine(kkt_handle *h, const double *d_values, const double *d_b
     if (!h->bound) return KKT_ERR_STATE;
     DeviceGuard dg(h->device);
     if (!dg.ok) return KKT_ERR_DEVICE;
-    if (!fused_ready(h, stream)) {
-        const int rc = kkt_refactor(h, d_values, stream);
-        return rc ? rc : kkt_refine(h, d_b, d_x, 1, h->sym.n, info, stream);
-    }
     const Dev &d = h->d;
     const int n = h->sym.n;
     const double *b = d_b;
@@ -1031,13 +1066,15 @@ int kkt_refactor_refine(kkt_handle *h, const double *d_values, const double *d_b
     }
     int rc = enqueue_update(h, d_values, stream);
     if (rc) return rc;
-    // bp, the unset unknowns and the tickets (the forward tail's included), then the graph
+    // bp, the unset unknowns and the tickets (the forward tail's included), then the levels
     const int ntick = 3;
-    k_solve_reset<<<blocks_for(std::max(n, ntick), 256), 256, 0, stream>>>(n, b, d.r, d.P, d.bp, d.y, d.xt, d.psum,
-                                                                          d.usum, 1, ntick, d.tick);
+    timed(h, KKT_PROF_LSOLVE, stream, [&] {
+        k_solve_reset<<<blocks_for(std::max(n, ntick), 256), 256, 0, stream>>>(n, b, d.r, d.P, d.bp, d.y, d.xt,
+                                                                              d.psum, d.usum, 1, ntick, d.tick);
+    });
     HIPCHK(hipGetLastError());
-    HIPCHK(hipGraphLaunch(h->fused, stream));
-    HIPCHK(hipEventRecord(h->levels_done, stream));
+    rc = run_fused_levels(h, stream);
+    if (rc) return rc;
     h->d_values = d_values;
     h->factored = true;
     kkt_info inf{};
@@ -1277,6 +1314,7 @@ int kkt_export_factors(kkt_handle *h, double *h_lu, double *h_r, double *h_c, hi
 
 int kkt_profile_enable(kkt_handle *h, int32_t on) {
     if (!h) return KKT_ERR_ARG;
+    close_run(h);
     h->prof = on != 0;
     if (h->prof) h->acc = kkt_profile{};
     return KKT_OK;
@@ -1284,6 +1322,7 @@ int kkt_profile_enable(kkt_handle *h, int32_t on) {
 
 int kkt_profile_read(kkt_handle *h, kkt_profile *out, hipStream_t stream) {
     if (!h || !out) return KKT_ERR_ARG;
+    close_run(h);
     if (!h->ev_pending.empty()) HIPCHK(sync_fold(h, stream));
     *out = h->acc;
     return KKT_OK;
@@ -1299,6 +1338,7 @@ void kkt_destroy(kkt_handle *h) {
     // the capture stream, the events and last the pinned staging buffer
     if (h->device >= 0) {
         DeviceGuard g(h->device);
+        close_run(h);
         if (h->levels_done) (void)hipEventSynchronize(h->levels_done);
         for (auto &pe : h->ev_pending) (void)hipEventSynchronize(pe.second.second);
         if (h->cap) (void)hipStreamSynchronize(h->cap);

@@ -121,3 +121,35 @@ def test_fused_full_size_grid70k():
         v, b, x, info = same_step(q, t, sep, fus)
         _, berr = oracle.residual(q.n, q.rowptr, q.colind, v, x.cpu().numpy(), b)
         assert info.status == K.OK and berr <= 1e-10, (t, berr, info)
+
+
+def test_fused_on_scratch_binding():
+    """A handle bound to the library's static array launches the fused levels one by one
+    (no graph); results equal the separate calls on an ordinary binding."""
+    print("[gpu] fused on the static scratch binding", flush=True)
+    q = kktgen.make_sequence(kktgen.small(1500, config_id=153, steps=3))
+    sep = K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0)).bind()
+    scr = K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0)).bind_scratch(0)
+    for t in range(3):
+        same_step(q, t, sep, scr, alias=(t == 1))
+
+
+def test_profiler_counts_every_level_launch():
+    """The launch profiler brackets runs of level launches with one event pair but still
+    counts each launch: per unit, the refactorization classes add up to the level count."""
+    print("[gpu] launch profiler counts", flush=True)
+    q = kktgen.make_sequence(kktgen.small(3000, config_id=149, steps=2))
+    sk = K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0)).bind()
+    vd, bd = cuda(q.values(1)), cuda(q.rhs(1))
+    for fused in (True, False):
+        sk.profile(True)
+        if fused:
+            sk.refactor_refine(vd, bd)
+        else:
+            sk.refactor(vd)
+            sk.refine(bd)
+        pr = sk.profile_read()
+        sk.profile(False)
+        levels = sum(pr[c][0] for c in ("refactor_large", "refactor_medium", "refactor_w256", "refactor_small"))
+        assert levels == sk.stats["gpu_levels_f"], (fused, pr)
+        assert all(pr[c][1] > 0 for c in pr if pr[c][0] > 0), pr
