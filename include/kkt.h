@@ -382,7 +382,8 @@ int kkt_server_add_pattern(kkt_server *s, int32_t n, const int64_t *rowptr, cons
 /* Queues a request; returns at once with *ticket.  d_values (FP64[nnz], CSR order of the
  * pattern), d_b and d_x (nrhs columns at stride ld >= n; d_x may equal d_b) are device
  * memory of the server's device, borrowed until kkt_server_wait returns for the ticket.
- * Errors: ARG, NOMEM. */
+ * A request runs as kkt_refactor then kkt_refine on its replica (as kkt_refactor_refine for
+ * one right-hand side: the same results).  Errors: ARG, NOMEM. */
 int kkt_server_submit(kkt_server *s, int32_t pattern, const double *d_values, const double *d_b, double *d_x,
                       int32_t nrhs, int64_t ld, int64_t *ticket);
 

@@ -169,10 +169,14 @@ void worker(kkt_server *s) {
             if (!rc) rc = kkt_bind(rep->h, rep->ws, rep->bytes, s->o.max_nrhs, st);
             r->new_replica = true;
         }
-        if (!rc) rc = kkt_refactor(rep->h, r->v, st);
         if (!rc) {
             r->info.resize(r->nrhs);
-            rc = kkt_refine(rep->h, r->b, r->x, r->nrhs, r->ld, r->info.data(), st);
+            if (r->nrhs == 1) {   // the forward substitution rides in the refactorization
+                rc = kkt_refactor_refine(rep->h, r->v, r->b, r->x, r->info.data(), st);
+            } else {
+                rc = kkt_refactor(rep->h, r->v, st);
+                if (!rc) rc = kkt_refine(rep->h, r->b, r->x, r->nrhs, r->ld, r->info.data(), st);
+            }
         }
         if (rc < 0) (void)hipStreamSynchronize(st);
         r->t_end = clock_type::now();
