@@ -219,9 +219,10 @@ int kkt_bind_scratch(kkt_handle *h, int32_t max_nrhs, hipStream_t stream);
 /* Value update and refactorization without pivoting (Algorithm 1, update the factor
  * object with the new values, refactor).  d_values: device FP64[nnz_a] in the analysed
  * CSR order, BORROWED until the next kkt_refactor or kkt_destroy (kkt_refine reads it for
- * residuals).  Asynchronous: the value update is launched on stream, then the level
- * launches, replayed from the graph recorded at the first call after kkt_bind when
- * opts.graph_refactor is set (the first call also records it, which takes longer).  Calls
+ * residuals).  Asynchronous: a one-thread launch stores the values pointer in the
+ * workspace, then the value update and the level launches run on stream, replayed from the
+ * graph recorded at the first call after kkt_bind when opts.graph_refactor is set (the first
+ * call also records it, which takes longer).  Calls
  * on one handle must be ordered by the caller (they share the workspace).  Errors: ARG,
  * STATE (not bound), DEVICE.  Tiny pivots and non-finite factors are reported by
  * kkt_refine / kkt_refactor_status. */

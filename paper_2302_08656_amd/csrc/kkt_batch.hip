@@ -18,12 +18,15 @@ struct BatchSys {
     const int2 *lu_src;
     double *r, *c, *part;
     int16_t *er, *ec;
-    int n, eq, nb_norm, q0, q1;
+    int n, eq, nb_norm;
+    CopyRanges rest;   // the copy after the last level
 };
 
 // One handle's share of a batched launch.
 struct BatchPart {
-    int sys, blk0, nblk, item0, nwide, small0, nsmall, c0, c1, pad0, pad1, pad2;
+    int sys, blk0, nblk, item0, nwide, small0, nsmall;
+    CopyRanges c;   // the level's chunk of the row-ordered copy
+    int pad0;
 };
 
 // the share that runs block b (shares are sorted by blk0, the first starts at 0)
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(C::kThreads, C::kWaves) void k_batch_level(const Ba
     extern __shared__ __align__(16) char sm[];
     const BatchPart P = parts[find_part(parts, nparts, blockIdx.x)];
     const RefArgs<typename C::T> a = sys[P.sys].ref;
-    refactor_block<C>(blockIdx.x - P.blk0, P.nblk, P.item0, a, P.nwide, P.small0, P.nsmall, P.c0, P.c1,
+    refactor_block<C>(blockIdx.x - P.blk0, P.nblk, P.item0, a, P.nwide, P.small0, P.nsmall, P.c,
                       FuseArgs<typename C::T>{}, sm);
 }
 
@@ -92,10 +95,8 @@ template <class T>
 __global__ void k_batch_copy(const BatchSys<T> *__restrict__ sys, const BatchPart *__restrict__ parts, int nparts) {
     const BatchPart P = parts[find_part(parts, nparts, blockIdx.x)];
     const BatchSys<T> &S = sys[P.sys];
-    const int q = S.q0 + (int)((blockIdx.x - P.blk0) * blockDim.x + threadIdx.x);
-    if (q < S.q1) {
-        S.ref.lucsr[S.ref.copy_k[q]] = S.ref.lu[S.ref.copy_src[q]];
-    }
+    copy_ranges(S.ref.copy_k, S.ref.copy_src, S.ref.lu, S.ref.lucsr, S.rest, blockIdx.x - P.blk0, P.nblk,
+                blockDim.x);
 }
 
 template <class T>
@@ -159,9 +160,7 @@ BatchSys<T> batch_sys(const kkt_handle *h) {
     b.n = h->sym.n;
     b.eq = h->opts.equilibrate != 0;
     b.nb_norm = norm_blocks(h->sym.n);
-    const int ncopy = (int)g.copy_ptr.size() - 1;
-    b.q0 = ncopy > 0 ? g.copy_ptr.back() : 0;
-    b.q1 = (int)g.copy_k.size();
+    b.rest = copy_rest(g, copy_carriers(g));
     return b;
 }
 
@@ -209,19 +208,18 @@ int batch_build(kkt_batch *b, std::vector<BatchPart> &parts, std::vector<char> &
             const Schedule &g = h->sch;
             if (l + 1 >= (int)g.f_lvl.size()) return 0;
             const int i0 = g.f_lvl[l], nw = g.f_nlarge[l], ns = g.f_lvl[l + 1] - i0 - nw;
-            const int ncopy = (int)g.copy_ptr.size() - 1, cc = l - g.copy_lvl;
+            const int ncopy = copy_carriers(g), cc = l - g.copy_lvl;
             const bool copy = cc >= 0 && cc < ncopy && nw > 0;
             p.item0 = i0;
             p.nwide = nw;
             p.small0 = i0 + nw;
             p.nsmall = ns;
-            p.c0 = copy ? g.copy_ptr[cc] : 0;
-            p.c1 = copy ? g.copy_ptr[cc + 1] : 0;
-            const int cb = p.c1 > p.c0 ? h->ncu : 0;
+            p.c = copy ? copy_chunk(g, cc, ncopy) : CopyRanges{0, 0, 0, 0};
+            const int cb = copy_count(p.c) > 0 ? h->ncu : 0;
             return nw + (int)blocks_for(ns, Big::kThreads / 16) + cb;
         }));
     }
-    add(6, shares([&](int i, BatchPart &) { return (int)blocks_for(sys[i].q1 - sys[i].q0, 256); }));
+    add(6, shares([&](int i, BatchPart &) { return (int)blocks_for(copy_count(sys[i].rest), 256); }));
     add(7, {});
     return KKT_OK;
 }

@@ -94,12 +94,13 @@ struct Schedule {
     // levels whose 32-column wide items run in 256-thread blocks (every factored panel of the
     // level has at most 256 rows): 1, else 0
     std::vector<int32_t> f_w256;
-    // row-ordered copy: copy_k lists CSR positions grouped by the launch that finishes their
-    // column (launch l: copy_k[copy_at[l] .. copy_at[l+1])); launch copy_lvl + c (c <
-    // copy_ptr.size() - 1) copies copy_k[copy_ptr[c] .. copy_ptr[c+1]), the copy after the
-    // last level the rest
+    // row-ordered copy: copy_k lists CSR positions, the strictly lower entries first (launch
+    // l's: copy_k[copy_lat[l] .. copy_lat[l+1])), then the others (launch l's: copy_k[
+    // copy_uat[l] .. copy_uat[l+1])), grouped by the launch that finishes their column;
+    // copy_src[q] = csr_src[copy_k[q]].  Launches copy_lvl on (every one with wide items) are
+    // the top levels, which leave most of the GPU idle and carry copy chunks.
     int32_t copy_lvl = 0;
-    std::vector<int32_t> copy_k, copy_src, copy_ptr, copy_at;   // copy_src[q] = csr_src[copy_k[q]]
+    std::vector<int32_t> copy_k, copy_src, copy_lat, copy_uat;
     // forward solve fused with the refactorization: the items of forward level k read only
     // columns final after refactor launch l_ready[k] (and unknowns of lower forward levels)
     std::vector<int32_t> l_ready;

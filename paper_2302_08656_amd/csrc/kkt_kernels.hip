@@ -76,6 +76,27 @@ __global__ __launch_bounds__(256) void k_clear_status(DevStatus *st, unsigned lo
     clear_status_body(st, pcount);
 }
 
+// The per-call inputs of the recorded graphs (the values of A, the right-hand side): a
+// one-thread launch stores them before a replay and the recorded kernels read them here, so
+// one recording serves every call.
+struct CallPtrs {
+    const double *v;
+    const double *b;
+};
+
+__global__ void k_set_call(CallPtrs *dst, const double *v, const double *b) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        dst->v = v;
+        dst->b = b;
+    }
+}
+
+// a pointer stored by an earlier launch, read past the non-coherent caches
+__device__ __forceinline__ const double *call_ptr(const double *const *p) {
+    return reinterpret_cast<const double *>(__hip_atomic_load(reinterpret_cast<const unsigned long long *>(p),
+                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
 // Rows of the update passes taken by one group of 8 lanes: the group issues the loads of
 // all its rows together, so a wavefront has that many times more loads in flight (the passes
 // are bound by the latency of their dependent loads, not by bandwidth).
@@ -131,10 +152,10 @@ __device__ __forceinline__ void row_scale_body(int blk, int n, const int32_t *__
 }
 
 __global__ __launch_bounds__(256) void k_row_scale(int n, const int32_t *__restrict__ rowptr,
-                                                   const double *__restrict__ v, int scale,
+                                                   const CallPtrs *call, int scale,
                                                    double *__restrict__ r, int16_t *__restrict__ er,
                                                    DevStatus *st) {
-    row_scale_body(blockIdx.x, n, rowptr, v, scale, r, er, st);
+    row_scale_body(blockIdx.x, n, rowptr, call_ptr(&call->v), scale, r, er, st);
 }
 
 // c from the row-scaled matrix and the scaled values into the factor, per column j
@@ -194,10 +215,10 @@ __device__ __forceinline__ void col_store_body(int blk, int n, const int32_t *__
 template <class T>
 __global__ __launch_bounds__(256) void k_col_store(int n, const int32_t *__restrict__ colptr,
                                                    const int2 *__restrict__ src, const int32_t *__restrict__ Q,
-                                                   const double *__restrict__ v, const int16_t *__restrict__ er,
+                                                   const CallPtrs *call, const int16_t *__restrict__ er,
                                                    int scale, double *__restrict__ c, int16_t *__restrict__ ec,
                                                    T *__restrict__ lu) {
-    col_store_body<T>(blockIdx.x, n, colptr, src, Q, v, er, scale, c, ec, lu);
+    col_store_body<T>(blockIdx.x, n, colptr, src, Q, call_ptr(&call->v), er, scale, c, ec, lu);
 }
 
 // The row sums of |A| and |R A C| in CSR order, 8 lanes per row and kRowsPerGroup rows per
@@ -265,10 +286,10 @@ __device__ __forceinline__ void norms_body(int blk, int nblk, int n, const int32
 }
 
 __global__ __launch_bounds__(256) void k_norms(int n, const int32_t *__restrict__ rowptr,
-                                               const int32_t *__restrict__ col, const double *__restrict__ v,
+                                               const int32_t *__restrict__ col, const CallPtrs *call,
                                                const double *__restrict__ r, const int16_t *__restrict__ ec,
                                                double *__restrict__ part) {
-    norms_body(blockIdx.x, gridDim.x, n, rowptr, col, v, r, ec, part);
+    norms_body(blockIdx.x, gridDim.x, n, rowptr, col, call_ptr(&call->v), r, ec, part);
 }
 
 // dst[j] = max over blocks b of part[nfield * b + j] (NaN propagates), j < nfield
@@ -318,13 +339,29 @@ __global__ __launch_bounds__(256) void k_sum_counts(const unsigned long long *__
     sum_counts_body(pcount, out);
 }
 
-// lucsr[copy_k[q]] = lu[copy_src[q]], q in [q0, q1) (copy_src[q]: factor slot of CSR position copy_k[q])
+// Two ranges [a0, a1) and [b0, b1) of the row-ordered copy list (entries of the strictly
+// lower and of the upper section)
+struct CopyRanges {
+    int a0, a1, b0, b1;
+};
+
+// lucsr[copy_k[q]] = lu[copy_src[q]] for q in the ranges (copy_src[q]: factor slot of CSR
+// position copy_k[q]), by block b of nb blocks of nthreads threads
 template <class T>
-__global__ void k_to_csr(int q0, int q1, const int32_t *__restrict__ copy_k, const int32_t *__restrict__ copy_src,
-                         const T *__restrict__ lu, T *__restrict__ lucsr) {
-    for (int q = q0 + (int)(blockIdx.x * blockDim.x + threadIdx.x); q < q1; q += gridDim.x * blockDim.x) {
+__device__ __forceinline__ void copy_ranges(const int32_t *__restrict__ copy_k, const int32_t *__restrict__ copy_src,
+                                            const T *__restrict__ lu, T *__restrict__ lucsr, const CopyRanges &c,
+                                            int b, int nb, int nthreads) {
+    const int na = c.a1 - c.a0, tot = na + (c.b1 - c.b0);
+    for (int t = b * nthreads + (int)threadIdx.x; t < tot; t += nb * nthreads) {
+        const int q = t < na ? c.a0 + t : c.b0 + (t - na);
         lucsr[copy_k[q]] = lu[copy_src[q]];
     }
+}
+
+template <class T>
+__global__ void k_to_csr(CopyRanges c, const int32_t *__restrict__ copy_k, const int32_t *__restrict__ copy_src,
+                         const T *__restrict__ lu, T *__restrict__ lucsr) {
+    copy_ranges(copy_k, copy_src, lu, lucsr, c, blockIdx.x, gridDim.x, blockDim.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -601,22 +638,18 @@ __device__ __forceinline__ void small_group(int item0, int nsmall, const RefArgs
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(&a.pcount[slot % kCountSlots], (unsigned long long)c);
 }
 
-// lucsr[copy_k[q]] = lu[copy_src[q]] for q in [c0, c1), by block b of nb blocks of
-// nthreads threads
 template <class T>
-__device__ __forceinline__ void copy_block(const RefArgs<T> &a, int c0, int c1, int b, int nb, int nthreads) {
-    for (int q = c0 + b * nthreads + (int)threadIdx.x; q < c1; q += nb * nthreads) {
-        a.lucsr[a.copy_k[q]] = a.lu[a.copy_src[q]];
-    }
+__device__ __forceinline__ void copy_block(const RefArgs<T> &a, const CopyRanges &c, int b, int nb, int nthreads) {
+    copy_ranges(a.copy_k, a.copy_src, a.lu, a.lucsr, c, b, nb, nthreads);
 }
 
 // A level without wide items: its narrow items, kBlock / 16 to a block; the blocks after
-// them copy copy_k[c0 .. c1) of the row-ordered factor (columns final before the launch)
+// them copy the ranges c of the row-ordered factor (columns final before the launch)
 template <class T, bool kPipe>
-__global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, RefArgs<T> a, int c0, int c1) {
+__global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, RefArgs<T> a, CopyRanges c) {
     const int nsb = (nsmall + kBlock / 16 - 1) / (kBlock / 16);
     if ((int)blockIdx.x >= nsb) {
-        copy_block(a, c0, c1, blockIdx.x - nsb, gridDim.x - nsb, kBlock);
+        copy_block(a, c, blockIdx.x - nsb, gridDim.x - nsb, kBlock);
         return;
     }
     small_group<T, kPipe>(item0, nsmall, a, blockIdx.x * (kBlock / 16) + (threadIdx.x >> 4),
@@ -1199,7 +1232,7 @@ __device__ __forceinline__ void wide_item(const int item, const RefArgs<typename
 // unknowns final before the launch), ahead of the narrow items so that they start beside the
 // factor work; the next ones run the level's narrow items small0 .. small0 + nsmall - 1,
 // C::kThreads / 16 to a block (they touch other columns than the wide items, so one launch
-// needs no ordering between them); any blocks after those copy copy_k[c0 .. c1) of the
+// needs no ordering between them); any blocks after those copy the ranges c of the
 // row-ordered factor (columns that no launch from this one on writes).
 // Block blk of nblk of one level launch (the work of one handle: its wide items, narrow
 // items and copy chunk).
@@ -1214,7 +1247,7 @@ template <class T> __device__ void fused_forward_block(const FuseArgs<T> &f, int
 
 template <class C>
 __device__ __forceinline__ void refactor_block(int blk, int nblk, int item0, const RefArgs<typename C::T> &a,
-                                               int nwide, int small0, int nsmall, int c0, int c1,
+                                               int nwide, int small0, int nsmall, const CopyRanges &c,
                                                const FuseArgs<typename C::T> &f, char *sm) {
     const int nsb = (nsmall + C::kThreads / 16 - 1) / (C::kThreads / 16);
     if (blk >= nwide && blk < nwide + f.nsolve) {
@@ -1223,7 +1256,7 @@ __device__ __forceinline__ void refactor_block(int blk, int nblk, int item0, con
     }
     if (blk >= nwide + f.nsolve + nsb) {
         const int b = blk - nwide - f.nsolve - nsb, nbc = nblk - nwide - f.nsolve - nsb;
-        copy_block(a, c0, c1, b, nbc, C::kThreads);
+        copy_block(a, c, b, nbc, C::kThreads);
         return;
     }
     if (blk >= nwide) {
@@ -1237,10 +1270,10 @@ __device__ __forceinline__ void refactor_block(int blk, int nblk, int item0, con
 
 template <class C>
 __global__ __launch_bounds__(C::kThreads, C::kWaves) void k_refactor_wide(int item0, RefArgs<typename C::T> a,
-                                                                         int nwide, int small0, int nsmall, int c0,
-                                                                         int c1, FuseArgs<typename C::T> f) {
+                                                                         int nwide, int small0, int nsmall,
+                                                                         CopyRanges c, FuseArgs<typename C::T> f) {
     extern __shared__ __align__(16) char sm[];
-    refactor_block<C>(blockIdx.x, gridDim.x, item0, a, nwide, small0, nsmall, c0, c1, f, sm);
+    refactor_block<C>(blockIdx.x, gridDim.x, item0, a, nwide, small0, nsmall, c, f, sm);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1679,12 +1712,14 @@ __device__ __forceinline__ void fused_forward_block(const FuseArgs<T> &f, int bl
     for (int item = f.j0 + blk; item < f.j1; item += f.nsolve) lsolve_item<false>(f.s, item, L.ext, L.blk, L.ys);
 }
 
-// bp = r[P] .* b[P]; with mark, every unknown of the persistent mode starts unset; the
-// first ntick item tickets start at zero (ntick <= n, or the grid covers ntick threads)
-__global__ void k_solve_reset(int n, const double *__restrict__ b, const double *__restrict__ r,
-                              const int32_t *__restrict__ P, double *__restrict__ bp, double *__restrict__ y,
-                              double *__restrict__ xt, double *__restrict__ psum, double *__restrict__ usum,
-                              int mark, int ntick, int *__restrict__ tick) {
+// bp = r[P] .* b[P] (b = b0, or the recorded call's right-hand side when b0 is null); with
+// mark, every unknown of the persistent mode starts unset; the first ntick item tickets start
+// at zero (ntick <= n, or the grid covers ntick threads)
+__global__ void k_solve_reset(int n, const double *__restrict__ b0, const CallPtrs *call,
+                              const double *__restrict__ r, const int32_t *__restrict__ P, double *__restrict__ bp,
+                              double *__restrict__ y, double *__restrict__ xt, double *__restrict__ psum,
+                              double *__restrict__ usum, int mark, int ntick, int *__restrict__ tick) {
+    const double *__restrict__ b = b0 ? b0 : call_ptr(&call->b);   // b0 null: the recorded call's
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < ntick) tick[i] = 0;
     if (i < n) {

@@ -36,6 +36,7 @@ struct Dev {
     DevStatus *st;
     ResNorms *rn;
     int *tick;          // ticket counters of the persistent solves (forward, backward, fused tail)
+    CallPtrs *call;     // the values and right-hand side of the current call (recorded graphs)
 };
 
 // most blocks of a refactor launch that run forward-solve items (kkt_refactor_refine; at 70k
@@ -163,6 +164,7 @@ void carve(const kkt_handle *h, char *base, Dev &d, size_t *bytes) {
     d.st = c.take<DevStatus>(1);
     d.rn = c.take<ResNorms>(1);
     d.tick = c.take<int>(3);
+    d.call = c.take<CallPtrs>(1);
     *bytes = c.off + 256;
 }
 
@@ -302,7 +304,7 @@ int enqueue_solve_t(kkt_handle *h, const double *b, double *x, hipStream_t s, bo
                     d.xt, x, d.psum, d.usum, &d.st->abort, d.tick};
     if (forward)
         timed(h, KKT_PROF_LSOLVE, s, [&] {
-            k_solve_reset<<<blocks_for(n, 256), 256, 0, s>>>(n, b, d.r, d.P, d.bp, d.y, d.xt, d.psum, d.usum,
+            k_solve_reset<<<blocks_for(n, 256), 256, 0, s>>>(n, b, d.call, d.r, d.P, d.bp, d.y, d.xt, d.psum, d.usum,
                                                              pers ? 1 : 0, pers ? 2 : 0, d.tick);
         });
     // forward: level launches below l_split, then the persistent launch
@@ -350,25 +352,33 @@ int enqueue_solve(kkt_handle *h, const double *b, double *x, hipStream_t s, bool
     return by_precision(h, [&](auto tag) { return enqueue_solve_t<decltype(tag)>(h, b, x, s, forward); });
 }
 
-// value update: scale factors, scaled values scattered into the factor, norms
-int enqueue_update(kkt_handle *h, const double *v, hipStream_t s) {
+// stores the call's values (and right-hand side, or null) for the recorded kernels
+int set_call(kkt_handle *h, const double *v, const double *b, hipStream_t s) {
+    k_set_call<<<1, 64, 0, s>>>(h->d.call, v, b);
+    HIPCHK(hipGetLastError());
+    return KKT_OK;
+}
+
+// value update of the values stored by set_call: scale factors, scaled values into the
+// factor, norms
+int enqueue_update(kkt_handle *h, hipStream_t s) {
     const Dev &d = h->d;
     const int n = h->sym.n;
     const int eq = h->opts.equilibrate != 0;
     timed(h, KKT_PROF_UPDATE, s, [&] { k_clear_status<<<1, 256, 0, s>>>(d.st, d.pcount); });
     timed(h, KKT_PROF_UPDATE, s, [&] {
-        k_row_scale<<<row_blocks(n), 256, 0, s>>>(n, d.a_rowptr, v, eq, d.r, d.er, d.st);
+        k_row_scale<<<row_blocks(n), 256, 0, s>>>(n, d.a_rowptr, d.call, eq, d.r, d.er, d.st);
     });
     timed(h, KKT_PROF_UPDATE, s, [&] {
         by_precision(h, [&](auto tag) {
             using T = decltype(tag);
-            k_col_store<T><<<col_blocks(n), 256, 0, s>>>(n, d.colptr, d.lu_src, d.Q, v, d.er, eq, d.c, d.ec,
-                                                      static_cast<T *>(d.lu));
+            k_col_store<T><<<col_blocks(n), 256, 0, s>>>(n, d.colptr, d.lu_src, d.Q, d.call, d.er, eq, d.c,
+                                                      d.ec, static_cast<T *>(d.lu));
             return 0;
         });
     });
     const int nbn = norm_blocks(n);
-    timed(h, KKT_PROF_UPDATE, s, [&] { k_norms<<<nbn, 256, 0, s>>>(n, d.a_rowptr, d.a_colind, v, d.r, d.ec, d.part); });
+    timed(h, KKT_PROF_UPDATE, s, [&] { k_norms<<<nbn, 256, 0, s>>>(n, d.a_rowptr, d.a_colind, d.call, d.r, d.ec, d.part); });
     timed(h, KKT_PROF_UPDATE, s, [&] { k_max_parts<<<1, 256, 0, s>>>(nbn, 2, d.part, &d.st->anorm_scaled); });
     HIPCHK(hipGetLastError());
     return KKT_OK;
@@ -379,9 +389,27 @@ int enqueue_update(kkt_handle *h, const double *v, hipStream_t s) {
 int copy_blocks(const kkt_handle *h, int entries, int threads) {
     return entries > 0 ? std::min(kCopyBlocksPerCu * h->ncu, (int)blocks_for(entries, threads)) : 0;
 }
+int copy_count(const CopyRanges &c) { return (c.a1 - c.a0) + (c.b1 - c.b0); }
 
-// the level launches of the refactorization, the row-ordered copy and the pivot count; they
-// read only workspace buffers, so one recording serves every later call.
+// kkt_refactor's row-ordered copy: the entries of every column final before the top levels
+// ride in up to kCopyLaunches of the top launches, chunk c of ncopy of each section; the rest
+// follows the last level
+int copy_carriers(const Schedule &g) {
+    return std::min<int>(kCopyLaunches, (int)g.f_lvl.size() - 1 - g.copy_lvl);
+}
+CopyRanges copy_chunk(const Schedule &g, int c, int ncopy) {
+    const int64_t nl = g.copy_lat[g.copy_lvl], u0 = g.copy_uat[0], nu = g.copy_uat[g.copy_lvl] - u0;
+    return CopyRanges{(int)(nl * c / ncopy), (int)(nl * (c + 1) / ncopy), (int)(u0 + nu * c / ncopy),
+                      (int)(u0 + nu * (c + 1) / ncopy)};
+}
+CopyRanges copy_rest(const Schedule &g, int ncopy) {
+    const int u0 = g.copy_uat[0], n = (int)g.copy_k.size();
+    return CopyRanges{ncopy > 0 ? g.copy_lat[g.copy_lvl] : 0, u0, ncopy > 0 ? g.copy_uat[g.copy_lvl] : u0, n};
+}
+
+// the value update (of the values stored by set_call), the level launches of the
+// refactorization, the row-ordered copy and the pivot count; they read only workspace
+// buffers, so one recording serves every later call.
 // fused: the forward solve of the right-hand side set up by k_solve_reset rides in the same
 // launches, so no launch waits on another queue.  Each launch has extra blocks that copy the
 // entries of the columns finished by the launches before it into the row-ordered copy; each
@@ -401,10 +429,26 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s, bool fused) {
                  tiny, h->opts.dense_mfma != 0, d.copy_k, d.copy_src, static_cast<T *>(d.lucsr),
                  d.pan_start, d.pan_r};
     const int nlev = (int)g.f_lvl.size() - 1;
-    const int ncopy = fused ? 0 : (int)g.copy_ptr.size() - 1;   // launches that carry a chunk of the copy
+    const int ncopy = fused ? 0 : copy_carriers(g);   // kkt_refactor: launches that carry a chunk of the copy
+    // fused: the upper section spread evenly over the top launches (as far as final)
+    const int u0 = g.copy_uat[0], nup = (int)g.copy_k.size() - u0, ntop = nlev - g.copy_lvl;
+    int ucopied = u0, ktop = 0;
     const SolveArgs<T> fs{d.l_item4, d.l_rows4, d.rinfo4, d.csr_col, d.Q, static_cast<const T *>(d.lucsr), d.c,
                           d.bp, d.y, d.xt, nullptr, d.psum, d.usum, &d.st->abort, d.tick + 2};
     const int nfl = (int)g.l_lvl.size() - 1;
+    {
+        const int rc = enqueue_update(h, s);
+        if (rc) return rc;
+    }
+    if (fused) {
+        // bp from the stored right-hand side, the unset unknowns and the tickets (the forward
+        // tail's included)
+        const int n = h->sym.n, ntick = 3;
+        timed(h, KKT_PROF_LSOLVE, s, [&] {
+            k_solve_reset<<<blocks_for(std::max(n, ntick), 256), 256, 0, s>>>(n, nullptr, d.call, d.r, d.P, d.bp, d.y,
+                                                                             d.xt, d.psum, d.usum, 1, ntick, d.tick);
+        });
+    }
     int copied = 0, solved = 0;   // fused: levels whose columns a launch copies, forward levels launched
     for (int l = 0; l < nlev; ++l) {
         // the kinds of items of a level touch disjoint target columns, so one launch runs the
@@ -413,26 +457,27 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s, bool fused) {
         const int nm = g.f_nmed[l], nb = g.f_nlarge[l] - nm, ns = g.f_lvl[l + 1] - g.f_lvl[l] - nb - nm;
         const int i0 = g.f_lvl[l];
         if (ns && !nb && !nm) {
-            // with fused, extra blocks copy the columns of the levels since the last launch
-            const int c0 = fused ? g.copy_at[copied] : 0, c1 = fused ? g.copy_at[l] : 0;
+            // with fused, extra blocks copy the lower entries of the columns of the levels since
+            // the last launch
+            const CopyRanges c{fused ? g.copy_lat[copied] : 0, fused ? g.copy_lat[l] : 0, 0, 0};
             if (fused) copied = l;
-            const int grid = (int)blocks_for(ns, kBlock / 16) + copy_blocks(h, c1 - c0, kBlock);
+            const int grid = (int)blocks_for(ns, kBlock / 16) + copy_blocks(h, copy_count(c), kBlock);
             timed(h, KKT_PROF_REFACTOR_SMALL, s, [&] {
                 // many items: keep more in flight; few: shorten each item's dependent chain
                 if (ns > kSmallPipeMax)
-                    k_refactor_small<T, false><<<grid, kBlock, 0, s>>>(i0, ns, a, c0, c1);
+                    k_refactor_small<T, false><<<grid, kBlock, 0, s>>>(i0, ns, a, c);
                 else
-                    k_refactor_small<T, true><<<grid, kBlock, 0, s>>>(i0, ns, a, c0, c1);
+                    k_refactor_small<T, true><<<grid, kBlock, 0, s>>>(i0, ns, a, c);
             }, true);
         }
         if (!nb && !nm) continue;
         // otherwise the narrow items are extra blocks of the level's wide launch, and so is a
-        // chunk of the row-ordered copy (columns already final): on the top levels, or with
-        // fused the columns of the levels since the last wide launch
+        // chunk of the row-ordered copy (columns already final): on the top levels; with fused
+        // the lower entries of the columns of the levels since the last launch, and on the top
+        // levels a share of the upper ones
         const int s0 = i0 + nb + nm, mb = nb ? ns : 0, mm = nb ? 0 : ns;
         const int cc = l - g.copy_lvl;
-        const bool copy = cc >= 0 && cc < ncopy;
-        int c0 = copy ? g.copy_ptr[cc] : 0, c1 = copy ? g.copy_ptr[cc + 1] : 0;
+        CopyRanges c = cc >= 0 && cc < ncopy ? copy_chunk(g, cc, ncopy) : CopyRanges{0, 0, 0, 0};
         FuseArgs<T> f{fs, 0, 0, 0};
         if (fused) {
             if (solved < nfl && g.l_ready[solved] < copied) {
@@ -441,35 +486,44 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s, bool fused) {
                 f.nsolve = std::min(f.j1 - f.j0, kFuseSolveBlocks);
                 ++solved;
             }
-            c0 = g.copy_at[copied];
-            c1 = g.copy_at[l];
+            c = CopyRanges{g.copy_lat[copied], g.copy_lat[l], 0, 0};
             copied = l;
+            if (cc >= 0) {
+                const int uend = std::min<int>(g.copy_uat[l], (int)(u0 + (int64_t)nup * (++ktop) / ntop));
+                if (uend > ucopied) {
+                    c.b0 = ucopied;
+                    c.b1 = uend;
+                    ucopied = uend;
+                }
+            }
         }
         const int threads = nb ? (g.f_w256[l] ? W256::kThreads : Big::kThreads) : Med::kThreads;
-        const int cb = copy_blocks(h, c1 - c0, threads);
+        const int cb = copy_blocks(h, copy_count(c), threads);
         if (nb && g.f_w256[l])
             timed(h, KKT_PROF_REFACTOR_W256, s, [&] {
                 const int grid = nb + (int)blocks_for(mb, W256::kThreads / 16) + f.nsolve + cb;
-                k_refactor_wide<W256><<<grid, W256::kThreads, W256::kLds, s>>>(i0, a, nb, s0, mb, c0, c1, f);
+                k_refactor_wide<W256><<<grid, W256::kThreads, W256::kLds, s>>>(i0, a, nb, s0, mb, c, f);
             }, true);
         else if (nb)
             timed(h, KKT_PROF_REFACTOR_LARGE, s, [&] {
                 const int grid = nb + (int)blocks_for(mb, Big::kThreads / 16) + f.nsolve + cb;
-                k_refactor_wide<Big><<<grid, Big::kThreads, Big::kLds, s>>>(i0, a, nb, s0, mb, c0, c1, f);
+                k_refactor_wide<Big><<<grid, Big::kThreads, Big::kLds, s>>>(i0, a, nb, s0, mb, c, f);
             }, true);
         else
             timed(h, KKT_PROF_REFACTOR_MEDIUM, s, [&] {
                 const int grid = nm + (int)blocks_for(mm, Med::kThreads / 16) + f.nsolve + cb;
-                k_refactor_wide<Med><<<grid, Med::kThreads, Med::kLds, s>>>(i0, a, nm, s0, mm, c0, c1, f);
+                k_refactor_wide<Med><<<grid, Med::kThreads, Med::kLds, s>>>(i0, a, nm, s0, mm, c, f);
             }, true);
     }
     // the rest of the copy: the columns of the top levels (all of it without such levels), or
-    // with fused the columns of the levels since the last wide launch; then the remaining
-    // forward levels
-    const int q0 = fused ? g.copy_at[copied] : ncopy > 0 ? g.copy_ptr.back() : 0, q1 = (int)g.copy_k.size();
-    if (q1 > q0)
-        timed(h, KKT_PROF_TO_CSR, s,
-              [&] { k_to_csr<T><<<blocks_for(q1 - q0, 256), 256, 0, s>>>(q0, q1, d.copy_k, d.copy_src, a.lu, a.lucsr); });
+    // with fused the lower entries of the columns of the levels since the last launch and the
+    // upper entries not copied yet; then the remaining forward levels
+    const CopyRanges rest = fused ? CopyRanges{g.copy_lat[copied], u0, ucopied, (int)g.copy_k.size()}
+                                  : copy_rest(g, ncopy);
+    if (copy_count(rest) > 0)
+        timed(h, KKT_PROF_TO_CSR, s, [&] {
+            k_to_csr<T><<<blocks_for(copy_count(rest), 256), 256, 0, s>>>(rest, d.copy_k, d.copy_src, a.lu, a.lucsr);
+        });
     if (fused && solved < nfl) {
         const int j0 = g.l_lvl[solved], j1 = g.l_lvl[nfl];
         timed(h, KKT_PROF_LSOLVE, s, [&] {
@@ -530,7 +584,7 @@ int enqueue_approx_solve_t(kkt_handle *h, const double *b, double *x, int sweeps
     const unsigned nb8 = blocks_for((int64_t)n * 8, 256), nb = blocks_for(n, 256);
     const unsigned nch = blocks_for(n, kGsChunk);
     timed(h, KKT_PROF_LSOLVE, s, [&] {
-        k_solve_reset<<<nb, 256, 0, s>>>(n, b, d.r, d.P, d.bp, d.y, d.xt, d.psum, d.usum, 0, 0, d.tick);
+        k_solve_reset<<<nb, 256, 0, s>>>(n, b, d.call, d.r, d.P, d.bp, d.y, d.xt, d.psum, d.usum, 0, 0, d.tick);
     });
     const double *yin = nullptr;
     double *ybuf[2] = {d.psum, d.y};
@@ -757,7 +811,10 @@ int kkt_get_stats(const kkt_handle *h, kkt_stats *out) {
     out->flops_refactor = h->sch.flops;
     out->nnz_lu_wide = h->sch.nnz_lu_wide;
     out->nnz_lu_medium = h->sch.nnz_lu_med;
-    out->copy_in_levels = h->sch.copy_ptr.empty() ? 0 : h->sch.copy_ptr.back();
+    {
+        const int nc = copy_carriers(h->sch);
+        out->copy_in_levels = nc > 0 ? copy_count(copy_chunk(h->sch, 0, 1)) : 0;
+    }
     out->nnz_lu_w256 = h->sch.nnz_lu_w256;
     return KKT_OK;
 }
@@ -1043,7 +1100,7 @@ int kkt_refactor(kkt_handle *h, const double *d_values, hipStream_t stream) {
     if (!h->bound) return KKT_ERR_STATE;
     DeviceGuard dg(h->device);
     if (!dg.ok) return KKT_ERR_DEVICE;
-    int rc = enqueue_update(h, d_values, stream);
+    int rc = set_call(h, d_values, nullptr, stream);
     if (!rc) rc = run_levels(h, stream);
     if (rc) return rc;
     h->d_values = d_values;
@@ -1064,15 +1121,8 @@ int kkt_refactor_refine(kkt_handle *h, const double *d_values, const double *d_b
         HIPCHK(hipMemcpyAsync(d.bsave, b, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
         b = d.bsave;
     }
-    int rc = enqueue_update(h, d_values, stream);
+    int rc = set_call(h, d_values, b, stream);
     if (rc) return rc;
-    // bp, the unset unknowns and the tickets (the forward tail's included), then the levels
-    const int ntick = 3;
-    timed(h, KKT_PROF_LSOLVE, stream, [&] {
-        k_solve_reset<<<blocks_for(std::max(n, ntick), 256), 256, 0, stream>>>(n, b, d.r, d.P, d.bp, d.y, d.xt,
-                                                                              d.psum, d.usum, 1, ntick, d.tick);
-    });
-    HIPCHK(hipGetLastError());
     rc = run_fused_levels(h, stream);
     if (rc) return rc;
     h->d_values = d_values;

@@ -555,34 +555,42 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
     }
     g.flops = fl;
     // the row-ordered copy of the factor: an entry can be copied once its column is final,
-    // i.e. after the launch that factors the column's panel.  copy_k lists the entries by the
-    // launch that finishes their column (copy_at[l] = first entry of launch l), in factor
-    // storage order within a launch, and copy_src[q] = csr_src[copy_k[q]]: a copy reads the
-    // factor nearly in order and scatters only its stores.  The top levels have few items and leave most of the GPU idle, so the
-    // entries of every column final before the first of them are copied by extra blocks of up
-    // to kCopyLaunches of those launches (in consecutive chunks); the rest after the last level
+    // i.e. after the launch that factors the column's panel.  copy_k lists the strictly lower
+    // (L) entries first, then the others (U and the diagonal); each section by the launch
+    // that finishes their column (copy_lat[l], copy_uat[l] = first entry of launch l in each),
+    // in factor storage order within a launch, and copy_src[q] = csr_src[copy_k[q]]: a copy
+    // reads the factor nearly in order and scatters only its stores.  The forward solve reads
+    // only L, so the fused refactorization copies L level by level and spreads U over its top
+    // launches.  The top levels (copy_lvl on) have few items and leave most of the GPU idle.
     const int32_t nlev_f = (int32_t)g.f_lvl.size() - 1;
     {
         int32_t win = nlev_f;
         while (win > 0 && g.f_lvl[win] - g.f_lvl[win - 1] <= kCopyItems && g.f_nlarge[win - 1] > 0) --win;
-        const int32_t nwin = std::min<int32_t>(kCopyLaunches, nlev_f - win);
         g.copy_lvl = win;
-        g.copy_at.assign(nlev_f + 1, 0);
-        for (int64_t q = 0; q < nlu; ++q) g.copy_at[plev[pan_of[g.csr_col[q]]] + 1]++;
-        for (int32_t l = 0; l < nlev_f; ++l) g.copy_at[l + 1] += g.copy_at[l];
+        std::vector<char> upper(nlu, 0);   // U or diagonal entry (CSR position)
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t q = g.csr_rowptr[i]; q < g.csr_rowptr[i + 1]; ++q) upper[q] = g.csr_col[q] >= i;
+        // counts per (section, level), then offsets: L section first
+        std::vector<int64_t> cnt(2 * (size_t)(nlev_f + 1), 0);
+        for (int64_t q = 0; q < nlu; ++q) cnt[upper[q] * (nlev_f + 1) + plev[pan_of[g.csr_col[q]]] + 1]++;
+        g.copy_lat.assign(nlev_f + 1, 0);
+        g.copy_uat.assign(nlev_f + 1, 0);
+        for (int32_t l = 0; l < nlev_f; ++l) g.copy_lat[l + 1] = g.copy_lat[l] + (int32_t)cnt[l + 1];
+        g.copy_uat[0] = g.copy_lat[nlev_f];
+        for (int32_t l = 0; l < nlev_f; ++l) g.copy_uat[l + 1] = g.copy_uat[l] + (int32_t)cnt[(nlev_f + 1) + l + 1];
         g.copy_k.resize(nlu);
-        {
-            std::vector<int32_t> nxt(g.copy_at.begin(), g.copy_at.end() - 1);
-            for (int64_t q = 0; q < nlu; ++q) g.copy_k[nxt[plev[pan_of[g.csr_col[q]]]]++] = (int32_t)q;
-            for (int32_t l = 0; l < nlev_f; ++l)
-                std::sort(g.copy_k.begin() + g.copy_at[l], g.copy_k.begin() + g.copy_at[l + 1],
-                          [&](int32_t a, int32_t b) { return g.csr_src[a] < g.csr_src[b]; });
-            g.copy_src.resize(nlu);
-            for (int64_t q = 0; q < nlu; ++q) g.copy_src[q] = g.csr_src[g.copy_k[q]];
+        std::vector<int32_t> nl(g.copy_lat.begin(), g.copy_lat.end() - 1), nu(g.copy_uat.begin(), g.copy_uat.end() - 1);
+        for (int64_t q = 0; q < nlu; ++q) {
+            const int32_t l = plev[pan_of[g.csr_col[q]]];
+            g.copy_k[upper[q] ? nu[l]++ : nl[l]++] = (int32_t)q;
         }
-        g.copy_ptr.assign(1, 0);
-        const int64_t ne = nwin > 0 ? g.copy_at[win] : 0;
-        for (int32_t c = 1; c <= nwin; ++c) g.copy_ptr.push_back((int32_t)(ne * c / nwin));
+        auto by_slot = [&](int32_t a, int32_t b) { return g.csr_src[a] < g.csr_src[b]; };
+        for (int32_t l = 0; l < nlev_f; ++l) {
+            std::sort(g.copy_k.begin() + g.copy_lat[l], g.copy_k.begin() + g.copy_lat[l + 1], by_slot);
+            std::sort(g.copy_k.begin() + g.copy_uat[l], g.copy_k.begin() + g.copy_uat[l + 1], by_slot);
+        }
+        g.copy_src.resize(nlu);
+        for (int64_t q = 0; q < nlu; ++q) g.copy_src[q] = g.csr_src[g.copy_k[q]];
     }
     // forward solve fused with the refactorization: the ready launch of a forward item is the
     // latest launch that finishes a column whose entries it reads (its own panel's included)
