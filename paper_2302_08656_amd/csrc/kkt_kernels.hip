@@ -221,15 +221,18 @@ __global__ __launch_bounds__(256) void k_col_store(int n, const int32_t *__restr
     col_store_body<T>(blockIdx.x, n, colptr, src, Q, call_ptr(&call->v), er, scale, c, ec, lu);
 }
 
-// The row sums of |A| and |R A C| in CSR order, 8 lanes per row and kRowsPerGroup rows per
-// group (grid-stride): the lanes load 8 consecutive entries of a row at once and the sums
-// add them in CSR order (left to right across the lanes); block maxima into part[2 * block].
+// The row sums of |A| and |R A C| in CSR order, kRowsPerGroup rows per group of 8 lanes
+// (grid-stride): the lanes load 8 consecutive entries of each row at once and leave their
+// terms in LDS, and lane k of the group adds row k's terms in CSR order (so the sums are
+// the sequential ones, bit for bit); block maxima into part[2 * block].  blockDim.x <= 256.
 __device__ __forceinline__ void norms_body(int blk, int nblk, int n, const int32_t *__restrict__ rowptr,
                                            const int32_t *__restrict__ col, const double *__restrict__ v,
                                            const double *__restrict__ r, const int16_t *__restrict__ ec,
                                            double *__restrict__ part) {
     __shared__ double red[2][4];
-    const int gl = threadIdx.x & 7;
+    __shared__ double terms[256 / 8][kRowsPerGroup][2][8];   // per group: row, {|r a c|, |a|}, entry
+    const int gl = threadIdx.x & 7, grp = threadIdx.x >> 3;
+    double (*T)[2][8] = terms[grp];
     double s = 0.0, a = 0.0;
     for (int i0 = ((blk * blockDim.x + threadIdx.x) >> 3) * kRowsPerGroup; i0 < n;
          i0 += ((nblk * blockDim.x) >> 3) * kRowsPerGroup) {
@@ -249,23 +252,44 @@ __device__ __forceinline__ void norms_body(int blk, int nblk, int n, const int32
         for (int k = 0; k < kRowsPerGroup; ++k) cj[k] = rp[k] + gl < rp[k + 1] ? scale_of(ec[cc[k]]) : 0.0;
 #pragma unroll
         for (int k = 0; k < kRowsPerGroup; ++k) {
-            double si = 0.0, ai = 0.0;
-            for (int q = rp[k]; q < rp[k + 1]; q += 8) {
-                double tv = 0.0, av = 0.0;
-                if (q == rp[k]) {
-                    tv = fabs((ri[k] * vv[k]) * cj[k]);
-                    av = fabs(vv[k]);
-                } else if (q + gl < rp[k + 1]) {
-                    const double x = v[q + gl];
-                    tv = fabs((ri[k] * x) * scale_of(ec[col[q + gl]]));
-                    av = fabs(x);
-                }
-                const int cnt = min(8, rp[k + 1] - q);
-                for (int t = 0; t < cnt; ++t) {
-                    ai = ai + __shfl(av, t, 8);
-                    si = si + __shfl(tv, t, 8);
+            T[k][0][gl] = fabs((ri[k] * vv[k]) * cj[k]);
+            T[k][1][gl] = fabs(vv[k]);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        // lane k: row k's first (up to) 8 terms in order
+        const int k = gl < kRowsPerGroup ? gl : 0;
+        const int len0 = min(8, rp[k + 1] - rp[k]);
+        double si = 0.0, ai = 0.0;
+        if (gl < kRowsPerGroup)
+            for (int t = 0; t < len0; ++t) {
+                si = si + T[k][0][t];
+                ai = ai + T[k][1][t];
+            }
+        // longer rows: the group loads each further chunk of 8, the row's lane adds it
+#pragma unroll
+        for (int kk = 0; kk < kRowsPerGroup; ++kk) {
+            for (int q = rp[kk] + 8; q < rp[kk + 1]; q += 8) {
+                __builtin_amdgcn_wave_barrier();
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                const bool h = q + gl < rp[kk + 1];
+                const double x = h ? v[q + gl] : 0.0;
+                T[0][0][gl] = h ? fabs((ri[kk] * x) * scale_of(ec[col[q + gl]])) : 0.0;
+                T[0][1][gl] = fabs(x);
+                __builtin_amdgcn_wave_barrier();
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                if (gl == kk) {
+                    const int cnt = min(8, rp[kk + 1] - q);
+                    for (int t = 0; t < cnt; ++t) {
+                        si = si + T[0][0][t];
+                        ai = ai + T[0][1][t];
+                    }
                 }
             }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (gl < kRowsPerGroup) {
             s = fmax(s, si);
             a = fmax(a, ai);
         }
