@@ -463,7 +463,7 @@ def main():
                  "refactor_w256": f"k_refactor_wide<WideCfg<{tname}, 256, 2, 128, 32, 4> >",
                  "refactor_small": "k_refactor_small",
                  "lsolve": "k_lsolve_persistent", "usolve": "k_usolve_persistent", "to_csr": "k_to_csr",
-                 "update": "k_clear_status..k_max_parts", "residual": "k_residual/k_spmv", "krylov": "krylov"}
+                 "update": "k_set_call..k_max_parts", "residual": "k_residual/k_spmv", "krylov": "krylov"}
     ranked = sorted((v[1], k) for k, v in prof.items())
     dom = ranked[-1][1]
     launches, ms = prof[dom]

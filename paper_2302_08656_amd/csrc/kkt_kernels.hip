@@ -72,10 +72,6 @@ __device__ __forceinline__ void clear_status_body(DevStatus *st, unsigned long l
     for (int t = threadIdx.x; t < kCountSlots; t += blockDim.x) pcount[t] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_clear_status(DevStatus *st, unsigned long long *pcount) {
-    clear_status_body(st, pcount);
-}
-
 // The per-call inputs of the recorded graphs (the values of A, the right-hand side): a
 // one-thread launch stores them before a replay and the recorded kernels read them here, so
 // one recording serves every call.
@@ -84,8 +80,12 @@ struct CallPtrs {
     const double *b;
 };
 
-__global__ void k_set_call(CallPtrs *dst, const double *v, const double *b) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+// stores the call's inputs and clears the status words and pivot counters of the call
+// (one block of 256 threads)
+__global__ __launch_bounds__(256) void k_set_call(CallPtrs *dst, const double *v, const double *b, DevStatus *st,
+                                                  unsigned long long *pcount) {
+    clear_status_body(st, pcount);
+    if (threadIdx.x == 0) {
         dst->v = v;
         dst->b = b;
     }
@@ -316,25 +316,36 @@ __global__ __launch_bounds__(256) void k_norms(int n, const int32_t *__restrict_
     norms_body(blockIdx.x, gridDim.x, n, rowptr, col, call_ptr(&call->v), r, ec, part);
 }
 
-// dst[j] = max over blocks b of part[nfield * b + j] (NaN propagates), j < nfield
+// max that propagates a NaN of either side
+__device__ __forceinline__ double max_nan(double m, double x) {
+    return (isnan(x) || isnan(m)) ? x + m : fmax(m, x);
+}
+
+// dst[j] = max over blocks b of part[nfield * b + j] (NaN propagates), j < nfield; each
+// thread keeps four maxima so that its loads are in flight together
 __device__ __forceinline__ void max_parts_body(int nblk, int nfield, const double *__restrict__ part,
                                                double *__restrict__ dst) {
     __shared__ double red[4];
     for (int j = 0; j < nfield; ++j) {
-        double m = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-            const double x = part[nfield * b + j];
-            m = (isnan(x) || isnan(m)) ? x + m : fmax(m, x);
+        double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+        const int step = blockDim.x;
+        int b = threadIdx.x;
+        for (; b + 3 * step < nblk; b += 4 * step) {
+            const double x0 = part[nfield * b + j], x1 = part[nfield * (b + step) + j];
+            const double x2 = part[nfield * (b + 2 * step) + j], x3 = part[nfield * (b + 3 * step) + j];
+            m0 = max_nan(m0, x0);
+            m1 = max_nan(m1, x1);
+            m2 = max_nan(m2, x2);
+            m3 = max_nan(m3, x3);
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            const double y = __shfl_xor(m, o);
-            m = (isnan(y) || isnan(m)) ? y + m : fmax(m, y);
-        }
+        for (; b < nblk; b += step) m0 = max_nan(m0, part[nfield * b + j]);
+        double m = max_nan(max_nan(m0, m1), max_nan(m2, m3));
+        for (int o = 32; o > 0; o >>= 1) m = max_nan(m, __shfl_xor(m, o));
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
         __syncthreads();
         if (threadIdx.x == 0) {
             double t = red[0];
-            for (int q = 1; q < 4; ++q) t = (isnan(t) || isnan(red[q])) ? t + red[q] : fmax(t, red[q]);
+            for (int q = 1; q < 4; ++q) t = max_nan(t, red[q]);
             dst[j] = t;
         }
         __syncthreads();

@@ -352,9 +352,10 @@ int enqueue_solve(kkt_handle *h, const double *b, double *x, hipStream_t s, bool
     return by_precision(h, [&](auto tag) { return enqueue_solve_t<decltype(tag)>(h, b, x, s, forward); });
 }
 
-// stores the call's values (and right-hand side, or null) for the recorded kernels
+// stores the call's values (and right-hand side, or null) for the recorded kernels and
+// clears the status words (before anything of the call can raise a flag)
 int set_call(kkt_handle *h, const double *v, const double *b, hipStream_t s) {
-    k_set_call<<<1, 64, 0, s>>>(h->d.call, v, b);
+    timed(h, KKT_PROF_UPDATE, s, [&] { k_set_call<<<1, 256, 0, s>>>(h->d.call, v, b, h->d.st, h->d.pcount); });
     HIPCHK(hipGetLastError());
     return KKT_OK;
 }
@@ -365,7 +366,6 @@ int enqueue_update(kkt_handle *h, hipStream_t s) {
     const Dev &d = h->d;
     const int n = h->sym.n;
     const int eq = h->opts.equilibrate != 0;
-    timed(h, KKT_PROF_UPDATE, s, [&] { k_clear_status<<<1, 256, 0, s>>>(d.st, d.pcount); });
     timed(h, KKT_PROF_UPDATE, s, [&] {
         k_row_scale<<<row_blocks(n), 256, 0, s>>>(n, d.a_rowptr, d.call, eq, d.r, d.er, d.st);
     });
