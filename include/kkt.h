@@ -286,13 +286,18 @@ int kkt_export_factors(kkt_handle *h, double *h_lu, double *h_r, double *h_c,
  *              pulls between them) whenever no outside dependency would wait for it, so a
  *              wide supernode costs one launch instead of one per panel; 0 = one panel per
  *              item (default: on the grid workloads the fused items serialise trailing
- *              updates that separate items run in parallel). */
+ *              updates that separate items run in parallel);
+ *   tiny_rows  narrow items whose panel and sources all have <= tiny_rows rows below run on
+ *              4 lanes instead of 16 in the launches of levels without wide items, so four
+ *              times as many are in flight (0..16; default 16; 0 = never).  Same operations
+ *              in the same order: the factors do not depend on it. */
 typedef struct {
     int32_t panel_max;
     int32_t small_rows;
     int32_t group;
     int32_t wide256;
     int32_t fuse_chains;
+    int32_t tiny_rows;
 } kkt_tuning;
 
 /* The handle's current schedule choices. */
@@ -304,7 +309,7 @@ int kkt_get_tuning(const kkt_handle *h, kkt_tuning *t);
 int kkt_set_tuning(kkt_handle *h, const kkt_tuning *t);
 
 /* Autotuner of the schedule: for each candidate (panel_max 32/16/8, small_rows 64/32,
- * group 32/16, wide256 1/0, fuse_chains 0/1) builds the schedule, binds a temporary workspace (allocated and freed
+ * group 32/16, wide256 1/0, fuse_chains 0/1; tiny_rows as set) builds the schedule, binds a temporary workspace (allocated and freed
  * here), refactors d_values (device FP64[nnz_a]) once and then reps times under HIP
  * events on stream, and keeps the fastest; returns with that schedule set and the handle
  * unbound (bind again).  best / best_ms (host, may be NULL) receive the choice and its

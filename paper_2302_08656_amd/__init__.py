@@ -44,7 +44,7 @@ class _Opts(C.Structure):
 
 class _Tuning(C.Structure):
     _fields_ = [("panel_max", C.c_int32), ("small_rows", C.c_int32), ("group", C.c_int32), ("wide256", C.c_int32),
-                ("fuse_chains", C.c_int32)]
+                ("fuse_chains", C.c_int32), ("tiny_rows", C.c_int32)]
 
 
 class _ServerOpts(C.Structure):
@@ -354,9 +354,9 @@ class KKTSolver:
             raise KKTError(rc, "kkt_get_tuning")
         return {f: getattr(t, f) for f, _ in _Tuning._fields_}
 
-    def set_tuning(self, panel_max, small_rows, group, wide256=1, fuse_chains=0):
+    def set_tuning(self, panel_max, small_rows, group, wide256=1, fuse_chains=0, tiny_rows=16):
         """Rebuilds the schedule (kkt_set_tuning); the handle must be bound again."""
-        t = _Tuning(int(panel_max), int(small_rows), int(group), int(wide256), int(fuse_chains))
+        t = _Tuning(int(panel_max), int(small_rows), int(group), int(wide256), int(fuse_chains), int(tiny_rows))
         rc = _lib().kkt_set_tuning(self._h, C.byref(t))
         if rc != OK:
             raise KKTError(rc, "kkt_set_tuning")

@@ -47,6 +47,10 @@ constexpr int kSolvePack = 64;
 // the source panel staged in LDS.  Targets sharing one source are grouped kGroup per item.
 constexpr int kSmallW = 4;
 constexpr int kSmallR = 64;
+// Narrow items whose panel and sources all have at most kTinyR rows below (tiny items) run
+// on kTinyLanes lanes in the launches of levels without wide items.
+constexpr int kTinyLanes = 4;
+constexpr int kTinyR = 16;
 constexpr int kGroup = 32;
 constexpr int kMedW = 16;
 constexpr int kMedRows = 256;
@@ -75,6 +79,7 @@ struct SchedParams {
     int32_t group = kGroup;          // targets of one source grouped into one pull item (1..kGroup)
     int32_t wide256 = 1;             // levels with many wide items, all fitting 256 rows, use 256-thread blocks
     int32_t fuse_chains = 0;         // consecutive panels of a supernode factored by one item when possible
+    int32_t tiny_rows = kTinyR;      // tiny items: narrow, every panel <= this many rows below (0 = none)
 };
 
 // Device schedule, built on the host once per pattern and uploaded by kkt_bind.
@@ -89,8 +94,9 @@ struct Schedule {
     // of at most kMedRows rows), the rest the 16-lane path (as extra blocks of the level's
     // wide launch, or as a launch of their own on a level without wide items).  An item owns the target
     // columns of its (source panel, target column) pairs, listed source-major, and then
-    // factors its panel (f_item_panel >= 0).
-    std::vector<int32_t> f_lvl, f_nlarge, f_nmed;
+    // factors its panel (f_item_panel >= 0).  The last f_ntiny[l] narrow items are tiny
+    // (4-lane groups in a launch of their own level's narrow kernel).
+    std::vector<int32_t> f_lvl, f_nlarge, f_nmed, f_ntiny;
     // levels whose 32-column wide items run in 256-thread blocks (every factored panel of the
     // level has at most 256 rows): 1, else 0
     std::vector<int32_t> f_w256;

@@ -475,10 +475,12 @@ __device__ __forceinline__ T perturb(T p, T thresh, int &npert) {
 // ----------------------------------------------------------------- 16-lane path
 
 // Source side of the update of target column k by a narrow source panel S (w <= kSmallW,
-// r <= kSmallR), loaded by one 16-lane group: S's diagonal block rows, its L rows and the
-// slots of those rows in the target.  Independent of the target's values, so the next
-// pair's source side is loaded while the current pair is applied.
+// r <= kSmallRows * kL), loaded by one group of kL lanes (16, or 4 for tiny items): S's
+// diagonal block rows, its L rows and the slots of those rows in the target; lane gl holds
+// rows gl, gl + kL, ...  Independent of the target's values, so the next pair's source side
+// is loaded while the current pair is applied.
 constexpr int kSmallRows = kSmallR / 16;
+static_assert(kTinyR == kSmallRows * kTinyLanes, "tiny items fill the rows of a 4-lane group");
 template <class T>
 struct SmallSrc {
     int ps, w, r;
@@ -488,7 +490,7 @@ struct SmallSrc {
 };
 
 // pa, pb: the pair's record {ldiag[s+1], pos, rel, ldiag[s+2]}, {ldiag[s+3], w, r, ldiag[s]}
-template <class T>
+template <int kL, class T>
 __device__ __forceinline__ void small_load_src(const RefArgs<T> &a, int4 pa, int4 pb, int gl, SmallSrc<T> &x) {
     const int ld[kSmallW] = {pb.w, pa.x, pa.w, pb.x};
     x.ps = pa.y;
@@ -500,7 +502,7 @@ __device__ __forceinline__ void small_load_src(const RefArgs<T> &a, int4 pa, int
     for (int j = 0; j < kSmallW - 1; ++j) x.l_row[j] = (j + 1 < w && gl > j && gl < w) ? a.lu[ld[j] + (gl - j)] : T(0);
 #pragma unroll
     for (int k = 0; k < kSmallRows; ++k) {
-        const int i = gl + 16 * k;
+        const int i = gl + kL * k;
         x.pos[k] = i < r ? rel[i] : 0;
 #pragma unroll
         for (int j = 0; j < kSmallW; ++j) x.lr[k][j] = (i < r && j < w) ? a.lu[ld[j] + 1 + (w - 1 - j) + i] : T(0);
@@ -509,26 +511,26 @@ __device__ __forceinline__ void small_load_src(const RefArgs<T> &a, int4 pa, int
 
 // Target side: rows s..s+w-1 of column k (from slot ps on) become final U entries (unit
 // lower solve with S's diagonal block) and the rows R of S lose L(R, S) times them.
-template <class T>
+template <int kL, class T>
 __device__ __forceinline__ void small_apply(const RefArgs<T> &a, const SmallSrc<T> &x, int gl) {
     const int w = x.w, r = x.r;
     // one round: the target's rows of S and of R
     T u = gl < w ? a.lu[x.ps + gl] : T(0);
     T tv[kSmallRows];
 #pragma unroll
-    for (int k = 0; k < kSmallRows; ++k) tv[k] = gl + 16 * k < r ? a.lu[x.pos[k]] : T(0);
+    for (int k = 0; k < kSmallRows; ++k) tv[k] = gl + kL * k < r ? a.lu[x.pos[k]] : T(0);
 #pragma unroll
     for (int j = 0; j < kSmallW - 1; ++j) {
-        const T uj = __shfl(u, j, 16);
+        const T uj = __shfl(u, j, kL);
         if (j + 1 < w && gl > j && gl < w) u = fma(-x.l_row[j], uj, u);
     }
     if (gl < w) a.lu[x.ps + gl] = u;
     T uu[kSmallW];
 #pragma unroll
-    for (int j = 0; j < kSmallW; ++j) uu[j] = __shfl(u, j, 16);
+    for (int j = 0; j < kSmallW; ++j) uu[j] = __shfl(u, j, kL);
 #pragma unroll
     for (int k = 0; k < kSmallRows; ++k) {
-        if (gl + 16 * k < r) {
+        if (gl + kL * k < r) {
             T acc = T(0);
 #pragma unroll
             for (int j = 0; j < kSmallW; ++j)
@@ -539,25 +541,26 @@ __device__ __forceinline__ void small_apply(const RefArgs<T> &a, const SmallSrc<
     __threadfence_block();   // a later source of the same column may read these rows
 }
 
-// Dense LU without pivoting of a narrow panel's block column (w <= kSmallW, r <= kSmallR).
-// pn = {s, w, r, slot of the first diagonal}.  Returns the number of replaced pivots (the
-// same value on every lane of the group).
-template <class T>
+// Dense LU without pivoting of a narrow panel's block column (w <= kSmallW,
+// r <= kSmallRows * kL) by a group of kL lanes.  pn = {s, w, r, slot of the first
+// diagonal}.  Returns the number of replaced pivots (the same value on every lane of the
+// group).
+template <int kL, class T>
 __device__ __forceinline__ int small_factor(const RefArgs<T> &a, int4 pn, int ldg, int gl, T thresh) {
     const int w = pn.y, r = pn.z;
     int sg[kSmallW];
 #pragma unroll
-    for (int c = 0; c < kSmallW; ++c) sg[c] = __shfl(ldg, c, 16) - c;
+    for (int c = 0; c < kSmallW; ++c) sg[c] = __shfl(ldg, c, kL) - c;
     // one round: the diagonal block (lane gl < w holds row gl) and this lane's rows below
     T d[kSmallW];
 #pragma unroll
     for (int c = 0; c < kSmallW; ++c) d[c] = (c < w && gl < w) ? a.lu[sg[c] + gl] : T(0);
-    constexpr int kRows = kSmallR / 16;
+    constexpr int kRows = kSmallRows;
     T x[kRows][kSmallW];
 #pragma unroll
     for (int k = 0; k < kRows; ++k)
 #pragma unroll
-        for (int c = 0; c < kSmallW; ++c) x[k][c] = (c < w && gl + 16 * k < r) ? a.lu[sg[c] + w + gl + 16 * k] : T(0);
+        for (int c = 0; c < kSmallW; ++c) x[k][c] = (c < w && gl + kL * k < r) ? a.lu[sg[c] + w + gl + kL * k] : T(0);
     int npert = 0, bad = 0;
     T U[kSmallW][kSmallW];   // final U of the diagonal block, known to every lane
 #pragma unroll
@@ -565,7 +568,7 @@ __device__ __forceinline__ int small_factor(const RefArgs<T> &a, int4 pn, int ld
         if (jj < w) {
             T ur[kSmallW];
 #pragma unroll
-            for (int c = 0; c < kSmallW; ++c) ur[c] = __shfl(d[c], jj, 16);
+            for (int c = 0; c < kSmallW; ++c) ur[c] = __shfl(d[c], jj, kL);
             const T p = perturb(ur[jj], thresh, npert);
             bad |= !isfinite(p);
             if (gl == jj) d[jj] = p;
@@ -588,7 +591,7 @@ __device__ __forceinline__ int small_factor(const RefArgs<T> &a, int4 pn, int ld
     }
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
-        if (gl + 16 * k < r) {
+        if (gl + kL * k < r) {
 #pragma unroll
             for (int jj = 0; jj < kSmallW; ++jj) {
                 if (jj < w) {
@@ -602,28 +605,30 @@ __device__ __forceinline__ int small_factor(const RefArgs<T> &a, int4 pn, int ld
             }
 #pragma unroll
             for (int c = 0; c < kSmallW; ++c)
-                if (c < w) a.lu[sg[c] + w + gl + 16 * k] = x[k][c];
+                if (c < w) a.lu[sg[c] + w + gl + kL * k] = x[k][c];
         }
     }
     if (bad) atomicOr(&a.st->flags, kFlagNonfinite);
     return npert;
 }
 
-// kBlock/16 items per block, one per 16-lane group.  kPipe: the next pair's source side is
-// loaded while the current pair is applied (fewer dependent rounds per item, more registers:
-// for levels with few items); otherwise one pair at a time (more items in flight).
-// Group g (16 lanes) runs narrow item item0 + g when g < nsmall; the wavefront's perturbed
-// pivots go to counter slot `slot`.  No block-wide synchronisation: the groups of a block
-// are independent.
-template <class T, bool kPipe>
+// One item per group of kL lanes (16; 4 for tiny items, whose panels have at most kTinyR
+// rows below, so a wavefront keeps four times as many of them in flight).  kPipe: the next
+// pair's source side is loaded while the current pair is applied (fewer dependent rounds
+// per item, more registers: for levels with few items); otherwise one pair at a time (more
+// items in flight).  Group g runs narrow item item0 + g when g < nsmall; the wavefront's
+// perturbed pivots go to counter slot `slot`.  No block-wide synchronisation: the groups of
+// a block are independent.  Every entry receives the same operations in the same order
+// whatever kL is.
+template <class T, bool kPipe, int kL = 16>
 __device__ __forceinline__ void small_group(int item0, int nsmall, const RefArgs<T> &a, int g, int slot) {
     const T thresh = pivot_threshold(a);
-    const int gl = threadIdx.x & 15;
+    const int gl = threadIdx.x & (kL - 1);
     int npert = 0;
     if (g < nsmall) {
         const int item = item0 + g;
         const int4 ia = a.item[3 * item], ib = a.item[3 * item + 1];
-        // one round: the records of up to 16 pairs (lane t holds pair p0 + t) and the
+        // one round: the records of up to kL pairs (lane t holds pair p0 + t) and the
         // diagonal slots of the panel to factor
         const int p0 = ia.y, np = ia.z - ia.y;
         int4 ra = int4{0, 0, 0, 0}, rb = int4{0, 0, 0, 0};
@@ -633,26 +638,26 @@ __device__ __forceinline__ void small_group(int item0, int nsmall, const RefArgs
         }
         const int ldg = (ia.x >= 0 && ib.y > 1 && gl > 0 && gl < ib.y) ? a.ldiag[ib.x + gl] : ib.w;
         auto rec = [&](int q, int4 &pa, int4 &pb) {
-            if (q >= 16) {   // items with more than 16 pairs read the rest on demand
+            if (q >= kL) {   // items with more than kL pairs read the rest on demand
                 pa = a.pair[2 * (p0 + q)];
                 pb = a.pair[2 * (p0 + q) + 1];
                 return;
             }
-            pa = int4{__shfl(ra.x, q, 16), __shfl(ra.y, q, 16), __shfl(ra.z, q, 16), __shfl(ra.w, q, 16)};
-            pb = int4{__shfl(rb.x, q, 16), __shfl(rb.y, q, 16), __shfl(rb.z, q, 16), __shfl(rb.w, q, 16)};
+            pa = int4{__shfl(ra.x, q, kL), __shfl(ra.y, q, kL), __shfl(ra.z, q, kL), __shfl(ra.w, q, kL)};
+            pb = int4{__shfl(rb.x, q, kL), __shfl(rb.y, q, kL), __shfl(rb.z, q, kL), __shfl(rb.w, q, kL)};
         };
         if constexpr (kPipe) {
             if (np > 0) {
                 SmallSrc<T> cur, nxt;
                 int4 pa, pb;
                 rec(0, pa, pb);
-                small_load_src(a, pa, pb, gl, cur);
+                small_load_src<kL>(a, pa, pb, gl, cur);
                 for (int q = 0; q < np; ++q) {
                     if (q + 1 < np) {
                         rec(q + 1, pa, pb);
-                        small_load_src(a, pa, pb, gl, nxt);
+                        small_load_src<kL>(a, pa, pb, gl, nxt);
                     }
-                    small_apply(a, cur, gl);
+                    small_apply<kL>(a, cur, gl);
                     cur = nxt;
                 }
             }
@@ -661,11 +666,11 @@ __device__ __forceinline__ void small_group(int item0, int nsmall, const RefArgs
                 SmallSrc<T> cur;
                 int4 pa, pb;
                 rec(q, pa, pb);
-                small_load_src(a, pa, pb, gl, cur);
-                small_apply(a, cur, gl);
+                small_load_src<kL>(a, pa, pb, gl, cur);
+                small_apply<kL>(a, cur, gl);
             }
         }
-        if (ia.x >= 0) npert = small_factor(a, ib, ldg, gl, thresh);
+        if (ia.x >= 0) npert = small_factor<kL>(a, ib, ldg, gl, thresh);
     }
     // one counter update per wavefront: group leaders contribute their count
     int c = gl == 0 ? npert : 0;
@@ -678,17 +683,25 @@ __device__ __forceinline__ void copy_block(const RefArgs<T> &a, const CopyRanges
     copy_ranges(a.copy_k, a.copy_src, a.lu, a.lucsr, c, b, nb, nthreads);
 }
 
-// A level without wide items: its narrow items, kBlock / 16 to a block; the blocks after
-// them copy the ranges c of the row-ordered factor (columns final before the launch)
+// A level without wide items: its nsmall narrow items, the last ntiny of them tiny.  The
+// first blocks run the others, kBlock / 16 to a block, the next ones the tiny items,
+// kBlock / kTinyLanes to a block; the blocks after them copy the ranges c of the
+// row-ordered factor (columns final before the launch)
 template <class T, bool kPipe>
-__global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, RefArgs<T> a, CopyRanges c) {
-    const int nsb = (nsmall + kBlock / 16 - 1) / (kBlock / 16);
-    if ((int)blockIdx.x >= nsb) {
-        copy_block(a, c, blockIdx.x - nsb, gridDim.x - nsb, kBlock);
-        return;
+__global__ __launch_bounds__(256) void k_refactor_small(int item0, int nsmall, int ntiny, RefArgs<T> a,
+                                                        CopyRanges c) {
+    const int nn = nsmall - ntiny;
+    const int nsb = (nn + kBlock / 16 - 1) / (kBlock / 16);
+    const int ntb = (ntiny + kBlock / kTinyLanes - 1) / (kBlock / kTinyLanes);
+    const int b = blockIdx.x, slot = b * 4 + (threadIdx.x >> 6);
+    if (b < nsb) {
+        small_group<T, kPipe>(item0, nn, a, b * (kBlock / 16) + (threadIdx.x >> 4), slot);
+    } else if (b < nsb + ntb) {
+        small_group<T, kPipe, kTinyLanes>(item0 + nn, ntiny, a,
+                                          (b - nsb) * (kBlock / kTinyLanes) + (threadIdx.x / kTinyLanes), slot);
+    } else {
+        copy_block(a, c, b - nsb - ntb, gridDim.x - nsb - ntb, kBlock);
     }
-    small_group<T, kPipe>(item0, nsmall, a, blockIdx.x * (kBlock / 16) + (threadIdx.x >> 4),
-                          blockIdx.x * 4 + (threadIdx.x >> 6));
 }
 
 // ----------------------------------------------------------------- 512-thread path

@@ -200,6 +200,12 @@ inline int row_blocks(int n) {
 }
 inline int col_blocks(int n) { return (int)std::max<unsigned>(1, blocks_for((int64_t)n * kColLanes, 256)); }
 inline int norm_blocks(int n) { return std::min(kNormRowBlocks, row_blocks(n)); }
+// blocks of `threads` threads for ns narrow items, the last nt of them tiny (one 16-lane
+// group per item, one kTinyLanes-lane group per tiny item)
+inline int narrow_blocks(int ns, int nt, int threads) {
+    if (ns == 0) return 0;
+    return (int)(blocks_for(ns - nt, threads / 16) + blocks_for(nt, threads / kTinyLanes));
+}
 
 // ends the open run of launches of the profiler (records its end event)
 void close_run(kkt_handle *h) {
@@ -461,13 +467,14 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s, bool fused) {
             // the last launch
             const CopyRanges c{fused ? g.copy_lat[copied] : 0, fused ? g.copy_lat[l] : 0, 0, 0};
             if (fused) copied = l;
-            const int grid = (int)blocks_for(ns, kBlock / 16) + copy_blocks(h, copy_count(c), kBlock);
+            const int nt = g.f_ntiny[l];
+            const int grid = narrow_blocks(ns, nt, kBlock) + copy_blocks(h, copy_count(c), kBlock);
             timed(h, KKT_PROF_REFACTOR_SMALL, s, [&] {
                 // many items: keep more in flight; few: shorten each item's dependent chain
                 if (ns > kSmallPipeMax)
-                    k_refactor_small<T, false><<<grid, kBlock, 0, s>>>(i0, ns, a, c);
+                    k_refactor_small<T, false><<<grid, kBlock, 0, s>>>(i0, ns, nt, a, c);
                 else
-                    k_refactor_small<T, true><<<grid, kBlock, 0, s>>>(i0, ns, a, c);
+                    k_refactor_small<T, true><<<grid, kBlock, 0, s>>>(i0, ns, nt, a, c);
             }, true);
         }
         if (!nb && !nm) continue;
@@ -1216,6 +1223,7 @@ int kkt_get_tuning(const kkt_handle *h, kkt_tuning *t) {
     t->group = h->sch.params.group;
     t->wide256 = h->sch.params.wide256;
     t->fuse_chains = h->sch.params.fuse_chains;
+    t->tiny_rows = h->sch.params.tiny_rows;
     return KKT_OK;
 }
 
@@ -1265,7 +1273,8 @@ int kkt_set_tuning(kkt_handle *h, const kkt_tuning *t) {
         const int rc = unbind(h);
         if (rc) return rc;
     }
-    return set_schedule(h, SchedParams{t->panel_max, t->small_rows, t->group, t->wide256, t->fuse_chains});
+    return set_schedule(h, SchedParams{t->panel_max, t->small_rows, t->group, t->wide256, t->fuse_chains,
+                                       t->tiny_rows});
 }
 
 int kkt_autotune(kkt_handle *h, const double *d_values, int32_t reps, kkt_tuning *best, double *best_ms,
@@ -1289,7 +1298,7 @@ int kkt_autotune(kkt_handle *h, const double *d_values, int32_t reps, kkt_tuning
             for (int32_t gr : {32, 16})
             for (int32_t w2 : {1, 0})
             for (int32_t fc : {0, 1}) {
-                rc = set_schedule(h, SchedParams{pm, sr, gr, w2, fc});
+                rc = set_schedule(h, SchedParams{pm, sr, gr, w2, fc, start.tiny_rows});
                 if (rc == KKT_ERR_SCHEDULE) { rc = KKT_OK; continue; }   // not a valid cut for this pattern
                 if (rc) break;
                 size_t bytes = 0;
@@ -1317,7 +1326,7 @@ int kkt_autotune(kkt_handle *h, const double *d_values, int32_t reps, kkt_tuning
                 if (urc) { rc = urc; break; }
                 if (ms / reps < win_ms) {
                     win_ms = ms / reps;
-                    win = SchedParams{pm, sr, gr, w2, fc};
+                    win = SchedParams{pm, sr, gr, w2, fc, start.tiny_rows};
                 }
             }
     (void)hipEventDestroy(e0);
@@ -1331,6 +1340,7 @@ int kkt_autotune(kkt_handle *h, const double *d_values, int32_t reps, kkt_tuning
         best->group = win.group;
         best->wide256 = win.wide256;
         best->fuse_chains = win.fuse_chains;
+        best->tiny_rows = win.tiny_rows;
     }
     if (best_ms) *best_ms = win_ms;
     return KKT_OK;

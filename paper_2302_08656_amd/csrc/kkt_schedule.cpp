@@ -31,7 +31,7 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
     const int32_t n = s.n;
     if (prm.panel_max < 1 || prm.panel_max > kPanelMax || prm.small_rows < 0 || prm.small_rows > kSmallR ||
         prm.group < 1 || prm.group > kGroup || (prm.wide256 != 0 && prm.wide256 != 1) ||
-        (prm.fuse_chains != 0 && prm.fuse_chains != 1))
+        (prm.fuse_chains != 0 && prm.fuse_chains != 1) || prm.tiny_rows < 0 || prm.tiny_rows > kTinyR)
         return KKT_ERR_ARG;
     g = Schedule{};
     g.params = prm;
@@ -174,9 +174,11 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
     for (int32_t p = 0; p < np; ++p) gsize[grp[p]]++;
     auto pw = [&](int32_t p) { return g.pan_start[p + 1] - g.pan_start[p]; };
     auto is_small = [&](int32_t p) { return pw(p) <= kSmallW && g.pan_r[p] <= prm.small_rows; };
+    auto is_tiny = [&](int32_t p) { return is_small(p) && g.pan_r[p] <= prm.tiny_rows; };
     g.f_lvl.assign(1, 0);
     g.f_nlarge.clear();
     g.f_nmed.clear();
+    g.f_ntiny.clear();
     g.f_w256.clear();
     g.f_item_panel.clear();
     g.f_item_npan.clear();
@@ -192,7 +194,7 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
         std::vector<std::pair<int32_t, int32_t>> pairs;   // (source, target)
         bool small;
         double cost;
-        int kind = 0;   // 0 wide (up to panel_max columns), 1 medium, 2 narrow
+        int kind = 0;   // 0 wide (up to panel_max columns), 1 medium, 2 narrow, 3 tiny
         int32_t npan = 1;   // panels factored (a group's leader and the panels after it)
     };
     for (int32_t l = 0; l < nlev; ++l) {
@@ -238,8 +240,10 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
         for (auto &it : items) {
             std::sort(it.pairs.begin(), it.pairs.end());
             int32_t mw = it.panel >= 0 ? pw(it.panel) : 0;
+            bool tiny = it.small && (it.panel < 0 || is_tiny(it.panel));
             for (const auto &pr : it.pairs) {
                 if (!is_small(pr.first)) it.small = false;
+                if (!is_tiny(pr.first)) tiny = false;
                 it.cost += (double)pw(pr.first) * (pw(pr.first) + g.pan_r[pr.first]);
                 mw = std::max(mw, pw(pr.first));
             }
@@ -249,7 +253,7 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
             }
             const bool fits_med =
                 mw <= kMedW && (it.panel < 0 || pw(it.panel) + g.pan_r[it.panel] <= kMedRows) && it.npan == 1;
-            it.kind = it.small ? 2 : fits_med ? 1 : 0;
+            it.kind = it.small ? (tiny ? 3 : 2) : fits_med ? 1 : 0;
         }
         // the medium configuration only where a level has no item that needs the big one
         // (one launch per level for the wide items)
@@ -271,8 +275,9 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
             if (a.kind != b.kind) return a.kind < b.kind;
             return a.cost > b.cost;
         });
-        int32_t nlarge = 0, nmed = 0;
+        int32_t nlarge = 0, nmed = 0, ntiny = 0;
         for (const auto &it : items) {
+            ntiny += it.kind == 3;
             // the wide path solves a source's targets kGroup at a time on the lanes of one
             // wavefront; narrow items take their pairs one at a time
             nlarge += !it.small;
@@ -301,6 +306,7 @@ int build_schedule(const Symbolic &s, const SchedParams &prm, Schedule &g) {
         }
         g.f_nlarge.push_back(nlarge);
         g.f_nmed.push_back(nmed);
+        g.f_ntiny.push_back(ntiny);
         g.f_lvl.push_back((int32_t)g.f_item_panel.size());
     }
     if (!by_launch[nlev].empty()) return KKT_ERR_SCHEDULE;   // top panels have no targets

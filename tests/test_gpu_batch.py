@@ -74,8 +74,11 @@ def test_batch_rejects_bad_input():
     b.close()
 
 
-@pytest.mark.parametrize("tuning", [(16, 32, 16, 1, 1), (8, 64, 32, 0, 1), (32, 0, 8, 1, 0), (32, 64, 32, 0, 0),
-                                    (32, 64, 32, 1, 1)])
+TUNING_FIELDS = ("panel_max", "small_rows", "group", "wide256", "fuse_chains", "tiny_rows")
+
+
+@pytest.mark.parametrize("tuning", [(16, 32, 16, 1, 1, 16), (8, 64, 32, 0, 1, 0), (32, 0, 8, 1, 0, 16),
+                                    (32, 64, 32, 0, 0, 0), (32, 64, 32, 1, 1, 8)])
 def test_set_tuning_parity(tuning):
     print(f"[gpu] tuned schedule {tuning}", flush=True)
     q = kktgen.make_sequence(kktgen.small(2000, config_id=147, steps=2))
@@ -83,7 +86,7 @@ def test_set_tuning_parity(tuning):
     so = oracle.Symbolic(q.n, q.rowptr, q.colind, v0)
     sk = K.KKTSolver(q.n, q.rowptr, q.colind, v0)
     sk.set_tuning(*tuning)
-    assert sk.tuning() == dict(zip(("panel_max", "small_rows", "group", "wide256", "fuse_chains"), tuning))
+    assert sk.tuning() == dict(zip(TUNING_FIELDS, tuning))
     sk.bind()
     for t in range(q.steps):
         v, b = q.values(t), q.rhs(t)
@@ -97,6 +100,37 @@ def test_set_tuning_parity(tuning):
         x, info = sk.refine(cuda(b))
         _, berr = oracle.residual(q.n, q.rowptr, q.colind, v, x.cpu().numpy(), b)
         assert info[0].status == K.OK and berr <= 1e-10
+
+
+@pytest.mark.parametrize("spec", [kktgen.small(2000, config_id=147, steps=2), kktgen.config(1)],
+                         ids=["grid2000", "grid25k"])
+def test_tiny_items_bitwise(spec):
+    # narrow items on 4-lane groups (tiny_rows 16, the default) or all on 16 lanes (0): the
+    # same operations in the same order, so the factors agree bit for bit
+    print(f"[gpu] tiny items on/off {spec.name}", flush=True)
+    q = kktgen.make_sequence(spec)
+    on = K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0))
+    off = K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0))
+    t = off.tuning()
+    assert t["tiny_rows"] == 16
+    off.set_tuning(t["panel_max"], t["small_rows"], t["group"], t["wide256"], t["fuse_chains"], 0)
+    on.bind()
+    off.bind()
+    for step in (0, q.steps - 1):
+        v = cuda(q.values(step))
+        on.refactor(v)
+        off.refactor(v)
+        assert on.refactor_status() == off.refactor_status()
+        lu_on, r_on, c_on = on.export_factors()
+        lu_off, r_off, c_off = off.export_factors()
+        assert np.array_equal(lu_on.view(np.uint64), lu_off.view(np.uint64)), step
+        assert np.array_equal(r_on, r_off) and np.array_equal(c_on, c_off)
+        b = cuda(q.rhs(step))
+        x_on, _ = on.refine(b)
+        x_off, _ = off.refine(b)
+        assert torch.equal(x_on, x_off), step
+    on.close()
+    off.close()
 
 
 def test_autotune_picks_a_valid_schedule():

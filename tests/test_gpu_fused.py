@@ -67,7 +67,7 @@ def test_fused_equals_refactor_then_refine(name, spec, kw):
     if fc:
         for sk in (sep, fus):
             t = sk.tuning()
-            sk.set_tuning(t["panel_max"], t["small_rows"], t["group"], t["wide256"], fc)
+            sk.set_tuning(t["panel_max"], t["small_rows"], t["group"], t["wide256"], fc, t["tiny_rows"])
             sk.bind()
     for t in range(q.steps):
         v, b, x, info = same_step(q, t, sep, fus)

@@ -155,6 +155,25 @@ def test_call_order_errors_without_device():
     assert sk.workspace_bytes(1) > 8 * (sk.nnz_lu * 2)
 
 
+def test_tiny_rows_tuning_host_checks():
+    """tiny_rows (4-lane narrow items) defaults to 16, accepts 0..16 and only reorders items
+    within a level: the workspace size does not change with it."""
+    q = kktgen.make_sequence(kktgen.small(300, config_id=140, steps=1))
+    sk = K.KKTSolver(q.n, q.rowptr, q.colind, q.values(0))
+    t = sk.tuning()
+    assert t["tiny_rows"] == 16
+    base = (t["panel_max"], t["small_rows"], t["group"], t["wide256"], t["fuse_chains"])
+    ws = sk.workspace_bytes(1)
+    for bad in (-1, 17):
+        with pytest.raises(K.KKTError) as e:
+            sk.set_tuning(*base, bad)
+        assert e.value.code == K.ERR_ARG
+    for ok in (0, 8, 16):
+        sk.set_tuning(*base, ok)
+        assert sk.tuning()["tiny_rows"] == ok
+        assert sk.workspace_bytes(1) == ws
+
+
 def test_scratch_bind_host_checks():
     """kkt_bind_scratch rejects bad arguments and systems whose workspace exceeds the static
     array before it touches a device; the binding's size constant matches the header's."""
