@@ -46,7 +46,9 @@ constexpr int kFuseSolveBlocks = 256;
 constexpr int kCopyBlocksPerCu = 4;
 constexpr int kDotBlocks = 512;
 constexpr int kNormRowBlocks = 4096;   // most blocks of the row-norm pass (8 lanes per row)
-constexpr int kSmallPipeMax = 100000;  // narrow items per level up to which the pipelined variant runs
+// narrow items per level up to which the pipelined variant runs (a tiny item counts a quarter:
+// its 4-lane group keeps four times as many items in flight)
+constexpr int kSmallPipeMax = 100000;
 constexpr int kNormBlocks = 4096;
 constexpr int kMaxSweeps = 1024;       // largest approx_sweeps accepted
 constexpr int kMaxRestart = 64;
@@ -469,9 +471,12 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s, bool fused) {
             if (fused) copied = l;
             const int nt = g.f_ntiny[l];
             const int grid = narrow_blocks(ns, nt, kBlock) + copy_blocks(h, copy_count(c), kBlock);
+            // many items: keep more in flight; few: shorten each item's dependent chain (only
+            // items that pull have one; a level of leaves keeps the plain variant's occupancy)
+            const bool pulls = g.f_item_pair[i0 + ns] > g.f_item_pair[i0];
+            const bool pipe = pulls && (ns - nt) + (nt + kTinyLanes - 1) / kTinyLanes <= kSmallPipeMax;
             timed(h, KKT_PROF_REFACTOR_SMALL, s, [&] {
-                // many items: keep more in flight; few: shorten each item's dependent chain
-                if (ns > kSmallPipeMax)
+                if (!pipe)
                     k_refactor_small<T, false><<<grid, kBlock, 0, s>>>(i0, ns, nt, a, c);
                 else
                     k_refactor_small<T, true><<<grid, kBlock, 0, s>>>(i0, ns, nt, a, c);
