@@ -393,10 +393,19 @@ __device__ __forceinline__ void copy_ranges(const int32_t *__restrict__ copy_k, 
     }
 }
 
+// the copy on all blocks but the last when pcount is set: that one sums the replaced-pivot
+// counter slots into *pout (every refactorization launch has finished)
 template <class T>
-__global__ void k_to_csr(CopyRanges c, const int32_t *__restrict__ copy_k, const int32_t *__restrict__ copy_src,
-                         const T *__restrict__ lu, T *__restrict__ lucsr) {
-    copy_ranges(copy_k, copy_src, lu, lucsr, c, blockIdx.x, gridDim.x, blockDim.x);
+__global__ __launch_bounds__(256) void k_to_csr(CopyRanges c, const int32_t *__restrict__ copy_k,
+                                                const int32_t *__restrict__ copy_src, const T *__restrict__ lu,
+                                                T *__restrict__ lucsr, const unsigned long long *__restrict__ pcount,
+                                                unsigned long long *pout) {
+    const int nb = (int)gridDim.x - (pcount ? 1 : 0);
+    if ((int)blockIdx.x == nb) {
+        sum_counts_body(pcount, pout);
+        return;
+    }
+    copy_ranges(copy_k, copy_src, lu, lucsr, c, blockIdx.x, nb, blockDim.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1763,12 +1772,12 @@ __device__ __forceinline__ void fused_forward_block(const FuseArgs<T> &f, int bl
 // bp = r[P] .* b[P] (b = b0, or the recorded call's right-hand side when b0 is null); with
 // mark, every unknown of the persistent mode starts unset; the first ntick item tickets start
 // at zero (ntick <= n, or the grid covers ntick threads)
-__global__ void k_solve_reset(int n, const double *__restrict__ b0, const CallPtrs *call,
-                              const double *__restrict__ r, const int32_t *__restrict__ P, double *__restrict__ bp,
-                              double *__restrict__ y, double *__restrict__ xt, double *__restrict__ psum,
-                              double *__restrict__ usum, int mark, int ntick, int *__restrict__ tick) {
-    const double *__restrict__ b = b0 ? b0 : call_ptr(&call->b);   // b0 null: the recorded call's
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void solve_reset_body(int i, int n, const double *__restrict__ b,
+                                                 const double *__restrict__ r, const int32_t *__restrict__ P,
+                                                 double *__restrict__ bp, double *__restrict__ y,
+                                                 double *__restrict__ xt, double *__restrict__ psum,
+                                                 double *__restrict__ usum, int mark, int ntick,
+                                                 int *__restrict__ tick) {
     if (i < ntick) tick[i] = 0;
     if (i < n) {
         const int pi = P[i];
@@ -1781,6 +1790,37 @@ __global__ void k_solve_reset(int n, const double *__restrict__ b0, const CallPt
             usum[i] = u;
         }
     }
+}
+
+__global__ void k_solve_reset(int n, const double *__restrict__ b0, const CallPtrs *call,
+                              const double *__restrict__ r, const int32_t *__restrict__ P, double *__restrict__ bp,
+                              double *__restrict__ y, double *__restrict__ xt, double *__restrict__ psum,
+                              double *__restrict__ usum, int mark, int ntick, int *__restrict__ tick) {
+    const double *__restrict__ b = b0 ? b0 : call_ptr(&call->b);   // b0 null: the recorded call's
+    solve_reset_body(blockIdx.x * blockDim.x + threadIdx.x, n, b, r, P, bp, y, xt, psum, usum, mark, ntick, tick);
+}
+
+// The column pass of the value update with the solve's set-up for the recorded call's
+// right-hand side (k_solve_reset with the unknowns marked unset) on its first nset blocks:
+// the set-up reads only the row scales and the call's inputs, so its blocks run beside the
+// column pass's gathers instead of in a launch of their own.
+template <class T>
+__global__ __launch_bounds__(256) void k_col_store_setup(int n, const int32_t *__restrict__ colptr,
+                                                         const int2 *__restrict__ src,
+                                                         const int32_t *__restrict__ Q, const CallPtrs *call,
+                                                         const int16_t *__restrict__ er, int scale,
+                                                         double *__restrict__ c, int16_t *__restrict__ ec,
+                                                         T *__restrict__ lu, int nset, const double *__restrict__ r,
+                                                         const int32_t *__restrict__ P, double *__restrict__ bp,
+                                                         double *__restrict__ y, double *__restrict__ xt,
+                                                         double *__restrict__ psum, double *__restrict__ usum,
+                                                         int ntick, int *__restrict__ tick) {
+    if ((int)blockIdx.x < nset) {
+        solve_reset_body(blockIdx.x * blockDim.x + threadIdx.x, n, call_ptr(&call->b), r, P, bp, y, xt, psum, usum,
+                         1, ntick, tick);
+        return;
+    }
+    col_store_body<T>(blockIdx.x - nset, n, colptr, src, Q, call_ptr(&call->v), er, scale, c, ec, lu);
 }
 
 // Approximate triangular solves for the preconditioner inside refinement (the triangular

@@ -369,8 +369,9 @@ int set_call(kkt_handle *h, const double *v, const double *b, hipStream_t s) {
 }
 
 // value update of the values stored by set_call: scale factors, scaled values into the
-// factor, norms
-int enqueue_update(kkt_handle *h, hipStream_t s) {
+// factor, norms; with setup, the column pass also runs the solve's set-up for the stored
+// right-hand side (the unknowns marked unset, ntick tickets cleared)
+int enqueue_update(kkt_handle *h, hipStream_t s, bool setup = false, int ntick = 0) {
     const Dev &d = h->d;
     const int n = h->sym.n;
     const int eq = h->opts.equilibrate != 0;
@@ -380,8 +381,15 @@ int enqueue_update(kkt_handle *h, hipStream_t s) {
     timed(h, KKT_PROF_UPDATE, s, [&] {
         by_precision(h, [&](auto tag) {
             using T = decltype(tag);
-            k_col_store<T><<<col_blocks(n), 256, 0, s>>>(n, d.colptr, d.lu_src, d.Q, d.call, d.er, eq, d.c,
-                                                      d.ec, static_cast<T *>(d.lu));
+            if (setup) {
+                const int nset = (int)blocks_for(std::max(n, ntick), 256);
+                k_col_store_setup<T><<<nset + col_blocks(n), 256, 0, s>>>(
+                    n, d.colptr, d.lu_src, d.Q, d.call, d.er, eq, d.c, d.ec, static_cast<T *>(d.lu), nset, d.r, d.P,
+                    d.bp, d.y, d.xt, d.psum, d.usum, ntick, d.tick);
+            } else {
+                k_col_store<T><<<col_blocks(n), 256, 0, s>>>(n, d.colptr, d.lu_src, d.Q, d.call, d.er, eq, d.c,
+                                                          d.ec, static_cast<T *>(d.lu));
+            }
             return 0;
         });
     });
@@ -445,17 +453,10 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s, bool fused) {
                           d.bp, d.y, d.xt, nullptr, d.psum, d.usum, &d.st->abort, d.tick + 2};
     const int nfl = (int)g.l_lvl.size() - 1;
     {
-        const int rc = enqueue_update(h, s);
+        // fused: the column pass also sets up the solve (bp from the stored right-hand side,
+        // the unset unknowns and the tickets, the forward tail's included)
+        const int rc = enqueue_update(h, s, fused, 3);
         if (rc) return rc;
-    }
-    if (fused) {
-        // bp from the stored right-hand side, the unset unknowns and the tickets (the forward
-        // tail's included)
-        const int n = h->sym.n, ntick = 3;
-        timed(h, KKT_PROF_LSOLVE, s, [&] {
-            k_solve_reset<<<blocks_for(std::max(n, ntick), 256), 256, 0, s>>>(n, nullptr, d.call, d.r, d.P, d.bp, d.y,
-                                                                             d.xt, d.psum, d.usum, 1, ntick, d.tick);
-        });
     }
     int copied = 0, solved = 0;   // fused: levels whose columns a launch copies, forward levels launched
     for (int l = 0; l < nlev; ++l) {
@@ -532,9 +533,12 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s, bool fused) {
     // upper entries not copied yet; then the remaining forward levels
     const CopyRanges rest = fused ? CopyRanges{g.copy_lat[copied], u0, ucopied, (int)g.copy_k.size()}
                                   : copy_rest(g, ncopy);
-    if (copy_count(rest) > 0)
+    // the copy's last block sums the replaced-pivot counters (a launch of their own without a copy)
+    const bool copy_rest_left = copy_count(rest) > 0;
+    if (copy_rest_left)
         timed(h, KKT_PROF_TO_CSR, s, [&] {
-            k_to_csr<T><<<blocks_for(copy_count(rest), 256), 256, 0, s>>>(rest, d.copy_k, d.copy_src, a.lu, a.lucsr);
+            k_to_csr<T><<<blocks_for(copy_count(rest), 256) + 1, 256, 0, s>>>(rest, d.copy_k, d.copy_src, a.lu,
+                                                                             a.lucsr, d.pcount, &d.st->perturbed);
         });
     if (fused && solved < nfl) {
         const int j0 = g.l_lvl[solved], j1 = g.l_lvl[nfl];
@@ -542,7 +546,8 @@ int enqueue_levels_t(kkt_handle *h, hipStream_t s, bool fused) {
             k_lsolve_persistent<T, true><<<std::min(j1 - j0, h->grid_l), kBlock, 0, s>>>(j0, j1, fs);
         });
     }
-    timed(h, KKT_PROF_UPDATE, s, [&] { k_sum_counts<<<1, 256, 0, s>>>(d.pcount, &d.st->perturbed); });
+    if (!copy_rest_left)
+        timed(h, KKT_PROF_UPDATE, s, [&] { k_sum_counts<<<1, 256, 0, s>>>(d.pcount, &d.st->perturbed); });
     HIPCHK(hipGetLastError());
     return KKT_OK;
 }
@@ -569,13 +574,15 @@ int residual_berr(kkt_handle *h, const double *x, const double *b, double *berr,
         k_residual<<<kNormBlocks, 256, 0, s>>>(n, d.a_rowptr, d.a_colind, h->d_values, x, b, d.res, d.part);
     });
     timed(h, KKT_PROF_RESIDUAL, s, [&] { k_max_parts<<<1, 256, 0, s>>>(kNormBlocks, 3, d.part, &d.rn->rnorm); });
-    HIPCHK(hipMemcpyAsync(h->h_small, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(h->h_small + 8, d.rn, sizeof(ResNorms), hipMemcpyDeviceToHost, s));
+    // the residual norms are carved right after the status block: one read-back takes both
+    const size_t off = static_cast<size_t>(reinterpret_cast<const char *>(d.rn) - reinterpret_cast<const char *>(d.st));
+    if (off < sizeof(DevStatus) || off + sizeof(ResNorms) > sizeof(h->h_stage)) return KKT_ERR_DEVICE;
+    HIPCHK(hipMemcpyAsync(h->h_small, d.st, off + sizeof(ResNorms), hipMemcpyDeviceToHost, s));
     HIPCHK(sync_fold(h, s));
     DevStatus st;
     ResNorms rn;
     std::memcpy(&st, h->h_small, sizeof(st));
-    std::memcpy(&rn, h->h_small + 8, sizeof(rn));
+    std::memcpy(&rn, reinterpret_cast<const char *>(h->h_small) + off, sizeof(rn));
     if (sto) *sto = st;
     if (st.abort) return KKT_ERR_DEVICE;
     *den = st.anorm * rn.xnorm + rn.bnorm;
